@@ -1,0 +1,201 @@
+"""The additive piece-wise smoother of the oracle (Sec. 3, eq. of L_l^{-1}).
+
+Test infrastructure only.
+
+L^{-1} = sum_T P_T L_T^{-1} P_T^T over the pieces T (patch interiors, faces,
+edges, vertices), P_T the indicator of the piece's dofs.
+
+Interior pieces: the subspace-corrected mass smoother, which the paper takes
+from its reference [HT:2016] without restating it.  Reading used here (parity
+unpinned against the paper; pinned only by self-consistency):
+
+* per direction c, on the 1D space of interior functions (indices 1..n-2,
+  vanishing at both ends), the subspace
+  S~ = {u : the even derivatives of order 2l, 1 <= l, 2l < p, vanish at 0 and 1}
+  and its M-orthogonal complement S1;
+* on S~ the 1D operator is sigma_c M (sigma_c = 5 h_c^{-2}, h_c = 1/nel_c, the
+  value sigma = h^{-2}/0.2 of Sec. 5), on S1 it is K;
+* the d-variate piece operators L_alpha = sum_c (x)_{j != c} M_{alpha_j} (x) Khat_{c,alpha_c}
+  over the 2^d products of these subspaces, times the geometry factor omega_k;
+* applied as (x)U_c D^{-1} (x)U_c^T, where U_c = [M-orthonormal basis of S~,
+  M-orthonormal eigenvectors of K on S1] and D = omega * sum_c mu_c.  The
+  tests check this against the literal sum over alpha.
+
+Faces (3D): the operator (h/p)(Kcal + p^2 h^{-2} Mcal) of Sec. 3 with Kcal
+replaced by the same subspace-corrected construction in the two tangential
+directions: D = omega (h/p)(mu_t0 + mu_t1 + p^2/h^2).
+Edges: L_T = omega ((h/p)^{d-1} K + (h/p)^{d-3} M) on the edge-interior
+functions, solved exactly.  Vertices: L_T = omega (h/p)^{d-2}.
+h for an interface piece is the geometric mean of 1/nel over the adjacent
+patches' normal directions; omega is the mean of the adjacent patches' omega.
+"""
+import itertools
+
+import numpy as np
+import scipy.linalg as sla
+
+from . import bspline
+
+
+def interior_1d(p, nel):
+    """Knots, interior mass/stiffness (m x m, m = n-2) and the constraint rows."""
+    t = bspline.open_uniform_knots(p, nel)
+    M, K = bspline.mass_stiffness(t, p)
+    n = M.shape[0]
+    Mi, Ki = M[1:n - 1, 1:n - 1], K[1:n - 1, 1:n - 1]
+    rows = []
+    l = 1
+    while 2 * l < p:
+        for x in (0.0, 1.0):
+            rows.append(bspline.eval_basis(t, p, [x], 2 * l)[0, 1:n - 1])
+        l += 1
+    C = np.array(rows).reshape(-1, n - 2)
+    return Mi, Ki, C
+
+
+def null_space(C, m, tol=1e-10):
+    """Orthonormal basis of {v : C v = 0} (rows normalised; relative SVD cut)."""
+    if C.shape[0] == 0:
+        return np.eye(m)
+    Cn = C / np.linalg.norm(C, axis=1, keepdims=True)
+    _, s, Vt = np.linalg.svd(Cn)
+    rank = int(np.sum(s > tol * s[0]))
+    return Vt[rank:].T
+
+
+def split_basis(Mi, Ki, C, sigma):
+    """U = [U0 U1], mu, dim S~ of the 1D splitting (see module header)."""
+    m = Mi.shape[0]
+    Z = null_space(C, m)
+    k0 = Z.shape[1]
+    if k0 > 0:
+        L0 = np.linalg.cholesky(Z.T @ Mi @ Z)
+        U0 = sla.solve_triangular(L0, Z.T, lower=True).T
+    else:
+        U0 = np.zeros((m, 0))
+    if k0 < m:
+        Y = null_space(Z.T @ Mi, m) if k0 > 0 else np.eye(m)
+        lam, V = sla.eigh(Y.T @ Ki @ Y, Y.T @ Mi @ Y)
+        U1 = Y @ V
+    else:
+        lam, U1 = np.zeros(0), np.zeros((m, 0))
+    U = np.concatenate([U0, U1], axis=1)
+    mu = np.concatenate([np.full(k0, sigma), lam])
+    return U, mu, k0, Z
+
+
+def _modes(T, mats, transpose):
+    """Apply mats[c] (or its transpose) along every direction c of the tensor T
+    (T indexed [.., i1, i0], direction 0 last)."""
+    d = T.ndim
+    for c in range(d):
+        A = mats[c].T if transpose else mats[c]
+        T = np.moveaxis(np.tensordot(A, T, axes=([1], [d - 1 - c])), 0, d - 1 - c)
+    return T
+
+
+class Smoother:
+    """L_l^{-1} on global free vectors of one level."""
+
+    def __init__(self, prob, level, dm, pcs, omegas, sigma_scale=5.0):
+        self.p = p = prob.degree
+        d = prob.dim
+        nel = prob.nel(level)
+        self.d = d
+        self.N = dm.N
+        self.pieces = []
+        cache = {}
+
+        def one_d(e):
+            if e not in cache:
+                Mi, Ki, C = interior_1d(p, e)
+                U, mu, _, _ = split_basis(Mi, Ki, C, sigma_scale * e * e)
+                cache[e] = (Mi, Ki, U, mu)
+            return cache[e]
+
+        for pc in pcs:
+            k = pc.owner
+            adj = [a for a, _ in pc.adjacent]
+            om = float(np.mean([omegas[a] for a in adj]))
+            if pc.kind == "interior":
+                ops = [one_d(int(nel[k][c])) for c in range(d)]
+                Us = [o[2] for o in ops]
+                D = om * sum(np.meshgrid(*[o[3] for o in reversed(ops)], indexing="ij")[d - 1 - c]
+                             for c in range(d))
+                self.pieces.append(("fd", pc.dofs, Us, D))
+                continue
+            hs = [1.0 / nel[a][c] for a, bd in pc.adjacent for c in bd]
+            h = float(np.exp(np.mean(np.log(hs))))
+            if pc.kind == "vertex":
+                self.pieces.append(("scalar", pc.dofs, om * (h / p) ** (d - 2)))
+            elif pc.kind == "edge":
+                c = [c for c in range(d) if c not in pc.bdirs][0]
+                Mi, Ki, _, _ = one_d(int(nel[k][c]))
+                L = om * ((h / p) ** (d - 1) * Ki + (h / p) ** (d - 3) * Mi)
+                self.pieces.append(("dense", pc.dofs, sla.cho_factor(L), L))
+            else:  # face, d == 3
+                tang = [c for c in range(d) if c not in pc.bdirs]
+                ops = [one_d(int(nel[k][c])) for c in tang]
+                Us = [o[2] for o in ops]
+                mu0, mu1 = ops[0][3], ops[1][3]
+                D = om * (h / p) * (mu1[:, None] + mu0[None, :] + p * p / (h * h))
+                self.pieces.append(("fd", pc.dofs, Us, D))
+        self.shapes = {id(pc): pc.local for pc in pcs}
+        self._local = [pc.local for pc in pcs]
+
+    def apply(self, r):
+        z = np.zeros_like(r)
+        for piece, shape in zip(self.pieces, self._local):
+            kind, dofs = piece[0], piece[1]
+            if kind == "scalar":
+                z[dofs] = r[dofs] / piece[2]
+            elif kind == "dense":
+                z[dofs] = sla.cho_solve(piece[2], r[dofs])
+            else:
+                Us, D = piece[2], piece[3]
+                T = r[dofs].reshape(list(reversed(shape)))
+                T = _modes(T, Us, transpose=True) / D
+                z[dofs] = _modes(T, Us, transpose=False).reshape(-1)
+        return z
+
+    def dense_inverse(self):
+        """Explicit L^{-1} (small problems only)."""
+        out = np.zeros((self.N, self.N))
+        for j in range(self.N):
+            e = np.zeros(self.N)
+            e[j] = 1.0
+            out[:, j] = self.apply(e)
+        return out
+
+
+def literal_interior_inverse(Mis, Kis, Cs, sigmas, om):
+    """Interior-piece inverse as the literal additive sum over alpha in {0,1}^d of
+    Q_alpha L_alpha^{-1} Q_alpha^T, with Q_alpha the Kronecker product of bases of
+    the 1D subspaces (no eigen-decomposition).  Used to pin ``split_basis``."""
+    d = len(Mis)
+    subs = []
+    for Mi, Ki, C, s in zip(Mis, Kis, Cs, sigmas):
+        m = Mi.shape[0]
+        Z = null_space(C, m)
+        Y = null_space(Z.T @ Mi, m) if Z.shape[1] > 0 else np.eye(m)
+        subs.append({0: (Z, s * Mi), 1: (Y, Ki)})
+    n = int(np.prod([M.shape[0] for M in Mis]))
+    out = np.zeros((n, n))
+    for alpha in itertools.product([0, 1], repeat=d):
+        Qs = [subs[c][alpha[c]][0] for c in range(d)]
+        if any(Q.shape[1] == 0 for Q in Qs):
+            continue
+        Mloc = [Q.T @ Mis[c] @ Q for c, Q in enumerate(Qs)]
+        Kloc = [Q.T @ subs[c][alpha[c]][1] @ Q for c, Q in enumerate(Qs)]
+        La = 0
+        for c in range(d):
+            facs = [Kloc[j] if j == c else Mloc[j] for j in range(d)]
+            term = facs[0]
+            for f in facs[1:]:
+                term = np.kron(f, term)
+            La = La + term
+        Q = Qs[0]
+        for f in Qs[1:]:
+            Q = np.kron(f, Q)
+        out += Q @ np.linalg.solve(om * La, Q.T)
+    return out

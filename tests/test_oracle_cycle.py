@@ -1,0 +1,127 @@
+"""Pins of the oracle's multigrid cycle and PCG (Sec. 3, Sec. 4, Algorithm 1)."""
+import json
+import os
+
+import numpy as np
+import pytest
+import scipy.linalg as sla
+
+from oracle import bspline
+from oracle.multigrid import Hierarchy, load_vector
+from paper_1804_02539_amd import workloads as W
+
+GOLD = os.path.join(os.path.dirname(__file__), "golden")
+
+
+def dense_cycle(H):
+    N = H.finest.N
+    B = np.zeros((N, N))
+    for j in range(N):
+        e = np.zeros(N)
+        e[j] = 1.0
+        B[:, j] = H.vcycle(e)
+    return B
+
+
+@pytest.mark.parametrize("make", [
+    lambda: W.unit_square_2x2(p=2, nel0=1, levels=3),
+    lambda: W.square_4x4_bezier(p=3, nel0=1, levels=2, seed=1),
+    lambda: W.cube_2x2x2_trilinear(p=2, nel0=1, levels=2),
+])
+def test_vcycle_is_symmetric_positive_definite(make):
+    H = Hierarchy(make())
+    B = dense_cycle(H)
+    assert np.allclose(B, B.T, atol=1e-12 * np.abs(B).max())
+    ev = np.linalg.eigvalsh(0.5 * (B + B.T))
+    assert ev.min() > 0
+    # as a preconditioner it is spectrally close to A^{-1}: eigenvalues of B A
+    A = H.finest.A.toarray()
+    lam = np.sort(np.linalg.eigvals(B @ A).real)
+    assert lam.min() > 0.05 and lam.max() < 1.5
+
+
+def test_pcg_matches_dense_cholesky(hierarchy):
+    prob = W.unit_square_2x2()
+    H = hierarchy("square2x2_p2", lambda: prob)
+    A = H.finest.A.toarray()
+    f = load_vector(prob, H.finest)
+    u, it, hist = H.pcg(f, tol=1e-8)
+    assert hist[-1] <= 1e-8 and np.linalg.norm(f - A @ u) <= 1e-8 * np.linalg.norm(f)
+    ustar = sla.cho_solve(sla.cho_factor(A), f)
+    kappa = np.linalg.cond(A)
+    assert np.linalg.norm(u - ustar) / np.linalg.norm(ustar) <= kappa * 1e-8
+    # monotone enough: the residual history ends below the tolerance within 40 steps
+    assert it < 40
+
+
+def _errors(prob, lev, u):
+    """L2 and H1-seminorm errors of the solution u against sin(pi x) sin(pi y) on
+    the identity-scaled square patches (parameter = physical up to scale)."""
+    e0 = e1 = 0.0
+    x, w = bspline.span_quadrature(bspline.open_uniform_knots(prob.degree, int(prob.nel(lev.level)[0][0])),
+                                   prob.degree + 3)
+    for k in range(prob.npatch):
+        op = lev.ops[k]
+        uk = lev.S[k].T @ u
+        X, J = op.geo.eval_grid([x, x])
+        v = op.eval_field(uk, [x, x])
+        dv0 = op.eval_field(uk, [x, x], deriv=0) / J[..., 0, 0]
+        dv1 = op.eval_field(uk, [x, x], deriv=1) / J[..., 1, 1]
+        ex = np.sin(np.pi * X[..., 0]) * np.sin(np.pi * X[..., 1])
+        gx = np.pi * np.cos(np.pi * X[..., 0]) * np.sin(np.pi * X[..., 1])
+        gy = np.pi * np.sin(np.pi * X[..., 0]) * np.cos(np.pi * X[..., 1])
+        Wq = np.outer(w, w) * np.abs(np.linalg.det(J))
+        e0 += np.sum(Wq * (v - ex) ** 2)
+        e1 += np.sum(Wq * ((dv0 - gx) ** 2 + (dv1 - gy) ** 2))
+    return np.sqrt(e0), np.sqrt(e1)
+
+
+@pytest.mark.parametrize("p", [2, 3])
+def test_manufactured_solution_rates(p):
+    # -Laplace u = 2 pi^2 sin sin has u = sin(pi x) sin(pi y): errors O(h^{p+1}) in
+    # L2 and O(h^p) in H1 (the approximation orders of S_{p,h})
+    prob = W.unit_square_2x2(p=p, nel0=2, levels=4)
+    H = Hierarchy(prob)
+    errs = []
+    for lev in H.levels[1:]:
+        A = lev.A.toarray()
+        f = load_vector(prob, lev)
+        u = sla.cho_solve(sla.cho_factor(A), f)
+        errs.append(_errors(prob, lev, u))
+    # the cycle solution on the finest level has the same error
+    u, _, _ = H.pcg(load_vector(prob, H.finest), tol=1e-12)
+    e_fin = _errors(prob, H.finest, u)
+    assert abs(e_fin[0] - errs[-1][0]) < 1e-6 * errs[-1][0]
+    errs = np.array(errs)
+    r0 = np.log2(errs[:-1, 0] / errs[1:, 0])
+    r1 = np.log2(errs[:-1, 1] / errs[1:, 1])
+    assert np.all(r0[-1:] > p + 1 - 0.3), r0
+    assert np.all(r1[-1:] > p - 0.3), r1
+
+
+def test_iteration_counts_flat_in_h_and_p():
+    # Sec. 5: counts are robust in grid size and spline degree
+    counts = {}
+    for p in (2, 3, 4):
+        for levels in (2, 3, 4):
+            prob = W.square_4x4_bezier(p=p, nel0=2, levels=levels, seed=2)
+            H = Hierarchy(prob)
+            f = W.random_rhs(H.finest.N, 2)
+            _, it, _ = H.pcg(f)
+            counts[(p, levels)] = it
+    vals = np.array(list(counts.values()))
+    # the paper's own tables span a factor of about 2 (25..51 in 2D, 22..44 in 3D)
+    assert vals.max() <= 2.0 * vals.min(), counts
+    assert vals.max() <= 51            # upper end of the paper's 2D table
+
+
+@pytest.mark.slow
+def test_fichera_iteration_count_near_paper():
+    # soft pin: level 1, p = 2 of the paper's 3D table (K = 448); the smoother's
+    # constants are a reading, so agreement within 30% is what is asserted
+    with open(os.path.join(GOLD, "iteration_counts.json")) as fh:
+        paper = json.load(fh)["fichera_K448"]["1"]["2"]
+    prob = W.fichera(2, 2, split=4)
+    H = Hierarchy(prob)
+    _, it, _ = H.pcg(load_vector(prob, H.finest))
+    assert abs(it - paper) <= 0.3 * paper, (it, paper)
