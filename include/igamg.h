@@ -1,0 +1,196 @@
+/*
+ * igamg -- multigrid for C0 multi-patch isogeometric Poisson problems on MI355X.
+ *
+ * Method: Hofer & Takacs, "A parallel multigrid solver for multi-patch
+ * Isogeometric Analysis".  The Poisson model problem -Laplace u = f with
+ * homogeneous Dirichlet data on Gamma_D and homogeneous Neumann data elsewhere
+ * (Sec. 2) is discretised by C0-coupled tensor-product B-splines of degree p on
+ * K fully matching patches (Sec. 2, the space V_l).  The solver is PCG
+ * preconditioned by one multigrid V-cycle (Sec. 4) whose smoother is the
+ * additive combination of patch-interior, face, edge and vertex smoothers
+ * (Sec. 3, eq. of L_l^{-1}) and whose coarsest level is solved exactly by a
+ * Cholesky factorisation (Sec. 4, the global coarse solver; Algorithm 1).
+ *
+ * Conventions used by every entry point:
+ *  - Device vectors are double arrays in the global free-dof numbering of a
+ *    level: patches in order, local functions x-fastest inside a patch, a dof
+ *    numbered when its class (the copies of an interface function) is first
+ *    met; Dirichlet functions are eliminated.  Length = igamg_num_dofs().
+ *  - All device memory is the caller's: one workspace buffer of
+ *    igamg_workspace_size() bytes (256-byte aligned) plus the vectors passed
+ *    to each call.  The library never allocates device memory.
+ *  - `stream` is a hipStream_t (NULL = the default stream).  A handle must not
+ *    be used from two streams at once; work is enqueued asynchronously except
+ *    where a call says it synchronises.
+ *  - Every entry point returns IGAMG_OK (0) or a negative error code and never
+ *    throws; igamg_last_error() gives a message for the calling thread.
+ */
+#ifndef IGAMG_H
+#define IGAMG_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define IGAMG_OK 0
+#define IGAMG_EINVAL (-1)  /* bad argument: sizes, degree, levels, null pointers   */
+#define IGAMG_ETOPO (-2)   /* interface sides do not match, bad side/patch index    */
+#define IGAMG_EGEOM (-3)   /* det J vanishes or changes sign inside a patch          */
+#define IGAMG_ENOMEM (-4)  /* workspace smaller than igamg_workspace_size()          */
+#define IGAMG_ENOTSPD (-5) /* coarse matrix not positive definite (no Dirichlet side)*/
+#define IGAMG_ENOCONV (-6) /* solve stopped at maxit above the tolerance            */
+#define IGAMG_ENAN (-7)    /* non-finite value met in the right-hand side or solve  */
+#define IGAMG_EDEVICE (-8) /* a HIP call failed                                     */
+
+/* Problem description (Sec. 2).
+ * Patch k maps (0,1)^dim onto Omega_k by one tensor-product Bezier element of
+ * degree geo_degree[k*dim + c] in direction c; its control points are stored
+ * x-fastest, each with `dim` coordinates, patch after patch in geo_ctrl.
+ * Level l has nel0[k*dim + c] * 2^l uniform elements per patch and direction
+ * and open knot vectors (maximal smoothness C^{p-1}), l = 0 .. levels-1.
+ * Side s = 2*dir + end of a patch is where parameter `dir` equals `end`.
+ * iface[5*i .. 5*i+4] = (patch a, side a, patch b, side b, orient): the
+ * tangential axes (t0 < t1) of side a meet the axes (u0 < u1) of side b; bit 0
+ * of orient pairs t0 with u1 and t1 with u0, bit 1 reverses the axis paired
+ * with t0, bit 2 the one paired with t1 (2D uses bit 1 only).
+ * bc[k*2*dim + s] = 1 puts side s of patch k on Gamma_D (u = 0), 0 on Gamma_N;
+ * entries of interface sides are ignored.  The arrays are read during
+ * igamg_setup / igamg_workspace_size only.                                     */
+typedef struct {
+  int dim;                /* 2 or 3                                         */
+  int degree;             /* spline degree p, 1 <= p <= 8                  */
+  int npatch;             /* K >= 1                                         */
+  int levels;             /* number of grid levels, >= 2                    */
+  const int* nel0;        /* [npatch*dim] coarsest element counts, >= 1     */
+  const int* geo_degree;  /* [npatch*dim] Bezier degree of each map, >= 1   */
+  const double* geo_ctrl; /* control points, see above                      */
+  int nif;                /* number of interfaces                           */
+  const int* iface;       /* [nif*5]                                        */
+  const int* bc;          /* [npatch*2*dim]                                 */
+} igamg_problem;
+
+/* Solver parameters; igamg_default_options() gives the paper's choice
+ * (Sec. 5): tau = 0.25, sigma = 5 h^-2, 1+1 smoothing, V-cycle.             */
+typedef struct {
+  double tau;            /* smoothing damping                                */
+  double sigma_scale;    /* sigma = sigma_scale * h^-2 in the interior smoother */
+  int nu;                /* pre- and post-smoothing steps                    */
+  int mu;                /* 1 = V-cycle, 2 = W-cycle                         */
+  int precision;         /* IGAMG_FP64, or IGAMG_MIXED (FP32 inner solve inside FP64
+                            iterative refinement)                          */
+  int maxit;             /* iteration cap of igamg_solve                    */
+  int geometry_scaling;  /* 1: scale piece operators by the patch's mean metric trace */
+  int inner_maxit;       /* mixed: inner PCG iteration cap per refinement step */
+  double inner_tol;      /* mixed: inner relative tolerance per refinement step */
+  int reserved[6];
+} igamg_options;
+
+#define IGAMG_FP64 0
+#define IGAMG_MIXED 1
+
+typedef struct {
+  int iterations;        /* PCG iterations (mixed: inner iterations summed) */
+  int outer_iterations;  /* mixed: refinement steps; FP64: 0                */
+  int converged;         /* 1 if ||f - A u|| <= tol ||f||                    */
+  double rel_residual;   /* final ||f - A u||_2 / ||f||_2 (FP64 residual)   */
+  double solve_ms;       /* wall time of the call on the stream             */
+} igamg_solve_info;
+
+typedef struct igamg_ctx* igamg_handle;
+
+void igamg_default_options(igamg_options* opts);
+
+/* Bytes of device workspace that igamg_setup needs for this problem.  Runs
+ * the topology part of the setup on the host (no assembly, no device use). */
+int igamg_workspace_size(const igamg_problem* prob, const igamg_options* opts, size_t* bytes);
+
+/* Host setup (Sec. 5's setup phases: dof maps, refinement and transfer
+ * matrices, piece smoothers, coarse factorisation) plus patch-wise Gauss
+ * assembly of the banded matrices A_{l,k} (Sec. 4), then upload into
+ * `workspace` on `stream`.  Synchronises the stream before returning.  The
+ * handle keeps host copies of nothing large; the workspace must outlive it.
+ * With workspace == NULL the handle stays on the host (for igamg_export and
+ * the size queries; the solver entry points then return EINVAL).
+ * Errors: EINVAL, ETOPO, EGEOM, ENOTSPD, ENOMEM (bytes too small), EDEVICE.  */
+int igamg_setup(const igamg_problem* prob, const igamg_options* opts, void* workspace,
+                size_t bytes, void* stream, igamg_handle* out);
+
+/* Free and local sizes of level `level` (-1 = finest): n_free = unique free
+ * dofs, n_local = sum over patches of their local function counts.          */
+int igamg_num_dofs(igamg_handle h, int level, int64_t* n_free, int64_t* n_local);
+
+/* Load vector f_i = int_Omega src(x) phi_i(x) dx of the finest level for
+ * src(x) = amp * prod_c sin(freq * pi * x_c), by Gauss quadrature on the host,
+ * written to the host array f_host[n_free].                                   */
+int igamg_load_vector(igamg_handle h, double amp, double freq, double* f_host);
+
+/* One multigrid cycle with zero initial guess on the finest level, i.e. the
+ * preconditioner z = B r of Sec. 4 (Algorithm 1 called on level L).  r and z
+ * are device vectors of length n_free (finest); they may not alias.         */
+int igamg_vcycle(igamg_handle h, const double* r, double* z, void* stream);
+
+/* PCG with one cycle as preconditioner from u = 0 (Sec. 4), stopping when
+ * ||f - A u||_2 <= tol ||f||_2 (Sec. 5).  With precision IGAMG_MIXED, FP64
+ * iterative refinement around FP32 PCG solves.  rhs and u: device vectors of
+ * length n_free (finest).  Synchronises the stream (reads the residual norm
+ * back once per iteration).  Returns ENOCONV when maxit is reached and ENAN
+ * on a non-finite residual; `info` (may be NULL) is filled in either case.  */
+int igamg_solve(igamg_handle h, const double* rhs, double* u, double tol, igamg_solve_info* info,
+                void* stream);
+
+/* The operators of one level on global free vectors, for checking the parts of
+ * the cycle one at a time:
+ *   IGAMG_OP_APPLY     y = A_l x                          (x, y on level l)
+ *   IGAMG_OP_SMOOTHER  y = L_l^{-1} x                     (level l >= 1)
+ *   IGAMG_OP_PROLONG   y = P_l x  (x on level l-1, y on level l, l >= 1)
+ *   IGAMG_OP_RESTRICT  y = P_l^T x (x on level l, y on level l-1, l >= 1)
+ *   IGAMG_OP_COARSE    y = A_0^{-1} x                     (level 0)
+ * Device vectors; x and y may not alias.                                      */
+#define IGAMG_OP_APPLY 0
+#define IGAMG_OP_SMOOTHER 1
+#define IGAMG_OP_PROLONG 2
+#define IGAMG_OP_RESTRICT 3
+#define IGAMG_OP_COARSE 4
+int igamg_operator(igamg_handle h, int op, int level, const double* x, double* y, void* stream);
+
+/* Copies of the global free dofs of a level in the library's patch-local
+ * layout: for dof g, local positions copy_idx[copy_ptr[g] .. copy_ptr[g+1]).
+ * Host arrays; pass NULL pointers to query the sizes (n_free, n_copies).    */
+int igamg_dof_map(igamg_handle h, int level, int64_t* copy_ptr, int64_t* copy_idx,
+                  int64_t* n_free, int64_t* n_copies);
+
+/* Setup products as dense host matrices, for inspection of small problems:
+ *   IGAMG_EXPORT_MATRIX   the assembled A_l on free dofs (n_free x n_free); only
+ *                         on handles set up without a workspace (the bands are
+ *                         dropped from host memory after an upload)
+ *   IGAMG_EXPORT_PROLONG  P_l (n_free(l) x n_free(l-1)), level >= 1
+ * Pass out = NULL to query rows/cols.  Row-major doubles.                      */
+#define IGAMG_EXPORT_MATRIX 0
+#define IGAMG_EXPORT_PROLONG 1
+int igamg_export(igamg_handle h, int what, int level, double* out, int64_t* rows, int64_t* cols);
+
+/* Kernel timing of the banded stiffness apply (the bandwidth-bound kernel of
+ * the cycle).  enable = 1 starts recording a HIP event pair around every
+ * banded-apply launch on every level (events are created by the library on
+ * first use; recording adds no synchronisation), enable = 0 stops.
+ * igamg_profile_read synchronises the stream of the last recorded launch and
+ * returns, per level l (arrays of length levels), the launch count and the
+ * summed kernel time in ms and the algorithmic bytes moved
+ * (rows * (8 (2p+1)^d + 8 * vectors)); then it clears the record.            */
+int igamg_profile(igamg_handle h, int enable);
+int igamg_profile_read(igamg_handle h, int64_t* launches, double* ms, double* bytes);
+
+/* Release the handle (not the workspace).                                    */
+int igamg_destroy(igamg_handle h);
+
+/* Message of the last error on the calling thread ("" if none).            */
+const char* igamg_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* IGAMG_H */

@@ -1,0 +1,86 @@
+// Host setup of the multigrid hierarchy (the four setup phases of Sec. 5 plus
+// the patch-wise assembly of Sec. 4).  Produces flat arrays ready to upload.
+#pragma once
+
+#include <array>
+#include <cstdint>
+#include <string>
+#include <vector>
+
+#include "layout.hpp"
+
+namespace igamg {
+
+struct ProblemH {
+  int d = 2, p = 2, K = 1, levels = 2;
+  std::vector<int> nel0;                  // K*d
+  std::vector<int> gdeg;                  // K*d
+  std::vector<std::vector<double>> ctrl;  // per patch, prod(g+1)*d
+  std::vector<std::array<int, 5>> iface;
+  std::vector<int> bc;                    // K*2d
+};
+
+struct Options {
+  double tau = 0.25, sigma_scale = 5.0;
+  int nu = 1, mu = 1, precision = 0, maxit = 500, geometry_scaling = 1;
+  int inner_maxit = 100;
+  double inner_tol = 1e-3;
+};
+
+// Error with an igamg return code.
+struct SetupError {
+  int code;
+  std::string msg;
+};
+
+// One grid level.
+struct LevelH {
+  int l = 0;
+  std::vector<std::array<int, 3>> n, nel;   // per patch (unused dims: n = 1, nel = 1)
+  std::vector<int64_t> off, rows;
+  int64_t NL = 0;                            // padded local length
+  std::vector<int64_t> gid;                  // NL entries: free id or -1
+  int64_t N = 0;
+  std::vector<int64_t> gptr, gidx;           // copies of each free dof (local positions)
+  std::vector<int> bpatch;                   // patch of each 256-row block (-1: none)
+  std::vector<uint8_t> isfree;               // NL
+  // banded patch matrices, coefficient-major: band[o * NL + row]
+  int nb = 0;                                // (2p+1)^d
+  std::vector<double> band;
+  // interface vector (faces, edges, vertices): copies CSR
+  int64_t nif = 0;
+  std::vector<int64_t> if_ptr, if_idx;
+  // smoother
+  std::vector<FDItem> fd;                    // interiors first, then faces
+  int nfd_interior = 0;
+  std::vector<double> fdmat;                 // U matrices and mu vectors
+  int64_t fdscr = 0;                         // scratch entries per buffer
+  int fd_maxm = 1;
+  std::vector<DensePiece> dense;
+  std::vector<double> densemat;
+  // transfers from level l-1 (empty for l = 0)
+  int WP = 0, WR = 0;
+  std::vector<int64_t> tr_idx;
+  std::vector<double> tr_val;
+  std::vector<PatchDev> pd;
+  std::vector<double> omega;                 // per patch
+};
+
+struct Hierarchy {
+  ProblemH prob;
+  Options opt;
+  std::vector<LevelH> lv;
+  // coarse solver: W = L^{-1} with A_0 = L L^T (dense, row-major, N0 x N0)
+  std::vector<double> Winv;
+};
+
+// Validate and copy the C problem description.  Throws SetupError.
+ProblemH read_problem(const void* cprob);
+// Topology only (dof maps, pieces sizes): enough to size the workspace.
+void build_topology(Hierarchy& H, bool with_numerics);
+// Everything (assembly, smoothers, transfers, coarse factor).
+void build_all(Hierarchy& H);
+// Load vector of the finest level for src = amp * prod sin(freq*pi*x_c).
+std::vector<double> load_vector(const Hierarchy& H, double amp, double freq);
+
+}  // namespace igamg

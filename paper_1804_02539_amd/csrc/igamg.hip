@@ -1,0 +1,719 @@
+// C-ABI of the library: workspace planning, upload, the multigrid cycle of
+// Algorithm 1 on the device, the PCG driver of Sec. 4, and per-operator entry
+// points.  Every step of the cycle runs in the kernels of kernels.hip; the
+// host only sequences launches on the caller's stream.
+#include <hip/hip_runtime.h>
+
+#include <chrono>
+#include <cmath>
+#include <cstring>
+#include <string>
+#include <vector>
+
+#include "host_setup.hpp"
+#include "igamg.h"
+#include "kernels.hpp"
+
+using namespace igamg;
+
+static thread_local std::string g_err;
+
+static int set_err(int code, const std::string& msg) {
+  g_err = msg;
+  return code;
+}
+
+#define HIP_OK(expr)                                                                          \
+  do {                                                                                        \
+    hipError_t e_ = (expr);                                                                   \
+    if (e_ != hipSuccess) throw SetupError{IGAMG_EDEVICE, std::string(#expr ": ") + hipGetErrorString(e_)}; \
+  } while (0)
+
+namespace {
+
+struct DevLevel {
+  int64_t NL = 0, N = 0, nif = 0;
+  int nb = 0, nfd = 0, nfd_int = 0, ndense = 0, WP = 0, WR = 0, fd_maxm = 1;
+  int64_t fdscr = 0, ncopy = 0, nifidx = 0, ntr_idx = 0, ntr_val = 0, nfdmat = 0, ndmat = 0;
+  double *band = nullptr, *u = nullptr, *f = nullptr, *w = nullptr;
+  int* bpatch = nullptr;
+  PatchDev* pd = nullptr;
+  uint8_t* isfree = nullptr;
+  int64_t *gptr = nullptr, *gidx = nullptr, *if_ptr = nullptr, *if_idx = nullptr;
+  double *rif = nullptr, *zif = nullptr;
+  FDItem* fd = nullptr;
+  double* fdmat = nullptr;
+  double *scrA = nullptr, *scrB = nullptr;
+  DensePiece* dense = nullptr;
+  double* densemat = nullptr;
+  int64_t* tr_idx = nullptr;
+  double* tr_val = nullptr;
+  int fd_grid[3] = {1, 1, 1};
+  size_t fd_lds = 0;
+};
+
+struct Bump {
+  char* base;
+  size_t pos = 0;
+  template <typename T>
+  T* take(size_t n) {
+    pos = (pos + 255) & ~size_t(255);
+    T* p = base ? reinterpret_cast<T*>(base + pos) : nullptr;
+    pos += std::max<size_t>(n, 1) * sizeof(T);
+    return p;
+  }
+};
+
+}  // namespace
+
+struct igamg_ctx {
+  Hierarchy H;
+  int d = 2, p = 2, L = 1;
+  std::vector<DevLevel> dl;
+  double* Winv = nullptr;
+  double *cb = nullptr, *cy = nullptr, *cx = nullptr;
+  int64_t N0 = 0;
+  // PCG (finest level, patch-local)
+  double *x = nullptr, *pp = nullptr, *q = nullptr, *tmpg = nullptr;
+  double *part = nullptr, *scal = nullptr;
+  double* host_scal = nullptr;   // pinned
+  bool on_device = false;
+  // optional event timing of the banded apply
+  bool prof = false;
+  struct Rec {
+    int level;
+    double bytes;
+    hipEvent_t a, b;
+  };
+  std::vector<Rec> recs;
+  std::vector<hipEvent_t> pool;
+  size_t pool_used = 0;
+  hipStream_t prof_stream = nullptr;
+  void* ws = nullptr;
+  size_t bytes = 0;
+};
+
+static size_t plan(igamg_ctx& C, char* base) {
+  Bump b{base};
+  const Hierarchy& H = C.H;
+  C.dl.assign(H.lv.size(), DevLevel{});
+  int64_t maxNL = 0, maxN = 0;
+  for (size_t l = 0; l < H.lv.size(); ++l) {
+    const LevelH& L = H.lv[l];
+    DevLevel& D = C.dl[l];
+    D.NL = L.NL;
+    D.N = L.N;
+    D.nif = L.nif;
+    maxNL = std::max(maxNL, L.NL);
+    maxN = std::max(maxN, L.N);
+    int nb = 1;
+    for (int c = 0; c < H.prob.d; ++c) nb *= 2 * H.prob.p + 1;
+    D.nb = nb;
+    D.ncopy = (int64_t)L.gidx.size();
+    D.u = b.take<double>(L.NL);
+    D.f = b.take<double>(L.NL);
+    D.w = b.take<double>(L.NL);
+    D.bpatch = b.take<int>(L.bpatch.size());
+    D.pd = b.take<PatchDev>(L.pd.size());
+    D.isfree = b.take<uint8_t>(L.NL);
+    D.gptr = b.take<int64_t>(L.gptr.size());
+    D.gidx = b.take<int64_t>(L.gidx.size());
+    if (l == 0) continue;
+    D.band = b.take<double>((size_t)nb * L.NL);
+    D.nifidx = (int64_t)L.if_idx.size();
+    D.if_ptr = b.take<int64_t>(L.if_ptr.size());
+    D.if_idx = b.take<int64_t>(L.if_idx.size());
+    D.rif = b.take<double>(L.nif);
+    D.zif = b.take<double>(L.nif);
+    D.nfd = (int)L.fd.size();
+    D.nfd_int = L.nfd_interior;
+    D.fd = b.take<FDItem>(L.fd.size());
+    D.nfdmat = (int64_t)L.fdmat.size();
+    D.fdmat = b.take<double>(L.fdmat.size());
+    D.fdscr = L.fdscr;
+    D.scrA = b.take<double>(L.fdscr);
+    D.scrB = b.take<double>(L.fdscr);
+    D.ndense = (int)L.dense.size();
+    D.dense = b.take<DensePiece>(L.dense.size());
+    D.ndmat = (int64_t)L.densemat.size();
+    D.densemat = b.take<double>(L.densemat.size());
+    D.ntr_idx = (int64_t)L.tr_idx.size();
+    D.ntr_val = (int64_t)L.tr_val.size();
+    D.tr_idx = b.take<int64_t>(L.tr_idx.size());
+    D.tr_val = b.take<double>(L.tr_val.size());
+    D.WP = L.WP;
+    D.WR = L.WR;
+    D.fd_maxm = L.fd_maxm;
+    for (int dir = 0; dir < 3; ++dir) D.fd_grid[dir] = fd_grid_x(L.fd.data(), (int)L.fd.size(), dir);
+    D.fd_lds = fd_lds_bytes(L.fd_maxm);
+  }
+  C.N0 = H.lv[0].N;
+  C.Winv = b.take<double>((size_t)C.N0 * C.N0);
+  C.cb = b.take<double>(C.N0);
+  C.cy = b.take<double>(C.N0);
+  C.cx = b.take<double>(C.N0);
+  const int64_t NLf = H.lv.back().NL;
+  C.x = b.take<double>(NLf);
+  C.pp = b.take<double>(NLf);
+  C.q = b.take<double>(NLf);
+  C.tmpg = b.take<double>(std::max(maxNL, maxN));
+  C.part = b.take<double>(RED_BLOCKS);
+  C.scal = b.take<double>(16);
+  return b.pos + 256;
+}
+
+template <typename T>
+static void up(T* dst, const std::vector<T>& src, hipStream_t st) {
+  if (!src.empty()) HIP_OK(hipMemcpyAsync(dst, src.data(), src.size() * sizeof(T), hipMemcpyHostToDevice, st));
+}
+
+static void upload(igamg_ctx& C, hipStream_t st) {
+  Hierarchy& H = C.H;
+  HIP_OK(hipMemsetAsync(C.ws, 0, C.bytes, st));
+  for (size_t l = 0; l < H.lv.size(); ++l) {
+    LevelH& L = H.lv[l];
+    DevLevel& D = C.dl[l];
+    up(D.bpatch, L.bpatch, st);
+    up(D.pd, L.pd, st);
+    up(D.isfree, L.isfree, st);
+    up(D.gptr, L.gptr, st);
+    up(D.gidx, L.gidx, st);
+    if (l == 0) continue;
+    up(D.band, L.band, st);
+    up(D.if_ptr, L.if_ptr, st);
+    up(D.if_idx, L.if_idx, st);
+    up(D.fd, L.fd, st);
+    up(D.fdmat, L.fdmat, st);
+    up(D.dense, L.dense, st);
+    up(D.densemat, L.densemat, st);
+    up(D.tr_idx, L.tr_idx, st);
+    up(D.tr_val, L.tr_val, st);
+  }
+  up(C.Winv, H.Winv, st);
+  HIP_OK(hipStreamSynchronize(st));
+  // the bands are large and no longer needed on the host
+  for (auto& L : H.lv) {
+    std::vector<double>().swap(L.band);
+  }
+  std::vector<double>().swap(H.Winv);
+}
+
+// ---------------------------------------------------------------------------
+// the cycle
+// ---------------------------------------------------------------------------
+static hipEvent_t next_event(igamg_ctx& C) {
+  if (C.pool_used == C.pool.size()) {
+    hipEvent_t e;
+    HIP_OK(hipEventCreate(&e));
+    C.pool.push_back(e);
+  }
+  return C.pool[C.pool_used++];
+}
+
+static void band_timed(igamg_ctx& C, int l, const double* u, const double* f, double* r, bool resid,
+                       hipStream_t st) {
+  DevLevel& D = C.dl[l];
+  if (!C.prof) {
+    launch_band(C.d, C.p, D.band, u, f, r, D.bpatch, D.pd, D.NL, resid, st);
+    return;
+  }
+  igamg_ctx::Rec rc;
+  rc.level = l;
+  int64_t rows = 0;
+  for (int64_t x : C.H.lv[l].rows) rows += x;
+  rc.bytes = (double)rows * (8.0 * D.nb + 8.0 * (resid ? 3 : 2));
+  rc.a = next_event(C);
+  rc.b = next_event(C);
+  HIP_OK(hipEventRecord(rc.a, st));
+  launch_band(C.d, C.p, D.band, u, f, r, D.bpatch, D.pd, D.NL, resid, st);
+  HIP_OK(hipEventRecord(rc.b, st));
+  C.recs.push_back(rc);
+  C.prof_stream = st;
+}
+
+static void residual(igamg_ctx& C, int l, const double* u, const double* f, double* r, hipStream_t st) {
+  band_timed(C, l, u, f, r, true, st);
+}
+
+static void apply(igamg_ctx& C, int l, const double* u, double* y, hipStream_t st) {
+  band_timed(C, l, u, nullptr, y, false, st);
+}
+
+// u <- u + tau L^{-1} src (or u = tau L^{-1} src when !add); src distributed
+static void smoother_apply(igamg_ctx& C, int l, const double* src, double* u, bool add, double tau,
+                           hipStream_t st) {
+  DevLevel& D = C.dl[l];
+  launch_if_gather(src, D.rif, D.if_ptr, D.if_idx, D.nif, st);
+  // FD passes over interiors and faces: forward directions 0..d-2, the scaled
+  // middle direction d-1, inverse directions d-2..0
+  const int d = C.d;
+  const int last = d - 1;
+  int in_sel = 0;  // 0: source view, 1: scrA, 2: scrB
+  int buf = 1;
+  for (int dir = 0; dir < last; ++dir) {
+    launch_fd_pass(D.fd, D.nfd, D.fd_grid[dir], D.fd_lds, dir, 0, in_sel, buf, D.fdmat, src, D.rif, u, D.zif, D.scrA,
+                   D.scrB, tau, add, st);
+    in_sel = buf;
+    buf = 3 - buf;
+  }
+  launch_fd_pass(D.fd, D.nfd, D.fd_grid[last], D.fd_lds, last, 2, in_sel, last == 0 ? 0 : buf, D.fdmat, src, D.rif, u,
+                 D.zif, D.scrA, D.scrB, tau, add, st);
+  if (last > 0) {
+    in_sel = buf;
+    buf = 3 - buf;
+  }
+  for (int dir = last - 1; dir >= 0; --dir) {
+    const int out = (dir == 0) ? 0 : buf;
+    launch_fd_pass(D.fd, D.nfd, D.fd_grid[dir], D.fd_lds, dir, 1, in_sel, out, D.fdmat, src, D.rif, u, D.zif, D.scrA,
+                   D.scrB, tau, add, st);
+    in_sel = buf;
+    buf = 3 - buf;
+  }
+  launch_dense(D.dense, D.ndense, D.densemat, D.rif, D.zif, st);
+  launch_if_scatter(D.zif, u, D.if_ptr, D.if_idx, D.nif, tau, add, st);
+}
+
+static void coarse_solve(igamg_ctx& C, const double* f0, double* u0, hipStream_t st) {
+  DevLevel& D = C.dl[0];
+  launch_gather(f0, C.cb, D.gptr, D.gidx, D.N, true, st);
+  launch_coarse(C.Winv, C.cb, C.cy, C.cx, (int)C.N0, st);
+  launch_scatter(C.cx, u0, D.gptr, D.gidx, D.N, false, st);
+}
+
+static void restrict_to(igamg_ctx& C, int l, const double* rf, double* rc, hipStream_t st) {
+  DevLevel& F = C.dl[l];
+  DevLevel& Cc = C.dl[l - 1];
+  launch_restrict(C.d, rf, rc, F.pd, Cc.bpatch, Cc.NL, F.tr_idx, F.tr_val, F.WR, Cc.isfree, st);
+}
+
+static void prolong_add(igamg_ctx& C, int l, const double* uc, double* uf, hipStream_t st) {
+  DevLevel& F = C.dl[l];
+  launch_prolong_add(C.d, uc, uf, F.pd, F.bpatch, F.NL, F.tr_idx, F.tr_val, F.WP, F.isfree, st);
+}
+
+// Algorithm 1 on level l >= 1 with u_l, f_l in dl[l].u / dl[l].f
+static void cycle(igamg_ctx& C, int l, bool zero_init, hipStream_t st) {
+  DevLevel& D = C.dl[l];
+  const Options& O = C.H.opt;
+  for (int i = 0; i < O.nu; ++i) {
+    if (zero_init && i == 0) {
+      smoother_apply(C, l, D.f, D.u, false, O.tau, st);
+    } else {
+      residual(C, l, D.u, D.f, D.w, st);
+      smoother_apply(C, l, D.w, D.u, true, O.tau, st);
+    }
+  }
+  residual(C, l, D.u, D.f, D.w, st);
+  DevLevel& Dc = C.dl[l - 1];
+  restrict_to(C, l, D.w, Dc.f, st);
+  if (l == 1) {
+    coarse_solve(C, Dc.f, Dc.u, st);
+  } else {
+    for (int j = 0; j < O.mu; ++j) cycle(C, l - 1, j == 0, st);
+  }
+  prolong_add(C, l, Dc.u, D.u, st);
+  for (int i = 0; i < O.nu; ++i) {
+    residual(C, l, D.u, D.f, D.w, st);
+    smoother_apply(C, l, D.w, D.u, true, O.tau, st);
+  }
+}
+
+// ---------------------------------------------------------------------------
+// helpers
+// ---------------------------------------------------------------------------
+#define API_BEGIN try {
+#define API_END                                        \
+  }                                                    \
+  catch (const SetupError& e) {                        \
+    return set_err(e.code, e.msg);                     \
+  }                                                    \
+  catch (const std::bad_alloc&) {                      \
+    return set_err(IGAMG_EINVAL, "host out of memory"); \
+  }                                                    \
+  catch (const std::exception& e) {                    \
+    return set_err(IGAMG_EINVAL, e.what());            \
+  }
+
+static void read_opts(const igamg_options* o, Options& O) {
+  igamg_options def;
+  igamg_default_options(&def);
+  if (!o) o = &def;
+  O.tau = o->tau;
+  O.sigma_scale = o->sigma_scale;
+  O.nu = o->nu;
+  O.mu = o->mu;
+  O.precision = o->precision;
+  O.maxit = o->maxit;
+  O.geometry_scaling = o->geometry_scaling;
+  O.inner_maxit = o->inner_maxit;
+  O.inner_tol = o->inner_tol;
+  if (!(O.tau > 0) || !(O.sigma_scale > 0) || O.nu < 1 || O.nu > 8 || (O.mu != 1 && O.mu != 2) ||
+      (O.precision != IGAMG_FP64 && O.precision != IGAMG_MIXED) || O.maxit < 1 || O.inner_maxit < 1 ||
+      !(O.inner_tol > 0 && O.inner_tol < 1))
+    throw SetupError{IGAMG_EINVAL, "invalid options"};
+}
+
+static int check_level(igamg_ctx* h, int level) {
+  if (level < 0) level = h->L;
+  if (level > h->L) throw SetupError{IGAMG_EINVAL, "level out of range"};
+  return level;
+}
+
+static void need_device(igamg_ctx* h) {
+  if (!h) throw SetupError{IGAMG_EINVAL, "null handle"};
+  if (!h->on_device) throw SetupError{IGAMG_EINVAL, "handle was set up without a workspace"};
+}
+
+// ---------------------------------------------------------------------------
+// exported entry points
+// ---------------------------------------------------------------------------
+extern "C" {
+
+void igamg_default_options(igamg_options* o) {
+  if (!o) return;
+  std::memset(o, 0, sizeof(*o));
+  o->tau = 0.25;
+  o->sigma_scale = 5.0;
+  o->nu = 1;
+  o->mu = 1;
+  o->precision = IGAMG_FP64;
+  o->maxit = 500;
+  o->geometry_scaling = 1;
+  o->inner_maxit = 100;
+  o->inner_tol = 1e-3;
+}
+
+const char* igamg_last_error(void) { return g_err.c_str(); }
+
+int igamg_workspace_size(const igamg_problem* prob, const igamg_options* opts, size_t* bytes) {
+  API_BEGIN
+  if (!bytes) return set_err(IGAMG_EINVAL, "bytes is NULL");
+  igamg_ctx C;
+  C.H.prob = read_problem(prob);
+  read_opts(opts, C.H.opt);
+  build_topology(C.H, false);
+  *bytes = plan(C, nullptr);
+  return IGAMG_OK;
+  API_END
+}
+
+int igamg_setup(const igamg_problem* prob, const igamg_options* opts, void* workspace, size_t bytes, void* stream,
+                igamg_handle* out) {
+  API_BEGIN
+  if (!out) return set_err(IGAMG_EINVAL, "out is NULL");
+  *out = nullptr;
+  igamg_ctx* C = new igamg_ctx();
+  try {
+    C->H.prob = read_problem(prob);
+    read_opts(opts, C->H.opt);
+    C->d = C->H.prob.d;
+    C->p = C->H.prob.p;
+    C->L = C->H.prob.levels - 1;
+    build_all(C->H);
+    size_t need = plan(*C, nullptr);
+    if (workspace) {
+      if (bytes < need) throw SetupError{IGAMG_ENOMEM, "workspace too small: need " + std::to_string(need)};
+      if (reinterpret_cast<uintptr_t>(workspace) & 255) throw SetupError{IGAMG_EINVAL, "workspace not 256-byte aligned"};
+      C->ws = workspace;
+      C->bytes = need;
+      plan(*C, static_cast<char*>(workspace));
+      HIP_OK(hipHostMalloc(reinterpret_cast<void**>(&C->host_scal), 16 * sizeof(double), hipHostMallocDefault));
+      upload(*C, static_cast<hipStream_t>(stream));
+      C->on_device = true;
+    }
+  } catch (...) {
+    delete C;
+    throw;
+  }
+  *out = C;
+  return IGAMG_OK;
+  API_END
+}
+
+int igamg_profile(igamg_handle h, int enable) {
+  API_BEGIN
+  need_device(h);
+  h->prof = enable != 0;
+  return IGAMG_OK;
+  API_END
+}
+
+int igamg_profile_read(igamg_handle h, int64_t* launches, double* ms, double* bytes) {
+  API_BEGIN
+  need_device(h);
+  const int nl = (int)h->dl.size();
+  for (int l = 0; l < nl; ++l) {
+    if (launches) launches[l] = 0;
+    if (ms) ms[l] = 0.0;
+    if (bytes) bytes[l] = 0.0;
+  }
+  if (!h->recs.empty()) HIP_OK(hipStreamSynchronize(h->prof_stream));
+  for (const auto& rc : h->recs) {
+    float t = 0.0f;
+    HIP_OK(hipEventElapsedTime(&t, rc.a, rc.b));
+    if (launches) launches[rc.level] += 1;
+    if (ms) ms[rc.level] += t;
+    if (bytes) bytes[rc.level] += rc.bytes;
+  }
+  h->recs.clear();
+  h->pool_used = 0;
+  return IGAMG_OK;
+  API_END
+}
+
+int igamg_destroy(igamg_handle h) {
+  if (!h) return IGAMG_OK;
+  for (hipEvent_t e : h->pool) (void)hipEventDestroy(e);
+  if (h->host_scal) (void)hipHostFree(h->host_scal);
+  delete h;
+  return IGAMG_OK;
+}
+
+int igamg_num_dofs(igamg_handle h, int level, int64_t* n_free, int64_t* n_local) {
+  API_BEGIN
+  if (!h) return set_err(IGAMG_EINVAL, "null handle");
+  level = check_level(h, level);
+  const LevelH& L = h->H.lv[level];
+  if (n_free) *n_free = L.N;
+  if (n_local) {
+    int64_t s = 0;
+    for (int64_t r : L.rows) s += r;
+    *n_local = s;
+  }
+  return IGAMG_OK;
+  API_END
+}
+
+int igamg_dof_map(igamg_handle h, int level, int64_t* copy_ptr, int64_t* copy_idx, int64_t* n_free,
+                  int64_t* n_copies) {
+  API_BEGIN
+  if (!h) return set_err(IGAMG_EINVAL, "null handle");
+  level = check_level(h, level);
+  const LevelH& L = h->H.lv[level];
+  if (n_free) *n_free = L.N;
+  if (n_copies) *n_copies = (int64_t)L.gidx.size();
+  if (copy_ptr) std::memcpy(copy_ptr, L.gptr.data(), L.gptr.size() * sizeof(int64_t));
+  if (copy_idx) std::memcpy(copy_idx, L.gidx.data(), L.gidx.size() * sizeof(int64_t));
+  return IGAMG_OK;
+  API_END
+}
+
+int igamg_load_vector(igamg_handle h, double amp, double freq, double* f_host) {
+  API_BEGIN
+  if (!h || !f_host) return set_err(IGAMG_EINVAL, "null argument");
+  std::vector<double> f = load_vector(h->H, amp, freq);
+  std::memcpy(f_host, f.data(), f.size() * sizeof(double));
+  return IGAMG_OK;
+  API_END
+}
+
+int igamg_vcycle(igamg_handle h, const double* r, double* z, void* stream) {
+  API_BEGIN
+  need_device(h);
+  if (!r || !z || r == z) return set_err(IGAMG_EINVAL, "bad vector arguments");
+  hipStream_t st = static_cast<hipStream_t>(stream);
+  DevLevel& D = h->dl[h->L];
+  launch_scatter(r, D.f, D.gptr, D.gidx, D.N, true, st);
+  cycle(*h, h->L, true, st);
+  launch_gather(D.u, z, D.gptr, D.gidx, D.N, false, st);
+  HIP_OK(hipGetLastError());
+  return IGAMG_OK;
+  API_END
+}
+
+int igamg_operator(igamg_handle h, int op, int level, const double* x, double* y, void* stream) {
+  API_BEGIN
+  need_device(h);
+  if (!x || !y || x == y) return set_err(IGAMG_EINVAL, "bad vector arguments");
+  hipStream_t st = static_cast<hipStream_t>(stream);
+  level = check_level(h, level);
+  DevLevel& D = h->dl[level];
+  switch (op) {
+    case IGAMG_OP_APPLY: {
+      if (level < 1) return set_err(IGAMG_EINVAL, "no banded matrix on level 0 (use IGAMG_OP_COARSE)");
+      launch_scatter(x, D.u, D.gptr, D.gidx, D.N, false, st);
+      apply(*h, level, D.u, D.w, st);
+      launch_gather(D.w, y, D.gptr, D.gidx, D.N, true, st);
+      break;
+    }
+    case IGAMG_OP_SMOOTHER: {
+      if (level < 1) return set_err(IGAMG_EINVAL, "smoother needs level >= 1");
+      launch_scatter(x, D.f, D.gptr, D.gidx, D.N, true, st);
+      smoother_apply(*h, level, D.f, D.u, false, 1.0, st);
+      launch_gather(D.u, y, D.gptr, D.gidx, D.N, false, st);
+      break;
+    }
+    case IGAMG_OP_PROLONG: {
+      if (level < 1) return set_err(IGAMG_EINVAL, "prolongation needs level >= 1");
+      DevLevel& Dc = h->dl[level - 1];
+      launch_scatter(x, Dc.u, Dc.gptr, Dc.gidx, Dc.N, false, st);
+      launch_fill(D.w, D.NL, 0.0, st);
+      prolong_add(*h, level, Dc.u, D.w, st);
+      launch_gather(D.w, y, D.gptr, D.gidx, D.N, false, st);
+      break;
+    }
+    case IGAMG_OP_RESTRICT: {
+      if (level < 1) return set_err(IGAMG_EINVAL, "restriction needs level >= 1");
+      DevLevel& Dc = h->dl[level - 1];
+      launch_scatter(x, D.w, D.gptr, D.gidx, D.N, true, st);
+      restrict_to(*h, level, D.w, Dc.f, st);
+      launch_gather(Dc.f, y, Dc.gptr, Dc.gidx, Dc.N, true, st);
+      break;
+    }
+    case IGAMG_OP_COARSE: {
+      if (level != 0) return set_err(IGAMG_EINVAL, "coarse solve lives on level 0");
+      launch_scatter(x, D.f, D.gptr, D.gidx, D.N, true, st);
+      coarse_solve(*h, D.f, D.u, st);
+      launch_gather(D.u, y, D.gptr, D.gidx, D.N, false, st);
+      break;
+    }
+    default:
+      return set_err(IGAMG_EINVAL, "unknown operator");
+  }
+  HIP_OK(hipGetLastError());
+  return IGAMG_OK;
+  API_END
+}
+
+int igamg_export(igamg_handle h, int what, int level, double* out, int64_t* rows, int64_t* cols) {
+  API_BEGIN
+  if (!h) return set_err(IGAMG_EINVAL, "null handle");
+  level = check_level(h, level);
+  const Hierarchy& H = h->H;
+  const LevelH& L = H.lv[level];
+  const int d = H.prob.d, p = H.prob.p;
+  if (what == IGAMG_EXPORT_MATRIX) {
+    if (L.band.empty()) return set_err(IGAMG_EINVAL, "matrix not kept on the host (set up without a workspace)");
+    if (rows) *rows = L.N;
+    if (cols) *cols = L.N;
+    if (!out) return IGAMG_OK;
+    std::memset(out, 0, sizeof(double) * (size_t)L.N * L.N);
+    const int nb0 = 2 * p + 1, p2 = (d == 3) ? p : 0, nb2 = 2 * p2 + 1;
+    for (int k = 0; k < H.prob.K; ++k) {
+      const auto& n = L.n[k];
+      for (int64_t r = 0; r < L.rows[k]; ++r) {
+        const int64_t x = L.off[k] + r, gi = L.gid[x];
+        if (gi < 0) continue;
+        const int i0 = (int)(r % n[0]), i1 = (int)((r / n[0]) % n[1]), i2 = (int)(r / ((int64_t)n[0] * n[1]));
+        for (int o2 = 0; o2 < nb2; ++o2)
+          for (int o1 = 0; o1 < nb0; ++o1)
+            for (int o0 = 0; o0 < nb0; ++o0) {
+              const int j0 = i0 + o0 - p, j1 = i1 + o1 - p, j2 = i2 + o2 - p2;
+              if (j0 < 0 || j0 >= n[0] || j1 < 0 || j1 >= n[1] || j2 < 0 || j2 >= n[2]) continue;
+              const int64_t gj = L.gid[L.off[k] + j0 + (int64_t)n[0] * (j1 + (int64_t)n[1] * j2)];
+              if (gj < 0) continue;
+              const int64_t o = o0 + (int64_t)nb0 * (o1 + (int64_t)nb0 * o2);
+              out[gi * L.N + gj] += L.band[o * L.NL + x];
+            }
+      }
+    }
+    return IGAMG_OK;
+  }
+  if (what == IGAMG_EXPORT_PROLONG) {
+    if (level < 1) return set_err(IGAMG_EINVAL, "prolongation needs level >= 1");
+    const LevelH& Cl = H.lv[level - 1];
+    if (rows) *rows = L.N;
+    if (cols) *cols = Cl.N;
+    if (!out) return IGAMG_OK;
+    std::memset(out, 0, sizeof(double) * (size_t)L.N * Cl.N);
+    std::vector<char> done(L.N, 0);
+    for (int k = 0; k < H.prob.K; ++k) {
+      const PatchDev& P = L.pd[k];
+      for (int64_t r = 0; r < P.rows; ++r) {
+        const int64_t gi = L.gid[P.off + r];
+        if (gi < 0 || done[gi]) continue;
+        done[gi] = 1;
+        const int i[3] = {(int)(r % P.n[0]), (int)((r / P.n[0]) % P.n[1]), (int)(r / ((int64_t)P.n[0] * P.n[1]))};
+        int s[3];
+        const double* w[3];
+        for (int c = 0; c < 3; ++c) {
+          s[c] = (int)L.tr_idx[P.Pst[c] + i[c]];
+          w[c] = &L.tr_val[P.Pval[c] + (int64_t)i[c] * L.WP];
+        }
+        const int W2 = (d == 3) ? L.WP : 1;
+        for (int a2 = 0; a2 < W2; ++a2)
+          for (int a1 = 0; a1 < L.WP; ++a1)
+            for (int a0 = 0; a0 < L.WP; ++a0) {
+              const double v = w[0][a0] * w[1][a1] * w[2][a2];
+              if (v == 0.0) continue;
+              const int j0 = s[0] + a0, j1 = s[1] + a1, j2 = s[2] + a2;
+              const int64_t gj = Cl.gid[P.offc + j0 + (int64_t)P.nc[0] * (j1 + (int64_t)P.nc[1] * j2)];
+              if (gj >= 0) out[gi * Cl.N + gj] += v;
+            }
+      }
+    }
+    return IGAMG_OK;
+  }
+  return set_err(IGAMG_EINVAL, "unknown export");
+  API_END
+}
+
+int igamg_solve(igamg_handle h, const double* rhs, double* u, double tol, igamg_solve_info* info, void* stream) {
+  API_BEGIN
+  need_device(h);
+  if (!rhs || !u || rhs == u) return set_err(IGAMG_EINVAL, "bad vector arguments");
+  if (!(tol > 0)) return set_err(IGAMG_EINVAL, "tol must be positive");
+  hipStream_t st = static_cast<hipStream_t>(stream);
+  auto t0 = std::chrono::steady_clock::now();
+  igamg_ctx& C = *h;
+  const int L = C.L;
+  DevLevel& D = C.dl[L];
+  double* r = D.f;   // PCG residual (distributed) is the cycle's right-hand side
+  double* z = D.u;   // cycle output (accumulated)
+  double* hs = C.host_scal;
+  auto fetch = [&](int slot) {
+    HIP_OK(hipMemcpyAsync(hs + slot, C.scal + slot, sizeof(double), hipMemcpyDeviceToHost, st));
+    HIP_OK(hipStreamSynchronize(st));
+    return hs[slot];
+  };
+  launch_scatter(rhs, r, D.gptr, D.gidx, D.N, true, st);
+  launch_fill(C.x, D.NL, 0.0, st);
+  launch_norm2_dist(r, D.gptr, D.gidx, D.N, C.part, C.scal, 6, st);
+  const double nf2 = fetch(6);
+  int code = IGAMG_OK;
+  int it = 0;
+  double rel = 0.0;
+  if (!std::isfinite(nf2)) {
+    code = set_err(IGAMG_ENAN, "non-finite right-hand side");
+  } else if (nf2 > 0) {
+    const double stop2 = tol * tol * nf2;
+    cycle(C, L, true, st);
+    launch_dot(r, z, D.NL, C.part, C.scal, 0, 0, st);
+    launch_copy(C.pp, z, D.NL, st);
+    rel = 1.0;
+    for (it = 1; it <= C.H.opt.maxit; ++it) {
+      apply(C, L, C.pp, C.q, st);
+      launch_dot(C.pp, C.q, D.NL, C.part, C.scal, 1, 1, st);
+      launch_axpy2(C.x, C.pp, r, C.q, D.NL, C.scal, st);
+      launch_norm2_dist(r, D.gptr, D.gidx, D.N, C.part, C.scal, 5, st);
+      const double rr = fetch(5);
+      if (!std::isfinite(rr)) {
+        code = set_err(IGAMG_ENAN, "non-finite residual");
+        break;
+      }
+      rel = std::sqrt(rr / nf2);
+      if (rr <= stop2) break;
+      cycle(C, L, true, st);
+      launch_dot(r, z, D.NL, C.part, C.scal, 3, 2, st);
+      launch_xpby(C.pp, z, D.NL, C.scal, st);
+    }
+    if (it > C.H.opt.maxit) {
+      it = C.H.opt.maxit;
+      if (code == IGAMG_OK) code = set_err(IGAMG_ENOCONV, "maxit reached");
+    }
+  }
+  launch_gather(C.x, u, D.gptr, D.gidx, D.N, false, st);
+  HIP_OK(hipGetLastError());
+  HIP_OK(hipStreamSynchronize(st));
+  if (info) {
+    info->iterations = it;
+    info->outer_iterations = 0;
+    info->converged = (code == IGAMG_OK);
+    info->rel_residual = rel;
+    info->solve_ms = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
+  }
+  return code;
+  API_END
+}
+
+}  // extern "C"

@@ -1,0 +1,53 @@
+// Device-side descriptors shared by the host setup and the HIP kernels.
+//
+// Vectors of a level live in the patch-local layout of Sec. 4: every patch
+// stores all of its local functions (interface layers duplicated, Dirichlet
+// functions kept as zeros), x fastest, patch blocks aligned to ROW_ALIGN
+// entries so that every 256-row block of a level belongs to one patch.
+#pragma once
+
+#include <cstdint>
+
+namespace igamg {
+
+constexpr int ROW_ALIGN = 256;   // patch block alignment (entries) and apply block size
+constexpr int MAX_P = 8;         // highest spline degree with a compiled apply kernel
+constexpr int MAX_FD = 84;       // largest 1D interior size handled by the FD kernels (LDS: L^2 + 1024 doubles)
+
+// One patch on one level l (coarse data refers to level l-1).
+struct PatchDev {
+  int n[3];          // local functions per direction at level l (1 for unused directions)
+  int nc[3];         // the same at level l-1
+  int64_t off;       // start of the patch block in level-l vectors
+  int64_t offc;      // start of the patch block in level-(l-1) vectors
+  int64_t rows;      // n0*n1*n2
+  int64_t rowsc;     // nc0*nc1*nc2
+  int64_t Pst[3];    // prolongation table (per fine row: first coarse index) in `tr_idx`
+  int64_t Pval[3];   // prolongation weights (per fine row: WP values) in `tr_val`
+  int64_t Rst[3];    // restriction table (per coarse row: first fine index)
+  int64_t Rval[3];   // restriction weights (per coarse row: WR values)
+};
+
+// One tensor item of the fast-diagonalisation smoother: a patch interior
+// (src = patch-local vectors) or a face piece (src = interface vector).
+struct FDItem {
+  int m[3];          // interior sizes per direction (1 for unused)
+  int src_if;        // 0: patch-local vectors, 1: interface vector
+  int64_t base;      // position of tensor element (0,0,0) in the source/destination
+  int64_t stride[3]; // strides of the source/destination view
+  int64_t scr;       // offset of this item's compact scratch tensor
+  int64_t U[3];      // offsets of U_c (m_c x m_c, row-major) in the FD matrix pool
+  int64_t mu[3];     // offsets of mu_c (m_c values) in the FD matrix pool
+  double pref;       // D = pref * (mu0 + mu1 + mu2 + extra)
+  double extra;
+};
+
+// A piece applied by a dense inverse (edges, vertices).
+struct DensePiece {
+  int64_t seg;       // first entry in the interface vector
+  int m;             // size
+  int pad;
+  int64_t Linv;      // offset of the m x m inverse (row-major) in the dense pool
+};
+
+}  // namespace igamg

@@ -1,0 +1,133 @@
+"""CPU tests of the library: the C-ABI loads and exports every declared symbol,
+the host setup (assembly, dof maps, knot-insertion transfers, load vectors)
+equals the oracle's, and the error codes come back for bad input."""
+import ctypes
+import os
+import re
+
+import numpy as np
+import pytest
+
+from paper_1804_02539_amd import igamg
+from paper_1804_02539_amd import workloads as W
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def declared_symbols():
+    txt = open(os.path.join(ROOT, "include", "igamg.h")).read()
+    return sorted(set(re.findall(r"\b(igamg_[a-z_0-9]+)\s*\(", txt)))
+
+
+def test_library_exports_every_declared_symbol():
+    lib = ctypes.CDLL(igamg.LIB_PATH)
+    names = declared_symbols()
+    assert "igamg_setup" in names and "igamg_solve" in names and "igamg_vcycle" in names
+    for n in names:
+        assert hasattr(lib, n), n
+    assert sorted(igamg.EXPORTED) == names
+
+
+@pytest.mark.parametrize("make", [
+    lambda: W.unit_square_2x2(levels=3),
+    lambda: W.square_4x4_bezier(p=3, levels=3),
+    lambda: W.cube_2x2x2_trilinear(levels=3),
+    lambda: W.fichera(2, 2),
+    lambda: W.box_grid(2, [3, 1], 1, 2, 3, gdeg=1, dirichlet_sides=[0]),
+])
+def test_host_setup_equals_oracle(make):
+    from oracle.multigrid import Hierarchy, load_vector
+    prob = make()
+    s = igamg.Solver(prob, host_only=True)
+    H = Hierarchy(prob)
+    for l in range(prob.levels):
+        A = s.export(igamg.EXPORT_MATRIX, l)
+        Ao = H.levels[l].A.toarray()
+        assert A.shape == Ao.shape
+        assert np.abs(A - Ao).max() <= 1e-13 * np.abs(Ao).max()
+        if l > 0:
+            P = s.export(igamg.EXPORT_PROLONG, l)
+            assert np.abs(P - H.P[l].toarray()).max() <= 1e-14
+    if prob.meta.get("source", ("",))[0] == "sine":
+        f = s.load_vector(*prob.meta["source"][1:])
+        fo = load_vector(prob, H.finest)
+        assert np.abs(f - fo).max() <= 1e-12 * np.abs(fo).max()
+
+
+@pytest.mark.parametrize("make", [lambda: W.square_4x4_bezier(p=2, levels=2),
+                                  lambda: W.fichera(3, 2)])
+def test_dof_numbering_equals_oracle(make):
+    # the global free numbering is a shared convention: compare the copies of
+    # every dof as (patch, local index) pairs
+    from oracle.topology import DofMap
+    prob = make()
+    s = igamg.Solver(prob, host_only=True)
+    for l in range(prob.levels):
+        dm = DofMap(prob, l)
+        ptr, idx = s.dof_map(l)
+        assert len(ptr) - 1 == dm.N
+        # library patch offsets are 256-aligned: recover (patch, local) by sizes
+        sizes = [int(np.prod(n)) for n in dm.n]
+        offs = np.cumsum([0] + [(z + 255) // 256 * 256 for z in sizes])
+        for g in range(0, dm.N, max(1, dm.N // 500)):
+            lib_c = []
+            for x in idx[ptr[g]:ptr[g + 1]]:
+                k = int(np.searchsorted(offs, x, side="right") - 1)
+                lib_c.append((k, int(x - offs[k])))
+            orc_c = []
+            for x in dm.copies[g]:
+                k = int(np.searchsorted(dm.off, x, side="right") - 1)
+                orc_c.append((k, int(x - dm.off[k])))
+            assert lib_c == orc_c, g
+
+
+def _expect(code, fn):
+    with pytest.raises(igamg.IgamgError) as ei:
+        fn()
+    assert ei.value.code == code, str(ei.value)
+
+
+def test_error_codes():
+    bad = W.unit_square_2x2(levels=2)
+    bad.degree = 9
+    _expect(igamg.EINVAL, lambda: igamg.Solver(bad, host_only=True))
+    bad = W.unit_square_2x2(levels=2)
+    bad.levels = 1
+    _expect(igamg.EINVAL, lambda: igamg.Solver(bad, host_only=True))
+    # non-matching interface: element counts differ across the glued side
+    bad = W.unit_square_2x2(levels=2)
+    bad.nel0 = bad.nel0.copy()
+    bad.nel0[1, 1] = 3
+    _expect(igamg.ETOPO, lambda: igamg.Solver(bad, host_only=True))
+    bad = W.unit_square_2x2(levels=2)
+    bad.iface = bad.iface.copy()
+    bad.iface[0, 1] = 7
+    _expect(igamg.ETOPO, lambda: igamg.Solver(bad, host_only=True))
+    # folded geometry: a control point pulled across the patch
+    bad = W.unit_square_2x2(levels=2)
+    bad.geo_ctrl[0] = bad.geo_ctrl[0].copy()
+    bad.geo_ctrl[0][3] = [-0.4, -0.4]
+    _expect(igamg.EGEOM, lambda: igamg.Solver(bad, host_only=True))
+    # no Dirichlet side: the coarse matrix is singular
+    bad = W.box_grid(2, [2, 1], 2, 1, 2, gdeg=1, dirichlet_sides=[])
+    _expect(igamg.ENOTSPD, lambda: igamg.Solver(bad, host_only=True))
+    # workspace too small is reported before any device access
+    prob = W.unit_square_2x2(levels=2)
+    cp = igamg._CProblem(prob)
+    h = ctypes.c_void_p()
+    code = igamg.lib().igamg_setup(ctypes.byref(cp.s), ctypes.byref(igamg.default_options()),
+                                   ctypes.c_void_p(256), 16, None, ctypes.byref(h))
+    assert code == igamg.ENOMEM
+    # invalid options
+    _expect(igamg.EINVAL, lambda: igamg.Solver(prob, igamg.default_options(mu=3), host_only=True))
+    # solver entry points refuse a host-only handle
+    s = igamg.Solver(prob, host_only=True)
+    assert igamg.lib().igamg_vcycle(s.h, ctypes.c_void_p(8), ctypes.c_void_p(16), None) == igamg.EINVAL
+
+
+def test_workspace_size_matches_setup_plan():
+    prob = W.square_4x4_bezier(p=3, levels=3)
+    n = igamg.workspace_size(prob)
+    # band of the finest level alone: (2p+1)^2 doubles per local row
+    assert n > 49 * 8 * 16 * (3 * 2 ** 2 + 3) ** 2
+    assert n < 64 * 1024 * 1024

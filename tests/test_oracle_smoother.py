@@ -77,9 +77,11 @@ def test_fd_independent_of_basis_within_subspace():
 
 
 def test_null_space_rank_gap():
-    # the subspace dimension decision must be clear-cut for every size used
-    for p in range(2, 7):
-        for nel in [1, 2, 3, 4, 6, 8, 12, 16, 24, 32, 48, 64]:
+    # the subspace dimension decision must be clear-cut for every size used: no
+    # relative singular value between 1e-13 and 1e-4, so any threshold in that
+    # window (the oracle cuts at 1e-10, a Gram-matrix route needs ~1e-5) agrees
+    for p in range(2, 9):
+        for nel in [1, 2, 3, 4, 5, 6, 8, 12, 16, 24, 32, 48, 64, 96]:
             Mi, Ki, C = interior_1d(p, nel)
             if C.shape[0] == 0:
                 continue
@@ -87,4 +89,4 @@ def test_null_space_rank_gap():
             small = s[s <= 1e-10 * s[0]]
             big = s[s > 1e-10 * s[0]]
             assert small.size == 0 or small.max() < 1e-13 * s[0]
-            assert big.min() > 1e-6 * s[0]
+            assert big.min() > 1e-4 * s[0]
