@@ -22,7 +22,7 @@ from .smoother import Smoother
 from .topology import DofMap, pieces
 
 
-EXPLICIT_LIMIT = 400_000   # local rows up to which a level's matrix is formed
+EXPLICIT_LIMIT = 120_000   # local rows up to which a level's matrix is formed
 
 
 class Level:

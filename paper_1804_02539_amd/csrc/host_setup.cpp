@@ -719,8 +719,9 @@ static void make_smoother(const ProblemH& P, const Options& O, LevelH& L) {
   std::map<int, OneD> cache;
   std::map<int, int64_t> Uoff, muoff;
   L.fdmat.clear();
-  // dummy direction: U = [1], mu = [0]
-  const int64_t dummyU = 0, dummyMu = 1;
+  // every U_c is stored followed by its transpose; dummy direction: U = U^T = [1], mu = [0]
+  const int64_t dummyU = 0, dummyMu = 2;
+  L.fdmat.push_back(1.0);
   L.fdmat.push_back(1.0);
   L.fdmat.push_back(0.0);
   auto get1d = [&](int nel) -> const OneD& {
@@ -730,6 +731,8 @@ static void make_smoother(const ProblemH& P, const Options& O, LevelH& L) {
       if (o.m > MAX_FD) fail(IGAMG_EINVAL, "patch too fine for the FD smoother (n-2 > 84)");
       Uoff[nel] = (int64_t)L.fdmat.size();
       L.fdmat.insert(L.fdmat.end(), o.U.begin(), o.U.end());
+      for (int i = 0; i < o.m; ++i)
+        for (int j = 0; j < o.m; ++j) L.fdmat.push_back(o.U[(size_t)j * o.m + i]);
       muoff[nel] = (int64_t)L.fdmat.size();
       L.fdmat.insert(L.fdmat.end(), o.mu.begin(), o.mu.end());
       it = cache.emplace(nel, std::move(o)).first;
@@ -1010,7 +1013,18 @@ void build_all(Hierarchy& H) {
     }
   }
   if (!cholesky(A, (int)N0)) fail(IGAMG_ENOTSPD, "coarse matrix is not positive definite (is any side Dirichlet?)");
-  H.Winv = lower_inverse(A, (int)N0);
+  // A_0^{-1} = L^{-T} L^{-1} from the Cholesky factor: the two triangular
+  // solves of the exact coarse solver become one dense mat-vec on the device
+  Mat W = lower_inverse(A, (int)N0);
+  H.Ainv.assign((size_t)N0 * N0, 0.0);
+  parallel_for((int)N0, [&](int i) {
+    for (int64_t j = i; j < N0; ++j) {
+      double s = 0.0;
+      for (int64_t k = j; k < N0; ++k) s += W[(size_t)k * N0 + i] * W[(size_t)k * N0 + j];
+      H.Ainv[(size_t)i * N0 + j] = s;
+      H.Ainv[(size_t)j * N0 + i] = s;
+    }
+  });
 }
 
 std::vector<double> load_vector(const Hierarchy& H, double amp, double freq) {

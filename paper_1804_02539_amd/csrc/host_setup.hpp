@@ -70,8 +70,8 @@ struct Hierarchy {
   ProblemH prob;
   Options opt;
   std::vector<LevelH> lv;
-  // coarse solver: W = L^{-1} with A_0 = L L^T (dense, row-major, N0 x N0)
-  std::vector<double> Winv;
+  // coarse solver: A_0^{-1} = L^{-T} L^{-1} with A_0 = L L^T (dense, row-major, N0 x N0)
+  std::vector<double> Ainv;
 };
 
 // Validate and copy the C problem description.  Throws SetupError.

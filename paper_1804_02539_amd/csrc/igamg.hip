@@ -40,7 +40,6 @@ struct DevLevel {
   PatchDev* pd = nullptr;
   uint8_t* isfree = nullptr;
   int64_t *gptr = nullptr, *gidx = nullptr, *if_ptr = nullptr, *if_idx = nullptr;
-  double *rif = nullptr, *zif = nullptr;
   FDItem* fd = nullptr;
   double* fdmat = nullptr;
   double *scrA = nullptr, *scrB = nullptr;
@@ -50,6 +49,8 @@ struct DevLevel {
   double* tr_val = nullptr;
   int fd_grid[3] = {1, 1, 1};
   size_t fd_lds = 0;
+  int max_m2 = 1, slab_grid = 1;
+  size_t slab_lds = 0;
 };
 
 struct Bump {
@@ -70,8 +71,8 @@ struct igamg_ctx {
   Hierarchy H;
   int d = 2, p = 2, L = 1;
   std::vector<DevLevel> dl;
-  double* Winv = nullptr;
-  double *cb = nullptr, *cy = nullptr, *cx = nullptr;
+  double* Ainv = nullptr;
+  double* cb = nullptr;
   int64_t N0 = 0;
   // PCG (finest level, patch-local)
   double *x = nullptr, *pp = nullptr, *q = nullptr, *tmpg = nullptr;
@@ -123,8 +124,6 @@ static size_t plan(igamg_ctx& C, char* base) {
     D.nifidx = (int64_t)L.if_idx.size();
     D.if_ptr = b.take<int64_t>(L.if_ptr.size());
     D.if_idx = b.take<int64_t>(L.if_idx.size());
-    D.rif = b.take<double>(L.nif);
-    D.zif = b.take<double>(L.nif);
     D.nfd = (int)L.fd.size();
     D.nfd_int = L.nfd_interior;
     D.fd = b.take<FDItem>(L.fd.size());
@@ -144,14 +143,18 @@ static size_t plan(igamg_ctx& C, char* base) {
     D.WP = L.WP;
     D.WR = L.WR;
     D.fd_maxm = L.fd_maxm;
-    for (int dir = 0; dir < 3; ++dir) D.fd_grid[dir] = fd_grid_x(L.fd.data(), (int)L.fd.size(), dir);
+    for (int dir = 0; dir < 3; ++dir) D.fd_grid[dir] = fd_grid_x(L.fd.data(), L.nfd_interior, dir);
     D.fd_lds = fd_lds_bytes(L.fd_maxm);
+    int maxdense = 1;
+    for (const auto& dp : L.dense) maxdense = std::max(maxdense, dp.m);
+    D.max_m2 = 1;
+    for (const auto& it : L.fd) D.max_m2 = std::max(D.max_m2, it.m[2]);
+    D.slab_lds = std::max(fd_slab_lds(L.fd_maxm), (size_t)maxdense * sizeof(double) + 64);
+    D.slab_grid = fd_slab_grid(L.fd.data(), (int)L.fd.size());
   }
   C.N0 = H.lv[0].N;
-  C.Winv = b.take<double>((size_t)C.N0 * C.N0);
+  C.Ainv = b.take<double>((size_t)C.N0 * C.N0);
   C.cb = b.take<double>(C.N0);
-  C.cy = b.take<double>(C.N0);
-  C.cx = b.take<double>(C.N0);
   const int64_t NLf = H.lv.back().NL;
   C.x = b.take<double>(NLf);
   C.pp = b.take<double>(NLf);
@@ -179,7 +182,18 @@ static void upload(igamg_ctx& C, hipStream_t st) {
     up(D.gptr, L.gptr, st);
     up(D.gidx, L.gidx, st);
     if (l == 0) continue;
-    up(D.band, L.band, st);
+    {
+      // tiled coefficient-major: the (2p+1)^d planes of each 256-row block are
+      // contiguous, band[(row/256)*nb*256 + o*256 + row%256]
+      std::vector<double> tiled(L.band.size());
+      const int64_t nblk = L.NL / ROW_ALIGN;
+      for (int64_t bk = 0; bk < nblk; ++bk)
+        for (int o = 0; o < D.nb; ++o)
+          std::memcpy(&tiled[((size_t)bk * D.nb + o) * ROW_ALIGN], &L.band[(size_t)o * L.NL + bk * ROW_ALIGN],
+                      ROW_ALIGN * sizeof(double));
+      up(D.band, tiled, st);
+      HIP_OK(hipStreamSynchronize(st));
+    }
     up(D.if_ptr, L.if_ptr, st);
     up(D.if_idx, L.if_idx, st);
     up(D.fd, L.fd, st);
@@ -189,13 +203,13 @@ static void upload(igamg_ctx& C, hipStream_t st) {
     up(D.tr_idx, L.tr_idx, st);
     up(D.tr_val, L.tr_val, st);
   }
-  up(C.Winv, H.Winv, st);
+  up(C.Ainv, H.Ainv, st);
   HIP_OK(hipStreamSynchronize(st));
   // the bands are large and no longer needed on the host
   for (auto& L : H.lv) {
     std::vector<double>().swap(L.band);
   }
-  std::vector<double>().swap(H.Winv);
+  std::vector<double>().swap(H.Ainv);
 }
 
 // ---------------------------------------------------------------------------
@@ -239,45 +253,24 @@ static void apply(igamg_ctx& C, int l, const double* u, double* y, hipStream_t s
   band_timed(C, l, u, nullptr, y, false, st);
 }
 
-// u <- u + tau L^{-1} src (or u = tau L^{-1} src when !add); src distributed
+// u <- u + tau L^{-1} src (or u = tau L^{-1} src when !add); src distributed.
+// Forward products (+ D^{-1} for 2D tensors, + the dense pieces), for 3D
+// interiors the scaled middle direction over pencils, inverse products.
 static void smoother_apply(igamg_ctx& C, int l, const double* src, double* u, bool add, double tau,
                            hipStream_t st) {
   DevLevel& D = C.dl[l];
-  launch_if_gather(src, D.rif, D.if_ptr, D.if_idx, D.nif, st);
-  // FD passes over interiors and faces: forward directions 0..d-2, the scaled
-  // middle direction d-1, inverse directions d-2..0
-  const int d = C.d;
-  const int last = d - 1;
-  int in_sel = 0;  // 0: source view, 1: scrA, 2: scrB
-  int buf = 1;
-  for (int dir = 0; dir < last; ++dir) {
-    launch_fd_pass(D.fd, D.nfd, D.fd_grid[dir], D.fd_lds, dir, 0, in_sel, buf, D.fdmat, src, D.rif, u, D.zif, D.scrA,
-                   D.scrB, tau, add, st);
-    in_sel = buf;
-    buf = 3 - buf;
-  }
-  launch_fd_pass(D.fd, D.nfd, D.fd_grid[last], D.fd_lds, last, 2, in_sel, last == 0 ? 0 : buf, D.fdmat, src, D.rif, u,
-                 D.zif, D.scrA, D.scrB, tau, add, st);
-  if (last > 0) {
-    in_sel = buf;
-    buf = 3 - buf;
-  }
-  for (int dir = last - 1; dir >= 0; --dir) {
-    const int out = (dir == 0) ? 0 : buf;
-    launch_fd_pass(D.fd, D.nfd, D.fd_grid[dir], D.fd_lds, dir, 1, in_sel, out, D.fdmat, src, D.rif, u, D.zif, D.scrA,
-                   D.scrB, tau, add, st);
-    in_sel = buf;
-    buf = 3 - buf;
-  }
-  launch_dense(D.dense, D.ndense, D.densemat, D.rif, D.zif, st);
-  launch_if_scatter(D.zif, u, D.if_ptr, D.if_idx, D.nif, tau, add, st);
+  launch_fd_fwd(D.fd, D.nfd, D.ndense, D.slab_grid, D.slab_lds, D.dense, D.densemat, D.fdmat, src, u, D.if_ptr,
+                D.if_idx, D.scrA, tau, add, st);
+  if (C.d == 3 && D.nfd_int > 0 && D.max_m2 > 1)
+    launch_fd_pass(D.fd, D.nfd_int, D.fd_grid[2], D.fd_lds, 2, 2, 1, 1, D.fdmat, nullptr, nullptr, nullptr, nullptr,
+                   D.scrA, D.scrB, 1.0, false, st);
+  launch_fd_inv(D.fd, D.nfd, D.slab_grid, D.slab_lds, D.fdmat, u, D.if_ptr, D.if_idx, D.scrA, tau, add, st);
 }
 
 static void coarse_solve(igamg_ctx& C, const double* f0, double* u0, hipStream_t st) {
   DevLevel& D = C.dl[0];
   launch_gather(f0, C.cb, D.gptr, D.gidx, D.N, true, st);
-  launch_coarse(C.Winv, C.cb, C.cy, C.cx, (int)C.N0, st);
-  launch_scatter(C.cx, u0, D.gptr, D.gidx, D.N, false, st);
+  launch_coarse(C.Ainv, C.cb, u0, D.gptr, D.gidx, (int)C.N0, st);
 }
 
 static void restrict_to(igamg_ctx& C, int l, const double* rf, double* rc, hipStream_t st) {

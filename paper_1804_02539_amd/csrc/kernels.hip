@@ -42,14 +42,16 @@ __global__ __launch_bounds__(256) void k_band(const TB* __restrict__ band, const
     c1[o] = min(max(i1 + o - P, 0), n1 - 1) * n0;
   }
   const double* ub = u + off;
-  const TB* bp = band + g;
+  // tiled coefficient-major band: this block's (2P+1)^D planes are contiguous
+  constexpr int NBT = (D == 2) ? NB * NB : NB * NB * NB;
+  const TB* bp = band + (int64_t)b * NBT * ROW_ALIGN + threadIdx.x;
   double s = 0.0;
   if constexpr (D == 2) {
 #pragma unroll
     for (int o1 = 0; o1 < NB; ++o1) {
       const double* ur = ub + c1[o1];
 #pragma unroll
-      for (int o0 = 0; o0 < NB; ++o0) s += (double)bp[(int64_t)(o0 + NB * o1) * NL] * ur[c0[o0]];
+      for (int o0 = 0; o0 < NB; ++o0) s += (double)bp[(o0 + NB * o1) * ROW_ALIGN] * ur[c0[o0]];
     }
   } else {
     const int64_t pl = (int64_t)n0 * n1;
@@ -58,9 +60,9 @@ __global__ __launch_bounds__(256) void k_band(const TB* __restrict__ band, const
 #pragma unroll
       for (int o1 = 0; o1 < NB; ++o1) {
         const double* ur = ub + z + c1[o1];
-        const TB* bq = bp + (int64_t)(NB * (o1 + NB * o2)) * NL;
+        const TB* bq = bp + (NB * (o1 + NB * o2)) * ROW_ALIGN;
 #pragma unroll
-        for (int o0 = 0; o0 < NB; ++o0) s += (double)bq[(int64_t)o0 * NL] * ur[c0[o0]];
+        for (int o0 = 0; o0 < NB; ++o0) s += (double)bq[o0 * ROW_ALIGN] * ur[c0[o0]];
       }
     }
   }
@@ -89,49 +91,9 @@ void launch_band(int d, int p, const double* band, const double* u, const double
 }
 
 // ---------------------------------------------------------------------------
-// interface vector: gather-sum of copies (the accumulation Sigma, eq. ops6)
-// and scatter of a piece correction to every copy
-// ---------------------------------------------------------------------------
-__global__ __launch_bounds__(256) void k_if_gather(const double* __restrict__ src, double* __restrict__ dst,
-                                                   const int64_t* __restrict__ ptr, const int64_t* __restrict__ idx,
-                                                   int64_t n) {
-  const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (t >= n) return;
-  double s = 0.0;
-  for (int64_t c = ptr[t]; c < ptr[t + 1]; ++c) s += src[idx[c]];
-  dst[t] = s;
-}
-
-__global__ __launch_bounds__(256) void k_if_scatter(const double* __restrict__ z, double* __restrict__ u,
-                                                    const int64_t* __restrict__ ptr,
-                                                    const int64_t* __restrict__ idx, int64_t n, double tau,
-                                                    int add) {
-  const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (t >= n) return;
-  const double v = tau * z[t];
-  for (int64_t c = ptr[t]; c < ptr[t + 1]; ++c) {
-    const int64_t x = idx[c];
-    u[x] = add ? u[x] + v : v;
-  }
-}
-
-void launch_if_gather(const double* src, double* dst, const int64_t* ptr, const int64_t* idx, int64_t n,
-                      hipStream_t st) {
-  if (n <= 0) return;
-  hipLaunchKernelGGL(k_if_gather, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, st, src, dst, ptr, idx, n);
-}
-
-void launch_if_scatter(const double* z, double* u, const int64_t* ptr, const int64_t* idx, int64_t n, double tau,
-                       bool add, hipStream_t st) {
-  if (n <= 0) return;
-  hipLaunchKernelGGL(k_if_scatter, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, st, z, u, ptr, idx, n, tau,
-                     (int)add);
-}
-
-// ---------------------------------------------------------------------------
-// fast-diagonalisation passes: one direction of (x)U^T, the scaled middle
-// direction U diag(1/D) U^T, or one direction of (x)U, over all items
-// (patch interiors and faces) of a level
+// fast-diagonalisation pencil pass: one direction of (x)U^T, the scaled middle
+// direction U diag(1/D) U^T, or one direction of (x)U, over the FD items of a
+// level (used for the middle direction of 3D patch interiors)
 // ---------------------------------------------------------------------------
 __device__ __forceinline__ int fd_lines_per_block(int L) { return max(1, min(64, 512 / L)); }
 
@@ -303,25 +265,181 @@ void launch_fd_pass(const FDItem* items, int nitems, int gridx, size_t lds, int 
 }
 
 // ---------------------------------------------------------------------------
-// dense pieces (edges, vertices): z = L_T^{-1} r on the interface vector
+// smoother kernels over 2D tensors (a 2D patch interior, a 3D face, or one
+// z-slab of a 3D patch interior), split into chunks of RB output rows:
+//   forward:  Y[I, :] = (U0[:, I]^T X) U1     (rows I of U0^T X U1)
+//   inverse:  Z[J, :] = (U0[J, :] Y) U1^T     (rows J of U0 Y U1^T)
+// For 2D tensors the forward kernel applies D^{-1}; for 3D interiors the
+// middle direction (with D^{-1}) runs in between as a pencil pass.  The
+// forward launch also runs the dense pieces (edges, vertices).  Interface
+// items gather their residual from all copies (the accumulation Sigma) and
+// add tau z to every copy; interiors use the patch-local vectors directly.
 // ---------------------------------------------------------------------------
-__global__ __launch_bounds__(128) void k_dense(const DensePiece* __restrict__ pcs, const double* __restrict__ mat,
-                                               const double* __restrict__ r, double* __restrict__ z) {
-  __shared__ double sr[MAX_FD + 8];
-  const DensePiece pc = pcs[blockIdx.x];
-  for (int j = threadIdx.x; j < pc.m; j += blockDim.x) sr[j] = r[pc.seg + j];
+constexpr int FD_RB = 8;
+
+__device__ __forceinline__ void fd_chunk(const FDItem& it, int& z, int& r0, int& nr) {
+  const int nch = (it.m[0] + FD_RB - 1) / FD_RB;
+  z = blockIdx.x / nch;
+  r0 = (blockIdx.x - z * nch) * FD_RB;
+  nr = min(FD_RB, it.m[0] - r0);
+}
+
+__global__ __launch_bounds__(256) void k_fd_fwd(const FDItem* __restrict__ items, int nitems,
+                                                const DensePiece* __restrict__ dense,
+                                                const double* __restrict__ densemat, const double* __restrict__ mat,
+                                                const double* __restrict__ src, double* __restrict__ u,
+                                                const int64_t* __restrict__ if_ptr, const int64_t* __restrict__ if_idx,
+                                                double* __restrict__ scr, double tau, int add) {
+  extern __shared__ double lds[];
+  const int y = blockIdx.y;
+  if (y >= nitems) {
+    // dense piece: gather (Sigma), z = L^{-1} r, scatter tau z to all copies
+    if (blockIdx.x != 0) return;
+    const DensePiece pc = dense[y - nitems];
+    double* sr = lds;
+    for (int j = threadIdx.x; j < pc.m; j += blockDim.x) {
+      double v = 0.0;
+      for (int64_t c = if_ptr[pc.seg + j]; c < if_ptr[pc.seg + j + 1]; ++c) v += src[if_idx[c]];
+      sr[j] = v;
+    }
+    __syncthreads();
+    const double* A = densemat + pc.Linv;
+    for (int k = threadIdx.x; k < pc.m; k += blockDim.x) {
+      double zz = 0.0;
+      for (int j = 0; j < pc.m; ++j) zz += A[(int64_t)k * pc.m + j] * sr[j];
+      zz *= tau;
+      for (int64_t c = if_ptr[pc.seg + k]; c < if_ptr[pc.seg + k + 1]; ++c) {
+        const int64_t x = if_idx[c];
+        u[x] = add ? u[x] + zz : zz;
+      }
+    }
+    return;
+  }
+  const FDItem it = items[y];
+  const int m0 = it.m[0], m1 = it.m[1];
+  int z, r0, nr;
+  fd_chunk(it, z, r0, nr);
+  if (z >= it.m[2]) return;
+  const int n = m0 * m1;
+  double* XT = lds;            // XT[j * m1 + b] = X[j, b]
+  double* W = lds + n;         // W[a * m1 + b], a < RB
+  const int64_t zoff = (int64_t)z * it.stride[2];
+  // X[j, b] is read with j fastest (coalesced) and stored transposed
+  if (it.src_if) {
+    for (int t = threadIdx.x; t < n; t += blockDim.x) {
+      const int j = t % m0, b = t / m0;
+      const int64_t e = it.base + t;  // face tensors are stored j fastest
+      double v = 0.0;
+      for (int64_t c = if_ptr[e]; c < if_ptr[e + 1]; ++c) v += src[if_idx[c]];
+      XT[j * m1 + b] = v;
+    }
+  } else {
+    for (int t = threadIdx.x; t < n; t += blockDim.x) {
+      const int j = t % m0, b = t / m0;
+      XT[j * m1 + b] = src[it.base + j * it.stride[0] + b * it.stride[1] + zoff];
+    }
+  }
   __syncthreads();
-  const double* A = mat + pc.Linv;
-  for (int k = threadIdx.x; k < pc.m; k += blockDim.x) {
+  const double* U0 = mat + it.U[0];
+  const double* U1 = mat + it.U[1];
+  // W[a, b] = sum_j U0[j, r0 + a] X[j, b]
+  for (int t = threadIdx.x; t < nr * m1; t += blockDim.x) {
+    const int b = t % m1, a = t / m1;
     double s = 0.0;
-    for (int j = 0; j < pc.m; ++j) s += A[(int64_t)k * pc.m + j] * sr[j];
-    z[pc.seg + k] = s;
+    for (int j = 0; j < m0; ++j) s += U0[j * m0 + r0 + a] * XT[j * m1 + b];
+    W[a * m1 + b] = s;
+  }
+  __syncthreads();
+  // Y[a, k] = sum_b W[a, b] U1[b, k]
+  const double* mu0 = mat + it.mu[0];
+  const double* mu1 = mat + it.mu[1];
+  const double mu2 = mat[it.mu[2]];
+  const bool full = (it.m[2] == 1);
+  double* S = scr + it.scr + (int64_t)z * n;
+  for (int t = threadIdx.x; t < nr * m1; t += blockDim.x) {
+    const int k = t % m1, a = t / m1;
+    const double* w = W + a * m1;
+    double s = 0.0;
+    for (int b = 0; b < m1; ++b) s += w[b] * U1[b * m1 + k];
+    if (full) s /= it.pref * (mu0[r0 + a] + mu1[k] + mu2 + it.extra);
+    S[(r0 + a) + m0 * k] = s;
   }
 }
 
-void launch_dense(const DensePiece* pcs, int n, const double* mat, const double* r, double* z, hipStream_t st) {
-  if (n <= 0) return;
-  hipLaunchKernelGGL(k_dense, dim3(n), dim3(128), 0, st, pcs, mat, r, z);
+__global__ __launch_bounds__(256) void k_fd_inv(const FDItem* __restrict__ items, const double* __restrict__ mat,
+                                                double* __restrict__ u, const int64_t* __restrict__ if_ptr,
+                                                const int64_t* __restrict__ if_idx, const double* __restrict__ scr,
+                                                double tau, int add) {
+  extern __shared__ double lds[];
+  const FDItem it = items[blockIdx.y];
+  const int m0 = it.m[0], m1 = it.m[1];
+  int z, r0, nr;
+  fd_chunk(it, z, r0, nr);
+  if (z >= it.m[2]) return;
+  const int n = m0 * m1;
+  double* YT = lds;      // YT[j * m1 + b] = Y[j, b]
+  double* W = lds + n;   // W[a * m1 + b]
+  const double* S = scr + it.scr + (int64_t)z * n;
+  for (int t = threadIdx.x; t < n; t += blockDim.x) {
+    const int j = t % m0, b = t / m0;
+    YT[j * m1 + b] = S[t];
+  }
+  __syncthreads();
+  const double* U0 = mat + it.U[0];
+  const double* U1T = mat + it.U[1] + (int64_t)m1 * m1;
+  // W[a, b] = sum_j U0[r0 + a, j] Y[j, b]
+  for (int t = threadIdx.x; t < nr * m1; t += blockDim.x) {
+    const int b = t % m1, a = t / m1;
+    const double* ur = U0 + (int64_t)(r0 + a) * m0;
+    double s = 0.0;
+    for (int j = 0; j < m0; ++j) s += ur[j] * YT[j * m1 + b];
+    W[a * m1 + b] = s;
+  }
+  __syncthreads();
+  // Z[a, k] = sum_b W[a, b] U1[k, b] = sum_b W[a, b] U1T[b, k]
+  const int64_t zoff = (int64_t)z * it.stride[2];
+  for (int t = threadIdx.x; t < nr * m1; t += blockDim.x) {
+    const int k = t % m1, a = t / m1;
+    const double* w = W + a * m1;
+    double s = 0.0;
+    for (int b = 0; b < m1; ++b) s += w[b] * U1T[b * m1 + k];
+    const double v = tau * s;
+    if (it.src_if) {
+      const int64_t e = it.base + (r0 + a) + (int64_t)m0 * k;
+      for (int64_t c = if_ptr[e]; c < if_ptr[e + 1]; ++c) {
+        const int64_t x = if_idx[c];
+        u[x] = add ? u[x] + v : v;
+      }
+    } else {
+      const int64_t x = it.base + (r0 + a) * it.stride[0] + k * it.stride[1] + zoff;
+      u[x] = add ? u[x] + v : v;
+    }
+  }
+}
+
+size_t fd_slab_lds(int maxm) { return ((size_t)maxm * maxm + (size_t)FD_RB * maxm) * sizeof(double) + 64; }
+
+int fd_slab_grid(const FDItem* items, int nitems) {
+  int g = 1;
+  for (int i = 0; i < nitems; ++i) g = std::max(g, items[i].m[2] * ((items[i].m[0] + FD_RB - 1) / FD_RB));
+  return g;
+}
+
+void launch_fd_fwd(const FDItem* items, int nitems, int ndense, int gridx, size_t lds, const DensePiece* dense,
+                   const double* densemat, const double* mat, const double* src, double* u, const int64_t* if_ptr,
+                   const int64_t* if_idx, double* scr, double tau, bool add, hipStream_t st) {
+  const int ny = nitems + ndense;
+  if (ny <= 0) return;
+  hipLaunchKernelGGL(k_fd_fwd, dim3(gridx, ny), dim3(256), lds, st, items, nitems, dense, densemat, mat, src, u,
+                     if_ptr, if_idx, scr, tau, (int)add);
+}
+
+void launch_fd_inv(const FDItem* items, int nitems, int gridx, size_t lds, const double* mat, double* u,
+                   const int64_t* if_ptr, const int64_t* if_idx, const double* scr, double tau, bool add,
+                   hipStream_t st) {
+  if (nitems <= 0) return;
+  hipLaunchKernelGGL(k_fd_inv, dim3(gridx, nitems), dim3(256), lds, st, items, mat, u, if_ptr, if_idx, scr, tau,
+                     (int)add);
 }
 
 // ---------------------------------------------------------------------------
@@ -495,32 +613,26 @@ void launch_scatter(const double* glob, double* loc, const int64_t* ptr, const i
     hipLaunchKernelGGL(k_scatter_acc, grid, dim3(256), 0, st, glob, loc, ptr, idx, n);
 }
 
-// y = W b, W lower triangular (n x n row-major): one wavefront per row
-__global__ __launch_bounds__(256) void k_trmv_lower(const double* __restrict__ W, const double* __restrict__ b,
-                                                    double* __restrict__ y, int n) {
+// x = A_0^{-1} b (dense, n x n row-major), one wavefront per row; x_i goes to
+// every local copy of coarse dof i (the restriction chi of the coarse solve)
+__global__ __launch_bounds__(256) void k_coarse_gemv(const double* __restrict__ Ainv, const double* __restrict__ b,
+                                                     double* __restrict__ u0, const int64_t* __restrict__ ptr,
+                                                     const int64_t* __restrict__ idx, int n) {
   const int lane = threadIdx.x & 63;
   const int row = blockIdx.x * 4 + (threadIdx.x >> 6);
   if (row >= n) return;
-  const double* wr = W + (int64_t)row * n;
+  const double* ar = Ainv + (int64_t)row * n;
   double s = 0.0;
-  for (int j = lane; j <= row; j += 64) s += wr[j] * b[j];
+  for (int j = lane; j < n; j += 64) s += ar[j] * b[j];
   for (int o = 32; o > 0; o >>= 1) s += __shfl_down(s, o, 64);
-  if (lane == 0) y[row] = s;
+  const int64_t c0 = ptr[row], c1 = ptr[row + 1];
+  s = __shfl(s, 0, 64);
+  for (int64_t c = c0 + lane; c < c1; c += 64) u0[idx[c]] = s;
 }
 
-// x = W^T y: x_i = sum_{j >= i} W[j, i] y_j, one thread per i (coalesced over i)
-__global__ __launch_bounds__(256) void k_trmv_upper_t(const double* __restrict__ W, const double* __restrict__ y,
-                                                      double* __restrict__ x, int n) {
-  const int i = blockIdx.x * blockDim.x + threadIdx.x;
-  if (i >= n) return;
-  double s = 0.0;
-  for (int j = i; j < n; ++j) s += W[(int64_t)j * n + i] * y[j];
-  x[i] = s;
-}
-
-void launch_coarse(const double* W, const double* b, double* y, double* x, int n, hipStream_t st) {
-  hipLaunchKernelGGL(k_trmv_lower, dim3((n + 3) / 4), dim3(256), 0, st, W, b, y, n);
-  hipLaunchKernelGGL(k_trmv_upper_t, dim3((n + 255) / 256), dim3(256), 0, st, W, y, x, n);
+void launch_coarse(const double* Ainv, const double* b, double* u0, const int64_t* ptr, const int64_t* idx, int n,
+                   hipStream_t st) {
+  hipLaunchKernelGGL(k_coarse_gemv, dim3((n + 3) / 4), dim3(256), 0, st, Ainv, b, u0, ptr, idx, n);
 }
 
 // ---------------------------------------------------------------------------

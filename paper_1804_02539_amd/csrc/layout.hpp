@@ -36,7 +36,7 @@ struct FDItem {
   int64_t base;      // position of tensor element (0,0,0) in the source/destination
   int64_t stride[3]; // strides of the source/destination view
   int64_t scr;       // offset of this item's compact scratch tensor
-  int64_t U[3];      // offsets of U_c (m_c x m_c, row-major) in the FD matrix pool
+  int64_t U[3];      // offsets of U_c (m_c x m_c, row-major), followed by U_c^T, in the FD pool
   int64_t mu[3];     // offsets of mu_c (m_c values) in the FD matrix pool
   double pref;       // D = pref * (mu0 + mu1 + mu2 + extra)
   double extra;

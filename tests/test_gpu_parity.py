@@ -159,11 +159,14 @@ def test_full_size_cube_sampled(torch_cuda):
     from paper_1804_02539_amd import igamg
     prob = W.cube_2x2x2_trilinear()
     H = Hierarchy(prob)
+    _say("  oracle hierarchy built")
     S = igamg.Solver(prob)
     assert S.N == H.finest.N == 300763
     r = np.random.default_rng(5).standard_normal(S.N)
     assert rel(S.operator(igamg.OP_APPLY, -1, r).cpu().numpy(), H.finest.apply(r)) < 1e-12
+    _say("  apply ok")
     assert rel(S.vcycle(r).cpu().numpy(), H.vcycle(r)) < 1e-10
+    _say("  cycle ok")
     f = load_vector(prob, H.finest)
     u, info = S.solve(f)
     assert info.converged
