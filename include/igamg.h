@@ -83,8 +83,8 @@ typedef struct {
                             iterative refinement)                          */
   int maxit;             /* iteration cap of igamg_solve                    */
   int geometry_scaling;  /* 1: scale piece operators by the patch's mean metric trace */
-  int inner_maxit;       /* mixed: inner PCG iteration cap per refinement step */
-  double inner_tol;      /* mixed: inner relative tolerance per refinement step */
+  int inner_maxit;       /* mixed: inner PCG iteration cap per refinement step (100) */
+  double inner_tol;      /* mixed: inner relative residual reduction per step (1e-4) */
   int reserved[6];
 } igamg_options;
 
@@ -134,7 +134,10 @@ int igamg_vcycle(igamg_handle h, const double* r, double* z, void* stream);
 
 /* PCG with one cycle as preconditioner from u = 0 (Sec. 4), stopping when
  * ||f - A u||_2 <= tol ||f||_2 (Sec. 5).  With precision IGAMG_MIXED, FP64
- * iterative refinement around FP32 PCG solves.  rhs and u: device vectors of
+ * iterative refinement around FP32 PCG solves: the residual f - A u and the
+ * update u += d are FP64 (FP64 band), each correction d is an FP32 PCG solve
+ * (FP32 bands, smoothers, transfers; the coarse solve stays FP64) to
+ * inner_tol, and `maxit` caps the inner iterations summed.  rhs and u: device vectors of
  * length n_free (finest).  Synchronises the stream (reads the residual norm
  * back once per iteration).  Returns ENOCONV when maxit is reached and ENAN
  * on a non-finite residual; `info` (may be NULL) is filled in either case.  */
@@ -148,12 +151,15 @@ int igamg_solve(igamg_handle h, const double* rhs, double* u, double tol, igamg_
  *   IGAMG_OP_PROLONG   y = P_l x  (x on level l-1, y on level l, l >= 1)
  *   IGAMG_OP_RESTRICT  y = P_l^T x (x on level l, y on level l-1, l >= 1)
  *   IGAMG_OP_COARSE    y = A_0^{-1} x                     (level 0)
+ *   IGAMG_OP_CYCLE_FP32 y = B r with the FP32 data of a IGAMG_MIXED handle
+ *                      (finest level; x rounded to FP32, y returned in FP64)
  * Device vectors; x and y may not alias.                                      */
 #define IGAMG_OP_APPLY 0
 #define IGAMG_OP_SMOOTHER 1
 #define IGAMG_OP_PROLONG 2
 #define IGAMG_OP_RESTRICT 3
 #define IGAMG_OP_COARSE 4
+#define IGAMG_OP_CYCLE_FP32 5
 int igamg_operator(igamg_handle h, int op, int level, const double* x, double* y, void* stream);
 
 /* Copies of the global free dofs of a level in the library's patch-local

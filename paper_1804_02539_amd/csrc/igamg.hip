@@ -1,7 +1,8 @@
 // C-ABI of the library: workspace planning, upload, the multigrid cycle of
-// Algorithm 1 on the device, the PCG driver of Sec. 4, and per-operator entry
-// points.  Every step of the cycle runs in the kernels of kernels.hip; the
-// host only sequences launches on the caller's stream.
+// Algorithm 1 on the device, the PCG driver of Sec. 4 (FP64, or FP32 inner
+// solves inside FP64 iterative refinement), and per-operator entry points.
+// Every step of the cycle runs in the kernels of kernels.hip; the host only
+// sequences launches on the caller's stream.
 #include <hip/hip_runtime.h>
 
 #include <chrono>
@@ -31,26 +32,42 @@ static int set_err(int code, const std::string& msg) {
 
 namespace {
 
+// storage of one level in one precision
+template <typename T>
+struct LevelData {
+  T *band = nullptr, *u = nullptr, *f = nullptr, *w = nullptr;
+  T *fdmat = nullptr, *densemat = nullptr, *tr_val = nullptr, *scr = nullptr;
+};
+
 struct DevLevel {
-  int64_t NL = 0, N = 0, nif = 0;
-  int nb = 0, nfd = 0, nfd_int = 0, ndense = 0, WP = 0, WR = 0, fd_maxm = 1;
-  int64_t fdscr = 0, ncopy = 0, nifidx = 0, ntr_idx = 0, ntr_val = 0, nfdmat = 0, ndmat = 0;
-  double *band = nullptr, *u = nullptr, *f = nullptr, *w = nullptr;
+  int64_t NL = 0, N = 0, rows = 0;
+  int nb = 0, nfd = 0, nfd_int = 0, ndense = 0, WP = 0, WR = 0, fd_maxm = 1, max_dense = 1;
   int* bpatch = nullptr;
   PatchDev* pd = nullptr;
   uint8_t* isfree = nullptr;
   int64_t *gptr = nullptr, *gidx = nullptr, *if_ptr = nullptr, *if_idx = nullptr;
   FDItem* fd = nullptr;
-  double* fdmat = nullptr;
-  double *scrA = nullptr, *scrB = nullptr;
   DensePiece* dense = nullptr;
-  double* densemat = nullptr;
   int64_t* tr_idx = nullptr;
-  double* tr_val = nullptr;
-  int fd_grid[3] = {1, 1, 1};
-  size_t fd_lds = 0;
-  int max_m2 = 1, slab_grid = 1;
-  size_t slab_lds = 0;
+  int slab_grid = 1, mid_grid = 1, max_m2 = 1;
+  LevelData<double> d64;
+  LevelData<float> d32;
+};
+
+template <typename T>
+LevelData<T>& dat(DevLevel& D);
+template <>
+LevelData<double>& dat<double>(DevLevel& D) {
+  return D.d64;
+}
+template <>
+LevelData<float>& dat<float>(DevLevel& D) {
+  return D.d32;
+}
+
+template <typename T>
+struct PcgVecs {
+  T *x = nullptr, *p = nullptr, *q = nullptr;
 };
 
 struct Bump {
@@ -70,12 +87,14 @@ struct Bump {
 struct igamg_ctx {
   Hierarchy H;
   int d = 2, p = 2, L = 1;
+  bool mixed = false;
   std::vector<DevLevel> dl;
   double* Ainv = nullptr;
   double* cb = nullptr;
   int64_t N0 = 0;
-  // PCG (finest level, patch-local)
-  double *x = nullptr, *pp = nullptr, *q = nullptr, *tmpg = nullptr;
+  PcgVecs<double> v64;
+  PcgVecs<float> v32;
+  double* fsave = nullptr;       // mixed: the right-hand side (patch-local, distributed)
   double *part = nullptr, *scal = nullptr;
   double* host_scal = nullptr;   // pinned
   bool on_device = false;
@@ -94,72 +113,73 @@ struct igamg_ctx {
   size_t bytes = 0;
 };
 
+template <typename T>
+static void plan_level_data(Bump& b, const LevelH& L, DevLevel& D, LevelData<T>& X, bool solver_level) {
+  X.u = b.take<T>(L.NL);
+  X.f = b.take<T>(L.NL);
+  X.w = b.take<T>(L.NL);
+  if (!solver_level) return;
+  X.band = b.take<T>((size_t)D.nb * L.NL);
+  X.fdmat = b.take<T>(L.fdmat.size());
+  X.densemat = b.take<T>(L.densemat.size());
+  X.tr_val = b.take<T>(L.tr_val.size());
+  X.scr = b.take<T>(L.fdscr);
+}
+
 static size_t plan(igamg_ctx& C, char* base) {
   Bump b{base};
   const Hierarchy& H = C.H;
   C.dl.assign(H.lv.size(), DevLevel{});
-  int64_t maxNL = 0, maxN = 0;
   for (size_t l = 0; l < H.lv.size(); ++l) {
     const LevelH& L = H.lv[l];
     DevLevel& D = C.dl[l];
     D.NL = L.NL;
     D.N = L.N;
-    D.nif = L.nif;
-    maxNL = std::max(maxNL, L.NL);
-    maxN = std::max(maxN, L.N);
+    D.rows = 0;
+    for (int64_t r : L.rows) D.rows += r;
     int nb = 1;
     for (int c = 0; c < H.prob.d; ++c) nb *= 2 * H.prob.p + 1;
     D.nb = nb;
-    D.ncopy = (int64_t)L.gidx.size();
-    D.u = b.take<double>(L.NL);
-    D.f = b.take<double>(L.NL);
-    D.w = b.take<double>(L.NL);
     D.bpatch = b.take<int>(L.bpatch.size());
     D.pd = b.take<PatchDev>(L.pd.size());
     D.isfree = b.take<uint8_t>(L.NL);
     D.gptr = b.take<int64_t>(L.gptr.size());
     D.gidx = b.take<int64_t>(L.gidx.size());
-    if (l == 0) continue;
-    D.band = b.take<double>((size_t)nb * L.NL);
-    D.nifidx = (int64_t)L.if_idx.size();
+    const bool sl = l > 0;
+    plan_level_data(b, L, D, D.d64, sl);
+    if (C.mixed) plan_level_data(b, L, D, D.d32, sl);
+    if (!sl) continue;
     D.if_ptr = b.take<int64_t>(L.if_ptr.size());
     D.if_idx = b.take<int64_t>(L.if_idx.size());
     D.nfd = (int)L.fd.size();
     D.nfd_int = L.nfd_interior;
     D.fd = b.take<FDItem>(L.fd.size());
-    D.nfdmat = (int64_t)L.fdmat.size();
-    D.fdmat = b.take<double>(L.fdmat.size());
-    D.fdscr = L.fdscr;
-    D.scrA = b.take<double>(L.fdscr);
-    D.scrB = b.take<double>(L.fdscr);
     D.ndense = (int)L.dense.size();
     D.dense = b.take<DensePiece>(L.dense.size());
-    D.ndmat = (int64_t)L.densemat.size();
-    D.densemat = b.take<double>(L.densemat.size());
-    D.ntr_idx = (int64_t)L.tr_idx.size();
-    D.ntr_val = (int64_t)L.tr_val.size();
     D.tr_idx = b.take<int64_t>(L.tr_idx.size());
-    D.tr_val = b.take<double>(L.tr_val.size());
     D.WP = L.WP;
     D.WR = L.WR;
     D.fd_maxm = L.fd_maxm;
-    for (int dir = 0; dir < 3; ++dir) D.fd_grid[dir] = fd_grid_x(L.fd.data(), L.nfd_interior, dir);
-    D.fd_lds = fd_lds_bytes(L.fd_maxm);
-    int maxdense = 1;
-    for (const auto& dp : L.dense) maxdense = std::max(maxdense, dp.m);
+    D.max_dense = 1;
+    for (const auto& dp : L.dense) D.max_dense = std::max(D.max_dense, dp.m);
     D.max_m2 = 1;
     for (const auto& it : L.fd) D.max_m2 = std::max(D.max_m2, it.m[2]);
-    D.slab_lds = std::max(fd_slab_lds(L.fd_maxm), (size_t)maxdense * sizeof(double) + 64);
     D.slab_grid = fd_slab_grid(L.fd.data(), (int)L.fd.size());
+    D.mid_grid = fd_mid_grid(L.fd.data(), L.nfd_interior);
   }
   C.N0 = H.lv[0].N;
   C.Ainv = b.take<double>((size_t)C.N0 * C.N0);
   C.cb = b.take<double>(C.N0);
   const int64_t NLf = H.lv.back().NL;
-  C.x = b.take<double>(NLf);
-  C.pp = b.take<double>(NLf);
-  C.q = b.take<double>(NLf);
-  C.tmpg = b.take<double>(std::max(maxNL, maxN));
+  C.v64.x = b.take<double>(NLf);
+  C.v64.p = b.take<double>(NLf);
+  C.v64.q = b.take<double>(NLf);
+  if (C.mixed) {
+    C.v32.x = b.take<float>(NLf);
+    C.v32.p = b.take<float>(NLf);
+    C.v32.q = b.take<float>(NLf);
+    C.fsave = b.take<double>(NLf);
+  }
   C.part = b.take<double>(RED_BLOCKS);
   C.scal = b.take<double>(16);
   return b.pos + 256;
@@ -167,8 +187,13 @@ static size_t plan(igamg_ctx& C, char* base) {
 
 template <typename T>
 static void up(T* dst, const std::vector<T>& src, hipStream_t st) {
-  if (!src.empty()) HIP_OK(hipMemcpyAsync(dst, src.data(), src.size() * sizeof(T), hipMemcpyHostToDevice, st));
+  if (!src.empty()) {
+    HIP_OK(hipMemcpyAsync(dst, src.data(), src.size() * sizeof(T), hipMemcpyHostToDevice, st));
+    HIP_OK(hipStreamSynchronize(st));
+  }
 }
+
+static std::vector<float> to_float(const std::vector<double>& v) { return std::vector<float>(v.begin(), v.end()); }
 
 static void upload(igamg_ctx& C, hipStream_t st) {
   Hierarchy& H = C.H;
@@ -191,29 +216,31 @@ static void upload(igamg_ctx& C, hipStream_t st) {
         for (int o = 0; o < D.nb; ++o)
           std::memcpy(&tiled[((size_t)bk * D.nb + o) * ROW_ALIGN], &L.band[(size_t)o * L.NL + bk * ROW_ALIGN],
                       ROW_ALIGN * sizeof(double));
-      up(D.band, tiled, st);
-      HIP_OK(hipStreamSynchronize(st));
+      up(D.d64.band, tiled, st);
+      if (C.mixed) up(D.d32.band, to_float(tiled), st);
     }
     up(D.if_ptr, L.if_ptr, st);
     up(D.if_idx, L.if_idx, st);
     up(D.fd, L.fd, st);
-    up(D.fdmat, L.fdmat, st);
     up(D.dense, L.dense, st);
-    up(D.densemat, L.densemat, st);
     up(D.tr_idx, L.tr_idx, st);
-    up(D.tr_val, L.tr_val, st);
+    up(D.d64.fdmat, L.fdmat, st);
+    up(D.d64.densemat, L.densemat, st);
+    up(D.d64.tr_val, L.tr_val, st);
+    if (C.mixed) {
+      up(D.d32.fdmat, to_float(L.fdmat), st);
+      up(D.d32.densemat, to_float(L.densemat), st);
+      up(D.d32.tr_val, to_float(L.tr_val), st);
+    }
   }
   up(C.Ainv, H.Ainv, st);
-  HIP_OK(hipStreamSynchronize(st));
   // the bands are large and no longer needed on the host
-  for (auto& L : H.lv) {
-    std::vector<double>().swap(L.band);
-  }
+  for (auto& L : H.lv) std::vector<double>().swap(L.band);
   std::vector<double>().swap(H.Ainv);
 }
 
 // ---------------------------------------------------------------------------
-// the cycle
+// the cycle, templated on the storage precision
 // ---------------------------------------------------------------------------
 static hipEvent_t next_event(igamg_ctx& C) {
   if (C.pool_used == C.pool.size()) {
@@ -224,91 +251,153 @@ static hipEvent_t next_event(igamg_ctx& C) {
   return C.pool[C.pool_used++];
 }
 
-static void band_timed(igamg_ctx& C, int l, const double* u, const double* f, double* r, bool resid,
-                       hipStream_t st) {
+template <typename T>
+static void band_op(igamg_ctx& C, int l, const T* u, const T* f, T* r, bool resid, hipStream_t st) {
   DevLevel& D = C.dl[l];
+  const T* band = dat<T>(D).band;
   if (!C.prof) {
-    launch_band(C.d, C.p, D.band, u, f, r, D.bpatch, D.pd, D.NL, resid, st);
+    launch_band<T>(C.d, C.p, band, u, f, r, D.bpatch, D.pd, D.NL, resid, st);
     return;
   }
   igamg_ctx::Rec rc;
   rc.level = l;
-  int64_t rows = 0;
-  for (int64_t x : C.H.lv[l].rows) rows += x;
-  rc.bytes = (double)rows * (8.0 * D.nb + 8.0 * (resid ? 3 : 2));
+  rc.bytes = (double)D.rows * sizeof(T) * ((double)D.nb + (resid ? 3 : 2));
   rc.a = next_event(C);
   rc.b = next_event(C);
   HIP_OK(hipEventRecord(rc.a, st));
-  launch_band(C.d, C.p, D.band, u, f, r, D.bpatch, D.pd, D.NL, resid, st);
+  launch_band<T>(C.d, C.p, band, u, f, r, D.bpatch, D.pd, D.NL, resid, st);
   HIP_OK(hipEventRecord(rc.b, st));
   C.recs.push_back(rc);
   C.prof_stream = st;
 }
 
-static void residual(igamg_ctx& C, int l, const double* u, const double* f, double* r, hipStream_t st) {
-  band_timed(C, l, u, f, r, true, st);
-}
-
-static void apply(igamg_ctx& C, int l, const double* u, double* y, hipStream_t st) {
-  band_timed(C, l, u, nullptr, y, false, st);
-}
-
 // u <- u + tau L^{-1} src (or u = tau L^{-1} src when !add); src distributed.
 // Forward products (+ D^{-1} for 2D tensors, + the dense pieces), for 3D
 // interiors the scaled middle direction over pencils, inverse products.
-static void smoother_apply(igamg_ctx& C, int l, const double* src, double* u, bool add, double tau,
-                           hipStream_t st) {
+template <typename T>
+static void smoother_apply(igamg_ctx& C, int l, const T* src, T* u, bool add, double tau, hipStream_t st) {
   DevLevel& D = C.dl[l];
-  launch_fd_fwd(D.fd, D.nfd, D.ndense, D.slab_grid, D.slab_lds, D.dense, D.densemat, D.fdmat, src, u, D.if_ptr,
-                D.if_idx, D.scrA, tau, add, st);
+  LevelData<T>& X = dat<T>(D);
+  const size_t lds = std::max(fd_slab_lds(D.fd_maxm, sizeof(T)), (size_t)D.max_dense * sizeof(T) + 64);
+  launch_fd_fwd<T>(D.fd, D.nfd, D.ndense, D.slab_grid, lds, D.dense, X.densemat, X.fdmat, src, u, D.if_ptr, D.if_idx,
+                   X.scr, tau, add, st);
   if (C.d == 3 && D.nfd_int > 0 && D.max_m2 > 1)
-    launch_fd_pass(D.fd, D.nfd_int, D.fd_grid[2], D.fd_lds, 2, 2, 1, 1, D.fdmat, nullptr, nullptr, nullptr, nullptr,
-                   D.scrA, D.scrB, 1.0, false, st);
-  launch_fd_inv(D.fd, D.nfd, D.slab_grid, D.slab_lds, D.fdmat, u, D.if_ptr, D.if_idx, D.scrA, tau, add, st);
+    launch_fd_mid<T>(D.fd, D.nfd_int, D.mid_grid, fd_mid_lds(D.fd_maxm, sizeof(T)), X.fdmat, X.scr, st);
+  launch_fd_inv<T>(D.fd, D.nfd, D.slab_grid, fd_slab_lds(D.fd_maxm, sizeof(T)), X.fdmat, u, D.if_ptr, D.if_idx,
+                   X.scr, tau, add, st);
 }
 
-static void coarse_solve(igamg_ctx& C, const double* f0, double* u0, hipStream_t st) {
+template <typename T>
+static void coarse_solve(igamg_ctx& C, const T* f0, T* u0, hipStream_t st) {
   DevLevel& D = C.dl[0];
-  launch_gather(f0, C.cb, D.gptr, D.gidx, D.N, true, st);
-  launch_coarse(C.Ainv, C.cb, u0, D.gptr, D.gidx, (int)C.N0, st);
+  launch_coarse<T>(C.Ainv, f0, C.cb, u0, D.gptr, D.gidx, (int)C.N0, st);
 }
 
-static void restrict_to(igamg_ctx& C, int l, const double* rf, double* rc, hipStream_t st) {
+template <typename T>
+static void restrict_to(igamg_ctx& C, int l, const T* rf, T* rc, hipStream_t st) {
   DevLevel& F = C.dl[l];
   DevLevel& Cc = C.dl[l - 1];
-  launch_restrict(C.d, rf, rc, F.pd, Cc.bpatch, Cc.NL, F.tr_idx, F.tr_val, F.WR, Cc.isfree, st);
+  launch_restrict<T>(C.d, rf, rc, F.pd, Cc.bpatch, Cc.NL, F.tr_idx, dat<T>(F).tr_val, F.WR, Cc.isfree, st);
 }
 
-static void prolong_add(igamg_ctx& C, int l, const double* uc, double* uf, hipStream_t st) {
+template <typename T>
+static void prolong_add(igamg_ctx& C, int l, const T* uc, T* uf, hipStream_t st) {
   DevLevel& F = C.dl[l];
-  launch_prolong_add(C.d, uc, uf, F.pd, F.bpatch, F.NL, F.tr_idx, F.tr_val, F.WP, F.isfree, st);
+  launch_prolong_add<T>(C.d, uc, uf, F.pd, F.bpatch, F.NL, F.tr_idx, dat<T>(F).tr_val, F.WP, F.isfree, st);
 }
 
-// Algorithm 1 on level l >= 1 with u_l, f_l in dl[l].u / dl[l].f
+// Algorithm 1 on level l >= 1 with u_l, f_l in dat<T>(dl[l]).u / .f
+template <typename T>
 static void cycle(igamg_ctx& C, int l, bool zero_init, hipStream_t st) {
-  DevLevel& D = C.dl[l];
+  LevelData<T>& X = dat<T>(C.dl[l]);
+  LevelData<T>& Xc = dat<T>(C.dl[l - 1]);
   const Options& O = C.H.opt;
   for (int i = 0; i < O.nu; ++i) {
     if (zero_init && i == 0) {
-      smoother_apply(C, l, D.f, D.u, false, O.tau, st);
+      smoother_apply<T>(C, l, X.f, X.u, false, O.tau, st);
     } else {
-      residual(C, l, D.u, D.f, D.w, st);
-      smoother_apply(C, l, D.w, D.u, true, O.tau, st);
+      band_op<T>(C, l, X.u, X.f, X.w, true, st);
+      smoother_apply<T>(C, l, X.w, X.u, true, O.tau, st);
     }
   }
-  residual(C, l, D.u, D.f, D.w, st);
-  DevLevel& Dc = C.dl[l - 1];
-  restrict_to(C, l, D.w, Dc.f, st);
+  band_op<T>(C, l, X.u, X.f, X.w, true, st);
+  restrict_to<T>(C, l, X.w, Xc.f, st);
   if (l == 1) {
-    coarse_solve(C, Dc.f, Dc.u, st);
+    coarse_solve<T>(C, Xc.f, Xc.u, st);
   } else {
-    for (int j = 0; j < O.mu; ++j) cycle(C, l - 1, j == 0, st);
+    for (int j = 0; j < O.mu; ++j) cycle<T>(C, l - 1, j == 0, st);
   }
-  prolong_add(C, l, Dc.u, D.u, st);
+  prolong_add<T>(C, l, Xc.u, X.u, st);
   for (int i = 0; i < O.nu; ++i) {
-    residual(C, l, D.u, D.f, D.w, st);
-    smoother_apply(C, l, D.w, D.u, true, O.tau, st);
+    band_op<T>(C, l, X.u, X.f, X.w, true, st);
+    smoother_apply<T>(C, l, X.w, X.u, true, O.tau, st);
   }
+}
+
+static double fetch(igamg_ctx& C, int slot, hipStream_t st) {
+  HIP_OK(hipMemcpyAsync(C.host_scal + slot, C.scal + slot, sizeof(double), hipMemcpyDeviceToHost, st));
+  HIP_OK(hipStreamSynchronize(st));
+  return C.host_scal[slot];
+}
+
+template <typename T>
+static PcgVecs<T>& vecs(igamg_ctx& C);
+template <>
+PcgVecs<double>& vecs<double>(igamg_ctx& C) {
+  return C.v64;
+}
+template <>
+PcgVecs<float>& vecs<float>(igamg_ctx& C) {
+  return C.v32;
+}
+
+// PCG with one cycle as preconditioner (Sec. 4) on the finest level in
+// precision T, from x = 0 for the right-hand side held in dat<T>(finest).f,
+// which is overwritten by the recurrence residual.  Stops when the residual
+// norm drops to rtol times its initial value.  Returns the iteration count;
+// *rel = final ||r|| / ||r_0||; *status = OK / ENOCONV / ENAN.
+template <typename T>
+static int pcg(igamg_ctx& C, double rtol, int maxit, hipStream_t st, double* rel, int* status) {
+  const int L = C.L;
+  DevLevel& D = C.dl[L];
+  LevelData<T>& X = dat<T>(D);
+  PcgVecs<T>& V = vecs<T>(C);
+  T* r = X.f;
+  T* z = X.u;
+  launch_fill<T>(V.x, D.NL, 0.0, st);
+  launch_norm2_dist<T>(r, D.gptr, D.gidx, D.N, C.part, C.scal, 6, st);
+  const double n02 = fetch(C, 6, st);
+  *status = IGAMG_OK;
+  *rel = 0.0;
+  if (!std::isfinite(n02)) {
+    *status = IGAMG_ENAN;
+    return 0;
+  }
+  if (n02 == 0.0) return 0;
+  const double stop2 = rtol * rtol * n02;
+  cycle<T>(C, L, true, st);
+  launch_dot<T>(r, z, D.NL, C.part, C.scal, 0, 0, st);
+  launch_copy<T>(V.p, z, D.NL, st);
+  *rel = 1.0;
+  int it;
+  for (it = 1; it <= maxit; ++it) {
+    band_op<T>(C, L, V.p, nullptr, V.q, false, st);
+    launch_dot<T>(V.p, V.q, D.NL, C.part, C.scal, 1, 1, st);
+    launch_axpy2<T>(V.x, V.p, r, V.q, D.NL, C.scal, st);
+    launch_norm2_dist<T>(r, D.gptr, D.gidx, D.N, C.part, C.scal, 5, st);
+    const double rr = fetch(C, 5, st);
+    if (!std::isfinite(rr)) {
+      *status = IGAMG_ENAN;
+      return it;
+    }
+    *rel = std::sqrt(rr / n02);
+    if (rr <= stop2) return it;
+    cycle<T>(C, L, true, st);
+    launch_dot<T>(r, z, D.NL, C.part, C.scal, 3, 2, st);
+    launch_xpby<T>(V.p, z, D.NL, C.scal, st);
+  }
+  *status = IGAMG_ENOCONV;
+  return maxit;
 }
 
 // ---------------------------------------------------------------------------
@@ -373,7 +462,7 @@ void igamg_default_options(igamg_options* o) {
   o->maxit = 500;
   o->geometry_scaling = 1;
   o->inner_maxit = 100;
-  o->inner_tol = 1e-3;
+  o->inner_tol = 1e-4;
 }
 
 const char* igamg_last_error(void) { return g_err.c_str(); }
@@ -384,6 +473,7 @@ int igamg_workspace_size(const igamg_problem* prob, const igamg_options* opts, s
   igamg_ctx C;
   C.H.prob = read_problem(prob);
   read_opts(opts, C.H.opt);
+  C.mixed = C.H.opt.precision == IGAMG_MIXED;
   build_topology(C.H, false);
   *bytes = plan(C, nullptr);
   return IGAMG_OK;
@@ -399,6 +489,7 @@ int igamg_setup(const igamg_problem* prob, const igamg_options* opts, void* work
   try {
     C->H.prob = read_problem(prob);
     read_opts(opts, C->H.opt);
+    C->mixed = C->H.opt.precision == IGAMG_MIXED;
     C->d = C->H.prob.d;
     C->p = C->H.prob.p;
     C->L = C->H.prob.levels - 1;
@@ -506,9 +597,9 @@ int igamg_vcycle(igamg_handle h, const double* r, double* z, void* stream) {
   if (!r || !z || r == z) return set_err(IGAMG_EINVAL, "bad vector arguments");
   hipStream_t st = static_cast<hipStream_t>(stream);
   DevLevel& D = h->dl[h->L];
-  launch_scatter(r, D.f, D.gptr, D.gidx, D.N, true, st);
-  cycle(*h, h->L, true, st);
-  launch_gather(D.u, z, D.gptr, D.gidx, D.N, false, st);
+  launch_scatter(r, D.d64.f, D.gptr, D.gidx, D.N, true, st);
+  cycle<double>(*h, h->L, true, st);
+  launch_gather(D.d64.u, z, D.gptr, D.gidx, D.N, false, st);
   HIP_OK(hipGetLastError());
   return IGAMG_OK;
   API_END
@@ -521,43 +612,54 @@ int igamg_operator(igamg_handle h, int op, int level, const double* x, double* y
   hipStream_t st = static_cast<hipStream_t>(stream);
   level = check_level(h, level);
   DevLevel& D = h->dl[level];
+  LevelData<double>& X = D.d64;
   switch (op) {
     case IGAMG_OP_APPLY: {
       if (level < 1) return set_err(IGAMG_EINVAL, "no banded matrix on level 0 (use IGAMG_OP_COARSE)");
-      launch_scatter(x, D.u, D.gptr, D.gidx, D.N, false, st);
-      apply(*h, level, D.u, D.w, st);
-      launch_gather(D.w, y, D.gptr, D.gidx, D.N, true, st);
+      launch_scatter(x, X.u, D.gptr, D.gidx, D.N, false, st);
+      band_op<double>(*h, level, X.u, nullptr, X.w, false, st);
+      launch_gather(X.w, y, D.gptr, D.gidx, D.N, true, st);
       break;
     }
     case IGAMG_OP_SMOOTHER: {
       if (level < 1) return set_err(IGAMG_EINVAL, "smoother needs level >= 1");
-      launch_scatter(x, D.f, D.gptr, D.gidx, D.N, true, st);
-      smoother_apply(*h, level, D.f, D.u, false, 1.0, st);
-      launch_gather(D.u, y, D.gptr, D.gidx, D.N, false, st);
+      launch_scatter(x, X.f, D.gptr, D.gidx, D.N, true, st);
+      smoother_apply<double>(*h, level, X.f, X.u, false, 1.0, st);
+      launch_gather(X.u, y, D.gptr, D.gidx, D.N, false, st);
       break;
     }
     case IGAMG_OP_PROLONG: {
       if (level < 1) return set_err(IGAMG_EINVAL, "prolongation needs level >= 1");
       DevLevel& Dc = h->dl[level - 1];
-      launch_scatter(x, Dc.u, Dc.gptr, Dc.gidx, Dc.N, false, st);
-      launch_fill(D.w, D.NL, 0.0, st);
-      prolong_add(*h, level, Dc.u, D.w, st);
-      launch_gather(D.w, y, D.gptr, D.gidx, D.N, false, st);
+      launch_scatter(x, Dc.d64.u, Dc.gptr, Dc.gidx, Dc.N, false, st);
+      launch_fill<double>(X.w, D.NL, 0.0, st);
+      prolong_add<double>(*h, level, Dc.d64.u, X.w, st);
+      launch_gather(X.w, y, D.gptr, D.gidx, D.N, false, st);
       break;
     }
     case IGAMG_OP_RESTRICT: {
       if (level < 1) return set_err(IGAMG_EINVAL, "restriction needs level >= 1");
       DevLevel& Dc = h->dl[level - 1];
-      launch_scatter(x, D.w, D.gptr, D.gidx, D.N, true, st);
-      restrict_to(*h, level, D.w, Dc.f, st);
-      launch_gather(Dc.f, y, Dc.gptr, Dc.gidx, Dc.N, true, st);
+      launch_scatter(x, X.w, D.gptr, D.gidx, D.N, true, st);
+      restrict_to<double>(*h, level, X.w, Dc.d64.f, st);
+      launch_gather(Dc.d64.f, y, Dc.gptr, Dc.gidx, Dc.N, true, st);
       break;
     }
     case IGAMG_OP_COARSE: {
       if (level != 0) return set_err(IGAMG_EINVAL, "coarse solve lives on level 0");
-      launch_scatter(x, D.f, D.gptr, D.gidx, D.N, true, st);
-      coarse_solve(*h, D.f, D.u, st);
-      launch_gather(D.u, y, D.gptr, D.gidx, D.N, false, st);
+      launch_scatter(x, X.f, D.gptr, D.gidx, D.N, true, st);
+      coarse_solve<double>(*h, X.f, X.u, st);
+      launch_gather(X.u, y, D.gptr, D.gidx, D.N, false, st);
+      break;
+    }
+    case IGAMG_OP_CYCLE_FP32: {
+      if (!h->mixed) return set_err(IGAMG_EINVAL, "the FP32 cycle needs precision IGAMG_MIXED");
+      if (level != h->L) return set_err(IGAMG_EINVAL, "the FP32 cycle runs on the finest level");
+      launch_scatter(x, X.f, D.gptr, D.gidx, D.N, true, st);
+      launch_to_f32(D.d32.f, X.f, D.NL, st);
+      cycle<float>(*h, level, true, st);
+      launch_to_f64(X.u, D.d32.u, D.NL, st);
+      launch_gather(X.u, y, D.gptr, D.gidx, D.N, false, st);
       break;
     }
     default:
@@ -649,58 +751,65 @@ int igamg_solve(igamg_handle h, const double* rhs, double* u, double tol, igamg_
   hipStream_t st = static_cast<hipStream_t>(stream);
   auto t0 = std::chrono::steady_clock::now();
   igamg_ctx& C = *h;
-  const int L = C.L;
-  DevLevel& D = C.dl[L];
-  double* r = D.f;   // PCG residual (distributed) is the cycle's right-hand side
-  double* z = D.u;   // cycle output (accumulated)
-  double* hs = C.host_scal;
-  auto fetch = [&](int slot) {
-    HIP_OK(hipMemcpyAsync(hs + slot, C.scal + slot, sizeof(double), hipMemcpyDeviceToHost, st));
-    HIP_OK(hipStreamSynchronize(st));
-    return hs[slot];
-  };
-  launch_scatter(rhs, r, D.gptr, D.gidx, D.N, true, st);
-  launch_fill(C.x, D.NL, 0.0, st);
-  launch_norm2_dist(r, D.gptr, D.gidx, D.N, C.part, C.scal, 6, st);
-  const double nf2 = fetch(6);
-  int code = IGAMG_OK;
-  int it = 0;
+  const Options& O = C.H.opt;
+  DevLevel& D = C.dl[C.L];
+  int code = IGAMG_OK, iters = 0, outer = 0;
   double rel = 0.0;
-  if (!std::isfinite(nf2)) {
-    code = set_err(IGAMG_ENAN, "non-finite right-hand side");
-  } else if (nf2 > 0) {
-    const double stop2 = tol * tol * nf2;
-    cycle(C, L, true, st);
-    launch_dot(r, z, D.NL, C.part, C.scal, 0, 0, st);
-    launch_copy(C.pp, z, D.NL, st);
-    rel = 1.0;
-    for (it = 1; it <= C.H.opt.maxit; ++it) {
-      apply(C, L, C.pp, C.q, st);
-      launch_dot(C.pp, C.q, D.NL, C.part, C.scal, 1, 1, st);
-      launch_axpy2(C.x, C.pp, r, C.q, D.NL, C.scal, st);
-      launch_norm2_dist(r, D.gptr, D.gidx, D.N, C.part, C.scal, 5, st);
-      const double rr = fetch(5);
-      if (!std::isfinite(rr)) {
-        code = set_err(IGAMG_ENAN, "non-finite residual");
-        break;
+  if (!C.mixed) {
+    // plain FP64 PCG; the recurrence residual is the stopping quantity
+    launch_scatter(rhs, D.d64.f, D.gptr, D.gidx, D.N, true, st);
+    iters = pcg<double>(C, tol, O.maxit, st, &rel, &code);
+    launch_gather(C.v64.x, u, D.gptr, D.gidx, D.N, false, st);
+  } else {
+    // FP64 iterative refinement: r = f - A x in FP64 (FP64 band), d from an FP32
+    // PCG solve with FP32 bands, smoothers and transfers (coarse solve in
+    // FP64), x += d in FP64
+    launch_scatter(rhs, C.fsave, D.gptr, D.gidx, D.N, true, st);
+    launch_fill<double>(C.v64.x, D.NL, 0.0, st);
+    launch_copy<double>(D.d64.f, C.fsave, D.NL, st);
+    launch_norm2_dist<double>(D.d64.f, D.gptr, D.gidx, D.N, C.part, C.scal, 7, st);
+    const double nf2 = fetch(C, 7, st);
+    if (!std::isfinite(nf2)) {
+      code = set_err(IGAMG_ENAN, "non-finite right-hand side");
+    } else if (nf2 > 0) {
+      rel = 1.0;
+      const int max_outer = 60;
+      for (outer = 1; outer <= max_outer; ++outer) {
+        launch_to_f32(D.d32.f, D.d64.f, D.NL, st);
+        double irel = 0.0;
+        int icode = IGAMG_OK;
+        iters += pcg<float>(C, O.inner_tol, O.inner_maxit, st, &irel, &icode);
+        if (icode == IGAMG_ENAN) {
+          code = set_err(IGAMG_ENAN, "non-finite inner residual");
+          break;
+        }
+        launch_add_f32(C.v64.x, C.v32.x, D.NL, st);
+        band_op<double>(C, C.L, C.v64.x, C.fsave, D.d64.f, true, st);
+        launch_norm2_dist<double>(D.d64.f, D.gptr, D.gidx, D.N, C.part, C.scal, 5, st);
+        const double rr = fetch(C, 5, st);
+        if (!std::isfinite(rr)) {
+          code = set_err(IGAMG_ENAN, "non-finite residual");
+          break;
+        }
+        rel = std::sqrt(rr / nf2);
+        if (rr <= tol * tol * nf2) break;
+        if (iters >= O.maxit) {
+          outer = std::min(outer, max_outer);
+          break;
+        }
       }
-      rel = std::sqrt(rr / nf2);
-      if (rr <= stop2) break;
-      cycle(C, L, true, st);
-      launch_dot(r, z, D.NL, C.part, C.scal, 3, 2, st);
-      launch_xpby(C.pp, z, D.NL, C.scal, st);
+      if (code == IGAMG_OK && rel > tol) code = IGAMG_ENOCONV;
+      if (outer > max_outer) outer = max_outer;
     }
-    if (it > C.H.opt.maxit) {
-      it = C.H.opt.maxit;
-      if (code == IGAMG_OK) code = set_err(IGAMG_ENOCONV, "maxit reached");
-    }
+    launch_gather(C.v64.x, u, D.gptr, D.gidx, D.N, false, st);
   }
-  launch_gather(C.x, u, D.gptr, D.gidx, D.N, false, st);
+  if (code == IGAMG_ENOCONV) set_err(code, "iteration cap reached above the tolerance");
+  if (code == IGAMG_ENAN && g_err.empty()) set_err(code, "non-finite residual");
   HIP_OK(hipGetLastError());
   HIP_OK(hipStreamSynchronize(st));
   if (info) {
-    info->iterations = it;
-    info->outer_iterations = 0;
+    info->iterations = iters;
+    info->outer_iterations = outer;
     info->converged = (code == IGAMG_OK);
     info->rel_residual = rel;
     info->solve_ms = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();

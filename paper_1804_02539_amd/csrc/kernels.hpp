@@ -1,4 +1,5 @@
 // Launchers of the HIP kernels (kernels.hip).  All take the stream last.
+// Templates are instantiated for double and float storage.
 #pragma once
 
 #include <hip/hip_runtime.h>
@@ -12,39 +13,54 @@ namespace igamg {
 
 constexpr int RED_BLOCKS = 512;   // partial sums per reduction
 
-void launch_band(int d, int p, const double* band, const double* u, const double* f, double* r, const int* bpatch,
-                 const PatchDev* pd, int64_t NL, bool resid, hipStream_t st);
-int fd_grid_x(const FDItem* items, int nitems, int dir);
-size_t fd_lds_bytes(int maxm);
-void launch_fd_pass(const FDItem* items, int nitems, int gridx, size_t lds, int dir, int mode, int in_sel, int out_sel,
-                    const double* mat, const double* src_loc, const double* src_if, double* dst_loc, double* dst_if,
-                    double* scrA, double* scrB, double tau, bool add, hipStream_t st);
-size_t fd_slab_lds(int maxm);
+template <typename T>
+void launch_band(int d, int p, const T* band, const T* u, const T* f, T* r, const int* bpatch, const PatchDev* pd,
+                 int64_t NL, bool resid, hipStream_t st);
+
+size_t fd_slab_lds(int maxm, size_t elem);
 int fd_slab_grid(const FDItem* items, int nitems);
+int fd_mid_grid(const FDItem* items, int nitems);
+size_t fd_mid_lds(int maxm, size_t elem);
+template <typename T>
 void launch_fd_fwd(const FDItem* items, int nitems, int ndense, int gridx, size_t lds, const DensePiece* dense,
-                   const double* densemat, const double* mat, const double* src, double* u, const int64_t* if_ptr,
-                   const int64_t* if_idx, double* scr, double tau, bool add, hipStream_t st);
-void launch_fd_inv(const FDItem* items, int nitems, int gridx, size_t lds, const double* mat, double* u,
-                   const int64_t* if_ptr, const int64_t* if_idx, const double* scr, double tau, bool add,
-                   hipStream_t st);
-void launch_restrict(int d, const double* rf, double* rc, const PatchDev* pd, const int* bpatch_c, int64_t NLc,
-                     const int64_t* tidx, const double* tval, int WR, const uint8_t* isfree_c, hipStream_t st);
-void launch_prolong_add(int d, const double* uc, double* uf, const PatchDev* pd, const int* bpatch_f, int64_t NLf,
-                        const int64_t* tidx, const double* tval, int WP, const uint8_t* isfree_f, hipStream_t st);
+                   const T* densemat, const T* mat, const T* src, T* u, const int64_t* if_ptr, const int64_t* if_idx,
+                   T* scr, double tau, bool add, hipStream_t st);
+template <typename T>
+void launch_fd_mid(const FDItem* items, int nitems, int gridx, size_t lds, const T* mat, T* scr, hipStream_t st);
+template <typename T>
+void launch_fd_inv(const FDItem* items, int nitems, int gridx, size_t lds, const T* mat, T* u, const int64_t* if_ptr,
+                   const int64_t* if_idx, const T* scr, double tau, bool add, hipStream_t st);
+
+template <typename T>
+void launch_restrict(int d, const T* rf, T* rc, const PatchDev* pd, const int* bpatch_c, int64_t NLc,
+                     const int64_t* tidx, const T* tval, int WR, const uint8_t* isfree_c, hipStream_t st);
+template <typename T>
+void launch_prolong_add(int d, const T* uc, T* uf, const PatchDev* pd, const int* bpatch_f, int64_t NLf,
+                        const int64_t* tidx, const T* tval, int WP, const uint8_t* isfree_f, hipStream_t st);
+
 void launch_gather(const double* loc, double* glob, const int64_t* ptr, const int64_t* idx, int64_t n, bool dist,
                    hipStream_t st);
 void launch_scatter(const double* glob, double* loc, const int64_t* ptr, const int64_t* idx, int64_t n, bool dist,
                     hipStream_t st);
-void launch_coarse(const double* Ainv, const double* b, double* u0, const int64_t* ptr, const int64_t* idx, int n,
+template <typename T>
+void launch_coarse(const double* Ainv, const T* f0, double* b, T* u0, const int64_t* ptr, const int64_t* idx, int n,
                    hipStream_t st);
-void launch_dot(const double* a, const double* b, int64_t n, double* part, double* scal, int slot, int op,
-                hipStream_t st);
-void launch_norm2_dist(const double* r, const int64_t* ptr, const int64_t* idx, int64_t n, double* part, double* scal,
+
+template <typename T>
+void launch_dot(const T* a, const T* b, int64_t n, double* part, double* scal, int slot, int op, hipStream_t st);
+template <typename T>
+void launch_norm2_dist(const T* r, const int64_t* ptr, const int64_t* idx, int64_t n, double* part, double* scal,
                        int slot, hipStream_t st);
-void launch_axpy2(double* x, const double* p, double* r, const double* q, int64_t n, const double* scal,
-                  hipStream_t st);
-void launch_xpby(double* p, const double* z, int64_t n, const double* scal, hipStream_t st);
-void launch_fill(double* x, int64_t n, double v, hipStream_t st);
-void launch_copy(double* y, const double* x, int64_t n, hipStream_t st);
+template <typename T>
+void launch_axpy2(T* x, const T* p, T* r, const T* q, int64_t n, const double* scal, hipStream_t st);
+template <typename T>
+void launch_xpby(T* p, const T* z, int64_t n, const double* scal, hipStream_t st);
+template <typename T>
+void launch_fill(T* x, int64_t n, double v, hipStream_t st);
+template <typename T>
+void launch_copy(T* y, const T* x, int64_t n, hipStream_t st);
+void launch_to_f32(float* y, const double* x, int64_t n, hipStream_t st);
+void launch_to_f64(double* y, const float* x, int64_t n, hipStream_t st);
+void launch_add_f32(double* x, const float* d, int64_t n, hipStream_t st);
 
 }  // namespace igamg

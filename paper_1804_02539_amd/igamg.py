@@ -15,7 +15,7 @@ LIB_PATH = os.path.join(_HERE, "libigamg.so")
 
 OK, EINVAL, ETOPO, EGEOM, ENOMEM, ENOTSPD, ENOCONV, ENAN, EDEVICE = 0, -1, -2, -3, -4, -5, -6, -7, -8
 FP64, MIXED = 0, 1
-OP_APPLY, OP_SMOOTHER, OP_PROLONG, OP_RESTRICT, OP_COARSE = 0, 1, 2, 3, 4
+OP_APPLY, OP_SMOOTHER, OP_PROLONG, OP_RESTRICT, OP_COARSE, OP_CYCLE_FP32 = 0, 1, 2, 3, 4, 5
 
 ERROR_NAMES = {EINVAL: "EINVAL", ETOPO: "ETOPO", EGEOM: "EGEOM", ENOMEM: "ENOMEM",
                ENOTSPD: "ENOTSPD", ENOCONV: "ENOCONV", ENAN: "ENAN", EDEVICE: "EDEVICE"}

@@ -171,3 +171,46 @@ def test_full_size_cube_sampled(torch_cuda):
     u, info = S.solve(f)
     assert info.converged
     assert np.linalg.norm(f - H.finest.apply(u.cpu().numpy())) <= 1.0001e-8 * np.linalg.norm(f)
+
+
+# --- mixed precision: FP32 inner solves inside FP64 iterative refinement ----
+
+@pytest.mark.parametrize("name", ["square4x4_p4_l4", "cube2x2x2_p3_l4", "fichera7_p2_l3", "cube_p4_l3_neumann"])
+def test_fp32_cycle_close_to_oracle(torch_cuda, name):
+    """The FP32 cycle (FP32 bands, smoothers, transfers; FP64 coarse solve)
+    against the oracle's FP64 cycle: FP32 rounding only."""
+    from paper_1804_02539_amd import igamg
+    _say(f"fp32 cycle {name}")
+    H = oracle_for(name)
+    S = gpu_for(name, precision=igamg.MIXED)
+    r = np.random.default_rng(7).standard_normal(H.finest.N)
+    z = S.operator(igamg.OP_CYCLE_FP32, -1, r).cpu().numpy()
+    err = rel(z, H.vcycle(r))
+    _say(f"  fp32 cycle max rel error {err:.2e}")
+    assert err < 1e-4
+
+
+@pytest.mark.parametrize("name", ["square2x2_p2", "square4x4_p4_l4", "cube2x2x2_p3_l4", "fichera7_p2_l3"])
+def test_mixed_solve_reaches_fp64_tolerance(torch_cuda, name):
+    from oracle.multigrid import load_vector
+    from paper_1804_02539_amd import igamg
+    _say(f"mixed solve {name}")
+    prob = CASES[name]()
+    H = oracle_for(name)
+    S = gpu_for(name, precision=igamg.MIXED)
+    if prob.meta["source"][0] == "sine":
+        f = load_vector(prob, H.finest)
+    else:
+        f = W.random_rhs(H.finest.N, prob.meta["source"][1])
+    u_ref, it_ref, _ = H.pcg(f, tol=1e-8)
+    u, info = S.solve(f, tol=1e-8)
+    u = u.cpu().numpy()
+    res = np.linalg.norm(f - H.finest.apply(u)) / np.linalg.norm(f)
+    err = np.linalg.norm(u - u_ref) / np.linalg.norm(u_ref)
+    _say(f"  mixed: {info.outer_iterations} refinements, {info.iterations} inner it "
+         f"(FP64 PCG {it_ref}); rel residual {res:.2e}; |u - u_oracle|/|u_oracle| {err:.2e}")
+    assert info.converged and res <= 1.0001e-8
+    assert err < 1e-6
+    # the FP64 handle of the same problem still gives the oracle's result
+    u64, info64 = gpu_for(name).solve(f, tol=1e-8)
+    assert abs(info64.iterations - it_ref) <= 1
