@@ -1,12 +1,15 @@
 """Benchmark: DOFs solved per second by PCG + multigrid V-cycle to relative
-residual 1e-8 on one MI355X, with solve-latency percentiles, the roofline of
-the banded stiffness apply and the FP64 oracle timed on the host.
+residual 1e-8 on one MI355X, mixed precision (FP32 inner solves inside FP64
+iterative refinement) against the plain FP64 solver, with solve-latency
+percentiles, the roofline of the banded stiffness apply and the FP64 oracle
+timed on the host.
 
     python bench.py [--gpus 1] [--steps K] [--warmup W] [--workload NAME]
-                    [--precision fp64|mixed] [--no-cpu-baseline]
+                    [--precision both|fp64|mixed] [--no-cpu-baseline]
 
 A step is one complete solve of the workload from u = 0 to ||f - A u|| <= 1e-8
-||f|| (setup excluded; inputs resident in HBM).  Prints one JSON line.
+||f|| (setup excluded; inputs resident in HBM).  Prints one JSON line; `value`
+is the mixed-precision rate when both precisions run.
 """
 import argparse
 import hashlib
@@ -53,7 +56,7 @@ def kernel_sha():
     return h.hexdigest()[:16]
 
 
-def traffic_from_profiles(workload, launches_bytes):
+def traffic_from_profiles(workload, precision):
     """HBM bytes per launch of the finest apply from committed rocprofv3 counter
     summaries, if they were taken on the current kernel source."""
     path = os.path.join(ROOT, "profiles", f"band_apply_{workload}_traffic.json")
@@ -63,7 +66,7 @@ def traffic_from_profiles(workload, launches_bytes):
         t = json.load(fh)
     if t.get("kernel_sha") != kernel_sha():
         return None
-    return t.get("hbm_bytes_per_launch")
+    return t.get(precision, {}).get("hbm_bytes_per_launch")
 
 
 def cpu_baseline(prob, rhs):
@@ -86,92 +89,120 @@ def cpu_baseline(prob, rhs):
             "iterations": it, "solve_s": t}
 
 
+def run(workload, prob, precision, steps, warmup, dev):
+    import torch
+    from paper_1804_02539_amd import igamg
+    opts = igamg.default_options(precision=igamg.MIXED if precision == "mixed" else igamg.FP64)
+    t0 = time.perf_counter()
+    S = igamg.Solver(prob, opts, device=dev)
+    setup_s = time.perf_counter() - t0
+    f = torch.as_tensor(rhs_for(prob, S), device=dev)
+    u = torch.empty_like(f)
+    stream = torch.cuda.current_stream()
+    for _ in range(warmup):
+        S.solve(f, tol=1e-8, u=u)
+    torch.cuda.synchronize()
+    S.profile(True)
+    lat, iters = [], []
+    torch.cuda.synchronize()
+    t_start = time.perf_counter()
+    for _ in range(steps):
+        t1 = time.perf_counter()
+        _, info = S.solve(f, tol=1e-8, u=u, stream=stream)
+        lat.append(time.perf_counter() - t1)
+        iters.append((info.iterations, info.outer_iterations))
+    torch.cuda.synchronize()
+    total = time.perf_counter() - t_start
+    S.profile(False)
+    cnt, ms, by = S.profile_read()
+    nl = prob.levels
+    Lf = nl - 1
+    # dominant banded kernel: FP32 finest level for mixed, FP64 finest otherwise
+    k = Lf + nl if precision == "mixed" else Lf
+    avg_ms = ms[k] / max(cnt[k], 1)
+    bytes_launch = by[k] / max(cnt[k], 1)
+    achieved = bytes_launch / (avg_ms * 1e-3) / 1e9 if avg_ms > 0 else 0.0
+    res = {
+        "value": S.N * steps / total,
+        "ms_per_step": 1e3 * total / steps,
+        "latency_ms": {"p50": 1e3 * float(np.percentile(lat, 50)),
+                       "p99": 1e3 * float(np.percentile(lat, 99)),
+                       "mean": 1e3 * float(np.mean(lat))},
+        "iterations": int(np.median([i for i, _ in iters])),
+        "refinements": int(np.median([o for _, o in iters])),
+        "final_rel_residual": info.rel_residual,
+        "converged": bool(info.converged),
+        "setup_s": setup_s,
+        "roofline": {"bound": "hbm",
+                     "kernel": ("k_band<float> finest-level FP32 banded residual/apply (inner solves)"
+                                if precision == "mixed" else "k_band<double> finest-level banded residual/apply"),
+                     "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                     "frac": achieved / HBM_PEAK_GBS,
+                     "traffic": traffic_from_profiles(workload, precision),
+                     "avg_launch_us": 1e3 * avg_ms,
+                     "algorithmic_bytes_per_launch": bytes_launch,
+                     "launches_per_step": float(cnt[k]) / steps,
+                     "band_ms_per_step_fp64_all_levels": float(ms[:nl].sum()) / steps,
+                     "band_ms_per_step_fp32_all_levels": float(ms[nl:].sum()) / steps},
+    }
+    return S, res
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--workload", default="square4x4_p4", choices=sorted(WORKLOADS))
-    ap.add_argument("--precision", default="fp64", choices=["fp64", "mixed"])
+    ap.add_argument("--precision", default="both", choices=["both", "fp64", "mixed"])
     ap.add_argument("--no-cpu-baseline", action="store_true")
     a = ap.parse_args()
     if a.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print("bench.py measures one GPU only: this build has no multi-GPU path "
               "(patch sharding across GPUs is a design note, not code)", file=sys.stderr)
         sys.exit(2)
-
-    import torch
-    from paper_1804_02539_amd import igamg
+    import torch  # noqa: F401
 
     dev = "cuda:0"
     prob = make_problem(a.workload)
-    opts = igamg.default_options(precision=igamg.MIXED if a.precision == "mixed" else igamg.FP64)
-    t0 = time.perf_counter()
-    S = igamg.Solver(prob, opts, device=dev)
-    setup_s = time.perf_counter() - t0
-    f_host = rhs_for(prob, S)
-    f = torch.as_tensor(f_host, device=dev)
-    u = torch.empty_like(f)
-    stream = torch.cuda.current_stream()
-
-    for _ in range(a.warmup):
-        S.solve(f, tol=1e-8, u=u)
-    torch.cuda.synchronize()
-    S.profile(True)
-    lat = []
-    iters = []
-    torch.cuda.synchronize()
-    t_start = time.perf_counter()
-    for _ in range(a.steps):
-        t1 = time.perf_counter()
-        _, info = S.solve(f, tol=1e-8, u=u, stream=stream)
-        lat.append(time.perf_counter() - t1)
-        iters.append(info.iterations)
-    torch.cuda.synchronize()
-    total = time.perf_counter() - t_start
-    S.profile(False)
-    cnt, ms, by = S.profile_read()
-    rel_res = info.rel_residual
-
-    Lf = prob.levels - 1
-    avg_ms = ms[Lf] / max(cnt[Lf], 1)
-    bytes_launch = by[Lf] / max(cnt[Lf], 1)
-    achieved = bytes_launch / (avg_ms * 1e-3) / 1e9
-    traffic = traffic_from_profiles(a.workload, bytes_launch)
-    value = S.N * a.steps / total
+    runs = {}
+    if a.precision in ("both", "fp64"):
+        S, runs["fp64"] = run(a.workload, prob, "fp64", a.steps, a.warmup, dev)
+    if a.precision in ("both", "mixed"):
+        S, runs["mixed"] = run(a.workload, prob, "mixed", a.steps, a.warmup, dev)
+    head = "mixed" if ("mixed" in runs and runs["mixed"]["converged"]) else "fp64"
+    h = runs[head]
     out = {
         "metric": "DOFs solved/s to rel. residual 1e-8",
-        "value": value,
+        "value": h["value"],
         "unit": "DOF/s",
         "n_gpus": 1,
         "steps": a.steps,
         "warmup": a.warmup,
-        "ms_per_step": 1e3 * total / a.steps,
+        "ms_per_step": h["ms_per_step"],
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
-        "dtype": "f64" if a.precision == "fp64" else "f64/f32",
+        "dtype": "f32 inner / f64 refinement" if head == "mixed" else "f64",
         "data": "synthetic",
         "config": {"workload": a.workload, "description": WORKLOADS[a.workload],
                    "n_free_dofs": S.N, "n_local_dofs": S.N_local, "degree": prob.degree,
-                   "patches": prob.npatch, "levels": prob.levels, "precision": a.precision,
+                   "patches": prob.npatch, "levels": prob.levels, "precision": head,
                    "solver": "PCG, one V-cycle (1+1 smoothing, tau=0.25, sigma=5/h^2) per iteration"},
-        "latency_ms": {"p50": 1e3 * float(np.percentile(lat, 50)),
-                       "p99": 1e3 * float(np.percentile(lat, 99)),
-                       "mean": 1e3 * float(np.mean(lat))},
-        "iterations": int(np.median(iters)),
-        "final_rel_residual": rel_res,
-        "setup_s": setup_s,
-        "roofline": {"bound": "hbm", "kernel": "k_band (finest-level banded residual/apply)",
-                     "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                     "frac": achieved / HBM_PEAK_GBS,
-                     "traffic": traffic, "avg_launch_us": 1e3 * avg_ms,
-                     "algorithmic_bytes_per_launch": bytes_launch,
-                     "launches_per_step": float(cnt[Lf]) / a.steps,
-                     "band_ms_per_step_all_levels": float(ms.sum()) / a.steps},
+        "latency_ms": h["latency_ms"],
+        "iterations": h["iterations"],
+        "final_rel_residual": h["final_rel_residual"],
+        "roofline": h["roofline"],
     }
+    for k, v in runs.items():
+        out[k] = {kk: vv for kk, vv in v.items() if kk != "roofline"}
+        out[k]["band_roofline_frac"] = v["roofline"]["frac"]
+        out[k]["band_avg_launch_us"] = v["roofline"]["avg_launch_us"]
+    if "fp64" in runs and "mixed" in runs:
+        out["speedup_mixed_vs_fp64"] = runs["mixed"]["value"] / runs["fp64"]["value"]
     if not a.no_cpu_baseline:
-        out["cpu_baseline"] = cpu_baseline(prob, f_host)
+        from paper_1804_02539_amd import igamg  # noqa: F401
+        out["cpu_baseline"] = cpu_baseline(prob, rhs_for(prob, S))
     print(json.dumps(out), flush=True)
 
 

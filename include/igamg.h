@@ -183,9 +183,10 @@ int igamg_export(igamg_handle h, int what, int level, double* out, int64_t* rows
  * banded-apply launch on every level (events are created by the library on
  * first use; recording adds no synchronisation), enable = 0 stops.
  * igamg_profile_read synchronises the stream of the last recorded launch and
- * returns, per level l (arrays of length levels), the launch count and the
- * summed kernel time in ms and the algorithmic bytes moved
- * (rows * (8 (2p+1)^d + 8 * vectors)); then it clears the record.            */
+ * returns, per level l, the launch count, the summed kernel time in ms and the
+ * algorithmic bytes moved (rows * s ((2p+1)^d + vectors), s = 8 or 4 bytes);
+ * arrays have 2*levels entries: [l] for FP64 launches, [levels + l] for FP32
+ * launches of a mixed-precision handle.  Then it clears the record.          */
 int igamg_profile(igamg_handle h, int enable);
 int igamg_profile_read(igamg_handle h, int64_t* launches, double* ms, double* bytes);
 

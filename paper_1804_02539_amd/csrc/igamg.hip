@@ -7,6 +7,8 @@
 
 #include <chrono>
 #include <cmath>
+#include <cstdio>
+#include <cstdlib>
 #include <cstring>
 #include <string>
 #include <vector>
@@ -180,7 +182,7 @@ static size_t plan(igamg_ctx& C, char* base) {
     C.v32.q = b.take<float>(NLf);
     C.fsave = b.take<double>(NLf);
   }
-  C.part = b.take<double>(RED_BLOCKS);
+  C.part = b.take<double>(2 * RED_BLOCKS);
   C.scal = b.take<double>(16);
   return b.pos + 256;
 }
@@ -260,7 +262,7 @@ static void band_op(igamg_ctx& C, int l, const T* u, const T* f, T* r, bool resi
     return;
   }
   igamg_ctx::Rec rc;
-  rc.level = l;
+  rc.level = l + (sizeof(T) == 4 ? (int)C.dl.size() : 0);
   rc.bytes = (double)D.rows * sizeof(T) * ((double)D.nb + (resid ? 3 : 2));
   rc.a = next_event(C);
   rc.b = next_event(C);
@@ -334,6 +336,11 @@ static void cycle(igamg_ctx& C, int l, bool zero_init, hipStream_t st) {
   }
 }
 
+static bool trace_enabled() {
+  static const bool on = std::getenv("IGAMG_TRACE") != nullptr;
+  return on;
+}
+
 static double fetch(igamg_ctx& C, int slot, hipStream_t st) {
   HIP_OK(hipMemcpyAsync(C.host_scal + slot, C.scal + slot, sizeof(double), hipMemcpyDeviceToHost, st));
   HIP_OK(hipStreamSynchronize(st));
@@ -356,8 +363,12 @@ PcgVecs<float>& vecs<float>(igamg_ctx& C) {
 // which is overwritten by the recurrence residual.  Stops when the residual
 // norm drops to rtol times its initial value.  Returns the iteration count;
 // *rel = final ||r|| / ||r_0||; *status = OK / ENOCONV / ENAN.
+// flexible: beta = -alpha (z_new . q) / rho (the Polak-Ribiere form of the
+// direction update), which tolerates a preconditioner that is symmetric only
+// up to rounding -- the FP32 cycle; the FP64 solve uses the classical
+// beta = rho_new / rho of PCG.
 template <typename T>
-static int pcg(igamg_ctx& C, double rtol, int maxit, hipStream_t st, double* rel, int* status) {
+static int pcg(igamg_ctx& C, double rtol, int maxit, hipStream_t st, double* rel, int* status, bool flexible) {
   const int L = C.L;
   DevLevel& D = C.dl[L];
   LevelData<T>& X = dat<T>(D);
@@ -365,7 +376,7 @@ static int pcg(igamg_ctx& C, double rtol, int maxit, hipStream_t st, double* rel
   T* r = X.f;
   T* z = X.u;
   launch_fill<T>(V.x, D.NL, 0.0, st);
-  launch_norm2_dist<T>(r, D.gptr, D.gidx, D.N, C.part, C.scal, 6, st);
+  launch_norm2_dist<T>(r, D.gptr, D.gidx, D.N, C.part, C.scal, 6, true, st);
   const double n02 = fetch(C, 6, st);
   *status = IGAMG_OK;
   *rel = 0.0;
@@ -384,16 +395,24 @@ static int pcg(igamg_ctx& C, double rtol, int maxit, hipStream_t st, double* rel
     band_op<T>(C, L, V.p, nullptr, V.q, false, st);
     launch_dot<T>(V.p, V.q, D.NL, C.part, C.scal, 1, 1, st);
     launch_axpy2<T>(V.x, V.p, r, V.q, D.NL, C.scal, st);
-    launch_norm2_dist<T>(r, D.gptr, D.gidx, D.N, C.part, C.scal, 5, st);
+    launch_norm2_dist<T>(r, D.gptr, D.gidx, D.N, C.part, C.scal, 5, true, st);
     const double rr = fetch(C, 5, st);
     if (!std::isfinite(rr)) {
       *status = IGAMG_ENAN;
       return it;
     }
     *rel = std::sqrt(rr / n02);
+    if (trace_enabled()) {
+      const double a = fetch(C, 2, st), rho = fetch(C, 0, st), pq = fetch(C, 1, st);
+      std::fprintf(stderr, "[igamg] pcg<%s> it %d rel %.3e alpha %.3e rho %.3e pq %.3e\n",
+                   sizeof(T) == 4 ? "f32" : "f64", it, *rel, a, rho, pq);
+    }
     if (rr <= stop2) return it;
     cycle<T>(C, L, true, st);
-    launch_dot<T>(r, z, D.NL, C.part, C.scal, 3, 2, st);
+    if (flexible)
+      launch_dot2_flex<T>(r, V.q, z, D.NL, C.part, C.scal, st);
+    else
+      launch_dot<T>(r, z, D.NL, C.part, C.scal, 3, 2, st);
     launch_xpby<T>(V.p, z, D.NL, C.scal, st);
   }
   *status = IGAMG_ENOCONV;
@@ -525,7 +544,7 @@ int igamg_profile(igamg_handle h, int enable) {
 int igamg_profile_read(igamg_handle h, int64_t* launches, double* ms, double* bytes) {
   API_BEGIN
   need_device(h);
-  const int nl = (int)h->dl.size();
+  const int nl = 2 * (int)h->dl.size();
   for (int l = 0; l < nl; ++l) {
     if (launches) launches[l] = 0;
     if (ms) ms[l] = 0.0;
@@ -758,7 +777,7 @@ int igamg_solve(igamg_handle h, const double* rhs, double* u, double tol, igamg_
   if (!C.mixed) {
     // plain FP64 PCG; the recurrence residual is the stopping quantity
     launch_scatter(rhs, D.d64.f, D.gptr, D.gidx, D.N, true, st);
-    iters = pcg<double>(C, tol, O.maxit, st, &rel, &code);
+    iters = pcg<double>(C, tol, O.maxit, st, &rel, &code, false);
     launch_gather(C.v64.x, u, D.gptr, D.gidx, D.N, false, st);
   } else {
     // FP64 iterative refinement: r = f - A x in FP64 (FP64 band), d from an FP32
@@ -767,7 +786,7 @@ int igamg_solve(igamg_handle h, const double* rhs, double* u, double tol, igamg_
     launch_scatter(rhs, C.fsave, D.gptr, D.gidx, D.N, true, st);
     launch_fill<double>(C.v64.x, D.NL, 0.0, st);
     launch_copy<double>(D.d64.f, C.fsave, D.NL, st);
-    launch_norm2_dist<double>(D.d64.f, D.gptr, D.gidx, D.N, C.part, C.scal, 7, st);
+    launch_norm2_dist<double>(D.d64.f, D.gptr, D.gidx, D.N, C.part, C.scal, 7, true, st);
     const double nf2 = fetch(C, 7, st);
     if (!std::isfinite(nf2)) {
       code = set_err(IGAMG_ENAN, "non-finite right-hand side");
@@ -778,14 +797,14 @@ int igamg_solve(igamg_handle h, const double* rhs, double* u, double tol, igamg_
         launch_to_f32(D.d32.f, D.d64.f, D.NL, st);
         double irel = 0.0;
         int icode = IGAMG_OK;
-        iters += pcg<float>(C, O.inner_tol, O.inner_maxit, st, &irel, &icode);
+        iters += pcg<float>(C, O.inner_tol, O.inner_maxit, st, &irel, &icode, true);
         if (icode == IGAMG_ENAN) {
           code = set_err(IGAMG_ENAN, "non-finite inner residual");
           break;
         }
         launch_add_f32(C.v64.x, C.v32.x, D.NL, st);
         band_op<double>(C, C.L, C.v64.x, C.fsave, D.d64.f, true, st);
-        launch_norm2_dist<double>(D.d64.f, D.gptr, D.gidx, D.N, C.part, C.scal, 5, st);
+        launch_norm2_dist<double>(D.d64.f, D.gptr, D.gidx, D.N, C.part, C.scal, 5, true, st);
         const double rr = fetch(C, 5, st);
         if (!std::isfinite(rr)) {
           code = set_err(IGAMG_ENAN, "non-finite residual");

@@ -582,16 +582,66 @@ __global__ __launch_bounds__(256) void k_dot_partial(const T* __restrict__ a, co
   if (threadIdx.x == 0) part[blockIdx.x] = s;
 }
 
-// squared norm of the accumulated version of a distributed vector
+// two dots in one pass: r.z into part[0..g) and q.z into part[g..2g)
 template <typename T>
-__global__ __launch_bounds__(256) void k_norm2_dist_partial(const T* __restrict__ r, const int64_t* __restrict__ ptr,
+__global__ __launch_bounds__(256) void k_dot2_partial(const T* __restrict__ r, const T* __restrict__ q,
+                                                      const T* __restrict__ z, int64_t n, double* __restrict__ part) {
+  __shared__ double sh[4];
+  double s1 = 0.0, s2 = 0.0;
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) {
+    const double zi = (double)z[i];
+    s1 += (double)r[i] * zi;
+    s2 += (double)q[i] * zi;
+  }
+  s1 = block_sum(s1, sh);
+  __syncthreads();
+  s2 = block_sum(s2, sh);
+  if (threadIdx.x == 0) {
+    part[blockIdx.x] = s1;
+    part[gridDim.x + blockIdx.x] = s2;
+  }
+}
+
+// flexible CG direction update: scal[3] = r.z (new rho), scal[8] = q.z,
+// beta = scal[4] = -alpha (q.z) / rho_old, rho <- rho_new
+__global__ __launch_bounds__(256) void k_finalize2(const double* __restrict__ part, int np, double* __restrict__ scal) {
+  __shared__ double sh[4];
+  double s1 = 0.0, s2 = 0.0;
+  for (int i = threadIdx.x; i < np; i += blockDim.x) {
+    s1 += part[i];
+    s2 += part[np + i];
+  }
+  s1 = block_sum(s1, sh);
+  __syncthreads();
+  s2 = block_sum(s2, sh);
+  if (threadIdx.x == 0) {
+    scal[3] = s1;
+    scal[8] = s2;
+    scal[4] = -scal[2] * s2 / scal[0];
+    scal[0] = s1;
+  }
+}
+
+// squared norm of the accumulated version of a distributed vector.  With
+// `canon`, the vector is also rewritten in canonical distributed form: the
+// sum of the copies (taken in FP64) on the first copy, zero on the others.
+// The copies of an interface dof carry the one-sided contributions of their
+// patches, which grow large and opposite while their sum (the residual)
+// shrinks; canonical form keeps the stored values at the size of the residual.
+template <typename T>
+__global__ __launch_bounds__(256) void k_norm2_dist_partial(T* __restrict__ r, const int64_t* __restrict__ ptr,
                                                             const int64_t* __restrict__ idx, int64_t n,
-                                                            double* __restrict__ part) {
+                                                            double* __restrict__ part, int canon) {
   __shared__ double sh[4];
   double s = 0.0;
   for (int64_t g = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; g < n; g += (int64_t)gridDim.x * blockDim.x) {
+    const int64_t c0 = ptr[g], c1 = ptr[g + 1];
     double v = 0.0;
-    for (int64_t c = ptr[g]; c < ptr[g + 1]; ++c) v += (double)r[idx[c]];
+    for (int64_t c = c0; c < c1; ++c) v += (double)r[idx[c]];
+    if (canon && c1 - c0 > 1) {
+      r[idx[c0]] = (T)v;
+      for (int64_t c = c0 + 1; c < c1; ++c) r[idx[c]] = T(0);
+    }
     s += v * v;
   }
   s = block_sum(s, sh);
@@ -664,10 +714,17 @@ void launch_dot(const T* a, const T* b, int64_t n, double* part, double* scal, i
 }
 
 template <typename T>
-void launch_norm2_dist(const T* r, const int64_t* ptr, const int64_t* idx, int64_t n, double* part, double* scal,
-                       int slot, hipStream_t st) {
+void launch_dot2_flex(const T* r, const T* q, const T* z, int64_t n, double* part, double* scal, hipStream_t st) {
   const unsigned g = red_grid(n);
-  hipLaunchKernelGGL(k_norm2_dist_partial<T>, dim3(g), dim3(256), 0, st, r, ptr, idx, n, part);
+  hipLaunchKernelGGL(k_dot2_partial<T>, dim3(g), dim3(256), 0, st, r, q, z, n, part);
+  hipLaunchKernelGGL(k_finalize2, dim3(1), dim3(256), 0, st, part, (int)g, scal);
+}
+
+template <typename T>
+void launch_norm2_dist(T* r, const int64_t* ptr, const int64_t* idx, int64_t n, double* part, double* scal, int slot,
+                       bool canon, hipStream_t st) {
+  const unsigned g = red_grid(n);
+  hipLaunchKernelGGL(k_norm2_dist_partial<T>, dim3(g), dim3(256), 0, st, r, ptr, idx, n, part, (int)canon);
   hipLaunchKernelGGL(k_finalize, dim3(1), dim3(256), 0, st, part, (int)g, scal, slot, 0);
 }
 
@@ -724,7 +781,8 @@ void launch_add_f32(double* x, const float* d, int64_t n, hipStream_t st) {
   template void launch_coarse<T>(const double*, const T*, double*, T*, const int64_t*, const int64_t*, int,            \
                                  hipStream_t);                                                                         \
   template void launch_dot<T>(const T*, const T*, int64_t, double*, double*, int, int, hipStream_t);                   \
-  template void launch_norm2_dist<T>(const T*, const int64_t*, const int64_t*, int64_t, double*, double*, int,         \
+  template void launch_dot2_flex<T>(const T*, const T*, const T*, int64_t, double*, double*, hipStream_t);             \
+  template void launch_norm2_dist<T>(T*, const int64_t*, const int64_t*, int64_t, double*, double*, int, bool,        \
                                      hipStream_t);                                                                     \
   template void launch_axpy2<T>(T*, const T*, T*, const T*, int64_t, const double*, hipStream_t);                      \
   template void launch_xpby<T>(T*, const T*, int64_t, const double*, hipStream_t);                                     \

@@ -11,7 +11,7 @@
 
 namespace igamg {
 
-constexpr int RED_BLOCKS = 512;   // partial sums per reduction
+constexpr int RED_BLOCKS = 512;   // partial sums per reduction (the flexible dot uses 2x)
 
 template <typename T>
 void launch_band(int d, int p, const T* band, const T* u, const T* f, T* r, const int* bpatch, const PatchDev* pd,
@@ -49,8 +49,10 @@ void launch_coarse(const double* Ainv, const T* f0, double* b, T* u0, const int6
 template <typename T>
 void launch_dot(const T* a, const T* b, int64_t n, double* part, double* scal, int slot, int op, hipStream_t st);
 template <typename T>
-void launch_norm2_dist(const T* r, const int64_t* ptr, const int64_t* idx, int64_t n, double* part, double* scal,
-                       int slot, hipStream_t st);
+void launch_dot2_flex(const T* r, const T* q, const T* z, int64_t n, double* part, double* scal, hipStream_t st);
+template <typename T>
+void launch_norm2_dist(T* r, const int64_t* ptr, const int64_t* idx, int64_t n, double* part, double* scal, int slot,
+                       bool canon, hipStream_t st);
 template <typename T>
 void launch_axpy2(T* x, const T* p, T* r, const T* q, int64_t n, const double* scal, hipStream_t st);
 template <typename T>

@@ -197,7 +197,9 @@ class Solver:
         _check(_lib.igamg_profile(self.h, int(enable)))
 
     def profile_read(self):
-        n = self.prob.levels
+        """Per-level banded-apply launch counts, ms and bytes: entries [0, levels)
+        for FP64 launches, [levels, 2 levels) for FP32 ones."""
+        n = 2 * self.prob.levels
         cnt = np.zeros(n, dtype=np.int64)
         ms = np.zeros(n)
         by = np.zeros(n)
