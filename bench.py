@@ -101,8 +101,7 @@ def run(workload, prob, precision, steps, warmup, dev):
     stream = torch.cuda.current_stream()
     for _ in range(warmup):
         S.solve(f, tol=1e-8, u=u)
-    torch.cuda.synchronize()
-    S.profile(True)
+    # timed pass: the product path (each PCG iteration replayed as HIP graphs)
     lat, iters = [], []
     torch.cuda.synchronize()
     t_start = time.perf_counter()
@@ -113,6 +112,15 @@ def run(workload, prob, precision, steps, warmup, dev):
         iters.append((info.iterations, info.outer_iterations))
     torch.cuda.synchronize()
     total = time.perf_counter() - t_start
+    # second timed pass of the same solves with a HIP event pair around every
+    # banded-apply launch (direct launches: HIP does not time events in graphs)
+    S.profile(True)
+    torch.cuda.synchronize()
+    t_p = time.perf_counter()
+    for _ in range(steps):
+        S.solve(f, tol=1e-8, u=u, stream=stream)
+    torch.cuda.synchronize()
+    total_prof = time.perf_counter() - t_p
     S.profile(False)
     cnt, ms, by = S.profile_read()
     nl = prob.levels
@@ -143,7 +151,9 @@ def run(workload, prob, precision, steps, warmup, dev):
                      "algorithmic_bytes_per_launch": bytes_launch,
                      "launches_per_step": float(cnt[k]) / steps,
                      "band_ms_per_step_fp64_all_levels": float(ms[:nl].sum()) / steps,
-                     "band_ms_per_step_fp32_all_levels": float(ms[nl:].sum()) / steps},
+                     "band_ms_per_step_fp32_all_levels": float(ms[nl:].sum()) / steps,
+                     "measured_over": f"a second timed pass of the same {steps} solves with per-launch "
+                                      f"HIP events ({1e3 * total_prof / steps:.2f} ms/solve, direct launches)"},
     }
     return S, res
 

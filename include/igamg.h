@@ -85,7 +85,8 @@ typedef struct {
   int geometry_scaling;  /* 1: scale piece operators by the patch's mean metric trace */
   int inner_maxit;       /* mixed: inner PCG iteration cap per refinement step (100) */
   double inner_tol;      /* mixed: inner relative residual reduction per step (1e-4) */
-  int reserved[6];
+  int graphs;            /* 1: replay each PCG iteration as HIP graphs (default); 0: direct launches */
+  int reserved[5];
 } igamg_options;
 
 #define IGAMG_FP64 0
@@ -144,6 +145,33 @@ int igamg_vcycle(igamg_handle h, const double* r, double* z, void* stream);
 int igamg_solve(igamg_handle h, const double* rhs, double* u, double tol, igamg_solve_info* info,
                 void* stream);
 
+/* Batched solves (continuous batching).  A batch steps any number of resident
+ * solves in lockstep: each step is one PCG iteration of every active request,
+ * replayed as two HIP graphs in which every request is an independent branch
+ * (its kernels overlap with the other requests' on the device).  Requests may
+ * be added and removed between steps; mixed-precision requests run their FP64
+ * refinement steps between inner solves.  A batch owns HIP streams, events and
+ * graphs (no device memory); one host thread drives it.
+ *   igamg_batch_add     starts the solve of A u = rhs on handle h (device vectors
+ *                       of length n_free; no other solve may use h meanwhile);
+ *                       returns the request's slot id in *slot
+ *   igamg_batch_step    runs one lockstep step on `stream` and synchronises it;
+ *                       *n_active = requests still running afterwards
+ *   igamg_batch_poll    *done = 1 once the request finished; *info and its code
+ *                       are then final (OK, ENOCONV or ENAN), u holds the result
+ *   igamg_batch_remove  frees a slot (a running request is abandoned)
+ * igamg_solve_batch solves n requests to completion with one batch.          */
+typedef struct igamg_batch_ctx* igamg_batch;
+int igamg_batch_create(igamg_batch* out);
+int igamg_batch_destroy(igamg_batch b);
+int igamg_batch_add(igamg_batch b, igamg_handle h, const double* rhs, double* u, double tol, void* stream,
+                    int* slot);
+int igamg_batch_step(igamg_batch b, void* stream, int* n_active);
+int igamg_batch_poll(igamg_batch b, int slot, int* done, igamg_solve_info* info, int* code);
+int igamg_batch_remove(igamg_batch b, int slot);
+int igamg_solve_batch(igamg_handle const* hs, const double* const* rhs, double* const* u, int n, double tol,
+                      igamg_solve_info* infos, int* codes, void* stream);
+
 /* The operators of one level on global free vectors, for checking the parts of
  * the cycle one at a time:
  *   IGAMG_OP_APPLY     y = A_l x                          (x, y on level l)
@@ -181,7 +209,9 @@ int igamg_export(igamg_handle h, int what, int level, double* out, int64_t* rows
 /* Kernel timing of the banded stiffness apply (the bandwidth-bound kernel of
  * the cycle).  enable = 1 starts recording a HIP event pair around every
  * banded-apply launch on every level (events are created by the library on
- * first use; recording adds no synchronisation), enable = 0 stops.
+ * first use; recording adds no synchronisation), enable = 0 stops.  While
+ * recording, solves launch their kernels directly instead of replaying HIP
+ * graphs (HIP does not time events recorded into graphs).
  * igamg_profile_read synchronises the stream of the last recorded launch and
  * returns, per level l, the launch count, the summed kernel time in ms and the
  * algorithmic bytes moved (rows * s ((2p+1)^d + vectors), s = 8 or 4 bytes);

@@ -24,7 +24,8 @@ struct Options {
   double tau = 0.25, sigma_scale = 5.0;
   int nu = 1, mu = 1, precision = 0, maxit = 500, geometry_scaling = 1;
   int inner_maxit = 100;
-  double inner_tol = 1e-3;
+  double inner_tol = 1e-4;
+  int graphs = 1;
 };
 
 // Error with an igamg return code.

@@ -5,7 +5,9 @@
 // sequences launches on the caller's stream.
 #include <hip/hip_runtime.h>
 
+#include <atomic>
 #include <chrono>
+#include <map>
 #include <cmath>
 #include <cstdio>
 #include <cstdlib>
@@ -107,12 +109,19 @@ struct igamg_ctx {
     double bytes;
     hipEvent_t a, b;
   };
-  std::vector<Rec> recs;
+  std::vector<Rec> recs;               // launches recorded outside graphs
   std::vector<hipEvent_t> pool;
   size_t pool_used = 0;
   hipStream_t prof_stream = nullptr;
+
   void* ws = nullptr;
   size_t bytes = 0;
+  struct igamg_batch_ctx* solo = nullptr;   // driver of igamg_solve
+  uint64_t uid = next_uid();                 // identity in graph caches (never reused)
+  static uint64_t next_uid() {
+    static std::atomic<uint64_t> n{1};
+    return n++;
+  }
 };
 
 template <typename T>
@@ -358,65 +367,57 @@ PcgVecs<float>& vecs<float>(igamg_ctx& C) {
   return C.v32;
 }
 
+// ---------------------------------------------------------------------------
 // PCG with one cycle as preconditioner (Sec. 4) on the finest level in
-// precision T, from x = 0 for the right-hand side held in dat<T>(finest).f,
-// which is overwritten by the recurrence residual.  Stops when the residual
-// norm drops to rtol times its initial value.  Returns the iteration count;
-// *rel = final ||r|| / ||r_0||; *status = OK / ENOCONV / ENAN.
-// flexible: beta = -alpha (z_new . q) / rho (the Polak-Ribiere form of the
-// direction update), which tolerates a preconditioner that is symmetric only
-// up to rounding -- the FP32 cycle; the FP64 solve uses the classical
-// beta = rho_new / rho of PCG.
+// precision T, split into the pieces the solve driver sequences.  The
+// right-hand side is in dat<T>(finest).f and becomes the (canonical,
+// distributed) recurrence residual; the iterate is vecs<T>.x.
+// Direction update: classical beta = rho_new / rho for the FP64 solve; the
+// flexible form beta = -alpha (z_new . q) / rho for the FP32 inner solves,
+// whose cycle is symmetric only up to rounding.
+// ---------------------------------------------------------------------------
 template <typename T>
-static int pcg(igamg_ctx& C, double rtol, int maxit, hipStream_t st, double* rel, int* status, bool flexible) {
-  const int L = C.L;
-  DevLevel& D = C.dl[L];
+static void pcg_start(igamg_ctx& C, hipStream_t st) {
+  DevLevel& D = C.dl[C.L];
+  launch_fill<T>(vecs<T>(C).x, D.NL, 0.0, st);
+  launch_norm2_dist<T>(dat<T>(D).f, D.gptr, D.gidx, D.N, C.part, C.scal, 6, true, st);
+  HIP_OK(hipMemcpyAsync(C.host_scal + 6, C.scal + 6, sizeof(double), hipMemcpyDeviceToHost, st));
+}
+
+template <typename T>
+static void pcg_first(igamg_ctx& C, hipStream_t st) {
+  DevLevel& D = C.dl[C.L];
+  LevelData<T>& X = dat<T>(D);
+  cycle<T>(C, C.L, true, st);
+  launch_dot<T>(X.f, X.u, D.NL, C.part, C.scal, 0, 0, st);
+  launch_copy<T>(vecs<T>(C).p, X.u, D.NL, st);
+}
+
+// q = A p, alpha = rho / (p.q), x += alpha p, r -= alpha q, ||r||^2 to the host
+template <typename T>
+static void pcg_body_a(igamg_ctx& C, hipStream_t st) {
+  DevLevel& D = C.dl[C.L];
   LevelData<T>& X = dat<T>(D);
   PcgVecs<T>& V = vecs<T>(C);
-  T* r = X.f;
-  T* z = X.u;
-  launch_fill<T>(V.x, D.NL, 0.0, st);
-  launch_norm2_dist<T>(r, D.gptr, D.gidx, D.N, C.part, C.scal, 6, true, st);
-  const double n02 = fetch(C, 6, st);
-  *status = IGAMG_OK;
-  *rel = 0.0;
-  if (!std::isfinite(n02)) {
-    *status = IGAMG_ENAN;
-    return 0;
-  }
-  if (n02 == 0.0) return 0;
-  const double stop2 = rtol * rtol * n02;
-  cycle<T>(C, L, true, st);
-  launch_dot<T>(r, z, D.NL, C.part, C.scal, 0, 0, st);
-  launch_copy<T>(V.p, z, D.NL, st);
-  *rel = 1.0;
-  int it;
-  for (it = 1; it <= maxit; ++it) {
-    band_op<T>(C, L, V.p, nullptr, V.q, false, st);
-    launch_dot<T>(V.p, V.q, D.NL, C.part, C.scal, 1, 1, st);
-    launch_axpy2<T>(V.x, V.p, r, V.q, D.NL, C.scal, st);
-    launch_norm2_dist<T>(r, D.gptr, D.gidx, D.N, C.part, C.scal, 5, true, st);
-    const double rr = fetch(C, 5, st);
-    if (!std::isfinite(rr)) {
-      *status = IGAMG_ENAN;
-      return it;
-    }
-    *rel = std::sqrt(rr / n02);
-    if (trace_enabled()) {
-      const double a = fetch(C, 2, st), rho = fetch(C, 0, st), pq = fetch(C, 1, st);
-      std::fprintf(stderr, "[igamg] pcg<%s> it %d rel %.3e alpha %.3e rho %.3e pq %.3e\n",
-                   sizeof(T) == 4 ? "f32" : "f64", it, *rel, a, rho, pq);
-    }
-    if (rr <= stop2) return it;
-    cycle<T>(C, L, true, st);
-    if (flexible)
-      launch_dot2_flex<T>(r, V.q, z, D.NL, C.part, C.scal, st);
-    else
-      launch_dot<T>(r, z, D.NL, C.part, C.scal, 3, 2, st);
-    launch_xpby<T>(V.p, z, D.NL, C.scal, st);
-  }
-  *status = IGAMG_ENOCONV;
-  return maxit;
+  band_op<T>(C, C.L, V.p, nullptr, V.q, false, st);
+  launch_dot<T>(V.p, V.q, D.NL, C.part, C.scal, 1, 1, st);
+  launch_axpy2<T>(V.x, V.p, X.f, V.q, D.NL, C.scal, st);
+  launch_norm2_dist<T>(X.f, D.gptr, D.gidx, D.N, C.part, C.scal, 5, true, st);
+  HIP_OK(hipMemcpyAsync(C.host_scal + 5, C.scal + 5, sizeof(double), hipMemcpyDeviceToHost, st));
+}
+
+// z = B r, beta, p = z + beta p
+template <typename T>
+static void pcg_body_b(igamg_ctx& C, hipStream_t st, bool flexible) {
+  DevLevel& D = C.dl[C.L];
+  LevelData<T>& X = dat<T>(D);
+  PcgVecs<T>& V = vecs<T>(C);
+  cycle<T>(C, C.L, true, st);
+  if (flexible)
+    launch_dot2_flex<T>(X.f, V.q, X.u, D.NL, C.part, C.scal, st);
+  else
+    launch_dot<T>(X.f, X.u, D.NL, C.part, C.scal, 3, 2, st);
+  launch_xpby<T>(V.p, X.u, D.NL, C.scal, st);
 }
 
 // ---------------------------------------------------------------------------
@@ -448,6 +449,7 @@ static void read_opts(const igamg_options* o, Options& O) {
   O.geometry_scaling = o->geometry_scaling;
   O.inner_maxit = o->inner_maxit;
   O.inner_tol = o->inner_tol;
+  O.graphs = o->graphs;
   if (!(O.tau > 0) || !(O.sigma_scale > 0) || O.nu < 1 || O.nu > 8 || (O.mu != 1 && O.mu != 2) ||
       (O.precision != IGAMG_FP64 && O.precision != IGAMG_MIXED) || O.maxit < 1 || O.inner_maxit < 1 ||
       !(O.inner_tol > 0 && O.inner_tol < 1))
@@ -463,6 +465,341 @@ static int check_level(igamg_ctx* h, int level) {
 static void need_device(igamg_ctx* h) {
   if (!h) throw SetupError{IGAMG_EINVAL, "null handle"};
   if (!h->on_device) throw SetupError{IGAMG_EINVAL, "handle was set up without a workspace"};
+}
+
+// ---------------------------------------------------------------------------
+// solve driver: per-request state machines stepped in lockstep.  One step is
+// one PCG iteration of every iterating request, as two HIP graphs (body A:
+// apply, alpha, update, residual norm; body B: cycle, beta, direction) in
+// which every request is an independent branch on its own stream.  Between
+// the graphs the host reads every request's residual norm; starts of a PCG
+// and the FP64 refinement steps of mixed requests run outside the graphs.
+// ---------------------------------------------------------------------------
+enum { RQ_FREE = 0, RQ_START_READ, RQ_ITER, RQ_OUTER_READ, RQ_DONE };
+
+struct Req {
+  igamg_ctx* C = nullptr;
+  const double* rhs = nullptr;
+  double* u = nullptr;
+  double tol = 1e-8;
+  int state = RQ_FREE;
+  bool mixed = false, first_outer = true, fresh_done = false;
+  int it = 0, iters = 0, outer = 0, code = IGAMG_OK;
+  double n02 = 0.0, nf2 = 0.0, rel = 1.0;
+  std::chrono::steady_clock::time_point t0;
+  double solve_ms = 0.0;
+};
+
+struct igamg_batch_ctx {
+  hipStream_t ds = nullptr;
+  std::vector<hipStream_t> br;
+  std::vector<hipEvent_t> ev_join;
+  hipEvent_t ev_fork = nullptr, ev_in = nullptr;
+  std::vector<Req> reqs;
+  struct Graph {
+    hipGraphExec_t ex = nullptr;
+  };
+  std::map<std::vector<uintptr_t>, Graph> cache;
+  ~igamg_batch_ctx() {
+    for (auto& kv : cache) (void)hipGraphExecDestroy(kv.second.ex);
+    for (auto e : ev_join) (void)hipEventDestroy(e);
+    for (auto s : br) (void)hipStreamDestroy(s);
+    if (ev_fork) (void)hipEventDestroy(ev_fork);
+    if (ev_in) (void)hipEventDestroy(ev_in);
+    if (ds) (void)hipStreamDestroy(ds);
+  }
+};
+
+static void batch_init(igamg_batch_ctx& B) {
+  if (B.ds) return;
+  HIP_OK(hipStreamCreateWithFlags(&B.ds, hipStreamNonBlocking));
+  HIP_OK(hipEventCreateWithFlags(&B.ev_fork, hipEventDisableTiming));
+  HIP_OK(hipEventCreateWithFlags(&B.ev_in, hipEventDisableTiming));
+}
+
+static void batch_branches(igamg_batch_ctx& B, size_t n) {
+  while (B.br.size() < n) {
+    hipStream_t s;
+    hipEvent_t e;
+    HIP_OK(hipStreamCreateWithFlags(&s, hipStreamNonBlocking));
+    HIP_OK(hipEventCreateWithFlags(&e, hipEventDisableTiming));
+    B.br.push_back(s);
+    B.ev_join.push_back(e);
+  }
+}
+
+// per-launch event timing (igamg_profile) runs with direct launches: HIP does
+// not time events that were recorded into a graph
+static bool graphs_enabled(const igamg_batch_ctx& B, const std::vector<int>& set) {
+  for (int i : set)
+    if (!B.reqs[i].C->H.opt.graphs || B.reqs[i].C->prof) return false;
+  return true;
+}
+
+static void sync_driver(igamg_batch_ctx& B) { HIP_OK(hipStreamSynchronize(B.ds)); }
+
+static void body(Req& q, int which, hipStream_t st) {
+  igamg_ctx& C = *q.C;
+  if (which == 0) {
+    if (q.mixed) pcg_body_a<float>(C, st); else pcg_body_a<double>(C, st);
+  } else {
+    if (q.mixed) pcg_body_b<float>(C, st, true); else pcg_body_b<double>(C, st, false);
+  }
+}
+
+// run body `which` for the requests in `set` on the driver stream
+static void run_bodies(igamg_batch_ctx& B, const std::vector<int>& set, int which) {
+  if (set.empty()) return;
+  if (!graphs_enabled(B, set)) {
+    for (int i : set) body(B.reqs[i], which, B.ds);
+    return;
+  }
+  std::vector<uintptr_t> key{(uintptr_t)which};
+  for (int i : set) {
+    key.push_back((uintptr_t)i);
+    key.push_back((uintptr_t)B.reqs[i].C->uid);
+  }
+  auto it = B.cache.find(key);
+  if (it == B.cache.end()) {
+    batch_branches(B, set.size());
+    if (B.cache.size() > 64) {
+      sync_driver(B);
+      for (auto& kv : B.cache) (void)hipGraphExecDestroy(kv.second.ex);
+      B.cache.clear();
+    }
+    igamg_batch_ctx::Graph G;
+    hipGraph_t g = nullptr;
+    HIP_OK(hipStreamBeginCapture(B.ds, hipStreamCaptureModeThreadLocal));
+    HIP_OK(hipEventRecord(B.ev_fork, B.ds));
+    for (size_t k = 0; k < set.size(); ++k) {
+      HIP_OK(hipStreamWaitEvent(B.br[k], B.ev_fork, 0));
+      body(B.reqs[set[k]], which, B.br[k]);
+      HIP_OK(hipEventRecord(B.ev_join[k], B.br[k]));
+      HIP_OK(hipStreamWaitEvent(B.ds, B.ev_join[k], 0));
+    }
+    HIP_OK(hipStreamEndCapture(B.ds, &g));
+    HIP_OK(hipGraphInstantiate(&G.ex, g, nullptr, nullptr, 0));
+    HIP_OK(hipGraphDestroy(g));
+    it = B.cache.emplace(key, std::move(G)).first;
+  }
+  HIP_OK(hipGraphLaunch(it->second.ex, B.ds));
+}
+
+static void rq_finish(Req& q, int code, hipStream_t st) {
+  igamg_ctx& C = *q.C;
+  DevLevel& D = C.dl[C.L];
+  launch_gather(C.v64.x, q.u, D.gptr, D.gidx, D.N, false, st);
+  q.code = code;
+  q.state = RQ_DONE;
+  q.fresh_done = true;
+}
+
+// mixed: start an inner FP32 solve for the current FP64 residual
+static void rq_start_inner(Req& q, hipStream_t st) {
+  igamg_ctx& C = *q.C;
+  DevLevel& D = C.dl[C.L];
+  launch_to_f32(D.d32.f, D.d64.f, D.NL, st);
+  pcg_start<float>(C, st);
+  q.it = 0;
+  q.state = RQ_START_READ;
+}
+
+// mixed: x += d, r = f - A x in FP64, ||r||^2 to the host
+static void rq_outer_update(Req& q, hipStream_t st) {
+  igamg_ctx& C = *q.C;
+  DevLevel& D = C.dl[C.L];
+  launch_add_f32(C.v64.x, C.v32.x, D.NL, st);
+  band_op<double>(C, C.L, C.v64.x, C.fsave, D.d64.f, true, st);
+  launch_norm2_dist<double>(D.d64.f, D.gptr, D.gidx, D.N, C.part, C.scal, 7, true, st);
+  HIP_OK(hipMemcpyAsync(C.host_scal + 7, C.scal + 7, sizeof(double), hipMemcpyDeviceToHost, st));
+  q.state = RQ_OUTER_READ;
+}
+
+static void rq_begin(Req& q, hipStream_t st) {
+  igamg_ctx& C = *q.C;
+  DevLevel& D = C.dl[C.L];
+  q.t0 = std::chrono::steady_clock::now();
+  q.it = q.iters = q.outer = 0;
+  q.code = IGAMG_OK;
+  q.rel = 1.0;
+  q.first_outer = true;
+  if (!q.mixed) {
+    launch_scatter(q.rhs, D.d64.f, D.gptr, D.gidx, D.N, true, st);
+    pcg_start<double>(C, st);
+    q.state = RQ_START_READ;
+  } else {
+    launch_scatter(q.rhs, C.fsave, D.gptr, D.gidx, D.N, true, st);
+    launch_fill<double>(C.v64.x, D.NL, 0.0, st);
+    launch_copy<double>(D.d64.f, C.fsave, D.NL, st);
+    launch_norm2_dist<double>(D.d64.f, D.gptr, D.gidx, D.N, C.part, C.scal, 7, true, st);
+    HIP_OK(hipMemcpyAsync(C.host_scal + 7, C.scal + 7, sizeof(double), hipMemcpyDeviceToHost, st));
+    q.state = RQ_OUTER_READ;
+  }
+}
+
+static void trace_iter(const Req& q, double rel) {
+  if (trace_enabled())
+    std::fprintf(stderr, "[igamg] %p pcg<%s> it %d rel %.3e\n", (void*)q.C, q.mixed ? "f32" : "f64", q.it, rel);
+}
+
+// process a request whose host readback (start or outer norm) is available
+static void rq_process_read(Req& q, hipStream_t st) {
+  igamg_ctx& C = *q.C;
+  const Options& O = C.H.opt;
+  if (q.state == RQ_START_READ) {
+    const double n02 = C.host_scal[6];
+    if (!std::isfinite(n02)) return rq_finish(q, IGAMG_ENAN, st);
+    if (n02 == 0.0) {
+      if (!q.mixed) {
+        q.rel = 0.0;
+        return rq_finish(q, IGAMG_OK, st);
+      }
+      return rq_outer_update(q, st);
+    }
+    q.n02 = n02;
+    if (q.mixed) pcg_first<float>(C, st); else pcg_first<double>(C, st);
+    q.state = RQ_ITER;
+    return;
+  }
+  if (q.state == RQ_OUTER_READ) {
+    const double rr = C.host_scal[7];
+    if (!std::isfinite(rr)) return rq_finish(q, IGAMG_ENAN, st);
+    if (q.first_outer) {
+      q.first_outer = false;
+      q.nf2 = rr;
+      if (rr == 0.0) {
+        q.rel = 0.0;
+        return rq_finish(q, IGAMG_OK, st);
+      }
+    } else {
+      q.outer++;
+      q.rel = std::sqrt(rr / q.nf2);
+      if (trace_enabled()) std::fprintf(stderr, "[igamg] %p refinement %d rel %.3e\n", (void*)q.C, q.outer, q.rel);
+      if (q.rel <= q.tol) return rq_finish(q, IGAMG_OK, st);
+      if (q.iters >= O.maxit || q.outer >= 60) return rq_finish(q, IGAMG_ENOCONV, st);
+    }
+    return rq_start_inner(q, st);
+  }
+}
+
+// after body A: one PCG iteration done for q
+static bool rq_after_iter(Req& q, hipStream_t st) {
+  igamg_ctx& C = *q.C;
+  const Options& O = C.H.opt;
+  const double rr = C.host_scal[5];
+  q.it++;
+  q.iters++;
+  if (!std::isfinite(rr)) {
+    rq_finish(q, IGAMG_ENAN, st);
+    return false;
+  }
+  const double rel = std::sqrt(rr / q.n02);
+  trace_iter(q, rel);
+  if (!q.mixed) {
+    q.rel = rel;
+    if (rel <= q.tol) {
+      rq_finish(q, IGAMG_OK, st);
+      return false;
+    }
+    if (q.iters >= O.maxit) {
+      rq_finish(q, IGAMG_ENOCONV, st);
+      return false;
+    }
+    return true;
+  }
+  if (rel <= O.inner_tol || q.it >= O.inner_maxit || q.iters >= O.maxit) {
+    rq_outer_update(q, st);
+    return false;
+  }
+  return true;
+}
+
+static int batch_step(igamg_batch_ctx& B, hipStream_t caller) {
+  batch_init(B);
+  HIP_OK(hipEventRecord(B.ev_in, caller));
+  HIP_OK(hipStreamWaitEvent(B.ds, B.ev_in, 0));
+  // settle every pending readback (a start may lead to another start)
+  for (int pass = 0; pass < 8; ++pass) {
+    bool pending = false;
+    for (auto& q : B.reqs) pending |= (q.state == RQ_START_READ || q.state == RQ_OUTER_READ);
+    if (!pending) break;
+    sync_driver(B);
+    std::vector<int> idx;
+    for (size_t i = 0; i < B.reqs.size(); ++i)
+      if (B.reqs[i].state == RQ_START_READ || B.reqs[i].state == RQ_OUTER_READ) idx.push_back((int)i);
+    for (int i : idx) rq_process_read(B.reqs[i], B.ds);
+  }
+  std::vector<int> set;
+  for (size_t i = 0; i < B.reqs.size(); ++i)
+    if (B.reqs[i].state == RQ_ITER) set.push_back((int)i);
+  bool finished = false;
+  if (!set.empty()) {
+    run_bodies(B, set, 0);
+    sync_driver(B);
+    std::vector<int> cont;
+    for (int i : set) {
+      if (rq_after_iter(B.reqs[i], B.ds))
+        cont.push_back(i);
+      else
+        finished |= (B.reqs[i].state == RQ_DONE);
+    }
+    run_bodies(B, cont, 1);
+  }
+  for (auto& q : B.reqs) finished |= q.fresh_done;
+  // a request reported done must have its result in place; otherwise the
+  // next step's work queues behind this one without a host round trip
+  if (finished) {
+    sync_driver(B);
+    const auto now = std::chrono::steady_clock::now();
+    for (auto& q : B.reqs)
+      if (q.fresh_done) {
+        q.fresh_done = false;
+        q.solve_ms = std::chrono::duration<double, std::milli>(now - q.t0).count();
+      }
+  }
+  int active = 0;
+  for (auto& q : B.reqs) active += (q.state != RQ_FREE && q.state != RQ_DONE);
+  return active;
+}
+
+static int batch_add(igamg_batch_ctx& B, igamg_ctx* h, const double* rhs, double* u, double tol, hipStream_t caller) {
+  need_device(h);
+  if (!rhs || !u || rhs == u) throw SetupError{IGAMG_EINVAL, "bad vector arguments"};
+  if (!(tol > 0)) throw SetupError{IGAMG_EINVAL, "tol must be positive"};
+  for (auto& q : B.reqs)
+    if (q.C == h && q.state != RQ_FREE && q.state != RQ_DONE)
+      throw SetupError{IGAMG_EINVAL, "handle already has a running solve in this batch"};
+  batch_init(B);
+  HIP_OK(hipEventRecord(B.ev_in, caller));
+  HIP_OK(hipStreamWaitEvent(B.ds, B.ev_in, 0));
+  int slot = -1;
+  for (size_t i = 0; i < B.reqs.size(); ++i)
+    if (B.reqs[i].state == RQ_FREE) {
+      slot = (int)i;
+      break;
+    }
+  if (slot < 0) {
+    slot = (int)B.reqs.size();
+    B.reqs.emplace_back();
+  }
+  Req& q = B.reqs[slot];
+  q = Req{};
+  q.C = h;
+  q.rhs = rhs;
+  q.u = u;
+  q.tol = tol;
+  q.mixed = h->mixed;
+  rq_begin(q, B.ds);
+  return slot;
+}
+
+static void fill_info(const Req& q, igamg_solve_info* info) {
+  if (!info) return;
+  info->iterations = q.iters;
+  info->outer_iterations = q.outer;
+  info->converged = (q.state == RQ_DONE && q.code == IGAMG_OK);
+  info->rel_residual = q.rel;
+  info->solve_ms = q.solve_ms;
 }
 
 // ---------------------------------------------------------------------------
@@ -482,6 +819,7 @@ void igamg_default_options(igamg_options* o) {
   o->geometry_scaling = 1;
   o->inner_maxit = 100;
   o->inner_tol = 1e-4;
+  o->graphs = 1;
 }
 
 const char* igamg_last_error(void) { return g_err.c_str(); }
@@ -551,6 +889,7 @@ int igamg_profile_read(igamg_handle h, int64_t* launches, double* ms, double* by
     if (bytes) bytes[l] = 0.0;
   }
   if (!h->recs.empty()) HIP_OK(hipStreamSynchronize(h->prof_stream));
+  if (h->solo && h->solo->ds) HIP_OK(hipStreamSynchronize(h->solo->ds));
   for (const auto& rc : h->recs) {
     float t = 0.0f;
     HIP_OK(hipEventElapsedTime(&t, rc.a, rc.b));
@@ -566,6 +905,7 @@ int igamg_profile_read(igamg_handle h, int64_t* launches, double* ms, double* by
 
 int igamg_destroy(igamg_handle h) {
   if (!h) return IGAMG_OK;
+  delete h->solo;
   for (hipEvent_t e : h->pool) (void)hipEventDestroy(e);
   if (h->host_scal) (void)hipHostFree(h->host_scal);
   delete h;
@@ -765,75 +1105,94 @@ int igamg_export(igamg_handle h, int what, int level, double* out, int64_t* rows
 int igamg_solve(igamg_handle h, const double* rhs, double* u, double tol, igamg_solve_info* info, void* stream) {
   API_BEGIN
   need_device(h);
-  if (!rhs || !u || rhs == u) return set_err(IGAMG_EINVAL, "bad vector arguments");
-  if (!(tol > 0)) return set_err(IGAMG_EINVAL, "tol must be positive");
   hipStream_t st = static_cast<hipStream_t>(stream);
-  auto t0 = std::chrono::steady_clock::now();
-  igamg_ctx& C = *h;
-  const Options& O = C.H.opt;
-  DevLevel& D = C.dl[C.L];
-  int code = IGAMG_OK, iters = 0, outer = 0;
-  double rel = 0.0;
-  if (!C.mixed) {
-    // plain FP64 PCG; the recurrence residual is the stopping quantity
-    launch_scatter(rhs, D.d64.f, D.gptr, D.gidx, D.N, true, st);
-    iters = pcg<double>(C, tol, O.maxit, st, &rel, &code, false);
-    launch_gather(C.v64.x, u, D.gptr, D.gidx, D.N, false, st);
-  } else {
-    // FP64 iterative refinement: r = f - A x in FP64 (FP64 band), d from an FP32
-    // PCG solve with FP32 bands, smoothers and transfers (coarse solve in
-    // FP64), x += d in FP64
-    launch_scatter(rhs, C.fsave, D.gptr, D.gidx, D.N, true, st);
-    launch_fill<double>(C.v64.x, D.NL, 0.0, st);
-    launch_copy<double>(D.d64.f, C.fsave, D.NL, st);
-    launch_norm2_dist<double>(D.d64.f, D.gptr, D.gidx, D.N, C.part, C.scal, 7, true, st);
-    const double nf2 = fetch(C, 7, st);
-    if (!std::isfinite(nf2)) {
-      code = set_err(IGAMG_ENAN, "non-finite right-hand side");
-    } else if (nf2 > 0) {
-      rel = 1.0;
-      const int max_outer = 60;
-      for (outer = 1; outer <= max_outer; ++outer) {
-        launch_to_f32(D.d32.f, D.d64.f, D.NL, st);
-        double irel = 0.0;
-        int icode = IGAMG_OK;
-        iters += pcg<float>(C, O.inner_tol, O.inner_maxit, st, &irel, &icode, true);
-        if (icode == IGAMG_ENAN) {
-          code = set_err(IGAMG_ENAN, "non-finite inner residual");
-          break;
-        }
-        launch_add_f32(C.v64.x, C.v32.x, D.NL, st);
-        band_op<double>(C, C.L, C.v64.x, C.fsave, D.d64.f, true, st);
-        launch_norm2_dist<double>(D.d64.f, D.gptr, D.gidx, D.N, C.part, C.scal, 5, true, st);
-        const double rr = fetch(C, 5, st);
-        if (!std::isfinite(rr)) {
-          code = set_err(IGAMG_ENAN, "non-finite residual");
-          break;
-        }
-        rel = std::sqrt(rr / nf2);
-        if (rr <= tol * tol * nf2) break;
-        if (iters >= O.maxit) {
-          outer = std::min(outer, max_outer);
-          break;
-        }
-      }
-      if (code == IGAMG_OK && rel > tol) code = IGAMG_ENOCONV;
-      if (outer > max_outer) outer = max_outer;
-    }
-    launch_gather(C.v64.x, u, D.gptr, D.gidx, D.N, false, st);
+  if (!h->solo) h->solo = new igamg_batch_ctx();
+  igamg_batch_ctx& B = *h->solo;
+  B.reqs.clear();
+  const int slot = batch_add(B, h, rhs, u, tol, st);
+  while (batch_step(B, st) > 0) {
   }
-  if (code == IGAMG_ENOCONV) set_err(code, "iteration cap reached above the tolerance");
-  if (code == IGAMG_ENAN && g_err.empty()) set_err(code, "non-finite residual");
-  HIP_OK(hipGetLastError());
-  HIP_OK(hipStreamSynchronize(st));
-  if (info) {
-    info->iterations = iters;
-    info->outer_iterations = outer;
-    info->converged = (code == IGAMG_OK);
-    info->rel_residual = rel;
-    info->solve_ms = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
-  }
+  Req& q = B.reqs[slot];
+  fill_info(q, info);
+  const int code = q.code;
+  q.state = RQ_FREE;
+  if (code == IGAMG_ENOCONV) return set_err(code, "iteration cap reached above the tolerance");
+  if (code == IGAMG_ENAN) return set_err(code, "non-finite residual");
   return code;
+  API_END
+}
+
+int igamg_batch_create(igamg_batch* out) {
+  API_BEGIN
+  if (!out) return set_err(IGAMG_EINVAL, "out is NULL");
+  *out = new igamg_batch_ctx();
+  return IGAMG_OK;
+  API_END
+}
+
+int igamg_batch_destroy(igamg_batch b) {
+  delete b;
+  return IGAMG_OK;
+}
+
+int igamg_batch_add(igamg_batch b, igamg_handle h, const double* rhs, double* u, double tol, void* stream,
+                    int* slot) {
+  API_BEGIN
+  if (!b || !slot) return set_err(IGAMG_EINVAL, "null argument");
+  *slot = batch_add(*b, h, rhs, u, tol, static_cast<hipStream_t>(stream));
+  return IGAMG_OK;
+  API_END
+}
+
+int igamg_batch_step(igamg_batch b, void* stream, int* n_active) {
+  API_BEGIN
+  if (!b) return set_err(IGAMG_EINVAL, "null batch");
+  const int a = batch_step(*b, static_cast<hipStream_t>(stream));
+  if (n_active) *n_active = a;
+  return IGAMG_OK;
+  API_END
+}
+
+int igamg_batch_poll(igamg_batch b, int slot, int* done, igamg_solve_info* info, int* code) {
+  API_BEGIN
+  if (!b || slot < 0 || slot >= (int)b->reqs.size() || b->reqs[slot].state == RQ_FREE)
+    return set_err(IGAMG_EINVAL, "bad batch slot");
+  const Req& q = b->reqs[slot];
+  if (done) *done = (q.state == RQ_DONE);
+  fill_info(q, info);
+  if (code) *code = (q.state == RQ_DONE) ? q.code : IGAMG_OK;
+  return IGAMG_OK;
+  API_END
+}
+
+int igamg_batch_remove(igamg_batch b, int slot) {
+  API_BEGIN
+  if (!b || slot < 0 || slot >= (int)b->reqs.size()) return set_err(IGAMG_EINVAL, "bad batch slot");
+  if (b->reqs[slot].state != RQ_DONE && b->reqs[slot].state != RQ_FREE) HIP_OK(hipStreamSynchronize(b->ds));
+  b->reqs[slot] = Req{};
+  return IGAMG_OK;
+  API_END
+}
+
+int igamg_solve_batch(igamg_handle const* hs, const double* const* rhs, double* const* u, int n, double tol,
+                      igamg_solve_info* infos, int* codes, void* stream) {
+  API_BEGIN
+  if (n < 0 || (n > 0 && (!hs || !rhs || !u))) return set_err(IGAMG_EINVAL, "bad batch arguments");
+  hipStream_t st = static_cast<hipStream_t>(stream);
+  igamg_batch_ctx B;
+  std::vector<int> slots;
+  for (int i = 0; i < n; ++i) slots.push_back(batch_add(B, hs[i], rhs[i], u[i], tol, st));
+  while (batch_step(B, st) > 0) {
+  }
+  int worst = IGAMG_OK;
+  for (int i = 0; i < n; ++i) {
+    const Req& q = B.reqs[slots[i]];
+    if (infos) fill_info(q, &infos[i]);
+    if (codes) codes[i] = q.code;
+    if (q.code != IGAMG_OK) worst = q.code;
+  }
+  if (worst != IGAMG_OK) return set_err(worst, "at least one request did not converge");
+  return IGAMG_OK;
   API_END
 }
 

@@ -39,7 +39,7 @@ class Options(ctypes.Structure):
     _fields_ = [("tau", ctypes.c_double), ("sigma_scale", ctypes.c_double), ("nu", ctypes.c_int),
                 ("mu", ctypes.c_int), ("precision", ctypes.c_int), ("maxit", ctypes.c_int),
                 ("geometry_scaling", ctypes.c_int), ("inner_maxit", ctypes.c_int),
-                ("inner_tol", ctypes.c_double), ("reserved", ctypes.c_int * 6)]
+                ("inner_tol", ctypes.c_double), ("graphs", ctypes.c_int), ("reserved", ctypes.c_int * 5)]
 
 
 class SolveInfo(ctypes.Structure):
@@ -67,6 +67,14 @@ def _load():
         "igamg_export": (ctypes.c_int, [vp, ctypes.c_int, ctypes.c_int, P(ctypes.c_double), i64p, i64p]),
         "igamg_profile": (ctypes.c_int, [vp, ctypes.c_int]),
         "igamg_profile_read": (ctypes.c_int, [vp, i64p, P(ctypes.c_double), P(ctypes.c_double)]),
+        "igamg_batch_create": (ctypes.c_int, [P(vp)]),
+        "igamg_batch_destroy": (ctypes.c_int, [vp]),
+        "igamg_batch_add": (ctypes.c_int, [vp, vp, vp, vp, ctypes.c_double, vp, P(ctypes.c_int)]),
+        "igamg_batch_step": (ctypes.c_int, [vp, vp, P(ctypes.c_int)]),
+        "igamg_batch_poll": (ctypes.c_int, [vp, ctypes.c_int, P(ctypes.c_int), P(SolveInfo), P(ctypes.c_int)]),
+        "igamg_batch_remove": (ctypes.c_int, [vp, ctypes.c_int]),
+        "igamg_solve_batch": (ctypes.c_int, [P(vp), P(vp), P(vp), ctypes.c_int, ctypes.c_double, P(SolveInfo),
+                                              P(ctypes.c_int), vp]),
         "igamg_destroy": (ctypes.c_int, [vp]),
         "igamg_last_error": (ctypes.c_char_p, []),
     }
@@ -81,7 +89,8 @@ _lib = _load()
 EXPORTED = ["igamg_default_options", "igamg_workspace_size", "igamg_setup", "igamg_num_dofs",
             "igamg_load_vector", "igamg_vcycle", "igamg_solve", "igamg_operator", "igamg_dof_map",
             "igamg_export", "igamg_profile", "igamg_profile_read", "igamg_destroy",
-            "igamg_last_error"]
+            "igamg_last_error", "igamg_batch_create", "igamg_batch_destroy", "igamg_batch_add",
+            "igamg_batch_step", "igamg_batch_poll", "igamg_batch_remove", "igamg_solve_batch"]
 EXPORT_MATRIX, EXPORT_PROLONG = 0, 1
 
 
@@ -166,7 +175,7 @@ class Solver:
 
     def __del__(self):
         h = getattr(self, "h", None)
-        if h is not None and h.value:
+        if h is not None and h.value and _lib is not None:
             _lib.igamg_destroy(h)
             self.h = None
 
@@ -248,3 +257,64 @@ class Solver:
             _check(code)
         self.last_code = code
         return u, info
+
+
+class Batch:
+    """Continuous batching of resident solves (igamg_batch_*): requests are
+    added and removed between lockstep steps; every step runs one PCG
+    iteration of every active request as HIP graphs with one branch each."""
+
+    def __init__(self):
+        self.b = ctypes.c_void_p()
+        _check(_lib.igamg_batch_create(ctypes.byref(self.b)))
+        self._keep = {}
+
+    def __del__(self):
+        b = getattr(self, "b", None)
+        if b is not None and b.value and _lib is not None:
+            _lib.igamg_batch_destroy(b)
+            self.b = None
+
+    def add(self, solver, rhs, u=None, tol=1e-8, stream=None):
+        import torch
+        rhs = solver._vec(rhs, solver.N)
+        if u is None:
+            u = torch.empty_like(rhs)
+        slot = ctypes.c_int()
+        _check(_lib.igamg_batch_add(self.b, solver.h, _dptr(rhs), _dptr(u), tol, _stream_ptr(stream),
+                                    ctypes.byref(slot)))
+        self._keep[slot.value] = (solver, rhs, u)
+        return slot.value
+
+    def step(self, stream=None):
+        n = ctypes.c_int()
+        _check(_lib.igamg_batch_step(self.b, _stream_ptr(stream), ctypes.byref(n)))
+        return n.value
+
+    def poll(self, slot):
+        done, code = ctypes.c_int(), ctypes.c_int()
+        info = SolveInfo()
+        _check(_lib.igamg_batch_poll(self.b, slot, ctypes.byref(done), ctypes.byref(info), ctypes.byref(code)))
+        return bool(done.value), info, code.value
+
+    def result(self, slot):
+        return self._keep[slot][2]
+
+    def remove(self, slot):
+        _check(_lib.igamg_batch_remove(self.b, slot))
+        self._keep.pop(slot, None)
+
+
+def solve_batch(solvers, rhss, tol=1e-8, stream=None):
+    """Solve several resident problems to completion in one batch."""
+    import torch
+    n = len(solvers)
+    rh = [s._vec(r, s.N) for s, r in zip(solvers, rhss)]
+    us = [torch.empty_like(r) for r in rh]
+    H = (ctypes.c_void_p * n)(*[s.h.value for s in solvers])
+    R = (ctypes.c_void_p * n)(*[r.data_ptr() for r in rh])
+    U = (ctypes.c_void_p * n)(*[u.data_ptr() for u in us])
+    infos = (SolveInfo * n)()
+    codes = (ctypes.c_int * n)()
+    code = _lib.igamg_solve_batch(H, R, U, n, tol, infos, codes, _stream_ptr(stream))
+    return us, list(infos), list(codes), code
