@@ -5,11 +5,13 @@ percentiles, the roofline of the banded stiffness apply and the FP64 oracle
 timed on the host.
 
     python bench.py [--gpus 1] [--steps K] [--warmup W] [--workload NAME]
-                    [--precision both|fp64|mixed] [--no-cpu-baseline]
+                    [--precision both|fp64|mixed] [--no-cpu-baseline] [--no-serve]
 
 A step is one complete solve of the workload from u = 0 to ||f - A u|| <= 1e-8
 ||f|| (setup excluded; inputs resident in HBM).  Prints one JSON line; `value`
-is the mixed-precision rate when both precisions run.
+is the mixed-precision rate when both precisions run.  The `serving` object
+reports continuous-batching throughput and p50/p99 latency over a seeded mix of
+resident problems (see paper_1804_02539_amd/serve.py).
 """
 import argparse
 import hashlib
@@ -158,6 +160,49 @@ def run(workload, prob, precision, steps, warmup, dev):
     return S, res
 
 
+def serving(precision, n_requests, n_families, seed, dev):
+    """Continuous-batching serving of a seeded request mix: first every request
+    at once with the hierarchies resident (saturated throughput), then the same
+    number of fresh requests arriving as a Poisson process at 0.7x that rate
+    (latency percentiles).  Setup runs once, before both timed phases."""
+    import torch
+    from paper_1804_02539_amd import igamg, serve
+    opts = igamg.default_options(precision=igamg.MIXED if precision == "mixed" else igamg.FP64)
+    free, total = torch.cuda.mem_get_info()
+    budget = int(0.75 * free)
+    S = serve.Server(budget, opts=opts, device=dev, handles_per_key=2, keep_results=False)
+    fams, _ = serve.request_mix(0, seed=seed, n_families=n_families)
+    warm = [serve.Request(f, lambda n: np.ones(n)) for f in fams for _ in range(2)]
+    t0 = time.perf_counter()
+    S.run([(0.0, r) for r in warm])              # builds two resident hierarchies per family
+    setup_s = time.perf_counter() - t0
+    burst = serve.requests_for(fams, n_requests, seed + 100)
+    S.finished.clear()
+    S.steps = 0
+    t_sat = S.run([(0.0, r) for r in burst])
+    sat = S.stats(t_sat)
+    rate = 0.7 * sat["requests_per_s"]
+    pois = serve.requests_for(fams, n_requests, seed + 200)
+    S.finished.clear()
+    S.steps = 0
+    offs = serve.poisson_offsets(n_requests, rate, seed=seed)
+    t_p = S.run([(float(o), r) for o, r in zip(offs, pois)])
+    lat = S.stats(t_p)
+    S.close()
+    sizes = sorted(f_n for f_n in {r.n for r in burst + pois})
+    return {"requests": n_requests, "families": n_families, "precision": precision,
+            "family_sizes_free_dofs": [int(sizes[0]), int(sizes[-1])],
+            "hbm_budget_bytes": budget, "resident_bytes": S.used, "setup_s": setup_s,
+            "saturated": {"requests_per_s": sat["requests_per_s"], "dofs_per_s": sat["dofs_per_s"],
+                          "makespan_s": sat["makespan_s"], "steps": sat["steps"],
+                          "latency_ms": sat["latency_ms"]},
+            "poisson": {"arrival_rate_per_s": rate, "requests_per_s": lat["requests_per_s"],
+                        "dofs_per_s": lat["dofs_per_s"], "latency_ms": lat["latency_ms"],
+                        "steps": lat["steps"], "failed": lat["failed"] + sat["failed"]},
+            "description": "seeded mix of 2D/3D multi-patch problems, p in 2..6, N log-uniform in "
+                           "[1e4, 3e5] free dofs per family, fresh U[-1,1] rhs per request"}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -166,6 +211,9 @@ def main():
     ap.add_argument("--workload", default="square4x4_p4", choices=sorted(WORKLOADS))
     ap.add_argument("--precision", default="both", choices=["both", "fp64", "mixed"])
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-serve", action="store_true")
+    ap.add_argument("--serve-requests", type=int, default=96)
+    ap.add_argument("--serve-families", type=int, default=12)
     a = ap.parse_args()
     if a.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print("bench.py measures one GPU only: this build has no multi-GPU path "
@@ -210,6 +258,9 @@ def main():
         out[k]["band_avg_launch_us"] = v["roofline"]["avg_launch_us"]
     if "fp64" in runs and "mixed" in runs:
         out["speedup_mixed_vs_fp64"] = runs["mixed"]["value"] / runs["fp64"]["value"]
+    if not a.no_serve:
+        out["serving"] = serving("mixed" if head == "mixed" else "fp64", a.serve_requests,
+                                 a.serve_families, 5, dev)
     if not a.no_cpu_baseline:
         from paper_1804_02539_amd import igamg  # noqa: F401
         out["cpu_baseline"] = cpu_baseline(prob, rhs_for(prob, S))

@@ -146,12 +146,14 @@ int igamg_solve(igamg_handle h, const double* rhs, double* u, double tol, igamg_
                 void* stream);
 
 /* Batched solves (continuous batching).  A batch steps any number of resident
- * solves in lockstep: each step is one PCG iteration of every active request,
- * replayed as two HIP graphs in which every request is an independent branch
- * (its kernels overlap with the other requests' on the device).  Requests may
+ * solves in lockstep: each step is one PCG iteration of every active request.
+ * Each handle captures the two halves of its PCG iteration as HIP graphs once
+ * (they stay with the handle until igamg_destroy) and the batch replays them,
+ * one branch stream per request, so the requests' kernels overlap on the
+ * device and requests joining or leaving cost no new capture.  Requests may
  * be added and removed between steps; mixed-precision requests run their FP64
- * refinement steps between inner solves.  A batch owns HIP streams, events and
- * graphs (no device memory); one host thread drives it.
+ * refinement steps between inner solves.  A batch owns HIP streams and events
+ * (no device memory); one host thread drives it.
  *   igamg_batch_add     starts the solve of A u = rhs on handle h (device vectors
  *                       of length n_free; no other solve may use h meanwhile);
  *                       returns the request's slot id in *slot

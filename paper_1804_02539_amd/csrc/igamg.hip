@@ -5,9 +5,7 @@
 // sequences launches on the caller's stream.
 #include <hip/hip_runtime.h>
 
-#include <atomic>
 #include <chrono>
-#include <map>
 #include <cmath>
 #include <cstdio>
 #include <cstdlib>
@@ -117,11 +115,7 @@ struct igamg_ctx {
   void* ws = nullptr;
   size_t bytes = 0;
   struct igamg_batch_ctx* solo = nullptr;   // driver of igamg_solve
-  uint64_t uid = next_uid();                 // identity in graph caches (never reused)
-  static uint64_t next_uid() {
-    static std::atomic<uint64_t> n{1};
-    return n++;
-  }
+  hipGraphExec_t gx[2] = {nullptr, nullptr}; // PCG bodies A and B of this hierarchy as graphs
 };
 
 template <typename T>
@@ -496,12 +490,7 @@ struct igamg_batch_ctx {
   std::vector<hipEvent_t> ev_join;
   hipEvent_t ev_fork = nullptr, ev_in = nullptr;
   std::vector<Req> reqs;
-  struct Graph {
-    hipGraphExec_t ex = nullptr;
-  };
-  std::map<std::vector<uintptr_t>, Graph> cache;
   ~igamg_batch_ctx() {
-    for (auto& kv : cache) (void)hipGraphExecDestroy(kv.second.ex);
     for (auto e : ev_join) (void)hipEventDestroy(e);
     for (auto s : br) (void)hipStreamDestroy(s);
     if (ev_fork) (void)hipEventDestroy(ev_fork);
@@ -547,6 +536,22 @@ static void body(Req& q, int which, hipStream_t st) {
   }
 }
 
+// The PCG bodies of one hierarchy, captured once as graphs.  A body touches
+// only its own hierarchy's memory, so the same graph serves every batch the
+// hierarchy ever joins, whatever the other members are.
+static hipGraphExec_t request_graph(igamg_batch_ctx& B, Req& q, int which) {
+  igamg_ctx& C = *q.C;
+  if (!C.gx[which]) {
+    hipGraph_t g = nullptr;
+    HIP_OK(hipStreamBeginCapture(B.ds, hipStreamCaptureModeThreadLocal));
+    body(q, which, B.ds);
+    HIP_OK(hipStreamEndCapture(B.ds, &g));
+    HIP_OK(hipGraphInstantiate(&C.gx[which], g, nullptr, nullptr, 0));
+    HIP_OK(hipGraphDestroy(g));
+  }
+  return C.gx[which];
+}
+
 // run body `which` for the requests in `set` on the driver stream
 static void run_bodies(igamg_batch_ctx& B, const std::vector<int>& set, int which) {
   if (set.empty()) return;
@@ -554,35 +559,22 @@ static void run_bodies(igamg_batch_ctx& B, const std::vector<int>& set, int whic
     for (int i : set) body(B.reqs[i], which, B.ds);
     return;
   }
-  std::vector<uintptr_t> key{(uintptr_t)which};
-  for (int i : set) {
-    key.push_back((uintptr_t)i);
-    key.push_back((uintptr_t)B.reqs[i].C->uid);
+  // one graph per hierarchy, each on a branch stream of its own: requests
+  // joining or leaving the batch cost no capture
+  std::vector<hipGraphExec_t> gs;
+  for (int i : set) gs.push_back(request_graph(B, B.reqs[i], which));
+  if (gs.size() == 1) {
+    HIP_OK(hipGraphLaunch(gs[0], B.ds));
+    return;
   }
-  auto it = B.cache.find(key);
-  if (it == B.cache.end()) {
-    batch_branches(B, set.size());
-    if (B.cache.size() > 64) {
-      sync_driver(B);
-      for (auto& kv : B.cache) (void)hipGraphExecDestroy(kv.second.ex);
-      B.cache.clear();
-    }
-    igamg_batch_ctx::Graph G;
-    hipGraph_t g = nullptr;
-    HIP_OK(hipStreamBeginCapture(B.ds, hipStreamCaptureModeThreadLocal));
-    HIP_OK(hipEventRecord(B.ev_fork, B.ds));
-    for (size_t k = 0; k < set.size(); ++k) {
-      HIP_OK(hipStreamWaitEvent(B.br[k], B.ev_fork, 0));
-      body(B.reqs[set[k]], which, B.br[k]);
-      HIP_OK(hipEventRecord(B.ev_join[k], B.br[k]));
-      HIP_OK(hipStreamWaitEvent(B.ds, B.ev_join[k], 0));
-    }
-    HIP_OK(hipStreamEndCapture(B.ds, &g));
-    HIP_OK(hipGraphInstantiate(&G.ex, g, nullptr, nullptr, 0));
-    HIP_OK(hipGraphDestroy(g));
-    it = B.cache.emplace(key, std::move(G)).first;
+  batch_branches(B, gs.size());
+  HIP_OK(hipEventRecord(B.ev_fork, B.ds));
+  for (size_t k = 0; k < gs.size(); ++k) {
+    HIP_OK(hipStreamWaitEvent(B.br[k], B.ev_fork, 0));
+    HIP_OK(hipGraphLaunch(gs[k], B.br[k]));
+    HIP_OK(hipEventRecord(B.ev_join[k], B.br[k]));
+    HIP_OK(hipStreamWaitEvent(B.ds, B.ev_join[k], 0));
   }
-  HIP_OK(hipGraphLaunch(it->second.ex, B.ds));
 }
 
 static void rq_finish(Req& q, int code, hipStream_t st) {
@@ -905,7 +897,12 @@ int igamg_profile_read(igamg_handle h, int64_t* launches, double* ms, double* by
 
 int igamg_destroy(igamg_handle h) {
   if (!h) return IGAMG_OK;
+  // the handle's own streams drain before its graphs and events go away; work
+  // that a caller's batch queued must have finished (igamg_batch_remove)
+  if (h->solo && h->solo->ds) (void)hipStreamSynchronize(h->solo->ds);
   delete h->solo;
+  for (hipGraphExec_t g : h->gx)
+    if (g) (void)hipGraphExecDestroy(g);
   for (hipEvent_t e : h->pool) (void)hipEventDestroy(e);
   if (h->host_scal) (void)hipHostFree(h->host_scal);
   delete h;

@@ -223,3 +223,51 @@ CONFIGS = {
     "square4x4_p4": lambda: square_4x4_bezier(),
     "cube2x2x2_p3": lambda: cube_2x2x2_trilinear(),
 }
+
+
+def serving_families(n_families, seed=5, n_min=1e4, n_max=3e5, band_bytes_max=1.5e9, n0_max=2500):
+    """Seeded problem families for the serving workload.
+
+    Each family draws d in {2, 3} and p in {2..6} uniformly, a patch grid of
+    2..4 patches per direction, and a target size N log-uniform in
+    [n_min, n_max]; the coarsest element count (1..3 per patch and direction)
+    and the level count are the pair whose finest size is closest to the target,
+    subject to the FP64 band of the finest level staying under band_bytes_max,
+    the coarsest level having at most n0_max unknowns (its dense Cholesky
+    factorisation runs on the host) and every patch having at most 84
+    interior functions per direction.
+    2D families are biquadratic grids with seeded interior control points
+    (Dirichlet on x=0 and y=0), 3D ones trilinear grids with every interior
+    macro vertex moved by up to 10% of the patch width (full Dirichlet).
+    """
+    rng = np.random.default_rng(seed)
+    fams = []
+    for j in range(n_families):
+        best = None
+        while best is None:       # redraw families that no size choice admits
+            d = int(rng.integers(2, 4))
+            p = int(rng.integers(2, 7))
+            npp = [int(rng.integers(2, 5)) for _ in range(d)]
+            target = float(np.exp(rng.uniform(np.log(n_min), np.log(n_max))))
+            for nel0 in (1, 2, 3):
+                for levels in range(2, 11):
+                    nel = nel0 * 2 ** (levels - 1)
+                    rows = int(np.prod([k * (nel + p) for k in npp]))
+                    n_est = float(np.prod([k * (nel + p - 1) + 1 for k in npp]))
+                    n0 = float(np.prod([k * (nel0 + p - 1) + 1 for k in npp]))
+                    if rows * (2 * p + 1) ** d * 8 > band_bytes_max or n0 > n0_max or nel + p - 2 > 84:
+                        continue
+                    score = abs(np.log(n_est / target))
+                    if best is None or score < best[0]:
+                        best = (score, nel0, levels)
+        _, nel0, levels = best
+        name = f"fam{j}_d{d}_p{p}_{'x'.join(map(str, npp))}_e{nel0}_L{levels}"
+        if d == 2:
+            prob = box_grid(2, npp, p, nel0, levels, gdeg=2, dirichlet_sides=[0, 2], name=name)
+            perturb_centres_2d(prob, 0.1, rng)
+        else:
+            prob = box_grid(3, npp, p, nel0, levels, gdeg=1, name=name)
+            perturb_interior_vertices_3d(prob, 0.1, rng)
+        prob.meta["target_n"] = target
+        fams.append(prob)
+    return fams

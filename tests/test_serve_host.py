@@ -1,0 +1,155 @@
+"""Host-side tests of the serving scheduler (admission, residency, eviction,
+rejection) with a fake backend: no GPU and no kernels involved."""
+import time
+
+import numpy as np
+import pytest
+
+from paper_1804_02539_amd import serve
+from paper_1804_02539_amd import workloads as W
+
+
+class FakeSolver:
+    def __init__(self, prob):
+        self.prob = prob
+        self.N = int(prob.meta["n"])
+
+
+class FakeBatch:
+    """Finishes a request after a number of steps that depends on its size."""
+
+    def __init__(self):
+        self.slots = {}
+        self.active_hist = []
+
+    def add(self, solver, rhs, tol=1e-8):
+        slot = max(self.slots, default=-1) + 1
+        self.slots[slot] = [solver, rhs, 3 + solver.N % 5]
+        return slot
+
+    def step(self):
+        act = [s for s in self.slots.values() if s[2] > 0]
+        self.active_hist.append(len(act))
+        for s in act:
+            s[2] -= 1
+
+    def poll(self, slot):
+        done = self.slots[slot][2] <= 0
+        return done, None, 0
+
+    def result(self, slot):
+        return self.slots[slot][1]
+
+    def remove(self, slot):
+        del self.slots[slot]
+
+
+def _fake_prob(i, n, nbytes):
+    p = W.box_grid(2, [2, 2], 2, 1, 2, name=f"p{i}")
+    p.geo_ctrl[0] = p.geo_ctrl[0] + 1e-3 * i     # distinct geometry per family
+    p.meta.update(n=n, nbytes=nbytes)
+    return p
+
+
+def _server(budget, **kw):
+    return serve.Server(budget, device="cpu", make_solver=FakeSolver,
+                        workspace_bytes=lambda prob: prob.meta["nbytes"], batch=FakeBatch(), **kw)
+
+
+def test_problem_key_tracks_geometry_and_size():
+    a = _fake_prob(0, 10, 1)
+    b = _fake_prob(1, 10, 1)
+    assert serve.problem_key(a) == serve.problem_key(_fake_prob(0, 10, 1))
+    assert serve.problem_key(a) != serve.problem_key(b)
+    c = _fake_prob(0, 10, 1)
+    c.levels += 1
+    assert serve.problem_key(a) != serve.problem_key(c)
+
+
+def test_admission_respects_budget_and_evicts_lru():
+    fams = [_fake_prob(i, 100 + i, 40) for i in range(6)]
+    rng = np.random.default_rng(0)
+    S = _server(100, handles_per_key=1)
+    reqs = [S.submit(serve.Request(fams[int(rng.integers(0, 6))], lambda n: np.zeros(n))) for _ in range(40)]
+    S.run(timeout=30)
+    S.close()
+    st = S.stats(1.0)
+    assert st["requests"] == 40 and st["rejected"] == 0
+    assert S.peak_used <= 100                      # never more than two 40-byte hierarchies
+    assert st["evictions"] > 0
+    assert all(r.done is not None and r.done >= r.admitted >= r.arrival for r in reqs)
+    # every result is the request's own right-hand side (no cross-talk)
+    assert all(r.result.shape[0] == r.n == r.problem.meta["n"] for r in reqs)
+
+
+def test_requests_of_one_family_share_a_resident_hierarchy():
+    fam = _fake_prob(0, 50, 10)
+    S = _server(1000, handles_per_key=2)
+    for _ in range(12):
+        S.submit(serve.Request(fam, lambda n: np.zeros(n)))
+    S.run(timeout=30)
+    S.close()
+    assert len(S.handles[serve.problem_key(fam)]) <= 2
+    assert sum(1 for e in S.events if e[1] == "resident") <= 2
+    assert len(S.finished) == 12
+
+
+def test_oversized_request_is_rejected_not_admitted():
+    big = _fake_prob(0, 10, 500)
+    small = _fake_prob(1, 10, 50)
+    S = _server(100)
+    rb = S.submit(serve.Request(big, lambda n: np.zeros(n)))
+    rs = S.submit(serve.Request(small, lambda n: np.zeros(n)))
+    S.run(timeout=30)
+    S.close()
+    assert rb in S.rejected and rb.error is not None
+    assert rs in S.finished and S.peak_used <= 100
+
+
+def test_failed_setup_releases_its_reservation():
+    ok = _fake_prob(0, 10, 60)
+    bad = _fake_prob(1, 10, 60)
+    bad.meta["fail"] = True
+
+    def make(prob):
+        if prob.meta.get("fail"):
+            raise RuntimeError("setup failed")
+        return FakeSolver(prob)
+
+    S = serve.Server(100, device="cpu", make_solver=make, workspace_bytes=lambda p: p.meta["nbytes"],
+                     batch=FakeBatch())
+    r1 = S.submit(serve.Request(bad, lambda n: np.zeros(n)))
+    r2 = S.submit(serve.Request(ok, lambda n: np.zeros(n)))
+    S.run(timeout=30)
+    S.close()
+    assert r1 in S.rejected and r2 in S.finished
+    assert S.used == 60
+
+
+def test_timed_arrivals_and_continuous_batching():
+    fams = [_fake_prob(i, 20 + i, 5) for i in range(3)]
+    S = _server(1000, handles_per_key=4)
+    offs = serve.poisson_offsets(20, rate=2000.0, seed=1)
+    arr = [(float(o), serve.Request(fams[i % 3], lambda n: np.zeros(n))) for i, o in enumerate(offs)]
+    t = S.run(arrivals=arr, timeout=30)
+    S.close()
+    st = S.stats(t)
+    assert st["requests"] == 20
+    assert st["latency_ms"]["p99"] >= st["latency_ms"]["p50"] > 0
+    # more than one request was stepped together at some point
+    assert max(S.batch.active_hist) > 1
+
+
+def test_serving_families_respect_their_limits():
+    fams = W.serving_families(16, seed=5)
+    assert len(fams) == 16
+    assert {f.dim for f in fams} == {2, 3}
+    for f in fams:
+        p = f.degree
+        nel = f.nel(f.levels - 1)
+        assert 2 <= p <= 6
+        assert int(nel.max()) + p - 2 <= 84
+        rows = sum(int(np.prod(n + p)) for n in nel)
+        assert rows * (2 * p + 1) ** f.dim * 8 <= 1.5e9
+    # the family draw is seeded
+    assert [f.name for f in fams] == [f.name for f in W.serving_families(16, seed=5)]
