@@ -215,7 +215,8 @@ int igamg_export(igamg_handle h, int what, int level, double* out, int64_t* rows
  * recording, solves launch their kernels directly instead of replaying HIP
  * graphs (HIP does not time events recorded into graphs).
  * igamg_profile_read synchronises the stream of the last recorded launch and
- * returns, per level l, the launch count, the summed kernel time in ms and the
+ * returns, per level l, the launch count, the summed kernel time in ms (timing
+ * events attached to each dispatch, so the time is the kernel's own) and the
  * algorithmic bytes moved (rows * s ((2p+1)^d + vectors), s = 8 or 4 bytes);
  * arrays have 2*levels entries: [l] for FP64 launches, [levels + l] for FP32
  * launches of a mixed-precision handle.  Then it clears the record.          */

@@ -261,7 +261,7 @@ static void band_op(igamg_ctx& C, int l, const T* u, const T* f, T* r, bool resi
   DevLevel& D = C.dl[l];
   const T* band = dat<T>(D).band;
   if (!C.prof) {
-    launch_band<T>(C.d, C.p, band, u, f, r, D.bpatch, D.pd, D.NL, resid, st);
+    HIP_OK(launch_band<T>(C.d, C.p, band, u, f, r, D.bpatch, D.pd, D.NL, resid, st));
     return;
   }
   igamg_ctx::Rec rc;
@@ -269,9 +269,7 @@ static void band_op(igamg_ctx& C, int l, const T* u, const T* f, T* r, bool resi
   rc.bytes = (double)D.rows * sizeof(T) * ((double)D.nb + (resid ? 3 : 2));
   rc.a = next_event(C);
   rc.b = next_event(C);
-  HIP_OK(hipEventRecord(rc.a, st));
-  launch_band<T>(C.d, C.p, band, u, f, r, D.bpatch, D.pd, D.NL, resid, st);
-  HIP_OK(hipEventRecord(rc.b, st));
+  HIP_OK(launch_band<T>(C.d, C.p, band, u, f, r, D.bpatch, D.pd, D.NL, resid, st, rc.a, rc.b));
   C.recs.push_back(rc);
   C.prof_stream = st;
 }
@@ -283,7 +281,7 @@ template <typename T>
 static void smoother_apply(igamg_ctx& C, int l, const T* src, T* u, bool add, double tau, hipStream_t st) {
   DevLevel& D = C.dl[l];
   LevelData<T>& X = dat<T>(D);
-  const size_t lds = std::max(fd_slab_lds(D.fd_maxm, sizeof(T)), (size_t)D.max_dense * sizeof(T) + 64);
+  const size_t lds = std::max(fd_slab_lds(D.fd_maxm, sizeof(T)), fd_dense_lds(D.max_dense, sizeof(T)));
   launch_fd_fwd<T>(D.fd, D.nfd, D.ndense, D.slab_grid, lds, D.dense, X.densemat, X.fdmat, src, u, D.if_ptr, D.if_idx,
                    X.scr, tau, add, st);
   if (C.d == 3 && D.nfd_int > 0 && D.max_m2 > 1)

@@ -7,6 +7,7 @@
 // solver and the outer refinement residual, float for the inner solve of the
 // mixed-precision solver (reductions always accumulate in double).
 #include <hip/hip_runtime.h>
+#include <hip/hip_ext.h>
 
 #include <algorithm>
 
@@ -23,78 +24,89 @@ namespace igamg {
 // banded stiffness apply: r = f - A u  (RESID) or r = A u   (Sec. 4: A_{l,k}
 // applied patch by patch to accumulated u gives a distributed result).
 // The band is tiled: the (2P+1)^D planes of each 256-row block are contiguous.
+// A workgroup takes a strip of 64 rows (one row per lane); its 4 waves split
+// the stencil lines (o1, o2) between them and add their partial sums in LDS,
+// so a launch has 4 x (rows / 256) x 4 waves to hide HBM latency with.  Each
+// wave reads every band plane of its lines as one coalesced 64-entry segment.
 // ---------------------------------------------------------------------------
+constexpr int BAND_STRIP = 64;
+
 template <int D, int P, bool RESID, typename TB, typename TV>
 __global__ __launch_bounds__(256) void k_band(const TB* __restrict__ band, const TV* __restrict__ u,
                                               const TV* __restrict__ f, TV* __restrict__ r,
                                               const int* __restrict__ bpatch, const PatchDev* __restrict__ pd) {
   constexpr int NB = 2 * P + 1;
-  constexpr int NBT = (D == 2) ? NB * NB : NB * NB * NB;
-  const int b = blockIdx.x;
-  const int k = bpatch[b];
-  if (k < 0) return;
+  constexpr int NLINE = (D == 2) ? NB : NB * NB;        // stencil lines (o1, o2)
+  constexpr int NBT = NLINE * NB;
+  __shared__ TV part[3][BAND_STRIP];
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+  const int64_t g = (int64_t)blockIdx.x * BAND_STRIP + lane;
+  const int64_t tile = g / ROW_ALIGN;                    // the same for the whole workgroup
+  const int k = bpatch[tile];
+  if (k < 0) return;                                     // uniform: a padding tile
   const int64_t off = pd[k].off;
   const int64_t rows = pd[k].rows;
-  const int64_t g = (int64_t)b * ROW_ALIGN + threadIdx.x;
-  const int64_t rl = g - off;
-  if (rl >= rows) return;
+  const int64_t rl0 = g - off;
+  const bool valid = rl0 < rows;
+  const int64_t rl = valid ? rl0 : rows - 1;             // padding lanes compute a real row, never store
   const int n0 = pd[k].n[0], n1 = pd[k].n[1], n2 = pd[k].n[2];
   const int i0 = (int)(rl % n0);
   const int64_t t = rl / n0;
   const int i1 = (int)(t % n1);
   const int i2 = (int)(t / n1);
-  int c0[NB], c1[NB];
+  int c0[NB];
 #pragma unroll
-  for (int o = 0; o < NB; ++o) {
-    c0[o] = min(max(i0 + o - P, 0), n0 - 1);
-    c1[o] = min(max(i1 + o - P, 0), n1 - 1) * n0;
-  }
+  for (int o = 0; o < NB; ++o) c0[o] = min(max(i0 + o - P, 0), n0 - 1);
   const TV* ub = u + off;
-  const TB* bp = band + (int64_t)b * NBT * ROW_ALIGN + threadIdx.x;
+  const TB* bp = band + tile * NBT * ROW_ALIGN + (g - tile * ROW_ALIGN);
+  const int64_t pl = (int64_t)n0 * n1;
   TV s = 0;
-  if constexpr (D == 2) {
+  for (int L = w; L < NLINE; L += 4) {
+    const int o1 = L % NB, o2 = L / NB;
+    int64_t base = (int64_t)min(max(i1 + o1 - P, 0), n1 - 1) * n0;
+    if constexpr (D == 3) base += (int64_t)min(max(i2 + o2 - P, 0), n2 - 1) * pl;
+    const TV* ur = ub + base;
+    const TB* bq = bp + (int64_t)L * NB * ROW_ALIGN;
 #pragma unroll
-    for (int o1 = 0; o1 < NB; ++o1) {
-      const TV* ur = ub + c1[o1];
-#pragma unroll
-      for (int o0 = 0; o0 < NB; ++o0) s += (TV)bp[(o0 + NB * o1) * ROW_ALIGN] * ur[c0[o0]];
-    }
-  } else {
-    const int64_t pl = (int64_t)n0 * n1;
-    for (int o2 = 0; o2 < NB; ++o2) {
-      const int64_t z = (int64_t)min(max(i2 + o2 - P, 0), n2 - 1) * pl;
-#pragma unroll
-      for (int o1 = 0; o1 < NB; ++o1) {
-        const TV* ur = ub + z + c1[o1];
-        const TB* bq = bp + (NB * (o1 + NB * o2)) * ROW_ALIGN;
-#pragma unroll
-        for (int o0 = 0; o0 < NB; ++o0) s += (TV)bq[o0 * ROW_ALIGN] * ur[c0[o0]];
-      }
-    }
+    for (int o0 = 0; o0 < NB; ++o0) s += (TV)bq[o0 * ROW_ALIGN] * ur[c0[o0]];
   }
-  if constexpr (RESID) r[g] = f[g] - s; else r[g] = s;
+  if (w > 0) part[w - 1][lane] = s;
+  __syncthreads();
+  if (w == 0 && valid) {
+    s += part[0][lane] + part[1][lane] + part[2][lane];
+    if constexpr (RESID) r[g] = f[g] - s; else r[g] = s;
+  }
 }
 
 template <int D, int P, typename T>
-static void launch_band_dp(const T* band, const T* u, const T* f, T* r, const int* bpatch, const PatchDev* pd,
-                           int64_t NL, bool resid, hipStream_t st) {
-  dim3 grid((unsigned)(NL / ROW_ALIGN)), block(ROW_ALIGN);
+static hipError_t launch_band_dp(const T* band, const T* u, const T* f, T* r, const int* bpatch, const PatchDev* pd,
+                                 int64_t NL, bool resid, hipStream_t st, hipEvent_t ev0, hipEvent_t ev1) {
+  dim3 grid((unsigned)(NL / BAND_STRIP)), block(256);
+  const void* fn = resid ? reinterpret_cast<const void*>(&k_band<D, P, true, T, T>)
+                         : reinterpret_cast<const void*>(&k_band<D, P, false, T, T>);
+  if (ev0) {
+    // timed launch: the events take the dispatch's own start and end stamps
+    void* args[] = {(void*)&band, (void*)&u, (void*)&f, (void*)&r, (void*)&bpatch, (void*)&pd};
+    return hipExtLaunchKernel(fn, grid, block, args, 0, st, ev0, ev1, 0);
+  }
   if (resid)
     hipLaunchKernelGGL((k_band<D, P, true, T, T>), grid, block, 0, st, band, u, f, r, bpatch, pd);
   else
     hipLaunchKernelGGL((k_band<D, P, false, T, T>), grid, block, 0, st, band, u, f, r, bpatch, pd);
+  return hipSuccess;
 }
 
 template <typename T>
-void launch_band(int d, int p, const T* band, const T* u, const T* f, T* r, const int* bpatch, const PatchDev* pd,
-                 int64_t NL, bool resid, hipStream_t st) {
+hipError_t launch_band(int d, int p, const T* band, const T* u, const T* f, T* r, const int* bpatch,
+                       const PatchDev* pd, int64_t NL, bool resid, hipStream_t st, hipEvent_t ev0, hipEvent_t ev1) {
 #define IGAMG_BAND_CASE(DD, PP) \
-  if (d == DD && p == PP) return launch_band_dp<DD, PP, T>(band, u, f, r, bpatch, pd, NL, resid, st);
+  if (d == DD && p == PP) return launch_band_dp<DD, PP, T>(band, u, f, r, bpatch, pd, NL, resid, st, ev0, ev1);
   IGAMG_BAND_CASE(2, 1) IGAMG_BAND_CASE(2, 2) IGAMG_BAND_CASE(2, 3) IGAMG_BAND_CASE(2, 4)
   IGAMG_BAND_CASE(2, 5) IGAMG_BAND_CASE(2, 6) IGAMG_BAND_CASE(2, 7) IGAMG_BAND_CASE(2, 8)
   IGAMG_BAND_CASE(3, 1) IGAMG_BAND_CASE(3, 2) IGAMG_BAND_CASE(3, 3) IGAMG_BAND_CASE(3, 4)
   IGAMG_BAND_CASE(3, 5) IGAMG_BAND_CASE(3, 6) IGAMG_BAND_CASE(3, 7) IGAMG_BAND_CASE(3, 8)
 #undef IGAMG_BAND_CASE
+  return hipErrorInvalidValue;
 }
 
 // ---------------------------------------------------------------------------
@@ -109,12 +121,52 @@ void launch_band(int d, int p, const T* band, const T* u, const T* f, T* r, cons
 // add tau z to every copy; interiors use the patch-local vectors directly.
 // ---------------------------------------------------------------------------
 constexpr int FD_RB = 8;
+// columns of a chunk per thread: a 256-thread block has 256 / m0 >= 3 row
+// groups for m0 <= MAX_FD, so 8 columns need at most 3 per thread
+constexpr int FD_RPT = 3;
+static_assert(256 / MAX_FD >= 3 && (FD_RB + 2) / 3 <= FD_RPT, "chunk columns per thread");
 
-__device__ __forceinline__ void fd_chunk(const FDItem& it, int& z, int& r0, int& nr) {
-  const int nch = (it.m[0] + FD_RB - 1) / FD_RB;
+// A chunk is FD_RB columns (second tensor index) of one z-slab, so that the
+// results of a chunk are whole columns, contiguous in memory.
+__device__ __forceinline__ void fd_chunk(const FDItem& it, int& z, int& c0, int& nc) {
+  const int nch = (it.m[1] + FD_RB - 1) / FD_RB;
   z = blockIdx.x / nch;
-  r0 = (blockIdx.x - z * nch) * FD_RB;
-  nr = min(FD_RB, it.m[0] - r0);
+  c0 = (blockIdx.x - z * nch) * FD_RB;
+  nc = min(FD_RB, it.m[1] - c0);
+}
+
+// Thread (j, g) of a block: row j of the tensor, columns g*cpg .. of the chunk.
+struct FdLanes {
+  int j, a0, na;
+  bool act;
+  __device__ FdLanes(int m0, int nc) {
+    const int G = blockDim.x / m0;
+    const int cpg = (nc + G - 1) / G;
+    const int g = threadIdx.x / m0;
+    j = threadIdx.x - g * m0;
+    a0 = g * cpg;
+    act = g < G && a0 < nc;
+    na = act ? min(cpg, nc - a0) : 0;
+  }
+};
+
+// acc[i] = sum_b A[j + m0 b] C[b * FD_RB + c_i]  (A column-major m0 x k, C: k x FD_RB)
+template <typename T>
+__device__ __forceinline__ void fd_rows_times_chunk(const T* A, const T* C, int m0, int k, const FdLanes& L, int nc,
+                                                    T* acc) {
+  int cc[FD_RPT];
+#pragma unroll
+  for (int i = 0; i < FD_RPT; ++i) {
+    cc[i] = min(L.a0 + i, nc - 1);
+    acc[i] = 0;
+  }
+  if (!L.act) return;
+#pragma unroll 8
+  for (int b = 0; b < k; ++b) {
+    const T x = A[L.j + m0 * b];
+#pragma unroll
+    for (int i = 0; i < FD_RPT; ++i) acc[i] += x * C[b * FD_RB + cc[i]];
+  }
 }
 
 template <typename T>
@@ -127,20 +179,26 @@ __global__ __launch_bounds__(256) void k_fd_fwd(const FDItem* __restrict__ items
   DYN_LDS(T, lds);
   const int y = blockIdx.y;
   if (y >= nitems) {
-    // dense piece: gather (Sigma), z = L^{-1} r, scatter tau z to all copies
+    // dense piece: gather (Sigma), z = L^{-1} r, scatter tau z to all copies;
+    // L^{-1} is staged in LDS with coalesced loads, then row k is thread k's
     if (blockIdx.x != 0) return;
     const DensePiece pc = dense[y - nitems];
-    T* sr = lds;
-    for (int j = threadIdx.x; j < pc.m; j += blockDim.x) {
+    const int m = pc.m;
+    T* sA = lds;             // L^{-1}, row-major m x m
+    T* sr = lds + m * m;     // gathered residual
+    const T* A = densemat + pc.Linv;
+    for (int t = threadIdx.x; t < m * m; t += blockDim.x) sA[t] = A[t];
+    for (int j = threadIdx.x; j < m; j += blockDim.x) {
       T v = 0;
       for (int64_t c = if_ptr[pc.seg + j]; c < if_ptr[pc.seg + j + 1]; ++c) v += src[if_idx[c]];
       sr[j] = v;
     }
     __syncthreads();
-    const T* A = densemat + pc.Linv;
-    for (int k = threadIdx.x; k < pc.m; k += blockDim.x) {
+    for (int k = threadIdx.x; k < m; k += blockDim.x) {
       T zz = 0;
-      for (int j = 0; j < pc.m; ++j) zz += A[(int64_t)k * pc.m + j] * sr[j];
+      const T* ar = sA + k * m;
+#pragma unroll 8
+      for (int j = 0; j < m; ++j) zz += ar[j] * sr[j];
       zz *= tau;
       for (int64_t c = if_ptr[pc.seg + k]; c < if_ptr[pc.seg + k + 1]; ++c) {
         const int64_t x = if_idx[c];
@@ -149,54 +207,58 @@ __global__ __launch_bounds__(256) void k_fd_fwd(const FDItem* __restrict__ items
     }
     return;
   }
+  // Y[:, c0 + c] = U0^T (X U1[:, c0 + c]) for the chunk's columns
   const FDItem it = items[y];
   const int m0 = it.m[0], m1 = it.m[1];
-  int z, r0, nr;
-  fd_chunk(it, z, r0, nr);
+  int z, c0, nc;
+  fd_chunk(it, z, c0, nc);
   if (z >= it.m[2]) return;
   const int n = m0 * m1;
-  T* XT = lds;       // XT[j * m1 + b] = X[j, b]
-  T* W = lds + n;    // W[a * m1 + b], a < FD_RB
+  T* X = lds;                        // X[j + m0 b]; later U0[j m0 + a]
+  T* C = lds + max(n, m0 * m0);      // U1[b, c0 + c] as C[b FD_RB + c]; later V[j FD_RB + c]
   const int64_t zoff = (int64_t)z * it.stride[2];
-  // X[j, b] is read with j fastest (coalesced) and stored transposed
+  const T* U0 = mat + it.U[0];
+  const T* U1 = mat + it.U[1];
   if (it.src_if) {
     for (int t = threadIdx.x; t < n; t += blockDim.x) {
-      const int j = t % m0, b = t / m0;
       const int64_t e = it.base + t;  // face tensors are stored j fastest
       T v = 0;
       for (int64_t c = if_ptr[e]; c < if_ptr[e + 1]; ++c) v += src[if_idx[c]];
-      XT[j * m1 + b] = v;
+      X[t] = v;
     }
   } else {
     for (int t = threadIdx.x; t < n; t += blockDim.x) {
       const int j = t % m0, b = t / m0;
-      XT[j * m1 + b] = src[it.base + j * it.stride[0] + b * it.stride[1] + zoff];
+      X[t] = src[it.base + j * it.stride[0] + b * it.stride[1] + zoff];
     }
   }
-  __syncthreads();
-  const T* U0 = mat + it.U[0];
-  const T* U1 = mat + it.U[1];
-  // W[a, b] = sum_j U0[j, r0 + a] X[j, b]
-  for (int t = threadIdx.x; t < nr * m1; t += blockDim.x) {
-    const int b = t % m1, a = t / m1;
-    T s = 0;
-    for (int j = 0; j < m0; ++j) s += U0[j * m0 + r0 + a] * XT[j * m1 + b];
-    W[a * m1 + b] = s;
+  for (int t = threadIdx.x; t < m1 * FD_RB; t += blockDim.x) {
+    const int c = t % FD_RB, b = t / FD_RB;
+    C[t] = c < nc ? U1[(int64_t)b * m1 + c0 + c] : (T)0;
   }
   __syncthreads();
-  // Y[a, k] = sum_b W[a, b] U1[b, k]   (then D^{-1} for 2D tensors)
+  const FdLanes L(m0, nc);
+  T acc[FD_RPT];
+  fd_rows_times_chunk(X, C, m0, m1, L, nc, acc);     // V[j, c] = sum_b X[j, b] U1[b, c0 + c]
+  __syncthreads();
+  for (int i = 0; i < L.na; ++i) C[L.j * FD_RB + L.a0 + i] = acc[i];
+  for (int t = threadIdx.x; t < m0 * m0; t += blockDim.x) X[t] = U0[t];
+  __syncthreads();
+  // Y[a, c] = sum_j U0[j, a] V[j, c]: row a is this thread's j; U0 is read as
+  // U0[j m0 + a] = column-major access of U0^T, hence the same helper
+  fd_rows_times_chunk(X, C, m0, m0, L, nc, acc);
+  if (!L.act) return;
   const T* mu0 = mat + it.mu[0];
   const T* mu1 = mat + it.mu[1];
   const T mu2 = mat[it.mu[2]];
   const bool full = (it.m[2] == 1);
   T* S = scr + it.scr + (int64_t)z * n;
-  for (int t = threadIdx.x; t < nr * m1; t += blockDim.x) {
-    const int k = t % m1, a = t / m1;
-    const T* w = W + a * m1;
-    T s = 0;
-    for (int b = 0; b < m1; ++b) s += w[b] * U1[b * m1 + k];
-    if (full) s /= (T)it.pref * (mu0[r0 + a] + mu1[k] + mu2 + (T)it.extra);
-    S[(r0 + a) + m0 * k] = s;
+  const int a = L.j;
+  for (int i = 0; i < L.na; ++i) {
+    const int k = c0 + L.a0 + i;
+    T v = acc[i];
+    if (full) v /= (T)it.pref * (mu0[a] + mu1[k] + mu2 + (T)it.extra);
+    S[a + m0 * k] = v;
   }
 }
 
@@ -205,48 +267,47 @@ __global__ __launch_bounds__(256) void k_fd_inv(const FDItem* __restrict__ items
                                                 T* __restrict__ u, const int64_t* __restrict__ if_ptr,
                                                 const int64_t* __restrict__ if_idx, const T* __restrict__ scr, T tau,
                                                 int add) {
+  // Z[:, c0 + c] = U0 (Y U1^T[:, c0 + c]) for the chunk's columns
   DYN_LDS(T, lds);
   const FDItem it = items[blockIdx.y];
   const int m0 = it.m[0], m1 = it.m[1];
-  int z, r0, nr;
-  fd_chunk(it, z, r0, nr);
+  int z, c0, nc;
+  fd_chunk(it, z, c0, nc);
   if (z >= it.m[2]) return;
   const int n = m0 * m1;
-  T* YT = lds;      // YT[j * m1 + b] = Y[j, b]
-  T* W = lds + n;   // W[a * m1 + b]
+  T* Y = lds;                        // Y[j + m0 b]; later U0^T[j m0 + a]
+  T* C = lds + max(n, m0 * m0);      // U1[c0 + c, b] as C[b FD_RB + c]; later V[j FD_RB + c]
   const T* S = scr + it.scr + (int64_t)z * n;
-  for (int t = threadIdx.x; t < n; t += blockDim.x) {
-    const int j = t % m0, b = t / m0;
-    YT[j * m1 + b] = S[t];
-  }
-  __syncthreads();
-  const T* U0 = mat + it.U[0];
+  const T* U0T = mat + it.U[0] + (int64_t)m0 * m0;
   const T* U1T = mat + it.U[1] + (int64_t)m1 * m1;
-  // W[a, b] = sum_j U0[r0 + a, j] Y[j, b]
-  for (int t = threadIdx.x; t < nr * m1; t += blockDim.x) {
-    const int b = t % m1, a = t / m1;
-    const T* ur = U0 + (int64_t)(r0 + a) * m0;
-    T s = 0;
-    for (int j = 0; j < m0; ++j) s += ur[j] * YT[j * m1 + b];
-    W[a * m1 + b] = s;
+  for (int t = threadIdx.x; t < n; t += blockDim.x) Y[t] = S[t];
+  for (int t = threadIdx.x; t < m1 * FD_RB; t += blockDim.x) {
+    const int c = t % FD_RB, b = t / FD_RB;
+    C[t] = c < nc ? U1T[(int64_t)b * m1 + c0 + c] : (T)0;
   }
   __syncthreads();
-  // Z[a, k] = sum_b W[a, b] U1[k, b] = sum_b W[a, b] U1T[b, k]
+  const FdLanes L(m0, nc);
+  T acc[FD_RPT];
+  fd_rows_times_chunk(Y, C, m0, m1, L, nc, acc);     // V[j, c] = sum_b Y[j, b] U1[c0 + c, b]
+  __syncthreads();
+  for (int i = 0; i < L.na; ++i) C[L.j * FD_RB + L.a0 + i] = acc[i];
+  for (int t = threadIdx.x; t < m0 * m0; t += blockDim.x) Y[t] = U0T[t];
+  __syncthreads();
+  fd_rows_times_chunk(Y, C, m0, m0, L, nc, acc);     // Z[a, c] = sum_j U0[a, j] V[j, c]
+  if (!L.act) return;
   const int64_t zoff = (int64_t)z * it.stride[2];
-  for (int t = threadIdx.x; t < nr * m1; t += blockDim.x) {
-    const int k = t % m1, a = t / m1;
-    const T* w = W + a * m1;
-    T s = 0;
-    for (int b = 0; b < m1; ++b) s += w[b] * U1T[b * m1 + k];
-    const T v = tau * s;
+  const int a = L.j;
+  for (int i = 0; i < L.na; ++i) {
+    const int k = c0 + L.a0 + i;
+    const T v = tau * acc[i];
     if (it.src_if) {
-      const int64_t e = it.base + (r0 + a) + (int64_t)m0 * k;
+      const int64_t e = it.base + a + (int64_t)m0 * k;
       for (int64_t c = if_ptr[e]; c < if_ptr[e + 1]; ++c) {
         const int64_t x = if_idx[c];
         u[x] = add ? u[x] + v : v;
       }
     } else {
-      const int64_t x = it.base + (r0 + a) * it.stride[0] + k * it.stride[1] + zoff;
+      const int64_t x = it.base + a * it.stride[0] + k * it.stride[1] + zoff;
       u[x] = add ? u[x] + v : v;
     }
   }
@@ -310,11 +371,12 @@ __global__ __launch_bounds__(256) void k_fd_mid(const FDItem* __restrict__ items
   }
 }
 
+size_t fd_dense_lds(int maxm, size_t elem) { return ((size_t)maxm * maxm + maxm) * elem + 64; }
 size_t fd_slab_lds(int maxm, size_t elem) { return ((size_t)maxm * maxm + (size_t)FD_RB * maxm) * elem + 64; }
 
 int fd_slab_grid(const FDItem* items, int nitems) {
   int g = 1;
-  for (int i = 0; i < nitems; ++i) g = std::max(g, items[i].m[2] * ((items[i].m[0] + FD_RB - 1) / FD_RB));
+  for (int i = 0; i < nitems; ++i) g = std::max(g, items[i].m[2] * ((items[i].m[1] + FD_RB - 1) / FD_RB));
   return g;
 }
 
@@ -767,8 +829,8 @@ void launch_add_f32(double* x, const float* d, int64_t n, hipStream_t st) {
 
 // explicit instantiations for the two storage types
 #define IGAMG_INST(T)                                                                                                  \
-  template void launch_band<T>(int, int, const T*, const T*, const T*, T*, const int*, const PatchDev*, int64_t, bool, \
-                               hipStream_t);                                                                           \
+  template hipError_t launch_band<T>(int, int, const T*, const T*, const T*, T*, const int*, const PatchDev*, int64_t,   \
+                                     bool, hipStream_t, hipEvent_t, hipEvent_t);                                       \
   template void launch_fd_fwd<T>(const FDItem*, int, int, int, size_t, const DensePiece*, const T*, const T*,          \
                                  const T*, T*, const int64_t*, const int64_t*, T*, double, bool, hipStream_t);         \
   template void launch_fd_mid<T>(const FDItem*, int, int, size_t, const T*, T*, hipStream_t);                          \

@@ -13,11 +13,15 @@ namespace igamg {
 
 constexpr int RED_BLOCKS = 512;   // partial sums per reduction (the flexible dot uses 2x)
 
+// ev0/ev1 (optional): timing events that record the dispatch's own start
+// and end; an unsupported (d, p) returns hipErrorInvalidValue
 template <typename T>
-void launch_band(int d, int p, const T* band, const T* u, const T* f, T* r, const int* bpatch, const PatchDev* pd,
-                 int64_t NL, bool resid, hipStream_t st);
+hipError_t launch_band(int d, int p, const T* band, const T* u, const T* f, T* r, const int* bpatch,
+                       const PatchDev* pd, int64_t NL, bool resid, hipStream_t st, hipEvent_t ev0 = nullptr,
+                       hipEvent_t ev1 = nullptr);
 
 size_t fd_slab_lds(int maxm, size_t elem);
+size_t fd_dense_lds(int maxm, size_t elem);
 int fd_slab_grid(const FDItem* items, int nitems);
 int fd_mid_grid(const FDItem* items, int nitems);
 size_t fd_mid_lds(int maxm, size_t elem);

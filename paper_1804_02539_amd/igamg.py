@@ -9,6 +9,10 @@ import ctypes
 import os
 
 import numpy as np
+# torch first: its HIP runtime must be the one the library binds to (the
+# library's libamdhip64 dependency then resolves to the copy already loaded;
+# two HIP runtimes in one process do not share the device)
+import torch  # noqa: F401
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_HERE, "libigamg.so")

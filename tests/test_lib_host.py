@@ -131,3 +131,15 @@ def test_workspace_size_matches_setup_plan():
     # band of the finest level alone: (2p+1)^2 doubles per local row
     assert n > 49 * 8 * 16 * (3 * 2 ** 2 + 3) ** 2
     assert n < 64 * 1024 * 1024
+
+
+def test_binding_loads_a_single_hip_runtime():
+    """The library must bind to the HIP runtime torch loads: importing the
+    binding first in a fresh process maps exactly one libamdhip64."""
+    import subprocess
+    import sys
+    code = ("import os, sys; sys.path.insert(0, %r); from paper_1804_02539_amd import igamg; "
+            "print(len({l.split()[-1] for l in open('/proc/self/maps') if 'libamdhip64' in l}))" % ROOT)
+    out = subprocess.run([sys.executable, "-c", code], capture_output=True, text=True, timeout=300)
+    assert out.returncode == 0, out.stderr
+    assert out.stdout.strip().splitlines()[-1] == "1"
