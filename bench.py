@@ -91,10 +91,10 @@ def cpu_baseline(prob, rhs):
             "iterations": it, "solve_s": t}
 
 
-def run(workload, prob, precision, steps, warmup, dev):
+def run(workload, prob, precision, steps, warmup, dev, fd_mfma=0):
     import torch
     from paper_1804_02539_amd import igamg
-    opts = igamg.default_options(precision=igamg.MIXED if precision == "mixed" else igamg.FP64)
+    opts = igamg.default_options(precision=igamg.MIXED if precision == "mixed" else igamg.FP64, fd_mfma=fd_mfma)
     t0 = time.perf_counter()
     S = igamg.Solver(prob, opts, device=dev)
     setup_s = time.perf_counter() - t0
@@ -213,6 +213,8 @@ def main():
     ap.add_argument("--precision", default="both", choices=["both", "fp64", "mixed"])
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-serve", action="store_true")
+    ap.add_argument("--fd-mfma", action="store_true",
+                    help="also time the mixed solver with the smoother's FP32 mode products on the matrix cores")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="first fill and copy a 256 MiB buffer: dispatches of known size against "
                          "which hardware byte counters are scaled")
@@ -239,6 +241,8 @@ def main():
         S, runs["fp64"] = run(a.workload, prob, "fp64", a.steps, a.warmup, dev)
     if a.precision in ("both", "mixed"):
         S, runs["mixed"] = run(a.workload, prob, "mixed", a.steps, a.warmup, dev)
+        if a.fd_mfma:
+            _, runs["mixed_fd_mfma"] = run(a.workload, prob, "mixed", a.steps, a.warmup, dev, fd_mfma=1)
     head = "mixed" if ("mixed" in runs and runs["mixed"]["converged"]) else "fp64"
     h = runs[head]
     out = {
@@ -271,6 +275,8 @@ def main():
         out[k]["band_traffic_bytes_per_launch"] = v["roofline"]["traffic"]
     if "fp64" in runs and "mixed" in runs:
         out["speedup_mixed_vs_fp64"] = runs["mixed"]["value"] / runs["fp64"]["value"]
+    if "mixed_fd_mfma" in runs and "mixed" in runs:
+        out["mixed_fd_mfma_vs_vector"] = runs["mixed_fd_mfma"]["value"] / runs["mixed"]["value"]
     if not a.no_serve:
         out["serving"] = serving("mixed" if head == "mixed" else "fp64", a.serve_requests,
                                  a.serve_families, 5, dev)

@@ -86,7 +86,10 @@ typedef struct {
   int inner_maxit;       /* mixed: inner PCG iteration cap per refinement step (100) */
   double inner_tol;      /* mixed: inner relative residual reduction per step (1e-4) */
   int graphs;            /* 1: replay each PCG iteration as HIP graphs (default); 0: direct launches */
-  int reserved[5];
+  int fd_mfma;           /* mixed precision only: 1 runs the FP32 forward and inverse fast-diagonalization
+                            mode products on the matrix cores (v_mfma_f32_16x16x4f32); 0 (default) uses
+                            vector FMAs, which are faster for the tile sizes of this method (m <= 84) */
+  int reserved[4];
 } igamg_options;
 
 #define IGAMG_FP64 0

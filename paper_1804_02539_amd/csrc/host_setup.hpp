@@ -26,6 +26,7 @@ struct Options {
   int inner_maxit = 100;
   double inner_tol = 1e-4;
   int graphs = 1;
+  int fd_mfma = 0;
 };
 
 // Error with an igamg return code.

@@ -11,6 +11,7 @@
 #include <cstdlib>
 #include <cstring>
 #include <string>
+#include <type_traits>
 #include <vector>
 
 #include "host_setup.hpp"
@@ -44,6 +45,7 @@ struct LevelData {
 struct DevLevel {
   int64_t NL = 0, N = 0, rows = 0;
   int nb = 0, nfd = 0, nfd_int = 0, ndense = 0, WP = 0, WR = 0, fd_maxm = 1, max_dense = 1;
+  int mfma_grid = 1;
   int* bpatch = nullptr;
   PatchDev* pd = nullptr;
   uint8_t* isfree = nullptr;
@@ -170,6 +172,7 @@ static size_t plan(igamg_ctx& C, char* base) {
     D.max_m2 = 1;
     for (const auto& it : L.fd) D.max_m2 = std::max(D.max_m2, it.m[2]);
     D.slab_grid = fd_slab_grid(L.fd.data(), (int)L.fd.size());
+    D.mfma_grid = fd_mfma_grid(L.fd.data(), (int)L.fd.size());
     D.mid_grid = fd_mid_grid(L.fd.data(), L.nfd_interior);
   }
   C.N0 = H.lv[0].N;
@@ -281,13 +284,28 @@ template <typename T>
 static void smoother_apply(igamg_ctx& C, int l, const T* src, T* u, bool add, double tau, hipStream_t st) {
   DevLevel& D = C.dl[l];
   LevelData<T>& X = dat<T>(D);
-  const size_t lds = std::max(fd_slab_lds(D.fd_maxm, sizeof(T)), fd_dense_lds(D.max_dense, sizeof(T)));
-  launch_fd_fwd<T>(D.fd, D.nfd, D.ndense, D.slab_grid, lds, D.dense, X.densemat, X.fdmat, src, u, D.if_ptr, D.if_idx,
-                   X.scr, tau, add, st);
-  if (C.d == 3 && D.nfd_int > 0 && D.max_m2 > 1)
-    launch_fd_mid<T>(D.fd, D.nfd_int, D.mid_grid, fd_mid_lds(D.fd_maxm, sizeof(T)), X.fdmat, X.scr, st);
-  launch_fd_inv<T>(D.fd, D.nfd, D.slab_grid, fd_slab_lds(D.fd_maxm, sizeof(T)), X.fdmat, u, D.if_ptr, D.if_idx,
-                   X.scr, tau, add, st);
+  if constexpr (std::is_same<T, float>::value) {
+    if (C.H.opt.fd_mfma) {
+      // FP32: forward and inverse mode products on the matrix cores
+      const size_t lds = std::max(fd_mfma_lds(D.fd_maxm), fd_dense_lds(D.max_dense, sizeof(T)));
+      launch_fd_fwd_mfma(D.fd, D.nfd, D.ndense, D.mfma_grid, lds, D.dense, X.densemat, X.fdmat, src, u, D.if_ptr,
+                         D.if_idx, X.scr, tau, add, st);
+      if (C.d == 3 && D.nfd_int > 0 && D.max_m2 > 1)
+        launch_fd_mid<T>(D.fd, D.nfd_int, D.mid_grid, fd_mid_lds(D.fd_maxm, sizeof(T)), X.fdmat, X.scr, st);
+      launch_fd_inv_mfma(D.fd, D.nfd, D.mfma_grid, fd_mfma_lds(D.fd_maxm), X.fdmat, u, D.if_ptr, D.if_idx, X.scr,
+                         tau, add, st);
+      return;
+    }
+  }
+  {
+    const size_t lds = std::max(fd_slab_lds(D.fd_maxm, sizeof(T)), fd_dense_lds(D.max_dense, sizeof(T)));
+    launch_fd_fwd<T>(D.fd, D.nfd, D.ndense, D.slab_grid, lds, D.dense, X.densemat, X.fdmat, src, u, D.if_ptr,
+                     D.if_idx, X.scr, tau, add, st);
+    if (C.d == 3 && D.nfd_int > 0 && D.max_m2 > 1)
+      launch_fd_mid<T>(D.fd, D.nfd_int, D.mid_grid, fd_mid_lds(D.fd_maxm, sizeof(T)), X.fdmat, X.scr, st);
+    launch_fd_inv<T>(D.fd, D.nfd, D.slab_grid, fd_slab_lds(D.fd_maxm, sizeof(T)), X.fdmat, u, D.if_ptr, D.if_idx,
+                     X.scr, tau, add, st);
+  }
 }
 
 template <typename T>
@@ -442,9 +460,10 @@ static void read_opts(const igamg_options* o, Options& O) {
   O.inner_maxit = o->inner_maxit;
   O.inner_tol = o->inner_tol;
   O.graphs = o->graphs;
+  O.fd_mfma = o->fd_mfma;
   if (!(O.tau > 0) || !(O.sigma_scale > 0) || O.nu < 1 || O.nu > 8 || (O.mu != 1 && O.mu != 2) ||
       (O.precision != IGAMG_FP64 && O.precision != IGAMG_MIXED) || O.maxit < 1 || O.inner_maxit < 1 ||
-      !(O.inner_tol > 0 && O.inner_tol < 1))
+      !(O.inner_tol > 0 && O.inner_tol < 1) || (O.fd_mfma != 0 && O.fd_mfma != 1))
     throw SetupError{IGAMG_EINVAL, "invalid options"};
 }
 

@@ -25,11 +25,22 @@ namespace igamg {
 // applied patch by patch to accumulated u gives a distributed result).
 // The band is tiled: the (2P+1)^D planes of each 256-row block are contiguous.
 // A workgroup takes a strip of 64 rows (one row per lane); its 4 waves split
-// the stencil lines (o1, o2) between them and add their partial sums in LDS,
+// the stencil lines (o1, o2) between them (the single planes, for 2D FP64)
+// and add their partial sums in LDS,
 // so a launch has 4 x (rows / 256) x 4 waves to hide HBM latency with.  Each
 // wave reads every band plane of its lines as one coalesced 64-entry segment.
 // ---------------------------------------------------------------------------
 constexpr int BAND_STRIP = 64;
+
+template <int P, int W, typename TB, typename TV>
+__device__ __forceinline__ TV band_planes_2d(const TB* __restrict__ bp, const TV* __restrict__ ub, const int* c0,
+                                             const int* c1) {
+  constexpr int NB = 2 * P + 1;
+  TV s = 0;
+#pragma unroll
+  for (int o = W; o < NB * NB; o += 4) s += (TV)bp[o * ROW_ALIGN] * ub[c1[o / NB] + c0[o % NB]];
+  return s;
+}
 
 template <int D, int P, bool RESID, typename TB, typename TV>
 __global__ __launch_bounds__(256) void k_band(const TB* __restrict__ band, const TV* __restrict__ u,
@@ -61,14 +72,31 @@ __global__ __launch_bounds__(256) void k_band(const TB* __restrict__ band, const
   const TB* bp = band + tile * NBT * ROW_ALIGN + (g - tile * ROW_ALIGN);
   const int64_t pl = (int64_t)n0 * n1;
   TV s = 0;
-  for (int L = w; L < NLINE; L += 4) {
-    const int o1 = L % NB, o2 = L / NB;
-    int64_t base = (int64_t)min(max(i1 + o1 - P, 0), n1 - 1) * n0;
-    if constexpr (D == 3) base += (int64_t)min(max(i2 + o2 - P, 0), n2 - 1) * pl;
-    const TV* ur = ub + base;
-    const TB* bq = bp + (int64_t)L * NB * ROW_ALIGN;
+  if constexpr (D == 2 && sizeof(TB) == 8) {
+    // 2D FP64: the (2P+1)^2 planes are dealt to the 4 waves one by one (plane
+    // o to wave o mod 4), which balances 2P+1 lines far better than whole
+    // lines (measured faster for double; for float the line split is faster);
+    // the wave index is a template argument so every plane's offsets stay
+    // compile-time register indices
+    int c1[NB];
 #pragma unroll
-    for (int o0 = 0; o0 < NB; ++o0) s += (TV)bq[o0 * ROW_ALIGN] * ur[c0[o0]];
+    for (int o = 0; o < NB; ++o) c1[o] = min(max(i1 + o - P, 0), n1 - 1) * n0;
+    switch (w) {
+      case 0: s = band_planes_2d<P, 0, TB, TV>(bp, ub, c0, c1); break;
+      case 1: s = band_planes_2d<P, 1, TB, TV>(bp, ub, c0, c1); break;
+      case 2: s = band_planes_2d<P, 2, TB, TV>(bp, ub, c0, c1); break;
+      default: s = band_planes_2d<P, 3, TB, TV>(bp, ub, c0, c1); break;
+    }
+  } else {
+    for (int L = w; L < NLINE; L += 4) {
+      const int o1 = L % NB, o2 = L / NB;
+      int64_t base = (int64_t)min(max(i1 + o1 - P, 0), n1 - 1) * n0;
+      if constexpr (D == 3) base += (int64_t)min(max(i2 + o2 - P, 0), n2 - 1) * pl;
+      const TV* ur = ub + base;
+      const TB* bq = bp + (int64_t)L * NB * ROW_ALIGN;
+#pragma unroll
+      for (int o0 = 0; o0 < NB; ++o0) s += (TV)bq[o0 * ROW_ALIGN] * ur[c0[o0]];
+    }
   }
   if (w > 0) part[w - 1][lane] = s;
   __syncthreads();
@@ -169,6 +197,37 @@ __device__ __forceinline__ void fd_rows_times_chunk(const T* A, const T* C, int 
   }
 }
 
+// Dense piece (edge or vertex): gather the residual over all copies (Sigma),
+// z = L^{-1} r with L^{-1} staged in LDS by coalesced loads (row k is thread
+// k's), and add (or set) tau z on every copy.
+template <typename T>
+__device__ void fd_dense_piece(const DensePiece pc, const T* __restrict__ densemat, const T* __restrict__ src,
+                               T* __restrict__ u, const int64_t* __restrict__ if_ptr,
+                               const int64_t* __restrict__ if_idx, T tau, int add, T* lds) {
+  const int m = pc.m;
+  T* sA = lds;             // L^{-1}, row-major m x m
+  T* sr = lds + m * m;     // gathered residual
+  const T* A = densemat + pc.Linv;
+  for (int t = threadIdx.x; t < m * m; t += blockDim.x) sA[t] = A[t];
+  for (int j = threadIdx.x; j < m; j += blockDim.x) {
+    T v = 0;
+    for (int64_t c = if_ptr[pc.seg + j]; c < if_ptr[pc.seg + j + 1]; ++c) v += src[if_idx[c]];
+    sr[j] = v;
+  }
+  __syncthreads();
+  for (int k = threadIdx.x; k < m; k += blockDim.x) {
+    T zz = 0;
+    const T* ar = sA + k * m;
+#pragma unroll 8
+    for (int j = 0; j < m; ++j) zz += ar[j] * sr[j];
+    zz *= tau;
+    for (int64_t c = if_ptr[pc.seg + k]; c < if_ptr[pc.seg + k + 1]; ++c) {
+      const int64_t x = if_idx[c];
+      u[x] = add ? u[x] + zz : zz;
+    }
+  }
+}
+
 template <typename T>
 __global__ __launch_bounds__(256) void k_fd_fwd(const FDItem* __restrict__ items, int nitems,
                                                 const DensePiece* __restrict__ dense,
@@ -179,32 +238,7 @@ __global__ __launch_bounds__(256) void k_fd_fwd(const FDItem* __restrict__ items
   DYN_LDS(T, lds);
   const int y = blockIdx.y;
   if (y >= nitems) {
-    // dense piece: gather (Sigma), z = L^{-1} r, scatter tau z to all copies;
-    // L^{-1} is staged in LDS with coalesced loads, then row k is thread k's
-    if (blockIdx.x != 0) return;
-    const DensePiece pc = dense[y - nitems];
-    const int m = pc.m;
-    T* sA = lds;             // L^{-1}, row-major m x m
-    T* sr = lds + m * m;     // gathered residual
-    const T* A = densemat + pc.Linv;
-    for (int t = threadIdx.x; t < m * m; t += blockDim.x) sA[t] = A[t];
-    for (int j = threadIdx.x; j < m; j += blockDim.x) {
-      T v = 0;
-      for (int64_t c = if_ptr[pc.seg + j]; c < if_ptr[pc.seg + j + 1]; ++c) v += src[if_idx[c]];
-      sr[j] = v;
-    }
-    __syncthreads();
-    for (int k = threadIdx.x; k < m; k += blockDim.x) {
-      T zz = 0;
-      const T* ar = sA + k * m;
-#pragma unroll 8
-      for (int j = 0; j < m; ++j) zz += ar[j] * sr[j];
-      zz *= tau;
-      for (int64_t c = if_ptr[pc.seg + k]; c < if_ptr[pc.seg + k + 1]; ++c) {
-        const int64_t x = if_idx[c];
-        u[x] = add ? u[x] + zz : zz;
-      }
-    }
+    if (blockIdx.x == 0) fd_dense_piece(dense[y - nitems], densemat, src, u, if_ptr, if_idx, tau, add, lds);
     return;
   }
   // Y[:, c0 + c] = U0^T (X U1[:, c0 + c]) for the chunk's columns
@@ -313,6 +347,195 @@ __global__ __launch_bounds__(256) void k_fd_inv(const FDItem* __restrict__ items
   }
 }
 
+// ---------------------------------------------------------------------------
+// The same forward and inverse products for FP32 on the matrix cores: every
+// mode product of a chunk is a (rows x K) x (K x 16) product done as 16x16
+// output tiles of v_mfma_f32_16x16x4f32 (16x4 by 4x16 per instruction, fp32
+// accumulation).  Operands are staged in LDS, zero-padded to whole tiles:
+// rows to 16, K to 4.  A chunk is 16 columns of one z-slab.
+//   lane l of a wave holds A[l % 16][l / 16] and B[l / 16][l % 16] of each
+//   4-wide K step, and D[4 (l / 16) + r][l % 16], r = 0..3, of the output tile.
+// ---------------------------------------------------------------------------
+typedef float fd_f4 __attribute__((ext_vector_type(4)));
+constexpr int FDM_N = 16;          // MFMA tile width
+constexpr int FDM_CW = 8;          // columns per chunk (<= FDM_N; the rest of the tile is zero)
+constexpr int FDM_TILES = 2;       // output row tiles per wave (4 waves x 2 x 16 >= 96 >= MAX_FD rows)
+static_assert(4 * FDM_TILES * 16 >= MAX_FD, "row tiles per wave");
+
+__device__ __forceinline__ int fdm_up(int x, int q) { return (x + q - 1) / q * q; }
+
+__device__ __forceinline__ void fdm_chunk(const FDItem& it, int& z, int& c0, int& nc) {
+  const int nch = (it.m[1] + FDM_CW - 1) / FDM_CW;
+  z = blockIdx.x / nch;
+  c0 = (blockIdx.x - z * nch) * FDM_CW;
+  nc = min(FDM_CW, it.m[1] - c0);
+}
+
+// acc[t] = (A B) rows 16 (w + 4 t) .. of the (mp x kp) A (column-major, leading
+// dimension mp) times the (kp x 16) B (row-major), for the tiles of wave w
+__device__ __forceinline__ void fdm_product(const float* A, int mp, const float* B, int kp, fd_f4* acc) {
+  const int l = threadIdx.x & 63, w = threadIdx.x >> 6;
+  const int li = l & 15, lk = l >> 4;
+#pragma unroll
+  for (int t = 0; t < FDM_TILES; ++t) acc[t] = fd_f4{0.f, 0.f, 0.f, 0.f};
+  for (int ks = 0; ks < kp; ks += 4) {
+    const float b = B[(ks + lk) * FDM_N + li];
+#pragma unroll
+    for (int t = 0; t < FDM_TILES; ++t) {
+      const int mt = w + 4 * t;
+      if (mt * 16 < mp) acc[t] = __builtin_amdgcn_mfma_f32_16x16x4f32(A[(mt * 16 + li) + mp * (ks + lk)], b, acc[t], 0, 0, 0);
+    }
+  }
+}
+
+__global__ __launch_bounds__(256) void k_fd_fwd_mfma(const FDItem* __restrict__ items, int nitems,
+                                                     const DensePiece* __restrict__ dense,
+                                                     const float* __restrict__ densemat, const float* __restrict__ mat,
+                                                     const float* __restrict__ src, float* __restrict__ u,
+                                                     const int64_t* __restrict__ if_ptr,
+                                                     const int64_t* __restrict__ if_idx, float* __restrict__ scr,
+                                                     float tau, int add) {
+  DYN_LDS(float, lds);
+  const int y = blockIdx.y;
+  if (y >= nitems) {
+    if (blockIdx.x == 0) fd_dense_piece(dense[y - nitems], densemat, src, u, if_ptr, if_idx, tau, add, lds);
+    return;
+  }
+  // Y[:, c0 + c] = U0^T (X U1[:, c0 + c])
+  const FDItem it = items[y];
+  const int m0 = it.m[0], m1 = it.m[1];
+  int z, c0, nc;
+  fdm_chunk(it, z, c0, nc);
+  if (z >= it.m[2]) return;
+  const int m0p = fdm_up(m0, 16), m1k = fdm_up(m1, 4), m0k = fdm_up(m0, 4);
+  float* X = lds;                                   // X[j + m0p b]; later U0 as A[a + m0p k] = U0[k, a]
+  float* C = lds + max(m0p * m1k, m0p * m0k);       // U1[k, c0 + c] as C[k 16 + c]; later V[i 16 + c]
+  const int64_t zoff = (int64_t)z * it.stride[2];
+  const float* U0 = mat + it.U[0];
+  const float* U1 = mat + it.U[1];
+  for (int t = threadIdx.x; t < m0p * m1k; t += blockDim.x) {
+    const int j = t % m0p, b = t / m0p;
+    float v = 0.f;
+    if (j < m0 && b < m1) {
+      if (it.src_if) {
+        const int64_t e = it.base + j + (int64_t)m0 * b;   // face tensors are stored j fastest
+        for (int64_t c = if_ptr[e]; c < if_ptr[e + 1]; ++c) v += src[if_idx[c]];
+      } else {
+        v = src[it.base + j * it.stride[0] + b * it.stride[1] + zoff];
+      }
+    }
+    X[t] = v;
+  }
+  for (int t = threadIdx.x; t < m1k * FDM_N; t += blockDim.x) {
+    const int c = t % FDM_N, k = t / FDM_N;
+    C[t] = (k < m1 && c < nc) ? U1[(int64_t)k * m1 + c0 + c] : 0.f;
+  }
+  __syncthreads();
+  fd_f4 acc[FDM_TILES];
+  fdm_product(X, m0p, C, m1k, acc);                  // V = X U1[:, chunk]
+  __syncthreads();
+  const int l = threadIdx.x & 63, w = threadIdx.x >> 6;
+  const int li = l & 15, lr = 4 * (l >> 4);
+#pragma unroll
+  for (int t = 0; t < FDM_TILES; ++t) {
+    const int mt = w + 4 * t;
+    if (mt * 16 < m0p)
+      for (int r = 0; r < 4; ++r) C[(mt * 16 + lr + r) * FDM_N + li] = acc[t][r];   // rows >= m0 hold 0
+  }
+  for (int t = threadIdx.x; t < m0k * m0p; t += blockDim.x) {
+    const int a = t % m0p, k = t / m0p;
+    X[t] = (a < m0 && k < m0) ? U0[(int64_t)k * m0 + a] : 0.f;
+  }
+  __syncthreads();
+  fdm_product(X, m0p, C, m0k, acc);                  // Y = U0^T V
+  const float* mu0 = mat + it.mu[0];
+  const float* mu1 = mat + it.mu[1];
+  const float mu2 = mat[it.mu[2]];
+  const bool full = (it.m[2] == 1);
+  float* S = scr + it.scr + (int64_t)z * m0 * m1;
+#pragma unroll
+  for (int t = 0; t < FDM_TILES; ++t) {
+    const int mt = w + 4 * t;
+    if (mt * 16 >= m0p) continue;
+    const int k = c0 + li;
+    for (int r = 0; r < 4; ++r) {
+      const int a = mt * 16 + lr + r;
+      if (a < m0 && li < nc) {
+        float v = acc[t][r];
+        if (full) v /= (float)it.pref * (mu0[a] + mu1[k] + mu2 + (float)it.extra);
+        S[a + m0 * k] = v;
+      }
+    }
+  }
+}
+
+__global__ __launch_bounds__(256) void k_fd_inv_mfma(const FDItem* __restrict__ items, const float* __restrict__ mat,
+                                                     float* __restrict__ u, const int64_t* __restrict__ if_ptr,
+                                                     const int64_t* __restrict__ if_idx, const float* __restrict__ scr,
+                                                     float tau, int add) {
+  // Z[:, c0 + c] = U0 (Y U1^T[:, c0 + c])
+  DYN_LDS(float, lds);
+  const FDItem it = items[blockIdx.y];
+  const int m0 = it.m[0], m1 = it.m[1];
+  int z, c0, nc;
+  fdm_chunk(it, z, c0, nc);
+  if (z >= it.m[2]) return;
+  const int m0p = fdm_up(m0, 16), m1k = fdm_up(m1, 4), m0k = fdm_up(m0, 4);
+  float* X = lds;                                   // Y[j + m0p b]; later U0 as A[a + m0p k] = U0[a, k]
+  float* C = lds + max(m0p * m1k, m0p * m0k);       // U1[c0 + c, k] as C[k 16 + c]; later V[i 16 + c]
+  const float* S = scr + it.scr + (int64_t)z * m0 * m1;
+  const float* U0T = mat + it.U[0] + (int64_t)m0 * m0;
+  const float* U1T = mat + it.U[1] + (int64_t)m1 * m1;
+  for (int t = threadIdx.x; t < m0p * m1k; t += blockDim.x) {
+    const int j = t % m0p, b = t / m0p;
+    X[t] = (j < m0 && b < m1) ? S[j + m0 * b] : 0.f;
+  }
+  for (int t = threadIdx.x; t < m1k * FDM_N; t += blockDim.x) {
+    const int c = t % FDM_N, k = t / FDM_N;
+    C[t] = (k < m1 && c < nc) ? U1T[(int64_t)k * m1 + c0 + c] : 0.f;
+  }
+  __syncthreads();
+  fd_f4 acc[FDM_TILES];
+  fdm_product(X, m0p, C, m1k, acc);                  // V = Y U1^T[:, chunk]
+  __syncthreads();
+  const int l = threadIdx.x & 63, w = threadIdx.x >> 6;
+  const int li = l & 15, lr = 4 * (l >> 4);
+#pragma unroll
+  for (int t = 0; t < FDM_TILES; ++t) {
+    const int mt = w + 4 * t;
+    if (mt * 16 < m0p)
+      for (int r = 0; r < 4; ++r) C[(mt * 16 + lr + r) * FDM_N + li] = acc[t][r];
+  }
+  for (int t = threadIdx.x; t < m0k * m0p; t += blockDim.x) {
+    const int a = t % m0p, k = t / m0p;
+    X[t] = (a < m0 && k < m0) ? U0T[(int64_t)k * m0 + a] : 0.f;
+  }
+  __syncthreads();
+  fdm_product(X, m0p, C, m0k, acc);                  // Z = U0 V
+  const int64_t zoff = (int64_t)z * it.stride[2];
+#pragma unroll
+  for (int t = 0; t < FDM_TILES; ++t) {
+    const int mt = w + 4 * t;
+    if (mt * 16 >= m0p) continue;
+    const int k = c0 + li;
+    for (int r = 0; r < 4; ++r) {
+      const int a = mt * 16 + lr + r;
+      if (a >= m0 || li >= nc) continue;
+      const float v = tau * acc[t][r];
+      if (it.src_if) {
+        const int64_t e = it.base + a + (int64_t)m0 * k;
+        for (int64_t c = if_ptr[e]; c < if_ptr[e + 1]; ++c) {
+          const int64_t x = if_idx[c];
+          u[x] = add ? u[x] + v : v;
+        }
+      } else {
+        const int64_t x = it.base + a * it.stride[0] + k * it.stride[1] + zoff;
+        u[x] = add ? u[x] + v : v;
+      }
+    }
+  }
+}
+
 // Middle direction of 3D patch interiors, in place on the compact scratch
 // tensor: along direction 2, y = U2 diag(1/D) U2^T x for every (i0, i1).
 __device__ __forceinline__ int fd_mid_lines(int L) { return max(1, min(64, 512 / L)); }
@@ -369,6 +592,34 @@ __global__ __launch_bounds__(256) void k_fd_mid(const FDItem* __restrict__ items
     const int j = t / nl, line = t - j * nl;
     S[line0 + line + j * plane] = sx[line * L + j];
   }
+}
+
+size_t fd_mfma_lds(int maxm) {
+  const size_t mp = (size_t)(maxm + 15) / 16 * 16;
+  return (mp * mp + (size_t)FDM_N * mp) * sizeof(float) + 64;
+}
+
+int fd_mfma_grid(const FDItem* items, int nitems) {
+  int g = 1;
+  for (int i = 0; i < nitems; ++i) g = std::max(g, items[i].m[2] * ((items[i].m[1] + FDM_CW - 1) / FDM_CW));
+  return g;
+}
+
+void launch_fd_fwd_mfma(const FDItem* items, int nitems, int ndense, int gridx, size_t lds, const DensePiece* dense,
+                        const float* densemat, const float* mat, const float* src, float* u, const int64_t* if_ptr,
+                        const int64_t* if_idx, float* scr, double tau, bool add, hipStream_t st) {
+  const int ny = nitems + ndense;
+  if (ny <= 0) return;
+  hipLaunchKernelGGL(k_fd_fwd_mfma, dim3(gridx, ny), dim3(256), lds, st, items, nitems, dense, densemat, mat, src, u,
+                     if_ptr, if_idx, scr, (float)tau, (int)add);
+}
+
+void launch_fd_inv_mfma(const FDItem* items, int nitems, int gridx, size_t lds, const float* mat, float* u,
+                        const int64_t* if_ptr, const int64_t* if_idx, const float* scr, double tau, bool add,
+                        hipStream_t st) {
+  if (nitems <= 0) return;
+  hipLaunchKernelGGL(k_fd_inv_mfma, dim3(gridx, nitems), dim3(256), lds, st, items, mat, u, if_ptr, if_idx, scr,
+                     (float)tau, (int)add);
 }
 
 size_t fd_dense_lds(int maxm, size_t elem) { return ((size_t)maxm * maxm + maxm) * elem + 64; }

@@ -29,6 +29,15 @@ template <typename T>
 void launch_fd_fwd(const FDItem* items, int nitems, int ndense, int gridx, size_t lds, const DensePiece* dense,
                    const T* densemat, const T* mat, const T* src, T* u, const int64_t* if_ptr, const int64_t* if_idx,
                    T* scr, double tau, bool add, hipStream_t st);
+// FP32 forward/inverse products on the matrix cores (16-column chunks)
+size_t fd_mfma_lds(int maxm);
+int fd_mfma_grid(const FDItem* items, int nitems);
+void launch_fd_fwd_mfma(const FDItem* items, int nitems, int ndense, int gridx, size_t lds, const DensePiece* dense,
+                        const float* densemat, const float* mat, const float* src, float* u, const int64_t* if_ptr,
+                        const int64_t* if_idx, float* scr, double tau, bool add, hipStream_t st);
+void launch_fd_inv_mfma(const FDItem* items, int nitems, int gridx, size_t lds, const float* mat, float* u,
+                        const int64_t* if_ptr, const int64_t* if_idx, const float* scr, double tau, bool add,
+                        hipStream_t st);
 template <typename T>
 void launch_fd_mid(const FDItem* items, int nitems, int gridx, size_t lds, const T* mat, T* scr, hipStream_t st);
 template <typename T>

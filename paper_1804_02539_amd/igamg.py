@@ -43,7 +43,8 @@ class Options(ctypes.Structure):
     _fields_ = [("tau", ctypes.c_double), ("sigma_scale", ctypes.c_double), ("nu", ctypes.c_int),
                 ("mu", ctypes.c_int), ("precision", ctypes.c_int), ("maxit", ctypes.c_int),
                 ("geometry_scaling", ctypes.c_int), ("inner_maxit", ctypes.c_int),
-                ("inner_tol", ctypes.c_double), ("graphs", ctypes.c_int), ("reserved", ctypes.c_int * 5)]
+                ("inner_tol", ctypes.c_double), ("graphs", ctypes.c_int), ("fd_mfma", ctypes.c_int),
+                ("reserved", ctypes.c_int * 4)]
 
 
 class SolveInfo(ctypes.Structure):

@@ -175,14 +175,17 @@ def test_full_size_cube_sampled(torch_cuda):
 
 # --- mixed precision: FP32 inner solves inside FP64 iterative refinement ----
 
-@pytest.mark.parametrize("name", ["square4x4_p4_l4", "cube2x2x2_p3_l4", "fichera7_p2_l3", "cube_p4_l3_neumann"])
-def test_fp32_cycle_close_to_oracle(torch_cuda, name):
+@pytest.mark.parametrize("fd_mfma", [0, 1])
+@pytest.mark.parametrize("name", ["square4x4_p4_l4", "cube2x2x2_p3_l4", "fichera7_p2_l3", "cube_p4_l3_neumann",
+                                  "single_patch_p5_l3"])
+def test_fp32_cycle_close_to_oracle(torch_cuda, name, fd_mfma):
     """The FP32 cycle (FP32 bands, smoothers, transfers; FP64 coarse solve)
-    against the oracle's FP64 cycle: FP32 rounding only."""
+    against the oracle's FP64 cycle: FP32 rounding only.  fd_mfma = 1 runs the
+    smoother's mode products on the matrix cores."""
     from paper_1804_02539_amd import igamg
-    _say(f"fp32 cycle {name}")
+    _say(f"fp32 cycle {name} fd_mfma={fd_mfma}")
     H = oracle_for(name)
-    S = gpu_for(name, precision=igamg.MIXED)
+    S = gpu_for(name, precision=igamg.MIXED, fd_mfma=fd_mfma)
     r = np.random.default_rng(7).standard_normal(H.finest.N)
     z = S.operator(igamg.OP_CYCLE_FP32, -1, r).cpu().numpy()
     err = rel(z, H.vcycle(r))
@@ -190,14 +193,15 @@ def test_fp32_cycle_close_to_oracle(torch_cuda, name):
     assert err < 1e-4
 
 
-@pytest.mark.parametrize("name", ["square2x2_p2", "square4x4_p4_l4", "cube2x2x2_p3_l4", "fichera7_p2_l3"])
-def test_mixed_solve_reaches_fp64_tolerance(torch_cuda, name):
+@pytest.mark.parametrize("name,fd_mfma", [("square2x2_p2", 0), ("square4x4_p4_l4", 0), ("cube2x2x2_p3_l4", 0),
+                                          ("fichera7_p2_l3", 0), ("square4x4_p4_l4", 1), ("fichera7_p2_l3", 1)])
+def test_mixed_solve_reaches_fp64_tolerance(torch_cuda, name, fd_mfma):
     from oracle.multigrid import load_vector
     from paper_1804_02539_amd import igamg
-    _say(f"mixed solve {name}")
+    _say(f"mixed solve {name} fd_mfma={fd_mfma}")
     prob = CASES[name]()
     H = oracle_for(name)
-    S = gpu_for(name, precision=igamg.MIXED)
+    S = gpu_for(name, precision=igamg.MIXED, fd_mfma=fd_mfma)
     if prob.meta["source"][0] == "sine":
         f = load_vector(prob, H.finest)
     else:
