@@ -33,13 +33,16 @@ WORKLOADS = {
     "cube2x2x2_p3": "3D Poisson, 2x2x2 trilinear patches with the centre vertex seeded-perturbed, "
                     "p=3, 32^3 elements per patch, 6 levels, full Dirichlet, f = 3 pi^2 sin sin sin",
     "square2x2_p2": "2D Poisson, 2x2 identity patches, p=2, 16x16 elements per patch, 4 levels",
+    "cube4x4x4_p5": "3D Poisson, 4x4x4 trilinear patches with seeded-perturbed interior vertices, per-slab "
+                    "element counts drawn from {8,16,24,32,48} (seed 4; N in [2e6,4e6]), p=5, 4 levels, "
+                    "full Dirichlet, seeded U[-1,1] rhs",
 }
 
 
 def make_problem(name):
     from paper_1804_02539_amd import workloads as W
     return {"square4x4_p4": W.square_4x4_bezier, "cube2x2x2_p3": W.cube_2x2x2_trilinear,
-            "square2x2_p2": W.unit_square_2x2}[name]()
+            "square2x2_p2": W.unit_square_2x2, "cube4x4x4_p5": W.batched_patch_cube}[name]()
 
 
 def rhs_for(prob, solver):

@@ -84,12 +84,15 @@ typedef struct {
   int maxit;             /* iteration cap of igamg_solve                    */
   int geometry_scaling;  /* 1: scale piece operators by the patch's mean metric trace */
   int inner_maxit;       /* mixed: inner PCG iteration cap per refinement step (100) */
-  double inner_tol;      /* mixed: inner relative residual reduction per step (1e-4) */
+  double inner_tol;      /* mixed: the largest reduction an inner FP32 solve is asked for (1e-4) */
   int graphs;            /* 1: replay each PCG iteration as HIP graphs (default); 0: direct launches */
   int fd_mfma;           /* mixed precision only: 1 runs the FP32 forward and inverse fast-diagonalization
                             mode products on the matrix cores (v_mfma_f32_16x16x4f32); 0 (default) uses
                             vector FMAs, which are faster for the tile sizes of this method (m <= 84) */
-  int reserved[4];
+  int coarse_factor;     /* factorization of the dense coarse matrix: 0 (default) on the host up to
+                            3000 coarse unknowns and on the device (rocSOLVER Cholesky and inverse, in
+                            the workspace) above; 1 always on the host; 2 always on the device */
+  int reserved[3];
 } igamg_options;
 
 #define IGAMG_FP64 0
@@ -140,8 +143,10 @@ int igamg_vcycle(igamg_handle h, const double* r, double* z, void* stream);
  * ||f - A u||_2 <= tol ||f||_2 (Sec. 5).  With precision IGAMG_MIXED, FP64
  * iterative refinement around FP32 PCG solves: the residual f - A u and the
  * update u += d are FP64 (FP64 band), each correction d is an FP32 PCG solve
- * (FP32 bands, smoothers, transfers; the coarse solve stays FP64) to
- * inner_tol, and `maxit` caps the inner iterations summed.  rhs and u: device vectors of
+ * (FP32 bands, smoothers, transfers; the coarse solve stays FP64) that
+ * reduces its residual by max(inner_tol, tol / (2 r)), r the outer relative
+ * residual before it (the last correction aims just past tol instead of a
+ * whole further inner_tol), and `maxit` caps the inner iterations summed.  rhs and u: device vectors of
  * length n_free (finest).  Synchronises the stream (reads the residual norm
  * back once per iteration).  Returns ENOCONV when maxit is reached and ENAN
  * on a non-finite residual; `info` (may be NULL) is filled in either case.  */

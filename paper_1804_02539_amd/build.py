@@ -44,7 +44,8 @@ def build():
         if p.wait() != 0:
             raise SystemExit("compilation failed")
     tmp = LIB + ".tmp"
-    run([HIPCC, "-shared", "-fPIC", f"--offload-arch={ARCH}", "-o", tmp] + objs + ["-pthread"])
+    run([HIPCC, "-shared", "-fPIC", f"--offload-arch={ARCH}", "-o", tmp] + objs +
+        ["-pthread", "-L/opt/rocm/lib", "-lrocsolver", "-lrocblas"])
     os.replace(tmp, LIB)
     return LIB
 

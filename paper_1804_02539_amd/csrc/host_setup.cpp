@@ -6,6 +6,9 @@
 #include "host_setup.hpp"
 
 #include <algorithm>
+#include <chrono>
+#include <cstdio>
+#include <cstdlib>
 #include <atomic>
 #include <cmath>
 #include <functional>
@@ -962,6 +965,16 @@ static void plain_patch_table(const ProblemH& P, LevelH& L) {
 // ---------------------------------------------------------------------------
 // drivers
 // ---------------------------------------------------------------------------
+void setup_progress(const char* what, double value) {
+  static const bool on = std::getenv("IGAMG_VERBOSE") != nullptr;
+  if (!on) return;
+  using clk = std::chrono::steady_clock;
+  static const clk::time_point t0 = clk::now();
+  std::fprintf(stderr, "[igamg setup %7.1f s] %s %.6g\n", std::chrono::duration<double>(clk::now() - t0).count(),
+               what, value);
+  std::fflush(stderr);
+}
+
 void build_topology(Hierarchy& H, bool with_numerics) {
   const ProblemH& P = H.prob;
   H.lv.assign(P.levels, LevelH{});
@@ -979,12 +992,16 @@ void build_topology(Hierarchy& H, bool with_numerics) {
     make_transfers(P, H.lv[l - 1], H.lv[l]);
   }
   plain_patch_table(P, H.lv[0]);
+  if (with_numerics) setup_progress("topology, smoothers and transfers done; finest local rows", (double)H.lv.back().NL);
 }
 
-void build_all(Hierarchy& H) {
+void build_all(Hierarchy& H, bool device) {
   build_topology(H, true);
   const ProblemH& P = H.prob;
-  for (int l = 0; l < P.levels; ++l) assemble_level(P, H.lv[l]);
+  for (int l = 0; l < P.levels; ++l) {
+    assemble_level(P, H.lv[l]);
+    setup_progress("assembled level", l);
+  }
   // coarse matrix (dense, free dofs of level 0) and its inverse Cholesky factor
   LevelH& L0 = H.lv[0];
   const int64_t N0 = L0.N;
@@ -1012,6 +1029,12 @@ void build_all(Hierarchy& H) {
           }
     }
   }
+  setup_progress("dense coarse matrix built; coarse unknowns", (double)N0);
+  if (coarse_on_device(H.opt, N0, device)) {
+    H.A0 = std::move(A);   // factored after upload
+    return;
+  }
+  if (N0 > COARSE_HOST_MAX && H.opt.coarse_factor != 1) return;   // host-only handle: no coarse solver needed
   if (!cholesky(A, (int)N0)) fail(IGAMG_ENOTSPD, "coarse matrix is not positive definite (is any side Dirichlet?)");
   // A_0^{-1} = L^{-T} L^{-1} from the Cholesky factor: the two triangular
   // solves of the exact coarse solver become one dense mat-vec on the device

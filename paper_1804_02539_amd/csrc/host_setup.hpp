@@ -20,6 +20,10 @@ struct ProblemH {
   std::vector<int> bc;                    // K*2d
 };
 
+// Coarse problems above this size are factored on the device when one is
+// available (O(N0^3) on the host takes minutes beyond a few thousand).
+constexpr int64_t COARSE_HOST_MAX = 3000;
+
 struct Options {
   double tau = 0.25, sigma_scale = 5.0;
   int nu = 1, mu = 1, precision = 0, maxit = 500, geometry_scaling = 1;
@@ -27,6 +31,7 @@ struct Options {
   double inner_tol = 1e-4;
   int graphs = 1;
   int fd_mfma = 0;
+  int coarse_factor = 0;   // 0 auto, 1 host, 2 device
 };
 
 // Error with an igamg return code.
@@ -72,16 +77,27 @@ struct Hierarchy {
   ProblemH prob;
   Options opt;
   std::vector<LevelH> lv;
-  // coarse solver: A_0^{-1} = L^{-T} L^{-1} with A_0 = L L^T (dense, row-major, N0 x N0)
+  // coarse solver: A_0^{-1} = L^{-T} L^{-1} with A_0 = L L^T (dense, row-major, N0 x N0),
+  // factored on the host; or the dense A_0 itself, to be factored on the device
   std::vector<double> Ainv;
+  std::vector<double> A0;
 };
+
+
 
 // Validate and copy the C problem description.  Throws SetupError.
 ProblemH read_problem(const void* cprob);
 // Topology only (dof maps, pieces sizes): enough to size the workspace.
 void build_topology(Hierarchy& H, bool with_numerics);
 // Everything (assembly, smoothers, transfers, coarse factor).
-void build_all(Hierarchy& H);
+void build_all(Hierarchy& H, bool device);
+// One line on stderr per setup phase when IGAMG_VERBOSE is set.
+void setup_progress(const char* what, double value);
+// Whether the coarse problem is factored on the device (a device is
+// available and the options or the size ask for it).
+inline bool coarse_on_device(const Options& o, int64_t N0, bool device) {
+  return device && (o.coarse_factor == 2 || (o.coarse_factor == 0 && N0 > COARSE_HOST_MAX));
+}
 // Load vector of the finest level for src = amp * prod sin(freq*pi*x_c).
 std::vector<double> load_vector(const Hierarchy& H, double amp, double freq);
 

@@ -4,6 +4,8 @@
 // Every step of the cycle runs in the kernels of kernels.hip; the host only
 // sequences launches on the caller's stream.
 #include <hip/hip_runtime.h>
+#include <rocblas/rocblas.h>
+#include <rocsolver/rocsolver.h>
 
 #include <chrono>
 #include <cmath>
@@ -88,12 +90,20 @@ struct Bump {
 
 }  // namespace
 
+// rocSOLVER scratch for the device Cholesky and inverse of an n x n coarse
+// matrix (measured: 1.15 n^2 doubles at n = 30056), with margin
+static size_t coarse_ws_bytes(int64_t n) { return (size_t)(1.25 * 8.0 * (double)n * (double)n) + ((size_t)256 << 20); }
+
 struct igamg_ctx {
   Hierarchy H;
   int d = 2, p = 2, L = 1;
   bool mixed = false;
   std::vector<DevLevel> dl;
   double* Ainv = nullptr;
+  void* coarse_ws = nullptr;      // rocSOLVER scratch (device coarse factorization only; overlaps level data)
+  size_t coarse_ws_bytes = 0;
+  int* coarse_info = nullptr;
+  size_t scratch_at = 0;          // workspace offset where the level data (and that scratch) begins
   double* cb = nullptr;
   int64_t N0 = 0;
   PcgVecs<double> v64;
@@ -136,6 +146,19 @@ static void plan_level_data(Bump& b, const LevelH& L, DevLevel& D, LevelData<T>&
 static size_t plan(igamg_ctx& C, char* base) {
   Bump b{base};
   const Hierarchy& H = C.H;
+  // the coarse inverse first: a device factorization uses the space after it,
+  // which the level data occupies later, as rocSOLVER's scratch
+  C.N0 = H.lv[0].N;
+  C.Ainv = b.take<double>((size_t)C.N0 * C.N0);
+  C.cb = b.take<double>(C.N0);
+  const size_t scratch_at = b.pos;
+  size_t scratch_end = 0;
+  if (coarse_on_device(H.opt, C.N0, true)) {
+    C.coarse_info = reinterpret_cast<int*>(base ? base + scratch_at : nullptr);
+    C.coarse_ws = base ? base + scratch_at + 256 : nullptr;
+    C.coarse_ws_bytes = coarse_ws_bytes(C.N0);
+    scratch_end = scratch_at + 256 + C.coarse_ws_bytes;
+  }
   C.dl.assign(H.lv.size(), DevLevel{});
   for (size_t l = 0; l < H.lv.size(); ++l) {
     const LevelH& L = H.lv[l];
@@ -175,9 +198,6 @@ static size_t plan(igamg_ctx& C, char* base) {
     D.mfma_grid = fd_mfma_grid(L.fd.data(), (int)L.fd.size());
     D.mid_grid = fd_mid_grid(L.fd.data(), L.nfd_interior);
   }
-  C.N0 = H.lv[0].N;
-  C.Ainv = b.take<double>((size_t)C.N0 * C.N0);
-  C.cb = b.take<double>(C.N0);
   const int64_t NLf = H.lv.back().NL;
   C.v64.x = b.take<double>(NLf);
   C.v64.p = b.take<double>(NLf);
@@ -190,7 +210,8 @@ static size_t plan(igamg_ctx& C, char* base) {
   }
   C.part = b.take<double>(2 * RED_BLOCKS);
   C.scal = b.take<double>(16);
-  return b.pos + 256;
+  C.scratch_at = scratch_at;
+  return std::max(b.pos, scratch_end) + 256;
 }
 
 template <typename T>
@@ -203,9 +224,61 @@ static void up(T* dst, const std::vector<T>& src, hipStream_t st) {
 
 static std::vector<float> to_float(const std::vector<double>& v) { return std::vector<float>(v.begin(), v.end()); }
 
+// The exact coarse solver of large coarse problems (Sec. 4): Cholesky
+// A_0 = L L^T and the inverse A_0^{-1} from it, both by rocSOLVER on the
+// device in place of the dense A_0 (the library's workspace serves as
+// rocBLAS's, so nothing is allocated), then the lower triangle mirrored so
+// that the coarse mat-vec reads whole rows.
+static void factor_coarse_on_device(igamg_ctx& C, hipStream_t st) {
+  struct Handle {
+    rocblas_handle h = nullptr;
+    ~Handle() {
+      if (h) (void)rocblas_destroy_handle(h);
+    }
+  } H;
+  auto ok = [](rocblas_status s, const char* what) {
+    if (s != rocblas_status_success)
+      throw SetupError{IGAMG_EDEVICE, std::string(what) + ": " + rocblas_status_to_string(s)};
+  };
+  const rocblas_int n = (rocblas_int)C.N0;
+  ok(rocblas_create_handle(&H.h), "rocblas_create_handle");
+  ok(rocblas_set_stream(H.h, st), "rocblas_set_stream");
+  size_t need = 0;
+  ok(rocblas_start_device_memory_size_query(H.h), "rocblas_start_device_memory_size_query");
+  (void)rocsolver_dpotrf(H.h, rocblas_fill_lower, n, C.Ainv, n, C.coarse_info);   // size query only
+  (void)rocsolver_dpotri(H.h, rocblas_fill_lower, n, C.Ainv, n, C.coarse_info);
+  ok(rocblas_stop_device_memory_size_query(H.h, &need), "rocblas_stop_device_memory_size_query");
+  if (need > C.coarse_ws_bytes)
+    throw SetupError{IGAMG_ENOMEM, "coarse factorization needs " + std::to_string(need) + " bytes of workspace"};
+  ok(rocblas_set_workspace(H.h, C.coarse_ws, C.coarse_ws_bytes), "rocblas_set_workspace");
+  int info = 0;
+  ok(rocsolver_dpotrf(H.h, rocblas_fill_lower, n, C.Ainv, n, C.coarse_info), "rocsolver_dpotrf");
+  HIP_OK(hipMemcpyAsync(&info, C.coarse_info, sizeof(int), hipMemcpyDeviceToHost, st));
+  HIP_OK(hipStreamSynchronize(st));
+  if (info != 0)
+    throw SetupError{IGAMG_ENOTSPD, "coarse matrix is not positive definite (is any side Dirichlet?)"};
+  ok(rocsolver_dpotri(H.h, rocblas_fill_lower, n, C.Ainv, n, C.coarse_info), "rocsolver_dpotri");
+  HIP_OK(hipMemcpyAsync(&info, C.coarse_info, sizeof(int), hipMemcpyDeviceToHost, st));
+  HIP_OK(hipStreamSynchronize(st));
+  if (info != 0) throw SetupError{IGAMG_ENOTSPD, "coarse inverse failed"};
+  launch_mirror_lower(C.Ainv, C.N0, st);
+  HIP_OK(hipStreamSynchronize(st));
+}
+
 static void upload(igamg_ctx& C, hipStream_t st) {
   Hierarchy& H = C.H;
   HIP_OK(hipMemsetAsync(C.ws, 0, C.bytes, st));
+  if (!H.A0.empty()) {
+    up(C.Ainv, H.A0, st);
+    std::vector<double>().swap(H.A0);
+    factor_coarse_on_device(C, st);
+    // the scratch was lent from the level data: zero it again
+    HIP_OK(hipMemsetAsync(static_cast<char*>(C.ws) + C.scratch_at, 0, C.bytes - C.scratch_at, st));
+    HIP_OK(hipStreamSynchronize(st));
+    setup_progress("coarse matrix factored on the device; unknowns", (double)C.N0);
+  } else {
+    up(C.Ainv, H.Ainv, st);
+  }
   for (size_t l = 0; l < H.lv.size(); ++l) {
     LevelH& L = H.lv[l];
     DevLevel& D = C.dl[l];
@@ -226,6 +299,8 @@ static void upload(igamg_ctx& C, hipStream_t st) {
                       ROW_ALIGN * sizeof(double));
       up(D.d64.band, tiled, st);
       if (C.mixed) up(D.d32.band, to_float(tiled), st);
+      std::vector<double>().swap(L.band);
+      setup_progress("uploaded band of level", (double)l);
     }
     up(D.if_ptr, L.if_ptr, st);
     up(D.if_idx, L.if_idx, st);
@@ -241,7 +316,6 @@ static void upload(igamg_ctx& C, hipStream_t st) {
       up(D.d32.tr_val, to_float(L.tr_val), st);
     }
   }
-  up(C.Ainv, H.Ainv, st);
   // the bands are large and no longer needed on the host
   for (auto& L : H.lv) std::vector<double>().swap(L.band);
   std::vector<double>().swap(H.Ainv);
@@ -461,9 +535,11 @@ static void read_opts(const igamg_options* o, Options& O) {
   O.inner_tol = o->inner_tol;
   O.graphs = o->graphs;
   O.fd_mfma = o->fd_mfma;
+  O.coarse_factor = o->coarse_factor;
   if (!(O.tau > 0) || !(O.sigma_scale > 0) || O.nu < 1 || O.nu > 8 || (O.mu != 1 && O.mu != 2) ||
       (O.precision != IGAMG_FP64 && O.precision != IGAMG_MIXED) || O.maxit < 1 || O.inner_maxit < 1 ||
-      !(O.inner_tol > 0 && O.inner_tol < 1) || (O.fd_mfma != 0 && O.fd_mfma != 1))
+      !(O.inner_tol > 0 && O.inner_tol < 1) || (O.fd_mfma != 0 && O.fd_mfma != 1) ||
+      O.coarse_factor < 0 || O.coarse_factor > 2)
     throw SetupError{IGAMG_EINVAL, "invalid options"};
 }
 
@@ -497,6 +573,7 @@ struct Req {
   bool mixed = false, first_outer = true, fresh_done = false;
   int it = 0, iters = 0, outer = 0, code = IGAMG_OK;
   double n02 = 0.0, nf2 = 0.0, rel = 1.0;
+  double inner_target = 1e-4;   // relative residual reduction the current inner solve stops at
   std::chrono::steady_clock::time_point t0;
   double solve_ms = 0.0;
 };
@@ -607,6 +684,9 @@ static void rq_finish(Req& q, int code, hipStream_t st) {
 static void rq_start_inner(Req& q, hipStream_t st) {
   igamg_ctx& C = *q.C;
   DevLevel& D = C.dl[C.L];
+  // reduce the outer residual (relative value q.rel) just past the target,
+  // with a margin of 2, but never ask an FP32 solve for more than inner_tol
+  q.inner_target = std::max(C.H.opt.inner_tol, 0.5 * q.tol / std::max(q.rel, 1e-300));
   launch_to_f32(D.d32.f, D.d64.f, D.NL, st);
   pcg_start<float>(C, st);
   q.it = 0;
@@ -716,7 +796,7 @@ static bool rq_after_iter(Req& q, hipStream_t st) {
     }
     return true;
   }
-  if (rel <= O.inner_tol || q.it >= O.inner_maxit || q.iters >= O.maxit) {
+  if (rel <= q.inner_target || q.it >= O.inner_maxit || q.iters >= O.maxit) {
     rq_outer_update(q, st);
     return false;
   }
@@ -859,7 +939,7 @@ int igamg_setup(const igamg_problem* prob, const igamg_options* opts, void* work
     C->d = C->H.prob.d;
     C->p = C->H.prob.p;
     C->L = C->H.prob.levels - 1;
-    build_all(C->H);
+    build_all(C->H, workspace != nullptr);
     size_t need = plan(*C, nullptr);
     if (workspace) {
       if (bytes < need) throw SetupError{IGAMG_ENOMEM, "workspace too small: need " + std::to_string(need)};

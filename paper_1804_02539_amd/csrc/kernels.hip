@@ -622,6 +622,21 @@ void launch_fd_inv_mfma(const FDItem* items, int nitems, int gridx, size_t lds, 
                      (float)tau, (int)add);
 }
 
+// A[j + i n] = A[i + j n] for i > j: the column-major lower triangle copied
+// to the upper one (a symmetric matrix reads the same in either order)
+__global__ __launch_bounds__(256) void k_mirror_lower(double* __restrict__ A, int64_t n) {
+  const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (t >= n * n) return;
+  const int64_t i = t % n, j = t / n;
+  if (i > j) A[j + i * n] = A[i + j * n];
+}
+
+void launch_mirror_lower(double* A, int64_t n, hipStream_t st) {
+  const int64_t tot = n * n;
+  if (tot <= 0) return;
+  hipLaunchKernelGGL(k_mirror_lower, dim3((unsigned)((tot + 255) / 256)), dim3(256), 0, st, A, n);
+}
+
 size_t fd_dense_lds(int maxm, size_t elem) { return ((size_t)maxm * maxm + maxm) * elem + 64; }
 size_t fd_slab_lds(int maxm, size_t elem) { return ((size_t)maxm * maxm + (size_t)FD_RB * maxm) * elem + 64; }
 

@@ -271,3 +271,34 @@ def serving_families(n_families, seed=5, n_min=1e4, n_max=3e5, band_bytes_max=1.
         prob.meta["target_n"] = target
         fams.append(prob)
     return fams
+
+
+def batched_patch_cube(seed=4, p=5, divide=1, levels=None, n_range=(2e6, 4e6), counts=(8, 16, 24, 32, 48)):
+    """The unit cube as 4x4x4 equal-width patches with uneven element counts.
+
+    Per direction, the 4 slabs draw element counts from ``counts`` (seeded);
+    the draw is repeated until the number of free dofs N lies in ``n_range``.
+    Every interior macro vertex of the trilinear maps moves by up to 10% of
+    the patch width; full Dirichlet; p=5; 4 levels, so the coarsest level has
+    count/8 elements per slab; seeded U[-1,1] right-hand side.
+
+    ``divide`` = 4 gives the down-scaled replica: counts/4 at the finest of 2
+    levels, the same topology, degree, geometry and coarsest level.
+    """
+    rng = np.random.default_rng(seed)
+    while True:
+        slabs = [[int(c) for c in rng.choice(counts, size=4)] for _ in range(3)]
+        n = float(np.prod([sum(s) + 4 * p - 5 for s in slabs]))
+        if n_range[0] <= n <= n_range[1]:
+            break
+    if levels is None:
+        levels = 4 if divide == 1 else 4 - int(np.log2(divide))
+    fine = [[c // divide for c in s] for s in slabs]
+    nel0 = [[c // 2 ** (levels - 1) for c in s] for s in fine]
+    assert all(c * 2 ** (levels - 1) == f for s0, s1 in zip(nel0, fine) for c, f in zip(s0, s1))
+    name = "cube4x4x4_p%d" % p + ("" if divide == 1 else "_div%d" % divide)
+    prob = box_grid(3, [4, 4, 4], p, nel0, levels, gdeg=1, name=name)
+    perturb_interior_vertices_3d(prob, 0.1, rng)
+    prob.meta["source"] = ("random", seed)
+    prob.meta["slabs"] = fine
+    return prob
