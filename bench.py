@@ -94,6 +94,10 @@ def cpu_baseline(prob, rhs):
             "iterations": it, "solve_s": t}
 
 
+def log(msg):
+    print(f"[bench] {msg}", file=sys.stderr, flush=True)
+
+
 def run(workload, prob, precision, steps, warmup, dev, fd_mfma=0):
     import torch
     from paper_1804_02539_amd import igamg
@@ -101,6 +105,7 @@ def run(workload, prob, precision, steps, warmup, dev, fd_mfma=0):
     t0 = time.perf_counter()
     S = igamg.Solver(prob, opts, device=dev)
     setup_s = time.perf_counter() - t0
+    log(f"{workload} {precision}{' fd_mfma' if fd_mfma else ''}: setup {setup_s:.1f} s, N = {S.N}")
     f = torch.as_tensor(rhs_for(prob, S), device=dev)
     u = torch.empty_like(f)
     stream = torch.cuda.current_stream()
@@ -117,6 +122,7 @@ def run(workload, prob, precision, steps, warmup, dev, fd_mfma=0):
         iters.append((info.iterations, info.outer_iterations))
     torch.cuda.synchronize()
     total = time.perf_counter() - t_start
+    log(f"  timed pass: {1e3 * total / steps:.2f} ms/solve")
     # second timed pass of the same solves with a HIP event pair around every
     # banded-apply launch (direct launches: HIP does not time events in graphs)
     S.profile(True)
@@ -127,6 +133,7 @@ def run(workload, prob, precision, steps, warmup, dev, fd_mfma=0):
     torch.cuda.synchronize()
     total_prof = time.perf_counter() - t_p
     S.profile(False)
+    log(f"  profiled pass: {1e3 * total_prof / steps:.2f} ms/solve")
     cnt, ms, by = S.profile_read()
     nl = prob.levels
     Lf = nl - 1
@@ -281,9 +288,11 @@ def main():
     if "mixed_fd_mfma" in runs and "mixed" in runs:
         out["mixed_fd_mfma_vs_vector"] = runs["mixed_fd_mfma"]["value"] / runs["mixed"]["value"]
     if not a.no_serve:
+        log("serving")
         out["serving"] = serving("mixed" if head == "mixed" else "fp64", a.serve_requests,
                                  a.serve_families, 5, dev)
     if not a.no_cpu_baseline:
+        log("cpu baseline (oracle)")
         from paper_1804_02539_amd import igamg  # noqa: F401
         out["cpu_baseline"] = cpu_baseline(prob, rhs_for(prob, S))
     print(json.dumps(out), flush=True)
