@@ -152,6 +152,7 @@ def run(workload, prob, precision, steps, warmup, dev, fd_mfma=0):
         "refinements": int(np.median([o for _, o in iters])),
         "final_rel_residual": info.rel_residual,
         "converged": bool(info.converged),
+        "smoother_variant_finest": igamg.FD_NAMES[S.tuning(-1, precision == "mixed")],
         "setup_s": setup_s,
         "roofline": {"bound": "hbm",
                      "kernel": ("k_band<float> finest-level FP32 banded residual/apply (inner solves)"

@@ -86,13 +86,16 @@ typedef struct {
   int inner_maxit;       /* mixed: inner PCG iteration cap per refinement step (100) */
   double inner_tol;      /* mixed: the largest reduction an inner FP32 solve is asked for (1e-4) */
   int graphs;            /* 1: replay each PCG iteration as HIP graphs (default); 0: direct launches */
-  int fd_mfma;           /* mixed precision only: 1 runs the FP32 forward and inverse fast-diagonalization
-                            mode products on the matrix cores (v_mfma_f32_16x16x4f32); 0 (default) uses
-                            vector FMAs, which are faster for the tile sizes of this method (m <= 84) */
+  int fd_mfma;           /* FP32 fast-diagonalization mode products (mixed precision): 0 (default) as the
+                            autotuner chooses, 1 always on the matrix cores (v_mfma_f32_16x16x4f32),
+                            2 always vector FMAs */
   int coarse_factor;     /* factorization of the dense coarse matrix: 0 (default) on the host up to
                             3000 coarse unknowns and on the device (rocSOLVER Cholesky and inverse, in
                             the workspace) above; 1 always on the host; 2 always on the device */
-  int reserved[3];
+  int autotune;          /* 1 (default): at setup, time the smoother variants of every level and
+                            precision on the device and keep the fastest (igamg_tuning); 0: vector
+                            FMAs with 8-column chunks */
+  int reserved[2];
 } igamg_options;
 
 #define IGAMG_FP64 0
@@ -230,6 +233,21 @@ int igamg_export(igamg_handle h, int what, int level, double* out, int64_t* rows
  * launches of a mixed-precision handle.  Then it clears the record.          */
 int igamg_profile(igamg_handle h, int enable);
 int igamg_profile_read(igamg_handle h, int64_t* launches, double* ms, double* bytes);
+
+/* Smoother variants (tile shapes of the fast-diagonalization kernels).      */
+#define IGAMG_FD_VEC8 0   /* vector FMAs, chunks of 8 columns per workgroup     */
+#define IGAMG_FD_VEC4 1   /* vector FMAs, chunks of 4 columns per workgroup     */
+#define IGAMG_FD_MFMA 2   /* FP32 only: 16x16x4 matrix-core tiles, 8 columns    */
+
+/* The smoother variant level `level` (>= 1) uses in FP64 (fp32 = 0) or in
+ * the FP32 inner solves (fp32 = 1).  With options.autotune = 1 setup times
+ * each candidate (VEC8, VEC4, and MFMA for FP32 unless fd_mfma fixes it) on
+ * the device over a few smoother applications and keeps the fastest.  The
+ * choice is cached per process under a key of the level's piece shapes, the
+ * degree and the precision, so handles of the same problem agree (and their
+ * results are identical); the environment variable IGAMG_TUNE_CACHE names a
+ * JSON file that persists the cache between processes.                      */
+int igamg_tuning(igamg_handle h, int level, int fp32, int* variant);
 
 /* Release the handle (not the workspace).                                    */
 int igamg_destroy(igamg_handle h);

@@ -32,6 +32,7 @@ struct Options {
   int graphs = 1;
   int fd_mfma = 0;
   int coarse_factor = 0;   // 0 auto, 1 host, 2 device
+  int autotune = 1;
 };
 
 // Error with an igamg return code.

@@ -12,6 +12,8 @@
 #include <cstdio>
 #include <cstdlib>
 #include <cstring>
+#include <map>
+#include <mutex>
 #include <string>
 #include <type_traits>
 #include <vector>
@@ -56,6 +58,8 @@ struct DevLevel {
   DensePiece* dense = nullptr;
   int64_t* tr_idx = nullptr;
   int slab_grid = 1, mid_grid = 1, max_m2 = 1;
+  int slab_grid4 = 1;
+  int fdv[2] = {IGAMG_FD_VEC8, IGAMG_FD_VEC8};   // smoother variant per precision: [0] FP64, [1] FP32
   LevelData<double> d64;
   LevelData<float> d32;
 };
@@ -194,7 +198,8 @@ static size_t plan(igamg_ctx& C, char* base) {
     for (const auto& dp : L.dense) D.max_dense = std::max(D.max_dense, dp.m);
     D.max_m2 = 1;
     for (const auto& it : L.fd) D.max_m2 = std::max(D.max_m2, it.m[2]);
-    D.slab_grid = fd_slab_grid(L.fd.data(), (int)L.fd.size());
+    D.slab_grid = fd_slab_grid(L.fd.data(), (int)L.fd.size(), 8);
+    D.slab_grid4 = fd_slab_grid(L.fd.data(), (int)L.fd.size(), 4);
     D.mfma_grid = fd_mfma_grid(L.fd.data(), (int)L.fd.size());
     D.mid_grid = fd_mid_grid(L.fd.data(), L.nfd_interior);
   }
@@ -358,8 +363,9 @@ template <typename T>
 static void smoother_apply(igamg_ctx& C, int l, const T* src, T* u, bool add, double tau, hipStream_t st) {
   DevLevel& D = C.dl[l];
   LevelData<T>& X = dat<T>(D);
+  const int variant = D.fdv[std::is_same<T, float>::value ? 1 : 0];
   if constexpr (std::is_same<T, float>::value) {
-    if (C.H.opt.fd_mfma) {
+    if (variant == IGAMG_FD_MFMA) {
       // FP32: forward and inverse mode products on the matrix cores
       const size_t lds = std::max(fd_mfma_lds(D.fd_maxm), fd_dense_lds(D.max_dense, sizeof(T)));
       launch_fd_fwd_mfma(D.fd, D.nfd, D.ndense, D.mfma_grid, lds, D.dense, X.densemat, X.fdmat, src, u, D.if_ptr,
@@ -372,13 +378,15 @@ static void smoother_apply(igamg_ctx& C, int l, const T* src, T* u, bool add, do
     }
   }
   {
+    const int rb = variant == IGAMG_FD_VEC4 ? 4 : 8;
+    const int grid = variant == IGAMG_FD_VEC4 ? D.slab_grid4 : D.slab_grid;
     const size_t lds = std::max(fd_slab_lds(D.fd_maxm, sizeof(T)), fd_dense_lds(D.max_dense, sizeof(T)));
-    launch_fd_fwd<T>(D.fd, D.nfd, D.ndense, D.slab_grid, lds, D.dense, X.densemat, X.fdmat, src, u, D.if_ptr,
-                     D.if_idx, X.scr, tau, add, st);
+    launch_fd_fwd<T>(D.fd, D.nfd, D.ndense, grid, lds, D.dense, X.densemat, X.fdmat, src, u, D.if_ptr, D.if_idx,
+                     X.scr, tau, add, rb, st);
     if (C.d == 3 && D.nfd_int > 0 && D.max_m2 > 1)
       launch_fd_mid<T>(D.fd, D.nfd_int, D.mid_grid, fd_mid_lds(D.fd_maxm, sizeof(T)), X.fdmat, X.scr, st);
-    launch_fd_inv<T>(D.fd, D.nfd, D.slab_grid, fd_slab_lds(D.fd_maxm, sizeof(T)), X.fdmat, u, D.if_ptr, D.if_idx,
-                     X.scr, tau, add, st);
+    launch_fd_inv<T>(D.fd, D.nfd, grid, fd_slab_lds(D.fd_maxm, sizeof(T)), X.fdmat, u, D.if_ptr, D.if_idx, X.scr,
+                     tau, add, rb, st);
   }
 }
 
@@ -536,9 +544,10 @@ static void read_opts(const igamg_options* o, Options& O) {
   O.graphs = o->graphs;
   O.fd_mfma = o->fd_mfma;
   O.coarse_factor = o->coarse_factor;
+  O.autotune = o->autotune;
   if (!(O.tau > 0) || !(O.sigma_scale > 0) || O.nu < 1 || O.nu > 8 || (O.mu != 1 && O.mu != 2) ||
       (O.precision != IGAMG_FP64 && O.precision != IGAMG_MIXED) || O.maxit < 1 || O.inner_maxit < 1 ||
-      !(O.inner_tol > 0 && O.inner_tol < 1) || (O.fd_mfma != 0 && O.fd_mfma != 1) ||
+      !(O.inner_tol > 0 && O.inner_tol < 1) || O.fd_mfma < 0 || O.fd_mfma > 2 || O.autotune < 0 || O.autotune > 1 ||
       O.coarse_factor < 0 || O.coarse_factor > 2)
     throw SetupError{IGAMG_EINVAL, "invalid options"};
 }
@@ -552,6 +561,134 @@ static int check_level(igamg_ctx* h, int level) {
 static void need_device(igamg_ctx* h) {
   if (!h) throw SetupError{IGAMG_EINVAL, "null handle"};
   if (!h->on_device) throw SetupError{IGAMG_EINVAL, "handle was set up without a workspace"};
+}
+
+
+// ---------------------------------------------------------------------------
+// autotuner of the smoother variants (tile shapes), run once per handle at
+// setup: per level and precision, every candidate is timed over a few
+// smoother applications on the device and the fastest is kept.  Choices are
+// cached per process (and in the JSON file named by IGAMG_TUNE_CACHE) under
+// a key of the level's piece shapes, degree and precision.
+// ---------------------------------------------------------------------------
+namespace {
+std::mutex g_tune_mu;
+std::map<std::string, int> g_tune;
+bool g_tune_loaded = false;
+
+const char* tune_file() { return std::getenv("IGAMG_TUNE_CACHE"); }
+
+// the cache file is a flat JSON object of "key": variant pairs (keys are made
+// of digits, letters and the characters x , : / only)
+void tune_load_locked() {
+  if (g_tune_loaded) return;
+  g_tune_loaded = true;
+  const char* path = tune_file();
+  if (!path) return;
+  FILE* f = std::fopen(path, "r");
+  if (!f) return;
+  std::string text;
+  char buf[4096];
+  size_t n;
+  while ((n = std::fread(buf, 1, sizeof buf, f)) > 0) text.append(buf, n);
+  std::fclose(f);
+  size_t pos = 0;
+  while ((pos = text.find('"', pos)) != std::string::npos) {
+    const size_t end = text.find('"', pos + 1);
+    if (end == std::string::npos) break;
+    const std::string key = text.substr(pos + 1, end - pos - 1);
+    const size_t colon = text.find(':', end);
+    if (colon == std::string::npos) break;
+    const int v = std::atoi(text.c_str() + colon + 1);
+    if (v >= IGAMG_FD_VEC8 && v <= IGAMG_FD_MFMA) g_tune[key] = v;
+    pos = text.find_first_of(",}", colon);
+    if (pos == std::string::npos) break;
+  }
+}
+
+void tune_save_locked() {
+  const char* path = tune_file();
+  if (!path) return;
+  const std::string tmp = std::string(path) + ".tmp";
+  FILE* f = std::fopen(tmp.c_str(), "w");
+  if (!f) return;
+  std::fprintf(f, "{\n");
+  size_t i = 0;
+  for (const auto& kv : g_tune)
+    std::fprintf(f, "  \"%s\": %d%s\n", kv.first.c_str(), kv.second, ++i < g_tune.size() ? "," : "");
+  std::fprintf(f, "}\n");
+  std::fclose(f);
+  std::rename(tmp.c_str(), path);
+}
+}  // namespace
+
+static std::string tune_key(const igamg_ctx& C, int l, bool fp32) {
+  const LevelH& L = C.H.lv[l];
+  std::string k = "gfx950/d" + std::to_string(C.d) + "p" + std::to_string(C.p) + (fp32 ? "/f32/" : "/f64/");
+  for (const auto& it : L.fd)
+    k += std::to_string(it.m[0]) + "x" + std::to_string(it.m[1]) + "x" + std::to_string(it.m[2]) +
+         (it.src_if ? "f," : ",");
+  k += ":" + std::to_string(L.dense.size()) + "x" + std::to_string(C.dl[l].max_dense);
+  return k;
+}
+
+template <typename T>
+static double time_smoother(igamg_ctx& C, int l, hipStream_t st) {
+  LevelData<T>& X = dat<T>(C.dl[l]);
+  hipEvent_t a, b;
+  HIP_OK(hipEventCreate(&a));
+  HIP_OK(hipEventCreate(&b));
+  for (int i = 0; i < 2; ++i) smoother_apply<T>(C, l, X.f, X.u, false, C.H.opt.tau, st);
+  HIP_OK(hipEventRecord(a, st));
+  constexpr int reps = 5;
+  for (int i = 0; i < reps; ++i) smoother_apply<T>(C, l, X.f, X.u, false, C.H.opt.tau, st);
+  HIP_OK(hipEventRecord(b, st));
+  HIP_OK(hipEventSynchronize(b));
+  float ms = 0.f;
+  HIP_OK(hipEventElapsedTime(&ms, a, b));
+  (void)hipEventDestroy(a);
+  (void)hipEventDestroy(b);
+  return ms / reps;
+}
+
+template <typename T>
+static void tune_level(igamg_ctx& C, int l, hipStream_t st) {
+  constexpr bool fp32 = std::is_same<T, float>::value;
+  DevLevel& D = C.dl[l];
+  int& v = D.fdv[fp32 ? 1 : 0];
+  const Options& O = C.H.opt;
+  if (fp32 && O.fd_mfma == 1) { v = IGAMG_FD_MFMA; return; }
+  if (fp32 && O.fd_mfma == 2) { v = IGAMG_FD_VEC8; return; }
+  if (!O.autotune || D.nfd + D.ndense == 0) { v = IGAMG_FD_VEC8; return; }
+  const std::string key = tune_key(C, l, fp32);
+  {
+    std::lock_guard<std::mutex> lk(g_tune_mu);
+    tune_load_locked();
+    auto it = g_tune.find(key);
+    if (it != g_tune.end()) { v = it->second; return; }
+  }
+  std::vector<int> cand{IGAMG_FD_VEC8, IGAMG_FD_VEC4};
+  if (fp32) cand.push_back(IGAMG_FD_MFMA);
+  int best = IGAMG_FD_VEC8;
+  double best_ms = 1e300;
+  for (int c : cand) {
+    v = c;
+    const double ms = time_smoother<T>(C, l, st);
+    if (ms < best_ms) { best_ms = ms; best = c; }
+  }
+  std::lock_guard<std::mutex> lk(g_tune_mu);
+  auto ins = g_tune.emplace(key, best);   // a concurrent setup may have tuned the same shapes first
+  v = ins.first->second;
+  if (ins.second) tune_save_locked();
+}
+
+static void autotune(igamg_ctx& C, hipStream_t st) {
+  for (int l = 1; l <= C.L; ++l) {
+    tune_level<double>(C, l, st);
+    if (C.mixed) tune_level<float>(C, l, st);
+  }
+  HIP_OK(hipStreamSynchronize(st));
+  setup_progress("smoother variants chosen", 0);
 }
 
 // ---------------------------------------------------------------------------
@@ -909,6 +1046,7 @@ void igamg_default_options(igamg_options* o) {
   o->inner_maxit = 100;
   o->inner_tol = 1e-4;
   o->graphs = 1;
+  o->autotune = 1;
 }
 
 const char* igamg_last_error(void) { return g_err.c_str(); }
@@ -950,6 +1088,7 @@ int igamg_setup(const igamg_problem* prob, const igamg_options* opts, void* work
       HIP_OK(hipHostMalloc(reinterpret_cast<void**>(&C->host_scal), 16 * sizeof(double), hipHostMallocDefault));
       upload(*C, static_cast<hipStream_t>(stream));
       C->on_device = true;
+      autotune(*C, static_cast<hipStream_t>(stream));
     }
   } catch (...) {
     delete C;
@@ -1004,6 +1143,18 @@ int igamg_destroy(igamg_handle h) {
   if (h->host_scal) (void)hipHostFree(h->host_scal);
   delete h;
   return IGAMG_OK;
+}
+
+int igamg_tuning(igamg_handle h, int level, int fp32, int* variant) {
+  API_BEGIN
+  if (!h || !variant) return set_err(IGAMG_EINVAL, "null argument");
+  if (!h->on_device) return set_err(IGAMG_EINVAL, "handle has no device data");
+  level = check_level(h, level);
+  if (level < 1) return set_err(IGAMG_EINVAL, "level 0 has no smoother");
+  if (fp32 && !h->mixed) return set_err(IGAMG_EINVAL, "not a mixed-precision handle");
+  *variant = h->dl[level].fdv[fp32 ? 1 : 0];
+  return IGAMG_OK;
+  API_END
 }
 
 int igamg_num_dofs(igamg_handle h, int level, int64_t* n_free, int64_t* n_local) {

@@ -154,13 +154,13 @@ constexpr int FD_RB = 8;
 constexpr int FD_RPT = 3;
 static_assert(256 / MAX_FD >= 3 && (FD_RB + 2) / 3 <= FD_RPT, "chunk columns per thread");
 
-// A chunk is FD_RB columns (second tensor index) of one z-slab, so that the
+// A chunk is rb <= FD_RB columns (second tensor index) of one z-slab, so that the
 // results of a chunk are whole columns, contiguous in memory.
-__device__ __forceinline__ void fd_chunk(const FDItem& it, int& z, int& c0, int& nc) {
-  const int nch = (it.m[1] + FD_RB - 1) / FD_RB;
+__device__ __forceinline__ void fd_chunk(const FDItem& it, int rb, int& z, int& c0, int& nc) {
+  const int nch = (it.m[1] + rb - 1) / rb;
   z = blockIdx.x / nch;
-  c0 = (blockIdx.x - z * nch) * FD_RB;
-  nc = min(FD_RB, it.m[1] - c0);
+  c0 = (blockIdx.x - z * nch) * rb;
+  nc = min(rb, it.m[1] - c0);
 }
 
 // Thread (j, g) of a block: row j of the tensor, columns g*cpg .. of the chunk.
@@ -234,7 +234,7 @@ __global__ __launch_bounds__(256) void k_fd_fwd(const FDItem* __restrict__ items
                                                 const T* __restrict__ densemat, const T* __restrict__ mat,
                                                 const T* __restrict__ src, T* __restrict__ u,
                                                 const int64_t* __restrict__ if_ptr, const int64_t* __restrict__ if_idx,
-                                                T* __restrict__ scr, T tau, int add) {
+                                                T* __restrict__ scr, T tau, int add, int rb) {
   DYN_LDS(T, lds);
   const int y = blockIdx.y;
   if (y >= nitems) {
@@ -245,7 +245,7 @@ __global__ __launch_bounds__(256) void k_fd_fwd(const FDItem* __restrict__ items
   const FDItem it = items[y];
   const int m0 = it.m[0], m1 = it.m[1];
   int z, c0, nc;
-  fd_chunk(it, z, c0, nc);
+  fd_chunk(it, rb, z, c0, nc);
   if (z >= it.m[2]) return;
   const int n = m0 * m1;
   T* X = lds;                        // X[j + m0 b]; later U0[j m0 + a]
@@ -300,13 +300,13 @@ template <typename T>
 __global__ __launch_bounds__(256) void k_fd_inv(const FDItem* __restrict__ items, const T* __restrict__ mat,
                                                 T* __restrict__ u, const int64_t* __restrict__ if_ptr,
                                                 const int64_t* __restrict__ if_idx, const T* __restrict__ scr, T tau,
-                                                int add) {
+                                                int add, int rb) {
   // Z[:, c0 + c] = U0 (Y U1^T[:, c0 + c]) for the chunk's columns
   DYN_LDS(T, lds);
   const FDItem it = items[blockIdx.y];
   const int m0 = it.m[0], m1 = it.m[1];
   int z, c0, nc;
-  fd_chunk(it, z, c0, nc);
+  fd_chunk(it, rb, z, c0, nc);
   if (z >= it.m[2]) return;
   const int n = m0 * m1;
   T* Y = lds;                        // Y[j + m0 b]; later U0^T[j m0 + a]
@@ -640,9 +640,9 @@ void launch_mirror_lower(double* A, int64_t n, hipStream_t st) {
 size_t fd_dense_lds(int maxm, size_t elem) { return ((size_t)maxm * maxm + maxm) * elem + 64; }
 size_t fd_slab_lds(int maxm, size_t elem) { return ((size_t)maxm * maxm + (size_t)FD_RB * maxm) * elem + 64; }
 
-int fd_slab_grid(const FDItem* items, int nitems) {
+int fd_slab_grid(const FDItem* items, int nitems, int rb) {
   int g = 1;
-  for (int i = 0; i < nitems; ++i) g = std::max(g, items[i].m[2] * ((items[i].m[1] + FD_RB - 1) / FD_RB));
+  for (int i = 0; i < nitems; ++i) g = std::max(g, items[i].m[2] * ((items[i].m[1] + rb - 1) / rb));
   return g;
 }
 
@@ -664,11 +664,11 @@ size_t fd_mid_lds(int maxm, size_t elem) {
 template <typename T>
 void launch_fd_fwd(const FDItem* items, int nitems, int ndense, int gridx, size_t lds, const DensePiece* dense,
                    const T* densemat, const T* mat, const T* src, T* u, const int64_t* if_ptr, const int64_t* if_idx,
-                   T* scr, double tau, bool add, hipStream_t st) {
+                   T* scr, double tau, bool add, int rb, hipStream_t st) {
   const int ny = nitems + ndense;
   if (ny <= 0) return;
   hipLaunchKernelGGL(k_fd_fwd<T>, dim3(gridx, ny), dim3(256), lds, st, items, nitems, dense, densemat, mat, src, u,
-                     if_ptr, if_idx, scr, (T)tau, (int)add);
+                     if_ptr, if_idx, scr, (T)tau, (int)add, rb);
 }
 
 template <typename T>
@@ -679,10 +679,10 @@ void launch_fd_mid(const FDItem* items, int nitems, int gridx, size_t lds, const
 
 template <typename T>
 void launch_fd_inv(const FDItem* items, int nitems, int gridx, size_t lds, const T* mat, T* u, const int64_t* if_ptr,
-                   const int64_t* if_idx, const T* scr, double tau, bool add, hipStream_t st) {
+                   const int64_t* if_idx, const T* scr, double tau, bool add, int rb, hipStream_t st) {
   if (nitems <= 0) return;
   hipLaunchKernelGGL(k_fd_inv<T>, dim3(gridx, nitems), dim3(256), lds, st, items, mat, u, if_ptr, if_idx, scr, (T)tau,
-                     (int)add);
+                     (int)add, rb);
 }
 
 // ---------------------------------------------------------------------------
@@ -1098,10 +1098,10 @@ void launch_add_f32(double* x, const float* d, int64_t n, hipStream_t st) {
   template hipError_t launch_band<T>(int, int, const T*, const T*, const T*, T*, const int*, const PatchDev*, int64_t,   \
                                      bool, hipStream_t, hipEvent_t, hipEvent_t);                                       \
   template void launch_fd_fwd<T>(const FDItem*, int, int, int, size_t, const DensePiece*, const T*, const T*,          \
-                                 const T*, T*, const int64_t*, const int64_t*, T*, double, bool, hipStream_t);         \
+                                 const T*, T*, const int64_t*, const int64_t*, T*, double, bool, int, hipStream_t);    \
   template void launch_fd_mid<T>(const FDItem*, int, int, size_t, const T*, T*, hipStream_t);                          \
   template void launch_fd_inv<T>(const FDItem*, int, int, size_t, const T*, T*, const int64_t*, const int64_t*,        \
-                                 const T*, double, bool, hipStream_t);                                                 \
+                                 const T*, double, bool, int, hipStream_t);                                            \
   template void launch_restrict<T>(int, const T*, T*, const PatchDev*, const int*, int64_t, const int64_t*, const T*,  \
                                    int, const uint8_t*, hipStream_t);                                                  \
   template void launch_prolong_add<T>(int, const T*, T*, const PatchDev*, const int*, int64_t, const int64_t*,         \

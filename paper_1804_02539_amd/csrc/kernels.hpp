@@ -22,13 +22,15 @@ hipError_t launch_band(int d, int p, const T* band, const T* u, const T* f, T* r
 
 size_t fd_slab_lds(int maxm, size_t elem);
 size_t fd_dense_lds(int maxm, size_t elem);
-int fd_slab_grid(const FDItem* items, int nitems);
+// vector FD kernels: chunks of rb in {2, 4, 8} columns (FD_RB_MAX = 8)
+constexpr int FD_RB_MAX = 8;
+int fd_slab_grid(const FDItem* items, int nitems, int rb);
 int fd_mid_grid(const FDItem* items, int nitems);
 size_t fd_mid_lds(int maxm, size_t elem);
 template <typename T>
 void launch_fd_fwd(const FDItem* items, int nitems, int ndense, int gridx, size_t lds, const DensePiece* dense,
                    const T* densemat, const T* mat, const T* src, T* u, const int64_t* if_ptr, const int64_t* if_idx,
-                   T* scr, double tau, bool add, hipStream_t st);
+                   T* scr, double tau, bool add, int rb, hipStream_t st);
 // FP32 forward/inverse products on the matrix cores (16-column chunks)
 size_t fd_mfma_lds(int maxm);
 int fd_mfma_grid(const FDItem* items, int nitems);
@@ -42,7 +44,7 @@ template <typename T>
 void launch_fd_mid(const FDItem* items, int nitems, int gridx, size_t lds, const T* mat, T* scr, hipStream_t st);
 template <typename T>
 void launch_fd_inv(const FDItem* items, int nitems, int gridx, size_t lds, const T* mat, T* u, const int64_t* if_ptr,
-                   const int64_t* if_idx, const T* scr, double tau, bool add, hipStream_t st);
+                   const int64_t* if_idx, const T* scr, double tau, bool add, int rb, hipStream_t st);
 
 template <typename T>
 void launch_restrict(int d, const T* rf, T* rc, const PatchDev* pd, const int* bpatch_c, int64_t NLc,

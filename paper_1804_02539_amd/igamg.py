@@ -19,6 +19,8 @@ LIB_PATH = os.path.join(_HERE, "libigamg.so")
 
 OK, EINVAL, ETOPO, EGEOM, ENOMEM, ENOTSPD, ENOCONV, ENAN, EDEVICE = 0, -1, -2, -3, -4, -5, -6, -7, -8
 FP64, MIXED = 0, 1
+FD_VEC8, FD_VEC4, FD_MFMA = 0, 1, 2
+FD_NAMES = {FD_VEC8: "vec8", FD_VEC4: "vec4", FD_MFMA: "mfma"}
 OP_APPLY, OP_SMOOTHER, OP_PROLONG, OP_RESTRICT, OP_COARSE, OP_CYCLE_FP32 = 0, 1, 2, 3, 4, 5
 
 ERROR_NAMES = {EINVAL: "EINVAL", ETOPO: "ETOPO", EGEOM: "EGEOM", ENOMEM: "ENOMEM",
@@ -44,7 +46,7 @@ class Options(ctypes.Structure):
                 ("mu", ctypes.c_int), ("precision", ctypes.c_int), ("maxit", ctypes.c_int),
                 ("geometry_scaling", ctypes.c_int), ("inner_maxit", ctypes.c_int),
                 ("inner_tol", ctypes.c_double), ("graphs", ctypes.c_int), ("fd_mfma", ctypes.c_int),
-                ("coarse_factor", ctypes.c_int), ("reserved", ctypes.c_int * 3)]
+                ("coarse_factor", ctypes.c_int), ("autotune", ctypes.c_int), ("reserved", ctypes.c_int * 2)]
 
 
 class SolveInfo(ctypes.Structure):
@@ -80,6 +82,7 @@ def _load():
         "igamg_batch_remove": (ctypes.c_int, [vp, ctypes.c_int]),
         "igamg_solve_batch": (ctypes.c_int, [P(vp), P(vp), P(vp), ctypes.c_int, ctypes.c_double, P(SolveInfo),
                                               P(ctypes.c_int), vp]),
+        "igamg_tuning": (ctypes.c_int, [vp, ctypes.c_int, ctypes.c_int, P(ctypes.c_int)]),
         "igamg_destroy": (ctypes.c_int, [vp]),
         "igamg_last_error": (ctypes.c_char_p, []),
     }
@@ -95,7 +98,7 @@ EXPORTED = ["igamg_default_options", "igamg_workspace_size", "igamg_setup", "iga
             "igamg_load_vector", "igamg_vcycle", "igamg_solve", "igamg_operator", "igamg_dof_map",
             "igamg_export", "igamg_profile", "igamg_profile_read", "igamg_destroy",
             "igamg_last_error", "igamg_batch_create", "igamg_batch_destroy", "igamg_batch_add",
-            "igamg_batch_step", "igamg_batch_poll", "igamg_batch_remove", "igamg_solve_batch"]
+            "igamg_batch_step", "igamg_batch_poll", "igamg_batch_remove", "igamg_solve_batch", "igamg_tuning"]
 EXPORT_MATRIX, EXPORT_PROLONG = 0, 1
 
 
@@ -206,6 +209,13 @@ class Solver:
         _check(_lib.igamg_export(self.h, what, level, out.ctypes.data_as(ctypes.POINTER(ctypes.c_double)),
                                  None, None))
         return out
+
+    def tuning(self, level=-1, fp32=False):
+        """Smoother variant (FD_VEC8, FD_VEC4, FD_MFMA) of a level in FP64 or FP32."""
+        L = self.prob.levels - 1 if level < 0 else level
+        v = ctypes.c_int()
+        _check(_lib.igamg_tuning(self.h, L, int(fp32), ctypes.byref(v)))
+        return v.value
 
     def profile(self, enable):
         _check(_lib.igamg_profile(self.h, int(enable)))
