@@ -120,8 +120,12 @@ int igamg_workspace_size(const igamg_problem* prob, const igamg_options* opts, s
 /* Host setup (Sec. 5's setup phases: dof maps, refinement and transfer
  * matrices, piece smoothers, coarse factorisation) plus patch-wise Gauss
  * assembly of the banded matrices A_{l,k} (Sec. 4), then upload into
- * `workspace` on `stream`.  Synchronises the stream before returning.  The
- * handle keeps host copies of nothing large; the workspace must outlive it.
+ * `workspace` on `stream`.  Coarse problems factored on the device (see
+ * options.coarse_factor) are factored there by rocSOLVER, which gets a part of
+ * the workspace as scratch; then the smoother variants are autotuned (see
+ * igamg_tuning).  Synchronises the stream before returning.  The handle
+ * keeps host copies of nothing large; the workspace must outlive it.
+ * IGAMG_VERBOSE set in the environment prints one line per setup phase.
  * With workspace == NULL the handle stays on the host (for igamg_export and
  * the size queries; the solver entry points then return EINVAL).
  * Errors: EINVAL, ETOPO, EGEOM, ENOTSPD, ENOMEM (bytes too small), EDEVICE.  */

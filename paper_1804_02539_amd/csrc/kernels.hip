@@ -139,16 +139,17 @@ hipError_t launch_band(int d, int p, const T* band, const T* u, const T* f, T* r
 
 // ---------------------------------------------------------------------------
 // smoother kernels over 2D tensors (a 2D patch interior, a 3D face, or one
-// z-slab of a 3D patch interior), split into chunks of FD_RB output rows:
-//   forward:  Y[I, :] = (U0[:, I]^T X) U1     (rows I of U0^T X U1)
-//   inverse:  Z[J, :] = (U0[J, :] Y) U1^T     (rows J of U0 Y U1^T)
+// z-slab of a 3D patch interior), split into chunks of rb output columns K
+// (rb = 8 or 4, chosen per level by the autotuner):
+//   forward:  Y[:, K] = U0^T (X U1[:, K])     (columns K of U0^T X U1)
+//   inverse:  Z[:, K] = U0 (Y U1^T[:, K])     (columns K of U0 Y U1^T)
 // For 2D tensors the forward kernel applies D^{-1}; for 3D interiors the
 // middle direction (with D^{-1}) runs in between as a pencil pass.  The
 // forward launch also runs the dense pieces (edges, vertices).  Interface
 // items gather their residual from all copies (the accumulation Sigma) and
 // add tau z to every copy; interiors use the patch-local vectors directly.
 // ---------------------------------------------------------------------------
-constexpr int FD_RB = 8;
+constexpr int FD_RB = 8;   // widest chunk; also the column stride of the LDS tile C
 // columns of a chunk per thread: a 256-thread block has 256 / m0 >= 3 row
 // groups for m0 <= MAX_FD, so 8 columns need at most 3 per thread
 constexpr int FD_RPT = 3;
