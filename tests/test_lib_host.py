@@ -143,3 +143,10 @@ def test_binding_loads_a_single_hip_runtime():
     out = subprocess.run([sys.executable, "-c", code], capture_output=True, text=True, timeout=300)
     assert out.returncode == 0, out.stderr
     assert out.stdout.strip().splitlines()[-1] == "1"
+
+
+def test_piece_wider_than_the_smoother_kernels_is_rejected():
+    """Patches with more than 84 interior functions in a direction are
+    rejected at setup (the fast-diagonalization kernels hold an 84 x 84 tile)."""
+    prob = W.box_grid(2, [1, 1], 2, 2, 7, gdeg=1)      # 128 elements per direction at the finest level
+    _expect(igamg.EINVAL, lambda: igamg.Solver(prob, host_only=True))
