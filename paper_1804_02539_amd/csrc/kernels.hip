@@ -691,10 +691,10 @@ void launch_fd_inv(const FDItem* items, int nitems, int gridx, size_t lds, const
 // univariate knot-insertion matrices; Sec. 4: P maps accumulated to
 // accumulated, P^T distributed to distributed vectors)
 // ---------------------------------------------------------------------------
-template <int D, typename T>
+template <int D, int WR, typename T>
 __global__ __launch_bounds__(256) void k_restrict(const T* __restrict__ rf, T* __restrict__ rc,
                                                   const PatchDev* __restrict__ pd, const int* __restrict__ bpatch_c,
-                                                  const int64_t* __restrict__ tidx, const T* __restrict__ tval, int WR,
+                                                  const int64_t* __restrict__ tidx, const T* __restrict__ tval,
                                                   const uint8_t* __restrict__ isfree_c) {
   const int b = blockIdx.x;
   const int k = bpatch_c[b];
@@ -717,30 +717,40 @@ __global__ __launch_bounds__(256) void k_restrict(const T* __restrict__ rf, T* _
   const T* w2 = tval + P.Rval[2] + (int64_t)j2 * WR;
   const int n0 = P.n[0], n1 = P.n[1], n2 = P.n[2];
   const T* src = rf + P.off;
+  // WR is the table width: rows with fewer weights are padded with zeros, and
+  // clamped indices keep every read inside the patch
+  T v0[WR], v1[WR];
+  int ix0[WR];
+#pragma unroll
+  for (int a = 0; a < WR; ++a) {
+    v0[a] = w0[a];
+    v1[a] = w1[a];
+    ix0[a] = min(s0 + a, n0 - 1);
+  }
   T s = 0;
-  const int W2 = (D == 3) ? WR : 1;
+  constexpr int W2 = (D == 3) ? WR : 1;
+#pragma unroll
   for (int a2 = 0; a2 < W2; ++a2) {
-    const T c2 = w2[a2];
-    if (c2 == T(0)) continue;
+    const T c2 = (D == 3) ? w2[a2] : T(1);
     const int64_t z = (int64_t)min(s2 + a2, n2 - 1) * n0 * n1;
+#pragma unroll
     for (int a1 = 0; a1 < WR; ++a1) {
-      const T c1 = w1[a1] * c2;
-      if (c1 == T(0)) continue;
       const T* row = src + z + (int64_t)min(s1 + a1, n1 - 1) * n0;
       T acc = 0;
-      for (int a0 = 0; a0 < WR; ++a0) acc += w0[a0] * row[min(s0 + a0, n0 - 1)];
-      s += c1 * acc;
+#pragma unroll
+      for (int a0 = 0; a0 < WR; ++a0) acc += v0[a0] * row[ix0[a0]];
+      s += c2 * v1[a1] * acc;
     }
   }
   rc[g] = s;
 }
 
-template <int D, typename T>
+template <int D, int WP, typename T>
 __global__ __launch_bounds__(256) void k_prolong_add(const T* __restrict__ uc, T* __restrict__ uf,
                                                      const PatchDev* __restrict__ pd,
                                                      const int* __restrict__ bpatch_f,
                                                      const int64_t* __restrict__ tidx, const T* __restrict__ tval,
-                                                     int WP, const uint8_t* __restrict__ isfree_f) {
+                                                     const uint8_t* __restrict__ isfree_f) {
   const int b = blockIdx.x;
   const int k = bpatch_f[b];
   if (k < 0) return;
@@ -759,42 +769,75 @@ __global__ __launch_bounds__(256) void k_prolong_add(const T* __restrict__ uc, T
   const T* w2 = tval + P.Pval[2] + (int64_t)i2 * WP;
   const int n0 = P.nc[0], n1 = P.nc[1], n2 = P.nc[2];
   const T* src = uc + P.offc;
+  T v0[WP], v1[WP];
+  int ix0[WP];
+#pragma unroll
+  for (int a = 0; a < WP; ++a) {
+    v0[a] = w0[a];
+    v1[a] = w1[a];
+    ix0[a] = min(s0 + a, n0 - 1);
+  }
   T s = 0;
-  const int W2 = (D == 3) ? WP : 1;
+  constexpr int W2 = (D == 3) ? WP : 1;
+#pragma unroll
   for (int a2 = 0; a2 < W2; ++a2) {
-    const T c2 = w2[a2];
-    if (c2 == T(0)) continue;
+    const T c2 = (D == 3) ? w2[a2] : T(1);
     const int64_t z = (int64_t)min(s2 + a2, n2 - 1) * n0 * n1;
+#pragma unroll
     for (int a1 = 0; a1 < WP; ++a1) {
-      const T c1 = w1[a1] * c2;
-      if (c1 == T(0)) continue;
       const T* row = src + z + (int64_t)min(s1 + a1, n1 - 1) * n0;
       T acc = 0;
-      for (int a0 = 0; a0 < WP; ++a0) acc += w0[a0] * row[min(s0 + a0, n0 - 1)];
-      s += c1 * acc;
+#pragma unroll
+      for (int a0 = 0; a0 < WP; ++a0) acc += v0[a0] * row[ix0[a0]];
+      s += c2 * v1[a1] * acc;
     }
   }
   uf[g] += s;
 }
 
+template <int D, typename T>
+static void restrict_w(const T* rf, T* rc, const PatchDev* pd, const int* bpatch_c, int64_t NLc, const int64_t* tidx,
+                       const T* tval, int WR, const uint8_t* isfree_c, hipStream_t st) {
+  dim3 grid((unsigned)(NLc / ROW_ALIGN)), block(ROW_ALIGN);
+  switch (WR) {
+#define IGAMG_W(W) \
+  case W: hipLaunchKernelGGL((k_restrict<D, W, T>), grid, block, 0, st, rf, rc, pd, bpatch_c, tidx, tval, isfree_c); return;
+    IGAMG_W(1) IGAMG_W(2) IGAMG_W(3) IGAMG_W(4) IGAMG_W(5) IGAMG_W(6) IGAMG_W(7) IGAMG_W(8) IGAMG_W(9) IGAMG_W(10)
+#undef IGAMG_W
+    default: break;
+  }
+}
+
+template <int D, typename T>
+static void prolong_w(const T* uc, T* uf, const PatchDev* pd, const int* bpatch_f, int64_t NLf, const int64_t* tidx,
+                      const T* tval, int WP, const uint8_t* isfree_f, hipStream_t st) {
+  dim3 grid((unsigned)(NLf / ROW_ALIGN)), block(ROW_ALIGN);
+  switch (WP) {
+#define IGAMG_W(W) \
+  case W: hipLaunchKernelGGL((k_prolong_add<D, W, T>), grid, block, 0, st, uc, uf, pd, bpatch_f, tidx, tval, isfree_f); return;
+    IGAMG_W(1) IGAMG_W(2) IGAMG_W(3) IGAMG_W(4) IGAMG_W(5) IGAMG_W(6) IGAMG_W(7) IGAMG_W(8) IGAMG_W(9) IGAMG_W(10)
+#undef IGAMG_W
+    default: break;
+  }
+}
+
+// table widths are at most p + 2 <= 10 (p <= 8)
 template <typename T>
 void launch_restrict(int d, const T* rf, T* rc, const PatchDev* pd, const int* bpatch_c, int64_t NLc,
                      const int64_t* tidx, const T* tval, int WR, const uint8_t* isfree_c, hipStream_t st) {
-  dim3 grid((unsigned)(NLc / ROW_ALIGN)), block(ROW_ALIGN);
   if (d == 2)
-    hipLaunchKernelGGL((k_restrict<2, T>), grid, block, 0, st, rf, rc, pd, bpatch_c, tidx, tval, WR, isfree_c);
+    restrict_w<2, T>(rf, rc, pd, bpatch_c, NLc, tidx, tval, WR, isfree_c, st);
   else
-    hipLaunchKernelGGL((k_restrict<3, T>), grid, block, 0, st, rf, rc, pd, bpatch_c, tidx, tval, WR, isfree_c);
+    restrict_w<3, T>(rf, rc, pd, bpatch_c, NLc, tidx, tval, WR, isfree_c, st);
 }
 
 template <typename T>
 void launch_prolong_add(int d, const T* uc, T* uf, const PatchDev* pd, const int* bpatch_f, int64_t NLf,
                         const int64_t* tidx, const T* tval, int WP, const uint8_t* isfree_f, hipStream_t st) {
-  dim3 grid((unsigned)(NLf / ROW_ALIGN)), block(ROW_ALIGN);
   if (d == 2)
-    hipLaunchKernelGGL((k_prolong_add<2, T>), grid, block, 0, st, uc, uf, pd, bpatch_f, tidx, tval, WP, isfree_f);
+    prolong_w<2, T>(uc, uf, pd, bpatch_f, NLf, tidx, tval, WP, isfree_f, st);
   else
-    hipLaunchKernelGGL((k_prolong_add<3, T>), grid, block, 0, st, uc, uf, pd, bpatch_f, tidx, tval, WP, isfree_f);
+    prolong_w<3, T>(uc, uf, pd, bpatch_f, NLf, tidx, tval, WP, isfree_f, st);
 }
 
 // ---------------------------------------------------------------------------
