@@ -226,6 +226,36 @@ def serving(precision, n_requests, n_families, seed, dev):
                            "[1e4, 3e5] free dofs per family, fresh U[-1,1] rhs per request"}
 
 
+def fichera_table(degrees, max_level, dev):
+    """FP64 PCG iteration counts on the Fichera corner with K=448 patches
+    (Sec. 5: 7 unit cubes split into 4^3 patches each, 1 element per patch on
+    the coarsest level, f = 75 pi^2 sin 5 pi x sin 5 pi y sin 5 pi z), beside
+    the counts the paper prints for the same cases."""
+    import torch
+    from paper_1804_02539_amd import igamg, workloads as W
+    with open(os.path.join(ROOT, "tests", "golden", "iteration_counts.json")) as fh:
+        paper = json.load(fh)["fichera_K448"]
+    rows = []
+    for p in degrees:
+        for lev in range(1, max_level + 1):
+            prob = W.fichera(p, lev + 1, split=4)
+            t0 = time.perf_counter()
+            S = igamg.Solver(prob, device=dev)
+            setup = time.perf_counter() - t0
+            f = torch.as_tensor(S.load_vector(75.0 * np.pi ** 2, 5.0), device=dev)
+            u, info = S.solve(f, tol=1e-8)
+            ref = paper.get(str(lev), {}).get(str(p))
+            rows.append({"p": p, "level": lev, "N": S.N, "N0": int(S.num_dofs(0)[0]),
+                         "iterations": info.iterations, "paper": ref, "converged": bool(info.converged),
+                         "rel_residual": info.rel_residual, "setup_s": round(setup, 1),
+                         "solve_ms": round(info.solve_ms, 1)})
+            log(f"fichera p={p} l={lev}: N={S.N}, {info.iterations} it (paper {ref}), setup {setup:.1f} s, "
+                f"solve {info.solve_ms:.0f} ms")
+            del S, u, f
+            torch.cuda.empty_cache()
+    return {"fichera_K448": rows}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -235,6 +265,10 @@ def main():
     ap.add_argument("--precision", default="both", choices=["both", "fp64", "mixed"])
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-serve", action="store_true")
+    ap.add_argument("--fichera-table", default="",
+                    help="instead of the benchmark line, print FP64 iteration counts on the Fichera corner "
+                         "(K=448) for these degrees, e.g. 2,3,4, levels 1..--fichera-max-level")
+    ap.add_argument("--fichera-max-level", type=int, default=4)
     ap.add_argument("--fd-mfma", action="store_true",
                     help="also time the mixed solver with the smoother's FP32 mode products on the matrix cores")
     ap.add_argument("--copy-calibration", action="store_true",
@@ -250,6 +284,10 @@ def main():
     import torch  # noqa: F401
 
     dev = "cuda:0"
+    if a.fichera_table:
+        degrees = [int(x) for x in a.fichera_table.split(",")]
+        print(json.dumps(fichera_table(degrees, a.fichera_max_level, dev)), flush=True)
+        return
     if a.copy_calibration:
         x = torch.empty(64 << 20, dtype=torch.float32, device=dev)
         x.fill_(1.0)

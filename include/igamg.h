@@ -90,8 +90,9 @@ typedef struct {
                             autotuner chooses, 1 always on the matrix cores (v_mfma_f32_16x16x4f32),
                             2 always vector FMAs */
   int coarse_factor;     /* factorization of the dense coarse matrix: 0 (default) on the host up to
-                            3000 coarse unknowns and on the device (rocSOLVER Cholesky and inverse, in
-                            the workspace) above; 1 always on the host; 2 always on the device */
+                            3000 coarse unknowns and on the device (rocSOLVER Cholesky, then the
+                            inverse by blocked solves against I, in the workspace) above; 1 always on
+                            the host; 2 always on the device; at most 60000 coarse unknowns */
   int autotune;          /* 1 (default): at setup, time the smoother variants of every level and
                             precision on the device and keep the fastest (igamg_tuning); 0: vector
                             FMAs with 8-column chunks */

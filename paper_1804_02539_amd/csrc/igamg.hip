@@ -96,7 +96,13 @@ struct Bump {
 
 // rocSOLVER scratch for the device Cholesky and inverse of an n x n coarse
 // matrix (measured: 1.15 n^2 doubles at n = 30056), with margin
-static size_t coarse_ws_bytes(int64_t n) { return (size_t)(1.25 * 8.0 * (double)n * (double)n) + ((size_t)256 << 20); }
+// device coarse factorization: the factor (n x n, column-major, padded to 256
+// bytes) followed by rocBLAS's workspace, a quarter of the factor's size plus
+// 256 MiB (the inverse is formed in column blocks narrow enough to fit it)
+static size_t coarse_factor_bytes(int64_t n) { return ((size_t)n * (size_t)n * sizeof(double) + 255) & ~(size_t)255; }
+static size_t coarse_ws_bytes(int64_t n) {
+  return coarse_factor_bytes(n) + (size_t)(0.25 * 8.0 * (double)n * (double)n) + ((size_t)256 << 20);
+}
 
 struct igamg_ctx {
   Hierarchy H;
@@ -106,7 +112,7 @@ struct igamg_ctx {
   double* Ainv = nullptr;
   void* coarse_ws = nullptr;      // rocSOLVER scratch (device coarse factorization only; overlaps level data)
   size_t coarse_ws_bytes = 0;
-  int* coarse_info = nullptr;
+  int64_t* coarse_info = nullptr;
   size_t scratch_at = 0;          // workspace offset where the level data (and that scratch) begins
   double* cb = nullptr;
   int64_t N0 = 0;
@@ -155,10 +161,10 @@ static size_t plan(igamg_ctx& C, char* base) {
   C.N0 = H.lv[0].N;
   C.Ainv = b.take<double>((size_t)C.N0 * C.N0);
   C.cb = b.take<double>(C.N0);
-  const size_t scratch_at = b.pos;
+  const size_t scratch_at = (b.pos + 255) & ~size_t(255);
   size_t scratch_end = 0;
   if (coarse_on_device(H.opt, C.N0, true)) {
-    C.coarse_info = reinterpret_cast<int*>(base ? base + scratch_at : nullptr);
+    C.coarse_info = reinterpret_cast<int64_t*>(base ? base + scratch_at : nullptr);
     C.coarse_ws = base ? base + scratch_at + 256 : nullptr;
     C.coarse_ws_bytes = coarse_ws_bytes(C.N0);
     scratch_end = scratch_at + 256 + C.coarse_ws_bytes;
@@ -230,10 +236,13 @@ static void up(T* dst, const std::vector<T>& src, hipStream_t st) {
 static std::vector<float> to_float(const std::vector<double>& v) { return std::vector<float>(v.begin(), v.end()); }
 
 // The exact coarse solver of large coarse problems (Sec. 4): Cholesky
-// A_0 = L L^T and the inverse A_0^{-1} from it, both by rocSOLVER on the
-// device in place of the dense A_0 (the library's workspace serves as
-// rocBLAS's, so nothing is allocated), then the lower triangle mirrored so
-// that the coarse mat-vec reads whole rows.
+// A_0 = L L^T by rocSOLVER on the device, then A_0^{-1} = L^{-T} L^{-1} by
+// solving L L^T X = I in blocks of columns.  The 64-bit (ILP64) entry points
+// are used throughout: the 32-bit ones take n and lda as 32-bit integers, and
+// A_0 of a coarse grid with more than 46,340 unknowns has more than 2^31
+// entries.  A_0 and L live at the start of the scratch region (which the level
+// data occupies later), rocBLAS's workspace after them, and the inverse is
+// formed in place of the identity in its own region, so nothing is allocated.
 static void factor_coarse_on_device(igamg_ctx& C, hipStream_t st) {
   struct Handle {
     rocblas_handle h = nullptr;
@@ -245,28 +254,46 @@ static void factor_coarse_on_device(igamg_ctx& C, hipStream_t st) {
     if (s != rocblas_status_success)
       throw SetupError{IGAMG_EDEVICE, std::string(what) + ": " + rocblas_status_to_string(s)};
   };
-  const rocblas_int n = (rocblas_int)C.N0;
+  const int64_t n = C.N0;
+  double* Lf = static_cast<double*>(C.coarse_ws);
+  const size_t lbytes = coarse_factor_bytes(n);
+  char* ws = static_cast<char*>(C.coarse_ws) + lbytes;
+  const size_t ws_bytes = C.coarse_ws_bytes - lbytes;
   ok(rocblas_create_handle(&H.h), "rocblas_create_handle");
   ok(rocblas_set_stream(H.h, st), "rocblas_set_stream");
-  size_t need = 0;
-  ok(rocblas_start_device_memory_size_query(H.h), "rocblas_start_device_memory_size_query");
-  (void)rocsolver_dpotrf(H.h, rocblas_fill_lower, n, C.Ainv, n, C.coarse_info);   // size query only
-  (void)rocsolver_dpotri(H.h, rocblas_fill_lower, n, C.Ainv, n, C.coarse_info);
-  ok(rocblas_stop_device_memory_size_query(H.h, &need), "rocblas_stop_device_memory_size_query");
-  if (need > C.coarse_ws_bytes)
-    throw SetupError{IGAMG_ENOMEM, "coarse factorization needs " + std::to_string(need) + " bytes of workspace"};
-  ok(rocblas_set_workspace(H.h, C.coarse_ws, C.coarse_ws_bytes), "rocblas_set_workspace");
-  int info = 0;
-  ok(rocsolver_dpotrf(H.h, rocblas_fill_lower, n, C.Ainv, n, C.coarse_info), "rocsolver_dpotrf");
-  HIP_OK(hipMemcpyAsync(&info, C.coarse_info, sizeof(int), hipMemcpyDeviceToHost, st));
+  auto query = [&](int64_t k) {
+    size_t need = 0;
+    ok(rocblas_start_device_memory_size_query(H.h), "rocblas_start_device_memory_size_query");
+    if (k == 0)
+      (void)rocsolver_dpotrf_64(H.h, rocblas_fill_lower, n, Lf, n, C.coarse_info);
+    else
+      (void)rocsolver_dpotrs_64(H.h, rocblas_fill_lower, n, k, Lf, n, C.Ainv, n);
+    ok(rocblas_stop_device_memory_size_query(H.h, &need), "rocblas_stop_device_memory_size_query");
+    return need;
+  };
+  const size_t need_f = query(0);
+  if (need_f > ws_bytes)
+    throw SetupError{IGAMG_ENOMEM, "coarse factorization needs " + std::to_string(need_f) + " bytes of workspace"};
+  int64_t kb = std::min<int64_t>(n, 8192);
+  while (kb > 64 && query(kb) > ws_bytes) kb /= 2;
+  if (query(kb) > ws_bytes)
+    throw SetupError{IGAMG_ENOMEM, "coarse inverse needs " + std::to_string(query(kb)) + " bytes of workspace"};
+  ok(rocblas_set_workspace(H.h, ws, ws_bytes), "rocblas_set_workspace");
+  int64_t info = 0;
+  ok(rocsolver_dpotrf_64(H.h, rocblas_fill_lower, n, Lf, n, C.coarse_info), "rocsolver_dpotrf_64");
+  HIP_OK(hipMemcpyAsync(&info, C.coarse_info, sizeof(info), hipMemcpyDeviceToHost, st));
   HIP_OK(hipStreamSynchronize(st));
   if (info != 0)
     throw SetupError{IGAMG_ENOTSPD, "coarse matrix is not positive definite (is any side Dirichlet?)"};
-  ok(rocsolver_dpotri(H.h, rocblas_fill_lower, n, C.Ainv, n, C.coarse_info), "rocsolver_dpotri");
-  HIP_OK(hipMemcpyAsync(&info, C.coarse_info, sizeof(int), hipMemcpyDeviceToHost, st));
-  HIP_OK(hipStreamSynchronize(st));
-  if (info != 0) throw SetupError{IGAMG_ENOTSPD, "coarse inverse failed"};
-  launch_mirror_lower(C.Ainv, C.N0, st);
+  setup_progress("coarse Cholesky factor on the device; unknowns", (double)n);
+  launch_set_diagonal(C.Ainv, n, 1.0, st);   // the region is zero: now the identity
+  for (int64_t c0 = 0; c0 < n; c0 += kb) {
+    const int64_t k = std::min(kb, n - c0);
+    ok(rocsolver_dpotrs_64(H.h, rocblas_fill_lower, n, k, Lf, n, C.Ainv + c0 * n, n), "rocsolver_dpotrs_64");
+  }
+  // column j of the result is A_0^{-1} e_j; copying the lower triangle over the
+  // upper one makes the stored inverse exactly symmetric
+  launch_mirror_lower(C.Ainv, n, st);
   HIP_OK(hipStreamSynchronize(st));
 }
 
@@ -274,7 +301,7 @@ static void upload(igamg_ctx& C, hipStream_t st) {
   Hierarchy& H = C.H;
   HIP_OK(hipMemsetAsync(C.ws, 0, C.bytes, st));
   if (!H.A0.empty()) {
-    up(C.Ainv, H.A0, st);
+    up(static_cast<double*>(C.coarse_ws), H.A0, st);
     std::vector<double>().swap(H.A0);
     factor_coarse_on_device(C, st);
     // the scratch was lent from the level data: zero it again

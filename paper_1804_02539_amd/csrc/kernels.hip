@@ -624,18 +624,33 @@ void launch_fd_inv_mfma(const FDItem* items, int nitems, int gridx, size_t lds, 
 }
 
 // A[j + i n] = A[i + j n] for i > j: the column-major lower triangle copied
-// to the upper one (a symmetric matrix reads the same in either order)
+// to the upper one (a symmetric matrix reads the same in either order); a
+// grid-stride loop, since n^2 may exceed what one dispatch can index
 __global__ __launch_bounds__(256) void k_mirror_lower(double* __restrict__ A, int64_t n) {
-  const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (t >= n * n) return;
-  const int64_t i = t % n, j = t / n;
-  if (i > j) A[j + i * n] = A[i + j * n];
+  const int64_t tot = n * n;
+  const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+  for (int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; t < tot; t += stride) {
+    const int64_t i = t % n, j = t / n;
+    if (i > j) A[j + i * n] = A[i + j * n];
+  }
 }
 
 void launch_mirror_lower(double* A, int64_t n, hipStream_t st) {
   const int64_t tot = n * n;
   if (tot <= 0) return;
-  hipLaunchKernelGGL(k_mirror_lower, dim3((unsigned)((tot + 255) / 256)), dim3(256), 0, st, A, n);
+  const int64_t blocks = std::min<int64_t>((tot + 255) / 256, (int64_t)1 << 20);
+  hipLaunchKernelGGL(k_mirror_lower, dim3((unsigned)blocks), dim3(256), 0, st, A, n);
+}
+
+// A[i + i n] = v for i < n
+__global__ __launch_bounds__(256) void k_set_diagonal(double* __restrict__ A, int64_t n, double v) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) A[i + i * n] = v;
+}
+
+void launch_set_diagonal(double* A, int64_t n, double v, hipStream_t st) {
+  if (n <= 0) return;
+  hipLaunchKernelGGL(k_set_diagonal, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, st, A, n, v);
 }
 
 size_t fd_dense_lds(int maxm, size_t elem) { return ((size_t)maxm * maxm + maxm) * elem + 64; }

@@ -77,6 +77,7 @@ void launch_fill(T* x, int64_t n, double v, hipStream_t st);
 template <typename T>
 void launch_copy(T* y, const T* x, int64_t n, hipStream_t st);
 void launch_mirror_lower(double* A, int64_t n, hipStream_t st);
+void launch_set_diagonal(double* A, int64_t n, double v, hipStream_t st);
 void launch_to_f32(float* y, const double* x, int64_t n, hipStream_t st);
 void launch_to_f64(double* y, const float* x, int64_t n, hipStream_t st);
 void launch_add_f32(double* x, const float* d, int64_t n, hipStream_t st);

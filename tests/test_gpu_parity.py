@@ -31,6 +31,7 @@ CASES = {
     "cube2x2x2_p3_l4": lambda: W.cube_2x2x2_trilinear(levels=4),
     "cube2x2x2_p2_l3": lambda: W.cube_2x2x2_trilinear(p=2, levels=3),
     "fichera7_p2_l3": lambda: W.fichera(2, 3),
+    "fichera448_p3_l1": lambda: W.fichera(3, 2, split=4),
     "box3x1_p1_l4": lambda: W.box_grid(2, [3, 1], 1, 2, 4, gdeg=1, dirichlet_sides=[0]),
     "single_patch_p5_l3": lambda: W.box_grid(2, [1, 1], 5, 2, 3, gdeg=1),
     "cube_p4_l3_neumann": lambda: W.box_grid(3, [2, 1, 1], 4, 1, 3, gdeg=1, dirichlet_sides=[0, 2]),
@@ -106,7 +107,8 @@ def test_wcycle_matches_oracle(torch_cuda):
     assert rel(S.vcycle(r).cpu().numpy(), H.vcycle(r)) < 1e-10
 
 
-@pytest.mark.parametrize("name", ["square2x2_p2", "square4x4_p4_l4", "cube2x2x2_p3_l4", "fichera7_p2_l3"])
+@pytest.mark.parametrize("name", ["square2x2_p2", "square4x4_p4_l4", "cube2x2x2_p3_l4", "fichera7_p2_l3",
+                                  "fichera448_p3_l1"])
 def test_solve_matches_oracle(torch_cuda, name):
     from oracle.multigrid import load_vector
     _say(f"solve {name}")
