@@ -226,7 +226,7 @@ def serving(precision, n_requests, n_families, seed, dev):
                            "[1e4, 3e5] free dofs per family, fresh U[-1,1] rhs per request"}
 
 
-def fichera_table(degrees, max_level, dev):
+def fichera_table(degrees, levels, dev):
     """FP64 PCG iteration counts on the Fichera corner with K=448 patches
     (Sec. 5: 7 unit cubes split into 4^3 patches each, 1 element per patch on
     the coarsest level, f = 75 pi^2 sin 5 pi x sin 5 pi y sin 5 pi z), beside
@@ -237,7 +237,7 @@ def fichera_table(degrees, max_level, dev):
         paper = json.load(fh)["fichera_K448"]
     rows = []
     for p in degrees:
-        for lev in range(1, max_level + 1):
+        for lev in levels:
             prob = W.fichera(p, lev + 1, split=4)
             t0 = time.perf_counter()
             S = igamg.Solver(prob, device=dev)
@@ -267,8 +267,8 @@ def main():
     ap.add_argument("--no-serve", action="store_true")
     ap.add_argument("--fichera-table", default="",
                     help="instead of the benchmark line, print FP64 iteration counts on the Fichera corner "
-                         "(K=448) for these degrees, e.g. 2,3,4, levels 1..--fichera-max-level")
-    ap.add_argument("--fichera-max-level", type=int, default=4)
+                         "(K=448) for these degrees, e.g. 2,3,4, on the levels --fichera-levels")
+    ap.add_argument("--fichera-levels", default="1,2,3,4")
     ap.add_argument("--fd-mfma", action="store_true",
                     help="also time the mixed solver with the smoother's FP32 mode products on the matrix cores")
     ap.add_argument("--copy-calibration", action="store_true",
@@ -286,7 +286,8 @@ def main():
     dev = "cuda:0"
     if a.fichera_table:
         degrees = [int(x) for x in a.fichera_table.split(",")]
-        print(json.dumps(fichera_table(degrees, a.fichera_max_level, dev)), flush=True)
+        levels = [int(x) for x in a.fichera_levels.split(",")]
+        print(json.dumps(fichera_table(degrees, levels, dev)), flush=True)
         return
     if a.copy_calibration:
         x = torch.empty(64 << 20, dtype=torch.float32, device=dev)

@@ -92,7 +92,7 @@ typedef struct {
   int coarse_factor;     /* factorization of the dense coarse matrix: 0 (default) on the host up to
                             3000 coarse unknowns and on the device (rocSOLVER Cholesky, then the
                             inverse by blocked solves against I, in the workspace) above; 1 always on
-                            the host; 2 always on the device; at most 60000 coarse unknowns */
+                            the host; 2 always on the device; at most 100000 coarse unknowns */
   int autotune;          /* 1 (default): at setup, time the smoother variants of every level and
                             precision on the device and keep the fastest (igamg_tuning); 0: vector
                             FMAs with 8-column chunks */

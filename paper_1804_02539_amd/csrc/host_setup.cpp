@@ -1005,7 +1005,7 @@ void build_all(Hierarchy& H, bool device) {
   // coarse matrix (dense, free dofs of level 0) and its inverse Cholesky factor
   LevelH& L0 = H.lv[0];
   const int64_t N0 = L0.N;
-  if (N0 > 60000) fail(IGAMG_EINVAL, "coarse problem too large for the dense coarse solver");
+  if (N0 > 100000) fail(IGAMG_EINVAL, "coarse problem too large for the dense coarse solver");
   Mat A((size_t)N0 * N0, 0.0);
   const int d = P.d, p = P.p;
   const int nb0 = 2 * p + 1, nb1 = 2 * p + 1, p2 = (d == 3) ? p : 0, nb2 = 2 * p2 + 1;

@@ -290,6 +290,10 @@ static void factor_coarse_on_device(igamg_ctx& C, hipStream_t st) {
   for (int64_t c0 = 0; c0 < n; c0 += kb) {
     const int64_t k = std::min(kb, n - c0);
     ok(rocsolver_dpotrs_64(H.h, rocblas_fill_lower, n, k, Lf, n, C.Ainv + c0 * n, n), "rocsolver_dpotrs_64");
+    if (n > 20000) {   // large inverses take minutes: one progress line per block
+      HIP_OK(hipStreamSynchronize(st));
+      setup_progress("coarse inverse, columns done", (double)(c0 + k));
+    }
   }
   // column j of the result is A_0^{-1} e_j; copying the lower triangle over the
   // upper one makes the stored inverse exactly symmetric
