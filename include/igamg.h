@@ -96,7 +96,11 @@ typedef struct {
   int autotune;          /* 1 (default): at setup, time the smoother variants of every level and
                             precision on the device and keep the fastest (igamg_tuning); 0: vector
                             FMAs with 8-column chunks */
-  int reserved[2];
+  int assembly;          /* banded matrices of levels >= 1: 0 (default) assembled on the device by
+                            sum-factorised Gauss quadrature, straight into the workspace; 1 on the host
+                            and uploaded (level 0, which forms the coarse matrix, is always assembled
+                            on the host) */
+  int reserved[1];
 } igamg_options;
 
 #define IGAMG_FP64 0
@@ -119,9 +123,11 @@ void igamg_default_options(igamg_options* opts);
 int igamg_workspace_size(const igamg_problem* prob, const igamg_options* opts, size_t* bytes);
 
 /* Host setup (Sec. 5's setup phases: dof maps, refinement and transfer
- * matrices, piece smoothers, coarse factorisation) plus patch-wise Gauss
- * assembly of the banded matrices A_{l,k} (Sec. 4), then upload into
- * `workspace` on `stream`.  Coarse problems factored on the device (see
+ * matrices, piece smoothers, coarse factorisation) and patch-wise Gauss
+ * assembly of the banded matrices A_{l,k} (Sec. 4), uploaded into `workspace`
+ * on `stream`.  By default (options.assembly) the levels above the coarsest
+ * are assembled on the device, directly into the workspace, with a part of
+ * the workspace as scratch.  Coarse problems factored on the device (see
  * options.coarse_factor) are factored there by rocSOLVER, which gets a part of
  * the workspace as scratch; then the smoother variants are autotuned (see
  * igamg_tuning).  Synchronises the stream before returning.  The handle

@@ -29,7 +29,7 @@ def build():
     os.makedirs(BUILD, exist_ok=True)
     objs = []
     procs = []
-    for src in ["kernels.hip", "igamg.hip"]:
+    for src in ["kernels.hip", "assemble.hip", "igamg.hip"]:
         obj = os.path.join(BUILD, src + ".o")
         cmd = [HIPCC] + HIP_FLAGS + ["-c", os.path.join(CSRC, src), "-o", obj]
         print(" ".join(cmd), flush=True)

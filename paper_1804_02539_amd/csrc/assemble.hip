@@ -1,0 +1,134 @@
+// Device assembly of the banded patch matrices A_{l,k} (Sec. 4):
+//
+//   A_k[i][j] = sum over Gauss points x of w(x) grad B_i(x)^T C(x) grad B_j(x),
+//   C = |det J| J^{-1} J^{-T}, J the Jacobian of the patch's Bezier map,
+//
+// with p+1 Gauss points per element and direction.  The tensor-product rule
+// is contracted one direction at a time (sum factorisation), one element slab
+// of direction 2 at a time:
+//   metric  Gs[ab][q2][q1][q0]        = w C_ab at the slab's points
+//   dir 0   T1[ab][q2][q1][o0][i0]     = sum_q0 Gs[ab] F0^{a==0}_{i0} F0^{b==0}_{j0}
+//   dir 1   T2[g][q2][i1][o1][o0][i0]  = sum_{(a,b) in g} sum_q1 F1^{a==1}_{i1} F1^{b==1}_{j1} T1[ab]
+//   dir 2   band[(i0,i1,i2)][(o0,o1,o2)] += sum_g sum_q2 F2^{s}_{i2} F2^{t}_{j2} T2[g]
+// where F^1 is the derivative and F^0 the value of a 1D basis function, j =
+// i + o - p, and g groups the (a, b) pairs by their direction-2 flags
+// (s, t) = (a == 2, b == 2).  Every output entry is owned by one thread, the
+// slabs of a patch are ordered on the stream, and i0 is the fastest index of
+// every intermediate, so all stages read and write coalesced and the last one
+// writes whole rows of the tiled band
+// band[(row/256)*nb*256 + o*256 + row%256].
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+
+#include "assemble_stages.hpp"
+#include "kernels.hpp"
+
+namespace igamg {
+
+namespace {
+
+// grid of at most 2^32 threads (every launch here stays far below)
+inline dim3 grid_for(int64_t tot) { return dim3((unsigned)((tot + 255) / 256)); }
+
+template <int D>
+__global__ __launch_bounds__(256) void k_asm_metric(AsmPatch P, const double* __restrict__ tab, int e2,
+                                                    double* __restrict__ Gs, int* __restrict__ flag) {
+  const int64_t tot = (int64_t)P.nq[2] * P.nel[1] * P.nq[1] * P.nel[0] * P.nq[0];
+  const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const bool valid = t < tot;
+  const double det = valid ? asm_metric_point<D>(P, tab, e2, t, Gs) : 1.0;
+  // the sign of det J over the patch, one atomic per wave: bit 0 positive,
+  // bit 1 negative, bit 2 zero or not a number
+  const unsigned long long pos = __ballot(valid && det > 0.0);
+  const unsigned long long neg = __ballot(valid && det < 0.0);
+  const unsigned long long bad = __ballot(valid && !(det > 0.0 || det < 0.0));
+  if ((threadIdx.x & 63) == 0) {
+    const int f = (pos ? 1 : 0) | (neg ? 2 : 0) | (bad ? 4 : 0);
+    if (f) atomicOr(flag, f);
+  }
+}
+
+template <int D>
+__global__ __launch_bounds__(256) void k_asm_dir0(AsmPatch P, const double* __restrict__ tab,
+                                                  const double* __restrict__ Gs, double* __restrict__ T1,
+                                                  int64_t tot) {
+  const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (t < tot) T1[t] = asm_dir0_entry<D>(P, tab, Gs, t);
+}
+
+template <int D>
+__global__ __launch_bounds__(256) void k_asm_dir1(AsmPatch P, const double* __restrict__ tab,
+                                                  const double* __restrict__ T1, double* __restrict__ T2,
+                                                  int64_t tot) {
+  const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (t < tot) T2[t] = asm_dir1_entry<D>(P, tab, T1, t);
+}
+
+template <int D, int P2>
+__global__ __launch_bounds__(256) void k_asm_dir2(AsmPatch P, const double* __restrict__ tab, int e2,
+                                                  const double* __restrict__ T2, double* __restrict__ band, int nbt,
+                                                  int64_t tot) {
+  const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (t < tot) asm_dir2_entry<D, P2>(P, tab, e2, T2, band, nbt, t);
+}
+
+template <int D>
+__global__ __launch_bounds__(256) void k_asm_mask(const PatchDev* __restrict__ pd, const int* __restrict__ bpatch,
+                                                  const uint8_t* __restrict__ isfree, double* __restrict__ band,
+                                                  int nbt, int p, int64_t tot) {
+  const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (t < tot) asm_mask_entry<D>(pd, bpatch, isfree, band, nbt, p, t);
+}
+
+template <int D, int P2>
+void launch_dir2(const AsmPatch& P, const double* tab, int e2, const double* T2, double* band, int nbt,
+                 hipStream_t st) {
+  const int64_t inner = asm_dir2_threads(P);
+  hipLaunchKernelGGL((k_asm_dir2<D, P2>), grid_for(inner), dim3(256), 0, st, P, tab, e2, T2, band, nbt, inner);
+}
+
+}  // namespace
+
+void asm_slab_sizes(int d, const AsmPatch& P, size_t out[3]) { asm_sizes(d, P, out); }
+
+hipError_t launch_asm_slab(int d, const AsmPatch& P, const double* tab, int e2, double* Gs, double* T1, double* T2,
+                           double* band, int nbt, int* flag, hipStream_t st) {
+  size_t sz[3];
+  asm_slab_sizes(d, P, sz);
+  const int p = P.pc[0];
+  if (d == 2) {
+    hipLaunchKernelGGL(k_asm_metric<2>, grid_for((int64_t)sz[0] / 4), dim3(256), 0, st, P, tab, e2, Gs, flag);
+    hipLaunchKernelGGL(k_asm_dir0<2>, grid_for((int64_t)sz[1]), dim3(256), 0, st, P, tab, Gs, T1, (int64_t)sz[1]);
+    hipLaunchKernelGGL(k_asm_dir1<2>, grid_for((int64_t)sz[2]), dim3(256), 0, st, P, tab, T1, T2, (int64_t)sz[2]);
+    launch_dir2<2, 0>(P, tab, e2, T2, band, nbt, st);
+    return hipGetLastError();
+  }
+  if (d != 3 || p < 1 || p > MAX_P) return hipErrorInvalidValue;
+  hipLaunchKernelGGL(k_asm_metric<3>, grid_for((int64_t)sz[0] / 9), dim3(256), 0, st, P, tab, e2, Gs, flag);
+  hipLaunchKernelGGL(k_asm_dir0<3>, grid_for((int64_t)sz[1]), dim3(256), 0, st, P, tab, Gs, T1, (int64_t)sz[1]);
+  hipLaunchKernelGGL(k_asm_dir1<3>, grid_for((int64_t)sz[2]), dim3(256), 0, st, P, tab, T1, T2, (int64_t)sz[2]);
+  switch (p) {
+    case 1: launch_dir2<3, 1>(P, tab, e2, T2, band, nbt, st); break;
+    case 2: launch_dir2<3, 2>(P, tab, e2, T2, band, nbt, st); break;
+    case 3: launch_dir2<3, 3>(P, tab, e2, T2, band, nbt, st); break;
+    case 4: launch_dir2<3, 4>(P, tab, e2, T2, band, nbt, st); break;
+    case 5: launch_dir2<3, 5>(P, tab, e2, T2, band, nbt, st); break;
+    case 6: launch_dir2<3, 6>(P, tab, e2, T2, band, nbt, st); break;
+    case 7: launch_dir2<3, 7>(P, tab, e2, T2, band, nbt, st); break;
+    default: launch_dir2<3, 8>(P, tab, e2, T2, band, nbt, st); break;
+  }
+  return hipGetLastError();
+}
+
+void launch_asm_mask(int d, int p, const PatchDev* pd, const int* bpatch, const uint8_t* isfree, double* band,
+                     int nbt, int64_t NL, hipStream_t st) {
+  const int64_t tot = NL * nbt;
+  if (tot <= 0) return;
+  if (d == 2)
+    hipLaunchKernelGGL(k_asm_mask<2>, grid_for(tot), dim3(256), 0, st, pd, bpatch, isfree, band, nbt, p, tot);
+  else
+    hipLaunchKernelGGL(k_asm_mask<3>, grid_for(tot), dim3(256), 0, st, pd, bpatch, isfree, band, nbt, p, tot);
+}
+
+}  // namespace igamg

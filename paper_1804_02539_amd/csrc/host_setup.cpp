@@ -517,6 +517,40 @@ static void assemble_level(const ProblemH& P, LevelH& L) {
   }
 }
 
+void make_assembly_tables(const ProblemH& P, const LevelH& L, std::vector<AsmPatch>& pt, std::vector<double>& pool) {
+  const int d = P.d, p = P.p;
+  pt.assign(P.K, AsmPatch{});
+  pool.clear();
+  auto put = [&](const std::vector<double>& v) {
+    const int64_t at = (int64_t)pool.size();
+    pool.insert(pool.end(), v.begin(), v.end());
+    return at;
+  };
+  for (int k = 0; k < P.K; ++k) {
+    AsmPatch& a = pt[k];
+    a.off = L.off[k];
+    for (int c = 0; c < 3; ++c) {
+      const bool dummy = c >= d;
+      const Quad1D Q = quad_1d(p, dummy ? 1 : L.nel[k][c], dummy);
+      a.n[c] = L.n[k][c];
+      a.nel[c] = dummy ? 1 : L.nel[k][c];
+      a.pc[c] = Q.pc;
+      a.nq[c] = dummy ? 1 : Q.nq;
+      a.g[c] = dummy ? 0 : P.gdeg[k * d + c];
+      a.w[c] = put(Q.w);
+      a.val[c] = put(Q.val);
+      a.der[c] = put(Q.der);
+      const int gc = a.g[c];
+      std::vector<double> bv(Q.x.size() * (gc + 1), 1.0), bd(Q.x.size() * (gc + 1), 0.0);
+      if (!dummy)
+        for (size_t i = 0; i < Q.x.size(); ++i) bernstein(gc, Q.x[i], &bv[i * (gc + 1)], &bd[i * (gc + 1)]);
+      a.gv[c] = put(bv);
+      a.gd[c] = put(bd);
+    }
+    a.ctrl = put(P.ctrl[k]);
+  }
+}
+
 // ---------------------------------------------------------------------------
 // smoother pieces
 // ---------------------------------------------------------------------------
@@ -998,7 +1032,8 @@ void build_topology(Hierarchy& H, bool with_numerics) {
 void build_all(Hierarchy& H, bool device) {
   build_topology(H, true);
   const ProblemH& P = H.prob;
-  for (int l = 0; l < P.levels; ++l) {
+  const int nasm = assemble_on_device(H.opt, device) ? 1 : P.levels;
+  for (int l = 0; l < nasm; ++l) {
     assemble_level(P, H.lv[l]);
     setup_progress("assembled level", l);
   }

@@ -33,6 +33,7 @@ struct Options {
   int fd_mfma = 0;
   int coarse_factor = 0;   // 0 auto, 1 host, 2 device
   int autotune = 1;
+  int assembly = 0;        // levels >= 1: 0 on the device when there is one, 1 on the host
 };
 
 // Error with an igamg return code.
@@ -90,8 +91,14 @@ struct Hierarchy {
 ProblemH read_problem(const void* cprob);
 // Topology only (dof maps, pieces sizes): enough to size the workspace.
 void build_topology(Hierarchy& H, bool with_numerics);
-// Everything (assembly, smoothers, transfers, coarse factor).
+// Everything (assembly, smoothers, transfers, coarse factor).  Levels >= 1
+// are left unassembled when they will be assembled on the device.
 void build_all(Hierarchy& H, bool device);
+// Whether levels >= 1 are assembled on the device.
+inline bool assemble_on_device(const Options& o, bool device) { return device && o.assembly == 0; }
+// Quadrature, basis and geometry tables of every patch of level L for device
+// assembly: one descriptor per patch, offsets into `pool`.
+void make_assembly_tables(const ProblemH& P, const LevelH& L, std::vector<AsmPatch>& pt, std::vector<double>& pool);
 // One line on stderr per setup phase when IGAMG_VERBOSE is set.
 void setup_progress(const char* what, double value);
 // Whether the coarse problem is factored on the device (a device is

@@ -114,6 +114,10 @@ struct igamg_ctx {
   size_t coarse_ws_bytes = 0;
   int64_t* coarse_info = nullptr;
   size_t scratch_at = 0;          // workspace offset where the level data (and that scratch) begins
+  // device assembly scratch (setup only; after the level data): per-patch
+  // det J sign flags, a level's tables, one element slab's intermediates
+  int* asm_flag = nullptr;
+  double *asm_tab = nullptr, *asm_gs = nullptr, *asm_t1 = nullptr, *asm_t2 = nullptr;
   double* cb = nullptr;
   int64_t N0 = 0;
   PcgVecs<double> v64;
@@ -222,6 +226,25 @@ static size_t plan(igamg_ctx& C, char* base) {
   C.part = b.take<double>(2 * RED_BLOCKS);
   C.scal = b.take<double>(16);
   C.scratch_at = scratch_at;
+  if (assemble_on_device(H.opt, true) && H.lv.size() > 1) {
+    size_t pool = 0, sz_max[3] = {0, 0, 0};
+    for (size_t l = 1; l < H.lv.size(); ++l) {
+      std::vector<AsmPatch> pt;
+      std::vector<double> tab;
+      make_assembly_tables(H.prob, H.lv[l], pt, tab);
+      pool = std::max(pool, tab.size());
+      for (const AsmPatch& a : pt) {
+        size_t sz[3];
+        asm_slab_sizes(H.prob.d, a, sz);
+        for (int i = 0; i < 3; ++i) sz_max[i] = std::max(sz_max[i], sz[i]);
+      }
+    }
+    C.asm_flag = b.take<int>(H.prob.K);
+    C.asm_tab = b.take<double>(pool);
+    C.asm_gs = b.take<double>(sz_max[0]);
+    C.asm_t1 = b.take<double>(sz_max[1]);
+    C.asm_t2 = b.take<double>(sz_max[2]);
+  }
   return std::max(b.pos, scratch_end) + 256;
 }
 
@@ -301,6 +324,36 @@ static void factor_coarse_on_device(igamg_ctx& C, hipStream_t st) {
   HIP_OK(hipStreamSynchronize(st));
 }
 
+// Assembles level l's banded patch matrices on the device, straight into its
+// tiled FP64 band (and the FP32 copy); the level's patch table, free flags and
+// row-block map must be on the device already.
+static void device_assemble(igamg_ctx& C, size_t l, hipStream_t st) {
+  const Hierarchy& H = C.H;
+  const LevelH& L = H.lv[l];
+  DevLevel& D = C.dl[l];
+  const int d = H.prob.d, K = H.prob.K;
+  std::vector<AsmPatch> pt;
+  std::vector<double> tab;
+  make_assembly_tables(H.prob, L, pt, tab);
+  up(C.asm_tab, tab, st);
+  HIP_OK(hipMemsetAsync(C.asm_flag, 0, (size_t)K * sizeof(int), st));
+  for (int k = 0; k < K; ++k)
+    for (int e2 = 0; e2 < pt[k].nel[2]; ++e2)
+      HIP_OK(launch_asm_slab(d, pt[k], C.asm_tab, e2, C.asm_gs, C.asm_t1, C.asm_t2, D.d64.band, D.nb, C.asm_flag + k,
+                             st));
+  launch_asm_mask(d, H.prob.p, D.pd, D.bpatch, D.isfree, D.d64.band, D.nb, D.NL, st);
+  HIP_OK(hipGetLastError());
+  std::vector<int> flags(K, 0);
+  HIP_OK(hipMemcpyAsync(flags.data(), C.asm_flag, (size_t)K * sizeof(int), hipMemcpyDeviceToHost, st));
+  HIP_OK(hipStreamSynchronize(st));
+  for (int k = 0; k < K; ++k)
+    if ((flags[k] & 4) || ((flags[k] & 1) && (flags[k] & 2)))
+      throw SetupError{IGAMG_EGEOM, "patch " + std::to_string(k) + ": det J vanishes or changes sign"};
+  if (C.mixed) launch_to_f32(D.d32.band, D.d64.band, (int64_t)D.nb * D.NL, st);
+  HIP_OK(hipStreamSynchronize(st));
+  setup_progress("assembled on the device: level", (double)l);
+}
+
 static void upload(igamg_ctx& C, hipStream_t st) {
   Hierarchy& H = C.H;
   HIP_OK(hipMemsetAsync(C.ws, 0, C.bytes, st));
@@ -324,7 +377,9 @@ static void upload(igamg_ctx& C, hipStream_t st) {
     up(D.gptr, L.gptr, st);
     up(D.gidx, L.gidx, st);
     if (l == 0) continue;
-    {
+    if (assemble_on_device(H.opt, true)) {
+      device_assemble(C, l, st);
+    } else {
       // tiled coefficient-major: the (2p+1)^d planes of each 256-row block are
       // contiguous, band[(row/256)*nb*256 + o*256 + row%256]
       std::vector<double> tiled(L.band.size());
@@ -576,10 +631,11 @@ static void read_opts(const igamg_options* o, Options& O) {
   O.fd_mfma = o->fd_mfma;
   O.coarse_factor = o->coarse_factor;
   O.autotune = o->autotune;
+  O.assembly = o->assembly;
   if (!(O.tau > 0) || !(O.sigma_scale > 0) || O.nu < 1 || O.nu > 8 || (O.mu != 1 && O.mu != 2) ||
       (O.precision != IGAMG_FP64 && O.precision != IGAMG_MIXED) || O.maxit < 1 || O.inner_maxit < 1 ||
       !(O.inner_tol > 0 && O.inner_tol < 1) || O.fd_mfma < 0 || O.fd_mfma > 2 || O.autotune < 0 || O.autotune > 1 ||
-      O.coarse_factor < 0 || O.coarse_factor > 2)
+      O.coarse_factor < 0 || O.coarse_factor > 2 || O.assembly < 0 || O.assembly > 1)
     throw SetupError{IGAMG_EINVAL, "invalid options"};
 }
 

@@ -79,6 +79,17 @@ void launch_copy(T* y, const T* x, int64_t n, hipStream_t st);
 void launch_mirror_lower(double* A, int64_t n, hipStream_t st);
 void launch_set_diagonal(double* A, int64_t n, double v, hipStream_t st);
 void launch_to_f32(float* y, const double* x, int64_t n, hipStream_t st);
+
+// device assembly (assemble.hip): doubles of one element slab's metric (Gs),
+// direction-0 (T1) and direction-1 (T2) intermediates of a patch
+void asm_slab_sizes(int d, const AsmPatch& P, size_t out[3]);
+// adds slab e2's contribution of patch P to the tiled FP64 band (nbt =
+// (2p+1)^d coefficients per row); ORs the sign bits of det J into *flag
+hipError_t launch_asm_slab(int d, const AsmPatch& P, const double* tab, int e2, double* Gs, double* T1, double* T2,
+                           double* band, int nbt, int* flag, hipStream_t st);
+// zeroes the couplings of Dirichlet functions and those leaving the patch
+void launch_asm_mask(int d, int p, const PatchDev* pd, const int* bpatch, const uint8_t* isfree, double* band,
+                     int nbt, int64_t NL, hipStream_t st);
 void launch_to_f64(double* y, const float* x, int64_t n, hipStream_t st);
 void launch_add_f32(double* x, const float* d, int64_t n, hipStream_t st);
 

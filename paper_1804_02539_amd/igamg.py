@@ -46,7 +46,8 @@ class Options(ctypes.Structure):
                 ("mu", ctypes.c_int), ("precision", ctypes.c_int), ("maxit", ctypes.c_int),
                 ("geometry_scaling", ctypes.c_int), ("inner_maxit", ctypes.c_int),
                 ("inner_tol", ctypes.c_double), ("graphs", ctypes.c_int), ("fd_mfma", ctypes.c_int),
-                ("coarse_factor", ctypes.c_int), ("autotune", ctypes.c_int), ("reserved", ctypes.c_int * 2)]
+                ("coarse_factor", ctypes.c_int), ("autotune", ctypes.c_int), ("assembly", ctypes.c_int),
+                ("reserved", ctypes.c_int * 1)]
 
 
 class SolveInfo(ctypes.Structure):
