@@ -241,9 +241,12 @@ static size_t plan(igamg_ctx& C, char* base) {
     }
     C.asm_flag = b.take<int>(H.prob.K);
     C.asm_tab = b.take<double>(pool);
-    C.asm_gs = b.take<double>(sz_max[0]);
+    // Gs is dead once direction 0 has read it, and T2 is written only after
+    // that (the next slab's metric stage follows this slab's last stage on
+    // the stream), so the two share one region
+    C.asm_gs = b.take<double>(std::max(sz_max[0], sz_max[2]));
+    C.asm_t2 = C.asm_gs;
     C.asm_t1 = b.take<double>(sz_max[1]);
-    C.asm_t2 = b.take<double>(sz_max[2]);
   }
   return std::max(b.pos, scratch_end) + 256;
 }
