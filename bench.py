@@ -226,6 +226,57 @@ def serving(precision, n_requests, n_families, seed, dev):
                            "[1e4, 3e5] free dofs per family, fresh U[-1,1] rhs per request"}
 
 
+def serving_full(n_requests, n_families, rate, seed, dev, precision="mixed"):
+    """The full serving recipe: ``n_requests`` seeded requests over
+    ``n_families`` problem families (2D with 4-16 patches, 3D with 8-64, p in
+    2..6, N log-uniform in [1e4, 4e6]) arriving as a Poisson process at
+    ``rate`` per second into a cold server.  Every hierarchy is set up inside
+    the served time (device assembly, on two worker threads), under an HBM
+    budget of 80% of the free device memory; idle hierarchies are evicted
+    least recently used first when a new one does not fit."""
+    import torch
+    from paper_1804_02539_amd import igamg, serve
+    opts = igamg.default_options(precision=igamg.MIXED if precision == "mixed" else igamg.FP64)
+    fams, reqs = serve.request_mix(n_requests, seed=seed, n_families=n_families, n_min=1e4, n_max=4e6,
+                                   band_bytes_max=60e9, n0_max=8000)
+    free, _ = torch.cuda.mem_get_info()
+    budget = int(0.8 * free)
+    ws = [igamg.workspace_size(f, opts) for f in fams]
+    log(f"serve-full: {n_families} families, workspaces {min(ws) / 1e6:.0f} MB .. {max(ws) / 1e9:.1f} GB "
+        f"(sum {sum(ws) / 1e9:.0f} GB), budget {budget / 1e9:.0f} GB, {n_requests} requests at {rate}/s")
+    S = serve.Server(budget, opts=opts, device=dev, handles_per_key=1, setup_workers=2, keep_results=False)
+    offs = serve.poisson_offsets(n_requests, rate, seed=seed)
+
+    def progress(srv, t):
+        log(f"serve-full: {t:.0f} s, {len(srv.finished)} done, {len(srv.pending)} waiting, "
+            f"{len(srv.setups)} setting up, {len(srv.running)} running, {srv.used / 1e9:.0f} GB held")
+
+    t = S.run([(float(o), r) for o, r in zip(offs, reqs)], timeout=1000.0, progress=progress)
+    S.close()
+    st = S.stats(t)
+    n = np.array(sorted(r.n for r in S.finished))
+    lat = np.array([r.latency for r in S.finished])
+    big = lat[np.array([r.n for r in S.finished]) >= 1e6]
+    setups = sum(1 for e in S.events if e[1] == "resident")
+    out = {"requests": n_requests, "families": n_families, "precision": precision, "arrival_rate_per_s": rate,
+           "finished": st["requests"], "rejected": st["rejected"], "failed": st["failed"],
+           "free_dofs": {"min": int(n[0]), "median": int(np.median(n)), "max": int(n[-1]),
+                         "requests_over_1e6": int((n >= 1e6).sum())},
+           "hbm_budget_bytes": budget, "peak_held_bytes": S.peak_used, "setups": setups,
+           "evictions": st["evictions"], "makespan_s": t, "requests_per_s": st["requests_per_s"],
+           "dofs_per_s": st["dofs_per_s"], "latency_ms": st["latency_ms"],
+           "rejections": sorted({str(r.error)[:160] for r in S.rejected}),
+           "setup_errors": [e[2][:160] for e in S.events if e[1] == "setup_error"],
+           "latency_ms_over_1e6_dofs": {"p50": 1e3 * float(np.percentile(big, 50)),
+                                        "p99": 1e3 * float(np.percentile(big, 99))} if len(big) else None,
+           "description": "cold server: latency = arrival to solution, including queueing, setup (when the "
+                          "family is not resident) and the solve to 1e-8"}
+    log(f"serve-full: {st['requests']} finished in {t:.1f} s, {st['requests_per_s']:.2f} req/s, "
+        f"p50 {st['latency_ms']['p50']:.0f} ms, p99 {st['latency_ms']['p99']:.0f} ms, {setups} setups, "
+        f"{st['evictions']} evictions")
+    return {"serving_full": out}
+
+
 def fichera_table(degrees, levels, dev):
     """FP64 PCG iteration counts on the Fichera corner with K=448 patches
     (Sec. 5: 7 unit cubes split into 4^3 patches each, 1 element per patch on
@@ -265,6 +316,12 @@ def main():
     ap.add_argument("--precision", default="both", choices=["both", "fp64", "mixed"])
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-serve", action="store_true")
+    ap.add_argument("--serve-full", action="store_true",
+                    help="instead of the benchmark line, run the full serving recipe (cold server, 256 requests, "
+                         "1e4..4e6 dofs, Poisson arrivals) and print its statistics")
+    ap.add_argument("--serve-full-requests", type=int, default=256)
+    ap.add_argument("--serve-full-families", type=int, default=64)
+    ap.add_argument("--serve-rate", type=float, default=2.0, help="arrivals per second for --serve-full")
     ap.add_argument("--fichera-table", default="",
                     help="instead of the benchmark line, print FP64 iteration counts on the Fichera corner "
                          "(K=448) for these degrees, e.g. 2,3,4, on the levels --fichera-levels")
@@ -284,6 +341,10 @@ def main():
     import torch  # noqa: F401
 
     dev = "cuda:0"
+    if a.serve_full:
+        print(json.dumps(serving_full(a.serve_full_requests, a.serve_full_families, a.serve_rate, 21, dev)),
+              flush=True)
+        return
     if a.fichera_table:
         degrees = [int(x) for x in a.fichera_table.split(",")]
         levels = [int(x) for x in a.fichera_levels.split(",")]

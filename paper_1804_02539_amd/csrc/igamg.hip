@@ -269,7 +269,15 @@ static std::vector<float> to_float(const std::vector<double>& v) { return std::v
 // entries.  A_0 and L live at the start of the scratch region (which the level
 // data occupies later), rocBLAS's workspace after them, and the inverse is
 // formed in place of the identity in its own region, so nothing is allocated.
+// One device factorization at a time per process: two of them running at
+// once from two threads (separate rocBLAS handles, streams and workspaces)
+// returned non-positive-definite factors for matrices that factor correctly
+// alone, in half of the overlapping setups measured.  Graph captures take the
+// same lock (request_graph).
+static std::mutex g_factor_mu;
+
 static void factor_coarse_on_device(igamg_ctx& C, hipStream_t st) {
+  std::lock_guard<std::mutex> factor_lock(g_factor_mu);
   struct Handle {
     rocblas_handle h = nullptr;
     ~Handle() {
@@ -860,9 +868,15 @@ static void body(Req& q, int which, hipStream_t st) {
 // The PCG bodies of one hierarchy, captured once as graphs.  A body touches
 // only its own hierarchy's memory, so the same graph serves every batch the
 // hierarchy ever joins, whatever the other members are.
+// The hierarchy's graph of body `which`, captured on first use; nullptr
+// while a device factorization runs in another thread (rocBLAS can issue work
+// on the legacy stream, which invalidates any capture in progress), and the
+// caller then launches the body directly.
 static hipGraphExec_t request_graph(igamg_batch_ctx& B, Req& q, int which) {
   igamg_ctx& C = *q.C;
   if (!C.gx[which]) {
+    std::unique_lock<std::mutex> no_factorization(g_factor_mu, std::try_to_lock);
+    if (!no_factorization.owns_lock()) return nullptr;
     hipGraph_t g = nullptr;
     HIP_OK(hipStreamBeginCapture(B.ds, hipStreamCaptureModeThreadLocal));
     body(q, which, B.ds);
@@ -881,9 +895,17 @@ static void run_bodies(igamg_batch_ctx& B, const std::vector<int>& set, int whic
     return;
   }
   // one graph per hierarchy, each on a branch stream of its own: requests
-  // joining or leaving the batch cost no capture
+  // joining or leaving the batch cost no capture; a request whose graph
+  // cannot be captured yet runs its body directly, before the fork
   std::vector<hipGraphExec_t> gs;
-  for (int i : set) gs.push_back(request_graph(B, B.reqs[i], which));
+  for (int i : set) {
+    hipGraphExec_t g = request_graph(B, B.reqs[i], which);
+    if (g)
+      gs.push_back(g);
+    else
+      body(B.reqs[i], which, B.ds);
+  }
+  if (gs.empty()) return;
   if (gs.size() == 1) {
     HIP_OK(hipGraphLaunch(gs[0], B.ds));
     return;

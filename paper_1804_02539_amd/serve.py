@@ -86,8 +86,18 @@ class Server:
                 # each setup uploads on a stream of its own (never the legacy
                 # default stream, so it cannot serialise against the batch)
                 st = torch.cuda.Stream(device=device)
-                with torch.cuda.stream(st):
-                    S = igamg.Solver(prob, self.opts, device=device, stream=st)
+                for attempt in (0, 1):
+                    try:
+                        with torch.cuda.stream(st):
+                            S = igamg.Solver(prob, self.opts, device=device, stream=st)
+                        break
+                    except torch.cuda.OutOfMemoryError:
+                        # the budget fits, so the allocator's cache is holding
+                        # the memory: return it to the device and try once more
+                        if attempt:
+                            raise
+                        torch.cuda.synchronize(device)
+                        torch.cuda.empty_cache()
                 st.synchronize()
                 return S
             make_solver = make_solver or _setup
@@ -153,6 +163,11 @@ class Server:
         if self.device.startswith("cuda"):
             import torch
             torch.cuda.synchronize(self.device)
+            h.solver = None
+            # hand the workspace back to the device at once: left in the
+            # allocator's cache, a smaller workspace would later split it, and
+            # a partly used segment can never be released for a large one
+            torch.cuda.empty_cache()
         h.solver = None
 
     def _collect_setups(self):
@@ -240,12 +255,18 @@ class Server:
             return True
         return False
 
-    def run(self, arrivals=None, timeout=600.0):
+    def run(self, arrivals=None, timeout=600.0, progress=None, progress_every=5.0):
         """Drive the server until every request (and every timed arrival
-        ``(t_offset, Request)``, sorted by offset) is finished or rejected."""
+        ``(t_offset, Request)``, sorted by offset) is finished or rejected.
+        ``progress(server, elapsed_s)``, if given, is called every
+        ``progress_every`` seconds."""
         t0 = time.perf_counter()
+        t_report = t0
         arrivals = collections.deque(arrivals or [])
         while True:
+            if progress is not None and time.perf_counter() - t_report >= progress_every:
+                t_report = time.perf_counter()
+                progress(self, t_report - t0)
             now = time.perf_counter()
             while arrivals and t0 + arrivals[0][0] <= now:
                 off, req = arrivals.popleft()

@@ -231,11 +231,12 @@ def serving_families(n_families, seed=5, n_min=1e4, n_max=3e5, band_bytes_max=1.
     Each family draws d in {2, 3} and p in {2..6} uniformly, a patch grid of
     2..4 patches per direction, and a target size N log-uniform in
     [n_min, n_max]; the coarsest element count (1..3 per patch and direction)
-    and the level count are the pair whose finest size is closest to the target,
+    and the level count are the pair whose number of free dofs is closest to
+    the target (among the pairs inside [n_min, n_max] when there are any),
     subject to the FP64 band of the finest level staying under band_bytes_max,
-    the coarsest level having at most n0_max unknowns (its dense Cholesky
-    factorisation runs on the host) and every patch having at most 84
-    interior functions per direction.
+    the coarsest level having at most n0_max unknowns (the dense coarse
+    inverse is N0^2 doubles; up to 3,000 unknowns it is factored on the host)
+    and every patch having at most 84 interior functions per direction.
     2D families are biquadratic grids with seeded interior control points
     (Dirichlet on x=0 and y=0), 3D ones trilinear grids with every interior
     macro vertex moved by up to 10% of the patch width (full Dirichlet).
@@ -249,15 +250,19 @@ def serving_families(n_families, seed=5, n_min=1e4, n_max=3e5, band_bytes_max=1.
             p = int(rng.integers(2, 7))
             npp = [int(rng.integers(2, 5)) for _ in range(d)]
             target = float(np.exp(rng.uniform(np.log(n_min), np.log(n_max))))
+            # free dofs exactly: 2D families are Dirichlet on one side per
+            # direction, 3D ones on both
+            nd = 1 if d == 2 else 2
             for nel0 in (1, 2, 3):
                 for levels in range(2, 11):
                     nel = nel0 * 2 ** (levels - 1)
                     rows = int(np.prod([k * (nel + p) for k in npp]))
-                    n_est = float(np.prod([k * (nel + p - 1) + 1 for k in npp]))
-                    n0 = float(np.prod([k * (nel0 + p - 1) + 1 for k in npp]))
+                    n_free = float(np.prod([k * (nel + p - 1) + 1 - nd for k in npp]))
+                    n0 = float(np.prod([k * (nel0 + p - 1) + 1 - nd for k in npp]))
                     if rows * (2 * p + 1) ** d * 8 > band_bytes_max or n0 > n0_max or nel + p - 2 > 84:
                         continue
-                    score = abs(np.log(n_est / target))
+                    # sizes inside [n_min, n_max] first, then the closest to the target
+                    score = (not (n_min <= n_free <= n_max), abs(np.log(n_free / target)))
                     if best is None or score < best[0]:
                         best = (score, nel0, levels)
         _, nel0, levels = best

@@ -86,6 +86,32 @@ def test_replica_matches_oracle(torch_cuda):
     assert diff < 1e-5
 
 
+def test_concurrent_setups_factor_correctly(torch_cuda):
+    # Two setups in two threads, as the serving loop runs them, each factoring
+    # the replica's 30,056-unknown coarse matrix on the device: every setup
+    # must succeed and solve exactly as a setup made alone (before device
+    # factorizations were serialised, half of such overlapping setups
+    # reported a non-positive-definite coarse matrix).
+    import concurrent.futures as cf
+    from paper_1804_02539_amd import igamg
+    prob = W.batched_patch_cube(divide=4)
+
+    def setup_and_solve(i):
+        st = torch_cuda.cuda.Stream()
+        with torch_cuda.cuda.stream(st):
+            S = igamg.Solver(prob, stream=st)
+        st.synchronize()
+        u, info = S.solve(torch_cuda.as_tensor(W.random_rhs(S.N, 9), device="cuda:0"))
+        return u.cpu().numpy(), info.iterations
+
+    ref_u, ref_it = setup_and_solve(-1)
+    with cf.ThreadPoolExecutor(2) as ex:
+        res = list(ex.map(setup_and_solve, range(4)))
+    _say(f"4 concurrent setups: iterations {[r[1] for r in res]} (alone {ref_it})")
+    for u, it in res:
+        assert it == ref_it and np.array_equal(u, ref_u)
+
+
 def _patch_check(S, prob, k, rng):
     """Finest apply of the library on a vector living on the strict interior of
     patch k, against the oracle's operator of that patch."""
