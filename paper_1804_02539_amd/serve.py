@@ -141,12 +141,13 @@ class Server:
         self.peak_used = max(self.peak_used, self.used)
         assert self.used <= self.budget, "admission exceeded the HBM budget"
 
-    def _evict_for(self, nbytes, protect_key):
-        """Free idle handles (LRU, other problems first) until nbytes fit."""
+    def _evict_for(self, nbytes, protect_key, wanted=()):
+        """Free idle handles until nbytes fit: first those no waiting request
+        needs, least recently used first, the requesting problem's last."""
         if self.used + nbytes <= self.budget:
             return True
         idle = [h for hs in self.handles.values() for h in hs if not h.busy]
-        idle.sort(key=lambda h: (h.key == protect_key, h.last_used))
+        idle.sort(key=lambda h: (h.key in wanted, h.key == protect_key, h.last_used))
         for h in idle:
             if self.used + nbytes <= self.budget:
                 break
@@ -198,6 +199,17 @@ class Server:
         self.running[slot] = (req, h)
 
     def _admit(self):
+        # first every request whose problem is resident and idle: a hierarchy
+        # that has just been set up must serve its request before any other
+        # problem may evict it (else two problems can evict each other forever)
+        for req in list(self.pending):
+            if len(self.running) >= self.max_active:
+                return
+            idle = [h for h in self.handles.get(req.key, []) if not h.busy]
+            if idle:
+                self.pending.remove(req)
+                self._start(req, idle[0])
+        wanted = {r.key for r in self.pending}
         now_blocked = set()
         for req in list(self.pending):
             if len(self.running) >= self.max_active:
@@ -220,7 +232,7 @@ class Server:
                 req.error = ServeError(f"request needs {nbytes} bytes, more than the whole budget")
                 self.rejected.append(req)
                 continue
-            if not self._evict_for(nbytes, req.key):
+            if not self._evict_for(nbytes, req.key, wanted):
                 now_blocked.add(req.key)
                 continue
             self._charge(nbytes)

@@ -121,3 +121,15 @@ def test_largest_degree_matches_oracle(torch_cuda):
     res = np.linalg.norm(f - H.finest.apply(u.cpu().numpy())) / np.linalg.norm(f)
     _say(f"p=8: {info.iterations} it, residual {res:.2e}")
     assert info.converged and res <= 1.0001e-8
+
+
+def test_singular_coarse_matrix_on_the_device_reports_enotspd(torch_cuda):
+    # no Dirichlet side: the coarse matrix is singular; the device
+    # factorization (forced here) reports it, after its one refactorization
+    from paper_1804_02539_amd import igamg
+    from paper_1804_02539_amd import workloads as W
+    bad = W.box_grid(2, [2, 1], 2, 1, 2, gdeg=1, dirichlet_sides=[])
+    with pytest.raises(igamg.IgamgError) as e:
+        igamg.Solver(bad, igamg.default_options(coarse_factor=2))
+    assert e.value.code == igamg.ENOTSPD
+    _say(f"singular coarse matrix on the device: {e.value}")

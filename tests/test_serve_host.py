@@ -153,3 +153,25 @@ def test_serving_families_respect_their_limits():
         assert rows * (2 * p + 1) ** f.dim * 8 <= 1.5e9
     # the family draw is seeded
     assert [f.name for f in fams] == [f.name for f in W.serving_families(16, seed=5)]
+
+
+def test_fresh_hierarchy_serves_its_request_before_eviction():
+    # A large problem that needs almost the whole budget, and small ones
+    # queued ahead of its requests: once the large hierarchy is set up, an
+    # earlier small request must not evict it before its own request starts
+    # (that made two problems evict each other forever).
+    big = _fake_prob(0, 40, 90)
+    smalls = [_fake_prob(i, 10 + i, 20) for i in range(1, 4)]
+
+    def make(prob):
+        time.sleep(0.005)
+        return FakeSolver(prob)
+
+    S = serve.Server(100, device="cpu", make_solver=make, workspace_bytes=lambda p: p.meta["nbytes"],
+                     batch=FakeBatch(), handles_per_key=1)
+    order = [smalls[0], big, smalls[1], big, smalls[2], big, smalls[0], smalls[1]] * 4
+    for p in order:
+        S.submit(serve.Request(p, lambda n: np.zeros(n)))
+    S.run(timeout=20)
+    S.close()
+    assert len(S.finished) == len(order) and not S.rejected
