@@ -14,6 +14,7 @@
 #include <cstdint>
 
 #include "layout.hpp"
+#include "assemble_layout.hpp"
 
 #ifndef IGAMG_HD
 #define IGAMG_HD __host__ __device__

@@ -8,6 +8,7 @@
 #include <cstdint>
 
 #include "layout.hpp"
+#include "assemble_layout.hpp"
 
 namespace igamg {
 
