@@ -49,20 +49,20 @@ __global__ __launch_bounds__(256) void k_asm_metric(AsmPatch P, const double* __
   }
 }
 
-template <int D>
-__global__ __launch_bounds__(256) void k_asm_dir0(AsmPatch P, const double* __restrict__ tab,
+template <int D, int P>
+__global__ __launch_bounds__(256) void k_asm_dir0(AsmPatch Pt, const double* __restrict__ tab,
                                                   const double* __restrict__ Gs, double* __restrict__ T1,
                                                   int64_t tot) {
   const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (t < tot) T1[t] = asm_dir0_entry<D>(P, tab, Gs, t);
+  if (t < tot) asm_dir0_row<D, P>(Pt, tab, Gs, T1, t);
 }
 
-template <int D>
-__global__ __launch_bounds__(256) void k_asm_dir1(AsmPatch P, const double* __restrict__ tab,
+template <int D, int P>
+__global__ __launch_bounds__(256) void k_asm_dir1(AsmPatch Pt, const double* __restrict__ tab,
                                                   const double* __restrict__ T1, double* __restrict__ T2,
                                                   int64_t tot) {
   const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (t < tot) T2[t] = asm_dir1_entry<D>(P, tab, T1, t);
+  if (t < tot) asm_dir1_row<D, P>(Pt, tab, T1, T2, t);
 }
 
 template <int D, int P2>
@@ -81,11 +81,36 @@ __global__ __launch_bounds__(256) void k_asm_mask(const PatchDev* __restrict__ p
   if (t < tot) asm_mask_entry<D>(pd, bpatch, isfree, band, nbt, p, t);
 }
 
-template <int D, int P2>
-void launch_dir2(const AsmPatch& P, const double* tab, int e2, const double* T2, double* band, int nbt,
-                 hipStream_t st) {
-  const int64_t inner = asm_dir2_threads(P);
-  hipLaunchKernelGGL((k_asm_dir2<D, P2>), grid_for(inner), dim3(256), 0, st, P, tab, e2, T2, band, nbt, inner);
+// the four launches of one slab; the direction-2 stage has degree P in 3D
+// and none in 2D
+template <int D, int P>
+void launch_slab(const AsmPatch& Pt, const double* tab, int e2, double* Gs, double* T1, double* T2, double* band,
+                 int nbt, int* flag, hipStream_t st) {
+  constexpr int P2 = (D == 3) ? P : 0;
+  size_t sz[3];
+  asm_sizes(D, Pt, sz);
+  const int64_t t0 = asm_dir0_threads(D, Pt), t1 = asm_dir1_threads(D, Pt), t2 = asm_dir2_threads(Pt);
+  hipLaunchKernelGGL(k_asm_metric<D>, grid_for((int64_t)sz[0] / (D * D)), dim3(256), 0, st, Pt, tab, e2, Gs, flag);
+  hipLaunchKernelGGL((k_asm_dir0<D, P>), grid_for(t0), dim3(256), 0, st, Pt, tab, Gs, T1, t0);
+  hipLaunchKernelGGL((k_asm_dir1<D, P>), grid_for(t1), dim3(256), 0, st, Pt, tab, T1, T2, t1);
+  hipLaunchKernelGGL((k_asm_dir2<D, P2>), grid_for(t2), dim3(256), 0, st, Pt, tab, e2, T2, band, nbt, t2);
+}
+
+template <int D>
+hipError_t launch_slab_d(const AsmPatch& Pt, const double* tab, int e2, double* Gs, double* T1, double* T2,
+                         double* band, int nbt, int* flag, hipStream_t st) {
+  switch (Pt.pc[0]) {
+    case 1: launch_slab<D, 1>(Pt, tab, e2, Gs, T1, T2, band, nbt, flag, st); break;
+    case 2: launch_slab<D, 2>(Pt, tab, e2, Gs, T1, T2, band, nbt, flag, st); break;
+    case 3: launch_slab<D, 3>(Pt, tab, e2, Gs, T1, T2, band, nbt, flag, st); break;
+    case 4: launch_slab<D, 4>(Pt, tab, e2, Gs, T1, T2, band, nbt, flag, st); break;
+    case 5: launch_slab<D, 5>(Pt, tab, e2, Gs, T1, T2, band, nbt, flag, st); break;
+    case 6: launch_slab<D, 6>(Pt, tab, e2, Gs, T1, T2, band, nbt, flag, st); break;
+    case 7: launch_slab<D, 7>(Pt, tab, e2, Gs, T1, T2, band, nbt, flag, st); break;
+    case 8: launch_slab<D, 8>(Pt, tab, e2, Gs, T1, T2, band, nbt, flag, st); break;
+    default: return hipErrorInvalidValue;
+  }
+  return hipGetLastError();
 }
 
 }  // namespace
@@ -94,31 +119,9 @@ void asm_slab_sizes(int d, const AsmPatch& P, size_t out[3]) { asm_sizes(d, P, o
 
 hipError_t launch_asm_slab(int d, const AsmPatch& P, const double* tab, int e2, double* Gs, double* T1, double* T2,
                            double* band, int nbt, int* flag, hipStream_t st) {
-  size_t sz[3];
-  asm_slab_sizes(d, P, sz);
-  const int p = P.pc[0];
-  if (d == 2) {
-    hipLaunchKernelGGL(k_asm_metric<2>, grid_for((int64_t)sz[0] / 4), dim3(256), 0, st, P, tab, e2, Gs, flag);
-    hipLaunchKernelGGL(k_asm_dir0<2>, grid_for((int64_t)sz[1]), dim3(256), 0, st, P, tab, Gs, T1, (int64_t)sz[1]);
-    hipLaunchKernelGGL(k_asm_dir1<2>, grid_for((int64_t)sz[2]), dim3(256), 0, st, P, tab, T1, T2, (int64_t)sz[2]);
-    launch_dir2<2, 0>(P, tab, e2, T2, band, nbt, st);
-    return hipGetLastError();
-  }
-  if (d != 3 || p < 1 || p > MAX_P) return hipErrorInvalidValue;
-  hipLaunchKernelGGL(k_asm_metric<3>, grid_for((int64_t)sz[0] / 9), dim3(256), 0, st, P, tab, e2, Gs, flag);
-  hipLaunchKernelGGL(k_asm_dir0<3>, grid_for((int64_t)sz[1]), dim3(256), 0, st, P, tab, Gs, T1, (int64_t)sz[1]);
-  hipLaunchKernelGGL(k_asm_dir1<3>, grid_for((int64_t)sz[2]), dim3(256), 0, st, P, tab, T1, T2, (int64_t)sz[2]);
-  switch (p) {
-    case 1: launch_dir2<3, 1>(P, tab, e2, T2, band, nbt, st); break;
-    case 2: launch_dir2<3, 2>(P, tab, e2, T2, band, nbt, st); break;
-    case 3: launch_dir2<3, 3>(P, tab, e2, T2, band, nbt, st); break;
-    case 4: launch_dir2<3, 4>(P, tab, e2, T2, band, nbt, st); break;
-    case 5: launch_dir2<3, 5>(P, tab, e2, T2, band, nbt, st); break;
-    case 6: launch_dir2<3, 6>(P, tab, e2, T2, band, nbt, st); break;
-    case 7: launch_dir2<3, 7>(P, tab, e2, T2, band, nbt, st); break;
-    default: launch_dir2<3, 8>(P, tab, e2, T2, band, nbt, st); break;
-  }
-  return hipGetLastError();
+  if (d == 2) return launch_slab_d<2>(P, tab, e2, Gs, T1, T2, band, nbt, flag, st);
+  if (d == 3) return launch_slab_d<3>(P, tab, e2, Gs, T1, T2, band, nbt, flag, st);
+  return hipErrorInvalidValue;
 }
 
 void launch_asm_mask(int d, int p, const PatchDev* pd, const int* bpatch, const uint8_t* isfree, double* band,

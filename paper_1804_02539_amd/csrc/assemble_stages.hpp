@@ -35,6 +35,16 @@ inline void asm_sizes(int d, const AsmPatch& P, size_t out[3]) {
   out[2] = (size_t)(g4 * NQ2 * P.n[1] * nb * nb * P.n[0]);
 }
 
+// threads of the direction-0 and direction-1 stages (one per row entry and
+// all its offsets)
+inline int64_t asm_dir0_threads(int d, const AsmPatch& P) {
+  return (int64_t)d * d * P.nq[2] * P.nel[1] * P.nq[1] * P.n[0];
+}
+inline int64_t asm_dir1_threads(int d, const AsmPatch& P) {
+  const int64_t nb = 2 * P.pc[0] + 1;
+  return (int64_t)((d == 3) ? 4 : 1) * P.nq[2] * P.n[1] * nb * P.n[0];
+}
+
 // threads of the direction-2 stage: one per (i0, o0, o1, i1)
 IGAMG_HD inline int64_t asm_dir2_threads(const AsmPatch& P) {
   const int64_t nb = 2 * P.pc[0] + 1;
@@ -103,70 +113,85 @@ IGAMG_HD inline double asm_metric_point(const AsmPatch& P, const double* tab, in
   return det;
 }
 
-// T1 entry t: direction 0 contracted over the elements shared by i0 and j0
-template <int D>
-IGAMG_HD inline double asm_dir0_entry(const AsmPatch& P, const double* tab, const double* Gs, int64_t t) {
-  const int n0 = P.n[0], p = P.pc[0], nb0 = 2 * p + 1, nq = P.nq[0], nel0 = P.nel[0];
+// direction 0 for thread t = (i0, q2*Q1 + q1, ab): the T1 entries of every
+// offset o0 of row i0 at once, so that each Gauss value and basis value is
+// loaded once rather than once per offset.  Each entry sums over the elements
+// e shared by i0 and j0 = i0 + o0 - P (element by element, point by point).
+template <int D, int P>
+IGAMG_HD inline void asm_dir0_row(const AsmPatch& Pt, const double* tab, const double* Gs, double* T1, int64_t t) {
+  constexpr int NB = 2 * P + 1, W = P + 1;
+  const int n0 = Pt.n[0], nq = Pt.nq[0], nel0 = Pt.nel[0];
   const int Q0 = nel0 * nq;
-  const int64_t plane = (int64_t)P.nq[2] * P.nel[1] * P.nq[1];
+  const int64_t plane = (int64_t)Pt.nq[2] * Pt.nel[1] * Pt.nq[1];
   const int i0 = (int)(t % n0);
-  int64_t r = t / n0;
-  const int o0 = (int)(r % nb0);
-  r /= nb0;
+  const int64_t r = t / n0;
   const int64_t qq = r % plane;
   const int ab = (int)(r / plane);
   const int a = ab / D, b = ab % D;
-  const double* Fs = tab + (a == 0 ? P.der[0] : P.val[0]);
-  const double* Ft = tab + (b == 0 ? P.der[0] : P.val[0]);
-  const int j0 = i0 + o0 - p;
-  double acc = 0.0;
-  if (j0 >= 0 && j0 < n0) {
-    const int lo = asm_imax(0, asm_imax(i0, j0) - p), hi = asm_imin(nel0 - 1, asm_imin(i0, j0));
-    const double* g = Gs + ((int64_t)ab * plane + qq) * Q0;
-    for (int e = lo; e <= hi; ++e)
-      for (int q = 0; q < nq; ++q) {
-        const int x = e * nq + q;
-        acc += g[x] * Fs[x * (p + 1) + i0 - e] * Ft[x * (p + 1) + j0 - e];
-      }
+  const double* Fs = tab + (a == 0 ? Pt.der[0] : Pt.val[0]);
+  const double* Ft = tab + (b == 0 ? Pt.der[0] : Pt.val[0]);
+  const double* g = Gs + ((int64_t)ab * plane + qq) * Q0;
+  double acc[NB];
+#pragma unroll
+  for (int o = 0; o < NB; ++o) acc[o] = 0.0;
+#pragma unroll
+  for (int el = 0; el < W; ++el) {
+    const int e = i0 - P + el;   // i0 is local function P - el of element e
+    if (e < 0 || e >= nel0) continue;
+    for (int q = 0; q < nq; ++q) {
+      const int x = e * nq + q;
+      const double gs = g[x] * Fs[x * W + P - el];
+#pragma unroll
+      for (int lp = 0; lp < W; ++lp) acc[el + lp] += gs * Ft[x * W + lp];   // j0 = e + lp
+    }
   }
-  return acc;
+  double* out = T1 + ((int64_t)ab * plane + qq) * NB * n0 + i0;
+#pragma unroll
+  for (int o = 0; o < NB; ++o) out[(int64_t)o * n0] = acc[o];
 }
 
-// T2 entry t: direction 1 contracted, the (a, b) pairs summed per group
-template <int D>
-IGAMG_HD inline double asm_dir1_entry(const AsmPatch& P, const double* tab, const double* T1, int64_t t) {
-  const int n0 = P.n[0], n1 = P.n[1], p = P.pc[1], nb = 2 * p + 1, nq = P.nq[1], nel1 = P.nel[1];
-  const int NQ2 = P.nq[2], Q1 = nel1 * nq;
+// direction 1 for thread t = (i0, o0, i1, q2, g): the T2 entries of every
+// offset o1 at once, the (a, b) pairs of group g summed in turn
+template <int D, int P>
+IGAMG_HD inline void asm_dir1_row(const AsmPatch& Pt, const double* tab, const double* T1, double* T2, int64_t t) {
+  constexpr int NB = 2 * P + 1, W = P + 1;
+  const int n0 = Pt.n[0], n1 = Pt.n[1], nq = Pt.nq[1], nel1 = Pt.nel[1];
+  const int NQ2 = Pt.nq[2], Q1 = nel1 * nq;
   const int i0 = (int)(t % n0);
   int64_t r = t / n0;
-  const int o0 = (int)(r % nb);
-  r /= nb;
-  const int o1 = (int)(r % nb);
-  r /= nb;
+  const int o0 = (int)(r % NB);
+  r /= NB;
   const int i1 = (int)(r % n1);
   r /= n1;
   const int q2l = (int)(r % NQ2);
   const int grp = (int)(r / NQ2);
   const int s2 = grp >> 1, t2 = grp & 1;
-  const int j1 = i1 + o1 - p;
-  double acc = 0.0;
-  if (j1 >= 0 && j1 < n1) {
-    const int lo = asm_imax(0, asm_imax(i1, j1) - p), hi = asm_imin(nel1 - 1, asm_imin(i1, j1));
-    const int64_t qstride = (int64_t)nb * n0;
-    for (int a = 0; a < D; ++a)
-      for (int b = 0; b < D; ++b) {
-        if ((a == 2 ? 1 : 0) != s2 || (b == 2 ? 1 : 0) != t2) continue;
-        const double* Fs = tab + (a == 1 ? P.der[1] : P.val[1]);
-        const double* Ft = tab + (b == 1 ? P.der[1] : P.val[1]);
-        const double* src = T1 + ((int64_t)(a * D + b) * NQ2 + q2l) * Q1 * qstride + (int64_t)o0 * n0 + i0;
-        for (int e = lo; e <= hi; ++e)
-          for (int q = 0; q < nq; ++q) {
-            const int x = e * nq + q;
-            acc += Fs[x * (p + 1) + i1 - e] * Ft[x * (p + 1) + j1 - e] * src[(int64_t)x * qstride];
-          }
+  const int64_t qstride = (int64_t)NB * n0;
+  double acc[NB];
+#pragma unroll
+  for (int o = 0; o < NB; ++o) acc[o] = 0.0;
+  for (int a = 0; a < D; ++a)
+    for (int b = 0; b < D; ++b) {
+      if ((a == 2 ? 1 : 0) != s2 || (b == 2 ? 1 : 0) != t2) continue;
+      const double* Fs = tab + (a == 1 ? Pt.der[1] : Pt.val[1]);
+      const double* Ft = tab + (b == 1 ? Pt.der[1] : Pt.val[1]);
+      const double* src = T1 + ((int64_t)(a * D + b) * NQ2 + q2l) * Q1 * qstride + (int64_t)o0 * n0 + i0;
+#pragma unroll
+      for (int el = 0; el < W; ++el) {
+        const int e = i1 - P + el;
+        if (e < 0 || e >= nel1) continue;
+        for (int q = 0; q < nq; ++q) {
+          const int x = e * nq + q;
+          const double sv = src[(int64_t)x * qstride];
+          const double fs = Fs[x * W + P - el];
+#pragma unroll
+          for (int lp = 0; lp < W; ++lp) acc[el + lp] += fs * Ft[x * W + lp] * sv;
+        }
       }
-  }
-  return acc;
+    }
+  double* out = T2 + (((int64_t)grp * NQ2 + q2l) * n1 + i1) * NB * NB * n0 + (int64_t)o0 * n0 + i0;
+#pragma unroll
+  for (int o = 0; o < NB; ++o) out[(int64_t)o * NB * n0] = acc[o];
 }
 
 // direction 2 for thread t = (i0, o0, o1, i1): adds slab e2's (P2+1)^2
