@@ -1217,7 +1217,7 @@ int igamg_setup(const igamg_problem* prob, const igamg_options* opts, void* work
       autotune(*C, static_cast<hipStream_t>(stream));
     }
   } catch (...) {
-    delete C;
+    igamg_destroy(C);   // also frees what a partial setup acquired (pinned scalars, graphs, events)
     throw;
   }
   *out = C;

@@ -1,0 +1,47 @@
+"""The device-assembly stages (Gauss quadrature sum-factorised over the
+tensor rule, Sec. 4) run on the host: their per-entry arithmetic is shared by
+the kernels of assemble.hip and this check, which builds it with g++ and
+compares the tiled bands with the library's host assembly (itself checked
+against the oracle in test_lib_host.py) for every level above the coarsest."""
+import ctypes
+import os
+import subprocess
+
+import pytest
+
+from paper_1804_02539_amd import igamg
+from paper_1804_02539_amd import workloads as W
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+CSRC = os.path.join(os.path.dirname(HERE), "paper_1804_02539_amd", "csrc")
+INCLUDE = os.path.join(os.path.dirname(HERE), "include")
+
+
+@pytest.fixture(scope="module")
+def stages(tmp_path_factory):
+    out = str(tmp_path_factory.mktemp("asm") / "asm_stages_host.so")
+    cmd = ["g++", "-O1", "-std=c++17", "-fPIC", "-shared", "-pthread", "-I", INCLUDE, "-I", CSRC,
+           "-I", "/opt/rocm/include", "-D__HIP_PLATFORM_AMD__", "-Wno-unknown-pragmas",
+           os.path.join(HERE, "asm_stages_host.cpp"), os.path.join(CSRC, "host_setup.cpp"), "-o", out]
+    subprocess.check_call(cmd)
+    lib = ctypes.CDLL(out)
+    lib.asm_stages_vs_host.restype = ctypes.c_int
+    return lib
+
+
+CASES = {
+    "square4x4_bezier_p4_l3": lambda: W.square_4x4_bezier(levels=3),
+    "cube2x2x2_trilinear_p3_l3": lambda: W.cube_2x2x2_trilinear(levels=3),
+    "fichera7_p2_l3": lambda: W.fichera(2, 3),
+    "cube_p4_neumann_l3": lambda: W.box_grid(3, [2, 1, 1], 4, 1, 3, gdeg=1, dirichlet_sides=[0, 2]),
+    "box1x2_p8_l2": lambda: W.box_grid(2, [1, 2], 8, 1, 2, gdeg=1),
+}
+
+
+@pytest.mark.parametrize("name", list(CASES))
+def test_stages_equal_host_assembly(stages, name):
+    cp = igamg._CProblem(CASES[name]())
+    rel, flags = ctypes.c_double(), ctypes.c_int()
+    assert stages.asm_stages_vs_host(ctypes.byref(cp.s), ctypes.byref(rel), ctypes.byref(flags)) == 0
+    assert rel.value < 1e-14, rel.value
+    assert flags.value == 1      # det J > 0 at every Gauss point
