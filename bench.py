@@ -335,8 +335,8 @@ def main():
     ap.add_argument("--serve-families", type=int, default=12)
     a = ap.parse_args()
     if a.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
-        print("bench.py measures one GPU only: this build has no multi-GPU path "
-              "(patch sharding across GPUs is a design note, not code)", file=sys.stderr)
+        print("bench.py measures one GPU only: the library has no multi-GPU path "
+              "(sharding patches across GPUs is described, not implemented)", file=sys.stderr)
         sys.exit(2)
     import torch  # noqa: F401
 
