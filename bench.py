@@ -6,6 +6,8 @@ timed on the host.
 
     python bench.py [--gpus 1] [--steps K] [--warmup W] [--workload NAME]
                     [--precision both|fp64|mixed] [--no-cpu-baseline] [--no-serve]
+    python bench.py --serve-full [--serve-rate R]     # the full serving recipe instead
+    python bench.py --fichera-table 2,3 [--fichera-levels 1,2]   # Fichera iteration counts instead
 
 A step is one complete solve of the workload from u = 0 to ||f - A u|| <= 1e-8
 ||f|| (setup excluded; inputs resident in HBM).  Prints one JSON line; `value`
