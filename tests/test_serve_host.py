@@ -175,3 +175,13 @@ def test_fresh_hierarchy_serves_its_request_before_eviction():
     S.run(timeout=20)
     S.close()
     assert len(S.finished) == len(order) and not S.rejected
+
+
+def test_serving_families_sizes_lie_in_their_range():
+    # the generator sizes families by their exact number of free dofs (checked
+    # here against the library's own count) and keeps them inside the range
+    from paper_1804_02539_amd import igamg
+    fams = W.serving_families(10, seed=8, n_min=2e3, n_max=2e4)
+    for f in fams:
+        n = igamg.Solver(f, host_only=True).N
+        assert 2e3 <= n <= 2e4, (f.name, n)
