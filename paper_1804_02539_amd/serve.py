@@ -161,15 +161,16 @@ class Server:
         # an idle handle has no queued work left in the batch (its request was
         # retired after the batch synchronised), but the workspace memory
         # returns to the allocator, so make sure no stream still reads it
-        if self.device.startswith("cuda"):
-            import torch
-            torch.cuda.synchronize(self.device)
+        if not self.device.startswith("cuda"):
             h.solver = None
-            # hand the workspace back to the device at once: left in the
-            # allocator's cache, a smaller workspace would later split it, and
-            # a partly used segment can never be released for a large one
-            torch.cuda.empty_cache()
+            return
+        import torch
+        torch.cuda.synchronize(self.device)
         h.solver = None
+        # hand the workspace back to the device at once: left in the
+        # allocator's cache, a smaller workspace would later split it, and a
+        # partly used segment can never be released for a large one
+        torch.cuda.empty_cache()
 
     def _collect_setups(self):
         for fut in [f for f in self.setups if f.done()]:
