@@ -1041,6 +1041,8 @@ void build_all(Hierarchy& H, bool device) {
   LevelH& L0 = H.lv[0];
   const int64_t N0 = L0.N;
   if (N0 > 100000) fail(IGAMG_EINVAL, "coarse problem too large for the dense coarse solver");
+  // a host-only handle of a large coarse problem needs no coarse solver
+  if (!coarse_on_device(H.opt, N0, device) && N0 > COARSE_HOST_MAX && H.opt.coarse_factor != 1) return;
   Mat A((size_t)N0 * N0, 0.0);
   const int d = P.d, p = P.p;
   const int nb0 = 2 * p + 1, nb1 = 2 * p + 1, p2 = (d == 3) ? p : 0, nb2 = 2 * p2 + 1;
@@ -1069,7 +1071,6 @@ void build_all(Hierarchy& H, bool device) {
     H.A0 = std::move(A);   // factored after upload
     return;
   }
-  if (N0 > COARSE_HOST_MAX && H.opt.coarse_factor != 1) return;   // host-only handle: no coarse solver needed
   if (!cholesky(A, (int)N0)) fail(IGAMG_ENOTSPD, "coarse matrix is not positive definite (is any side Dirichlet?)");
   // A_0^{-1} = L^{-T} L^{-1} from the Cholesky factor: the two triangular
   // solves of the exact coarse solver become one dense mat-vec on the device
