@@ -1043,38 +1043,48 @@ void build_all(Hierarchy& H, bool device) {
   if (N0 > 100000) fail(IGAMG_EINVAL, "coarse problem too large for the dense coarse solver");
   // a host-only handle of a large coarse problem needs no coarse solver
   if (!coarse_on_device(H.opt, N0, device) && N0 > COARSE_HOST_MAX && H.opt.coarse_factor != 1) return;
-  Mat A((size_t)N0 * N0, 0.0);
+  DenseBuf A((size_t)N0 * N0);   // zeroed below, row block by row block
   const int d = P.d, p = P.p;
   const int nb0 = 2 * p + 1, nb1 = 2 * p + 1, p2 = (d == 3) ? p : 0, nb2 = 2 * p2 + 1;
-  for (int k = 0; k < P.K; ++k) {
-    const auto& n = L0.n[k];
-    for (int64_t r = 0; r < L0.rows[k]; ++r) {
-      const int64_t x = L0.off[k] + r;
-      const int64_t gi = L0.gid[x];
-      if (gi < 0) continue;
-      const int i0 = (int)(r % n[0]), i1 = (int)((r / n[0]) % n[1]), i2 = (int)(r / ((int64_t)n[0] * n[1]));
-      for (int o2 = 0; o2 < nb2; ++o2)
-        for (int o1 = 0; o1 < nb1; ++o1)
-          for (int o0 = 0; o0 < nb0; ++o0) {
-            const int j0 = i0 + o0 - p, j1 = i1 + o1 - p, j2 = i2 + o2 - p2;
-            if (j0 < 0 || j0 >= n[0] || j1 < 0 || j1 >= n[1] || j2 < 0 || j2 >= n[2]) continue;
-            const int64_t y = L0.off[k] + j0 + (int64_t)n[0] * (j1 + (int64_t)n[1] * j2);
-            const int64_t gj = L0.gid[y];
-            if (gj < 0) continue;
-            const int64_t o = o0 + (int64_t)nb0 * (o1 + (int64_t)nb1 * o2);
-            A[(size_t)gi * N0 + gj] += L0.band[o * L0.NL + x];
-          }
-    }
-  }
+  // Each block of global rows is zeroed and filled by one thread.  A row gi
+  // takes its copies in ascending local order and each copy's couplings in
+  // offset order: every entry receives the same sums in the same order as a
+  // serial pass over patches, rows and offsets.
+  const int nblk = (int)std::min<int64_t>(N0, 256);
+  parallel_for(nblk, [&](int b) {
+    const int64_t r0 = N0 * b / nblk, r1 = N0 * (b + 1) / nblk;
+    std::fill(A.begin() + r0 * N0, A.begin() + r1 * N0, 0.0);
+    for (int64_t gi = r0; gi < r1; ++gi)
+      for (int64_t c = L0.gptr[gi]; c < L0.gptr[gi + 1]; ++c) {
+        const int64_t x = L0.gidx[c];
+        const int k = patch_of(L0, x);
+        const auto& n = L0.n[k];
+        const int64_t r = x - L0.off[k];
+        const int i0 = (int)(r % n[0]), i1 = (int)((r / n[0]) % n[1]), i2 = (int)(r / ((int64_t)n[0] * n[1]));
+        for (int o2 = 0; o2 < nb2; ++o2)
+          for (int o1 = 0; o1 < nb1; ++o1)
+            for (int o0 = 0; o0 < nb0; ++o0) {
+              const int j0 = i0 + o0 - p, j1 = i1 + o1 - p, j2 = i2 + o2 - p2;
+              if (j0 < 0 || j0 >= n[0] || j1 < 0 || j1 >= n[1] || j2 < 0 || j2 >= n[2]) continue;
+              const int64_t y = L0.off[k] + j0 + (int64_t)n[0] * (j1 + (int64_t)n[1] * j2);
+              const int64_t gj = L0.gid[y];
+              if (gj < 0) continue;
+              const int64_t o = o0 + (int64_t)nb0 * (o1 + (int64_t)nb1 * o2);
+              A[(size_t)gi * N0 + gj] += L0.band[o * L0.NL + x];
+            }
+      }
+  });
   setup_progress("dense coarse matrix built; coarse unknowns", (double)N0);
   if (coarse_on_device(H.opt, N0, device)) {
     H.A0 = std::move(A);   // factored after upload
     return;
   }
-  if (!cholesky(A, (int)N0)) fail(IGAMG_ENOTSPD, "coarse matrix is not positive definite (is any side Dirichlet?)");
+  Mat Ah(A.begin(), A.end());
+  DenseBuf().swap(A);
+  if (!cholesky(Ah, (int)N0)) fail(IGAMG_ENOTSPD, "coarse matrix is not positive definite (is any side Dirichlet?)");
   // A_0^{-1} = L^{-T} L^{-1} from the Cholesky factor: the two triangular
   // solves of the exact coarse solver become one dense mat-vec on the device
-  Mat W = lower_inverse(A, (int)N0);
+  Mat W = lower_inverse(Ah, (int)N0);
   H.Ainv.assign((size_t)N0 * N0, 0.0);
   parallel_for((int)N0, [&](int i) {
     for (int64_t j = i; j < N0; ++j) {

@@ -3,6 +3,8 @@
 #pragma once
 
 #include <array>
+#include <memory>
+#include <utility>
 #include <cstdint>
 #include <string>
 #include <vector>
@@ -76,6 +78,29 @@ struct LevelH {
   std::vector<double> omega;                 // per patch
 };
 
+// A vector of doubles whose elements start uninitialised: the dense coarse
+// matrix (N0^2 doubles, up to 75 GB) is zeroed and filled by row blocks in
+// parallel instead of by a serial value-initialisation.
+template <class T>
+struct UninitAlloc : std::allocator<T> {
+  template <class U>
+  struct rebind {
+    using other = UninitAlloc<U>;
+  };
+  UninitAlloc() = default;
+  template <class U>
+  UninitAlloc(const UninitAlloc<U>&) noexcept {}
+  template <class U>
+  void construct(U* p) noexcept {
+    ::new (static_cast<void*>(p)) U;
+  }
+  template <class U, class... A>
+  void construct(U* p, A&&... a) {
+    ::new (static_cast<void*>(p)) U(std::forward<A>(a)...);
+  }
+};
+using DenseBuf = std::vector<double, UninitAlloc<double>>;
+
 struct Hierarchy {
   ProblemH prob;
   Options opt;
@@ -83,7 +108,7 @@ struct Hierarchy {
   // coarse solver: A_0^{-1} = L^{-T} L^{-1} with A_0 = L L^T (dense, row-major, N0 x N0),
   // factored on the host; or the dense A_0 itself, to be factored on the device
   std::vector<double> Ainv;
-  std::vector<double> A0;
+  DenseBuf A0;
 };
 
 

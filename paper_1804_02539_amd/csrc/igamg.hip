@@ -251,8 +251,8 @@ static size_t plan(igamg_ctx& C, char* base) {
   return std::max(b.pos, scratch_end) + 256;
 }
 
-template <typename T>
-static void up(T* dst, const std::vector<T>& src, hipStream_t st) {
+template <typename T, typename Alloc>
+static void up(T* dst, const std::vector<T, Alloc>& src, hipStream_t st) {
   if (!src.empty()) {
     HIP_OK(hipMemcpyAsync(dst, src.data(), src.size() * sizeof(T), hipMemcpyHostToDevice, st));
     HIP_OK(hipStreamSynchronize(st));
@@ -385,7 +385,7 @@ static void upload(igamg_ctx& C, hipStream_t st) {
         setup_progress("device factorization reported an indefinite matrix; factoring again, unknowns", (double)C.N0);
       }
     }
-    std::vector<double>().swap(H.A0);
+    DenseBuf().swap(H.A0);
     // the scratch was lent from the level data: zero it again
     HIP_OK(hipMemsetAsync(static_cast<char*>(C.ws) + C.scratch_at, 0, C.bytes - C.scratch_at, st));
     HIP_OK(hipStreamSynchronize(st));
