@@ -1,10 +1,12 @@
-// Test helper: runs the device-assembly stages (the per-entry arithmetic of
+// Test helper, built with g++ by test_assembly_stages_host.py (not part of
+// the library): runs the device-assembly stages (the arithmetic of
 // assemble.hip) on the host over exactly sized buffers and compares the tiled
-// band with the host assembly of every level >= 1.  Built by
-// test_assembly_stages_host.py with g++; not part of the library.
+// band with the host assembly of every level >= 1; and compares the parallel
+// dense coarse build with a serial one.
 #define IGAMG_HD
 #include <algorithm>
 #include <cmath>
+#include <cstring>
 #include <vector>
 
 #include "assemble_stages.hpp"
@@ -95,5 +97,47 @@ extern "C" int asm_stages_vs_host(const void* cprob, double* rel, int* flags) {
     return 0;
   } catch (const SetupError&) {
     return 1;
+  }
+}
+
+// The dense coarse matrix of a device setup (built by blocks of global rows
+// in parallel, kept for upload) against a serial pass over patches, rows and
+// offsets: returns the number of entries that differ in any bit (-1 when the
+// coarse problem is small enough for the host factorization, -2 on a setup
+// error).
+extern "C" long coarse_dense_vs_serial(const void* cprob) {
+  try {
+    Hierarchy H;
+    H.prob = read_problem(cprob);
+    build_all(H, true);
+    if (H.A0.empty()) return -1;
+    const ProblemH& P = H.prob;
+    const LevelH& L0 = H.lv[0];
+    const int64_t N0 = L0.N;
+    std::vector<double> A((size_t)N0 * N0, 0.0);
+    const int d = P.d, p = P.p, nb0 = 2 * p + 1, nb1 = 2 * p + 1, p2 = (d == 3) ? p : 0, nb2 = 2 * p2 + 1;
+    for (int k = 0; k < P.K; ++k) {
+      const auto& n = L0.n[k];
+      for (int64_t r = 0; r < L0.rows[k]; ++r) {
+        const int64_t x = L0.off[k] + r, gi = L0.gid[x];
+        if (gi < 0) continue;
+        const int i0 = (int)(r % n[0]), i1 = (int)((r / n[0]) % n[1]), i2 = (int)(r / ((int64_t)n[0] * n[1]));
+        for (int o2 = 0; o2 < nb2; ++o2)
+          for (int o1 = 0; o1 < nb1; ++o1)
+            for (int o0 = 0; o0 < nb0; ++o0) {
+              const int j0 = i0 + o0 - p, j1 = i1 + o1 - p, j2 = i2 + o2 - p2;
+              if (j0 < 0 || j0 >= n[0] || j1 < 0 || j1 >= n[1] || j2 < 0 || j2 >= n[2]) continue;
+              const int64_t y = L0.off[k] + j0 + (int64_t)n[0] * (j1 + (int64_t)n[1] * j2);
+              const int64_t gj = L0.gid[y];
+              if (gj < 0) continue;
+              A[(size_t)gi * N0 + gj] += L0.band[(o0 + (int64_t)nb0 * (o1 + (int64_t)nb1 * o2)) * L0.NL + x];
+            }
+      }
+    }
+    long diff = 0;
+    for (size_t i = 0; i < A.size(); ++i) diff += std::memcmp(&A[i], &H.A0[i], sizeof(double)) != 0;
+    return diff;
+  } catch (const SetupError&) {
+    return -2;
   }
 }

@@ -26,6 +26,7 @@ def stages(tmp_path_factory):
     subprocess.check_call(cmd)
     lib = ctypes.CDLL(out)
     lib.asm_stages_vs_host.restype = ctypes.c_int
+    lib.coarse_dense_vs_serial.restype = ctypes.c_long
     return lib
 
 
@@ -45,3 +46,16 @@ def test_stages_equal_host_assembly(stages, name):
     assert stages.asm_stages_vs_host(ctypes.byref(cp.s), ctypes.byref(rel), ctypes.byref(flags)) == 0
     assert rel.value < 1e-14, rel.value
     assert flags.value == 1      # det J > 0 at every Gauss point
+
+
+@pytest.mark.parametrize("name,prob", [
+    ("box3d_p4_4x3x2_e3", lambda: W.box_grid(3, [4, 3, 2], 4, 3, 2, gdeg=1)),
+    ("box3d_p5_2x2x4_e3", lambda: W.box_grid(3, [2, 2, 4], 5, 3, 2, gdeg=1)),
+    ("box2d_p3_4x4_e16", lambda: W.box_grid(2, [4, 4], 3, 16, 2, gdeg=2, dirichlet_sides=[0, 2])),
+])
+def test_parallel_coarse_build_equals_serial(stages, name, prob):
+    # coarse problems above the host factorization limit are built for the
+    # device by blocks of rows in parallel; every entry must match a serial
+    # pass bit for bit
+    cp = igamg._CProblem(prob())
+    assert stages.coarse_dense_vs_serial(ctypes.byref(cp.s)) == 0
