@@ -6,11 +6,14 @@ timed on the host.
 
     python bench.py [--gpus 1] [--steps K] [--warmup W] [--workload NAME]
                     [--precision both|fp64|mixed] [--no-cpu-baseline] [--no-serve]
+                    [--profile-steps 3] [--secondary square4x4_p4]
     python bench.py --serve-full [--serve-rate R]     # the full serving recipe instead
     python bench.py --fichera-table 2,3 [--fichera-levels 1,2]   # Fichera iteration counts instead
 
 A step is one complete solve of the workload from u = 0 to ||f - A u|| <= 1e-8
-||f|| (setup excluded; inputs resident in HBM).  Prints one JSON line; `value`
+||f|| (setup excluded; inputs resident in HBM).  The default workload is the
+64-patch p=5 cube (2.87M free dofs), the largest single-GPU configuration; the
+2D 16-patch p=4 square is timed beside it in the `secondary` object.  Prints one JSON line; `value`
 is the mixed-precision rate when both precisions run.  The `serving` object
 reports continuous-batching throughput and p50/p99 latency over a seeded mix of
 resident problems (see paper_1804_02539_amd/serve.py).
@@ -81,15 +84,30 @@ def traffic_from_profiles(workload, precision):
     return t.get(precision, {}).get("hbm_bytes_per_launch")
 
 
+def _host_cores():
+    try:
+        from threadpoolctl import threadpool_info
+        return max([i.get("num_threads", 1) for i in threadpool_info()] + [1])
+    except Exception:
+        return os.cpu_count() or 1
+
+
+def _cpu_model():
+    try:
+        with open("/proc/cpuinfo") as fh:
+            for line in fh:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
+
+
 def cpu_baseline(prob, rhs, min_seconds=10.0, max_solves=50):
     """The oracle's PCG solve of the same workload on the host (setup
     excluded), repeated until about min_seconds of solving have elapsed."""
     from oracle.multigrid import Hierarchy
-    try:
-        from threadpoolctl import threadpool_info
-        cores = max([i.get("num_threads", 1) for i in threadpool_info()] + [1])
-    except Exception:
-        cores = os.cpu_count() or 1
+    cores = _host_cores()
     t0 = time.perf_counter()
     H = Hierarchy(prob)
     t_setup = time.perf_counter() - t0
@@ -102,16 +120,51 @@ def cpu_baseline(prob, rhs, min_seconds=10.0, max_solves=50):
         if t >= min_seconds or solves >= max_solves:
             break
     return {"value": H.finest.N * solves / t, "unit": "DOF/s", "cores": int(cores), "kind": "oracle",
+            "cpu_model": _cpu_model(),
             "sample": f"{solves} full PCG solves of the same workload (N={H.finest.N}, {it} iterations each, "
                       f"{t:.1f} s of solving; oracle setup {t_setup:.1f} s excluded)",
             "iterations": it, "solve_s": t / solves}
+
+
+def cpu_baseline_sampled(prob_replica, iterations_full, n_full, seconds=20.0):
+    """The oracle on a bounded sample of a workload too large for it: the
+    replica with every element count divided by 4 (same patches, degree,
+    geometry and coarsest level).  A number of its PCG iterations is timed
+    (about ``seconds`` of CPU work, oracle setup excluded); the rate is then
+    scaled to the full workload as N / (iterations_full * t_iter * N / N_rep),
+    i.e. it assumes the oracle's time per iteration grows linearly with the
+    number of unknowns, and takes the full workload's FP64 iteration count."""
+    from oracle.multigrid import Hierarchy
+    from paper_1804_02539_amd import workloads as W
+    cores = _host_cores()
+    t0 = time.perf_counter()
+    H = Hierarchy(prob_replica)
+    t_setup = time.perf_counter() - t0
+    n_rep = H.finest.N
+    rhs = W.random_rhs(n_rep, prob_replica.meta["source"][1])
+    t0 = time.perf_counter()
+    H.finest.apply(H.vcycle(rhs))
+    t_one = time.perf_counter() - t0
+    k = int(max(2, min(40, seconds / max(t_one, 1e-3))))
+    t0 = time.perf_counter()
+    _, it, hist = H.pcg(rhs, tol=1e-8, maxit=k)
+    t = time.perf_counter() - t0
+    t_iter = t / max(it, 1)
+    value = n_rep / (iterations_full * t_iter)
+    return {"value": value, "unit": "DOF/s", "cores": int(cores), "kind": "oracle", "cpu_model": _cpu_model(),
+            "sample": f"{it} PCG iterations of the oracle on the replica with element counts / 4 "
+                      f"(N_rep={n_rep}, {t:.1f} s, {t_iter:.2f} s per iteration; oracle setup {t_setup:.1f} s "
+                      f"excluded), scaled to the full workload (N={n_full}) as linear time per unknown and "
+                      f"{iterations_full} iterations (the GPU FP64 solve's count)",
+            "replica_n_free": int(n_rep), "replica_s_per_iteration": t_iter, "replica_iterations_run": int(it),
+            "replica_rel_residual_after_sample": float(hist[-1])}
 
 
 def log(msg):
     print(f"[bench] {msg}", file=sys.stderr, flush=True)
 
 
-def run(workload, prob, precision, steps, warmup, dev, fd_mfma=0):
+def run(workload, prob, precision, steps, warmup, dev, fd_mfma=0, profile_steps=3):
     import torch
     from paper_1804_02539_amd import igamg
     opts = igamg.default_options(precision=igamg.MIXED if precision == "mixed" else igamg.FP64, fd_mfma=fd_mfma)
@@ -141,12 +194,13 @@ def run(workload, prob, precision, steps, warmup, dev, fd_mfma=0):
     S.profile(True)
     torch.cuda.synchronize()
     t_p = time.perf_counter()
-    for _ in range(steps):
+    psteps = max(1, min(profile_steps, steps))
+    for _ in range(psteps):
         S.solve(f, tol=1e-8, u=u, stream=stream)
     torch.cuda.synchronize()
     total_prof = time.perf_counter() - t_p
     S.profile(False)
-    log(f"  profiled pass: {1e3 * total_prof / steps:.2f} ms/solve")
+    log(f"  profiled pass: {1e3 * total_prof / psteps:.2f} ms/solve")
     cnt, ms, by = S.profile_read()
     nl = prob.levels
     Lf = nl - 1
@@ -175,12 +229,12 @@ def run(workload, prob, precision, steps, warmup, dev, fd_mfma=0):
                      "traffic": traffic_from_profiles(workload, precision),
                      "avg_launch_us": 1e3 * avg_ms,
                      "algorithmic_bytes_per_launch": bytes_launch,
-                     "launches_per_step": float(cnt[k]) / steps,
-                     "band_ms_per_step_fp64_all_levels": float(ms[:nl].sum()) / steps,
-                     "band_ms_per_step_fp32_all_levels": float(ms[nl:].sum()) / steps,
-                     "measured_over": f"a second timed pass of the same {steps} solves, direct launches, each "
-                                      f"banded launch timed by HIP events attached to its dispatch "
-                                      f"({1e3 * total_prof / steps:.2f} ms/solve)"},
+                     "launches_per_step": float(cnt[k]) / psteps,
+                     "band_ms_per_step_fp64_all_levels": float(ms[:nl].sum()) / psteps,
+                     "band_ms_per_step_fp32_all_levels": float(ms[nl:].sum()) / psteps,
+                     "measured_over": f"a second timed pass of {psteps} of the same solves, direct launches, "
+                                      f"each banded launch timed by HIP events attached to its dispatch "
+                                      f"({1e3 * total_prof / psteps:.2f} ms/solve)"},
     }
     return S, res
 
@@ -314,7 +368,11 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=3)
-    ap.add_argument("--workload", default="square4x4_p4", choices=sorted(WORKLOADS))
+    ap.add_argument("--workload", default="cube4x4x4_p5", choices=sorted(WORKLOADS))
+    ap.add_argument("--profile-steps", type=int, default=3,
+                    help="solves in the second, per-launch timed pass (roofline)")
+    ap.add_argument("--secondary", default="square4x4_p4",
+                    help="comma-separated workloads also timed (FP64 and mixed) in a secondary object; '' for none")
     ap.add_argument("--precision", default="both", choices=["both", "fp64", "mixed"])
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-serve", action="store_true")
@@ -362,11 +420,20 @@ def main():
     prob = make_problem(a.workload)
     runs = {}
     if a.precision in ("both", "fp64"):
-        S, runs["fp64"] = run(a.workload, prob, "fp64", a.steps, a.warmup, dev)
+        S, runs["fp64"] = run(a.workload, prob, "fp64", a.steps, a.warmup, dev, profile_steps=a.profile_steps)
+        N_free, N_local = S.N, S.N_local
+        rhs_cpu = rhs_for(prob, S)
+        del S
+        torch.cuda.empty_cache()
     if a.precision in ("both", "mixed"):
-        S, runs["mixed"] = run(a.workload, prob, "mixed", a.steps, a.warmup, dev)
+        S, runs["mixed"] = run(a.workload, prob, "mixed", a.steps, a.warmup, dev, profile_steps=a.profile_steps)
+        N_free, N_local = S.N, S.N_local
         if a.fd_mfma:
-            _, runs["mixed_fd_mfma"] = run(a.workload, prob, "mixed", a.steps, a.warmup, dev, fd_mfma=1)
+            _, runs["mixed_fd_mfma"] = run(a.workload, prob, "mixed", a.steps, a.warmup, dev, fd_mfma=1,
+                                           profile_steps=a.profile_steps)
+        rhs_cpu = rhs_for(prob, S)
+        del S
+        torch.cuda.empty_cache()
     head = "mixed" if ("mixed" in runs and runs["mixed"]["converged"]) else "fp64"
     h = runs[head]
     out = {
@@ -383,7 +450,7 @@ def main():
         "dtype": "f32 inner / f64 refinement" if head == "mixed" else "f64",
         "data": "synthetic",
         "config": {"workload": a.workload, "description": WORKLOADS[a.workload],
-                   "n_free_dofs": S.N, "n_local_dofs": S.N_local, "degree": prob.degree,
+                   "n_free_dofs": N_free, "n_local_dofs": N_local, "degree": prob.degree,
                    "patches": prob.npatch, "levels": prob.levels, "precision": head,
                    "solver": "PCG, one V-cycle (1+1 smoothing, tau=0.25, sigma=5/h^2) per iteration"},
         "latency_ms": h["latency_ms"],
@@ -401,14 +468,34 @@ def main():
         out["speedup_mixed_vs_fp64"] = runs["mixed"]["value"] / runs["fp64"]["value"]
     if "mixed_fd_mfma" in runs and "mixed" in runs:
         out["mixed_fd_mfma_vs_vector"] = runs["mixed_fd_mfma"]["value"] / runs["mixed"]["value"]
+    secondary = {}
+    for wname in [w for w in a.secondary.split(",") if w and w != a.workload]:
+        sprob = make_problem(wname)
+        srun = {}
+        for prec in ("fp64", "mixed"):
+            Ss, r = run(wname, sprob, prec, a.steps, a.warmup, dev, profile_steps=a.profile_steps)
+            srun[prec] = {kk: vv for kk, vv in r.items() if kk != "roofline"}
+            srun[prec]["n_free_dofs"] = Ss.N
+            srun[prec]["band_roofline_frac"] = r["roofline"]["frac"]
+            srun[prec]["band_avg_launch_us"] = r["roofline"]["avg_launch_us"]
+            del Ss
+        srun["speedup_mixed_vs_fp64"] = srun["mixed"]["value"] / srun["fp64"]["value"]
+        srun["description"] = WORKLOADS[wname]
+        secondary[wname] = srun
+    if secondary:
+        out["secondary"] = secondary
     if not a.no_serve:
         log("serving")
         out["serving"] = serving("mixed" if head == "mixed" else "fp64", a.serve_requests,
                                  a.serve_families, 5, dev)
     if not a.no_cpu_baseline:
         log("cpu baseline (oracle)")
-        from paper_1804_02539_amd import igamg  # noqa: F401
-        out["cpu_baseline"] = cpu_baseline(prob, rhs_for(prob, S))
+        if a.workload == "cube4x4x4_p5":
+            from paper_1804_02539_amd import workloads as W
+            it_full = runs["fp64"]["iterations"] if "fp64" in runs else h["iterations"]
+            out["cpu_baseline"] = cpu_baseline_sampled(W.batched_patch_cube(divide=4), it_full, N_free)
+        else:
+            out["cpu_baseline"] = cpu_baseline(prob, rhs_cpu)
     print(json.dumps(out), flush=True)
 
 

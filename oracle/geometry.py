@@ -73,3 +73,16 @@ def omega(geo, nq=8):
     for _ in range(geo.d - 1):
         W = np.multiply.outer(w, W)
     return float(np.sum(W * tr))
+
+
+def axis_lengths(geo, nq=8):
+    """Mean physical length of each parameter direction of a patch: the
+    parameter-domain average of |dG/dxi_c| (the c-th Jacobian column), with the
+    nq-point Gauss rule per direction.  Used by the physical-h reading of the
+    smoother (h_c = length_c / nel_c)."""
+    x, w = bspline.gauss_legendre(nq)
+    _, J = geo.eval_grid([x] * geo.d)
+    W = w
+    for _ in range(geo.d - 1):
+        W = np.multiply.outer(w, W)
+    return [float(np.sum(W * np.linalg.norm(J[..., :, c], axis=-1))) for c in range(geo.d)]

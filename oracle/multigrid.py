@@ -26,7 +26,7 @@ EXPLICIT_LIMIT = 120_000   # local rows up to which a level's matrix is formed
 
 
 class Level:
-    def __init__(self, prob, level, explicit=None, sigma_scale=5.0):
+    def __init__(self, prob, level, explicit=None, sigma_scale=5.0, reading=None):
         self.level = level
         self.dm = DofMap(prob, level)
         self.N = self.dm.N
@@ -45,8 +45,16 @@ class Level:
             self.A = A.tocsr()
         omegas = [geometry.omega(op.geo) for op in self.ops]
         self.omegas = omegas
+        self.lengths = [geometry.axis_lengths(op.geo) for op in self.ops]
         self.pieces = pieces(self.dm)
-        self.smoother = Smoother(prob, level, self.dm, self.pieces, omegas, sigma_scale)
+        self.prob = prob
+        self.sigma_scale = sigma_scale
+        self.set_reading(reading)
+
+    def set_reading(self, reading):
+        """(Re)build the smoother under a reading of its constants (see oracle.smoother)."""
+        self.smoother = Smoother(self.prob, self.level, self.dm, self.pieces, self.omegas,
+                                 self.sigma_scale, reading=reading, lengths=self.lengths)
 
     def apply(self, u):
         """A_l u (eq. of the linear system) on free dofs."""
@@ -97,16 +105,21 @@ def prolongation(prob, coarse, fine):
 
 
 class Hierarchy:
-    def __init__(self, prob, tau=0.25, nu=1, mu=1, sigma_scale=5.0, explicit=None):
+    def __init__(self, prob, tau=0.25, nu=1, mu=1, sigma_scale=5.0, explicit=None, reading=None):
         self.prob = prob
         self.tau, self.nu, self.mu = tau, nu, mu
         self.levels = [Level(prob, l, explicit=(True if l == 0 else explicit),
-                             sigma_scale=sigma_scale)
+                             sigma_scale=sigma_scale, reading=reading)
                        for l in range(prob.levels)]
         self.P = [None] + [prolongation(prob, self.levels[l - 1], self.levels[l])
                            for l in range(1, prob.levels)]
         A0 = self.levels[0].A.toarray()
         self.coarse_factor = sla.cho_factor(A0, lower=True)
+
+    def set_reading(self, reading):
+        """Rebuild every level's smoother under another reading of its constants."""
+        for lev in self.levels:
+            lev.set_reading(reading)
 
     @property
     def finest(self):

@@ -28,6 +28,16 @@ Edges: L_T = omega ((h/p)^{d-1} K + (h/p)^{d-3} M) on the edge-interior
 functions, solved exactly.  Vertices: L_T = omega (h/p)^{d-2}.
 h for an interface piece is the geometric mean of 1/nel over the adjacent
 patches' normal directions; omega is the mean of the adjacent patches' omega.
+
+Other readings, selected by the ``reading`` argument (used to compare the
+readings' iteration counts with the paper's Fichera table, Sec. 5):
+* omega = "one": no geometry factor (omega = 1 for every piece);
+* h = "physical": h_c = (mean length of the patch's c-th Jacobian column)/nel_c
+  instead of the parameter-domain 1/nel_c, in sigma and in the interface formulas;
+* k1 = "K+sigmaM": the operator on S1 is K + sigma M instead of K (the
+  eigenvalues on the S1 columns become lambda + sigma);
+* mult = True: every interface piece operator is multiplied by the number of
+  patches adjacent to it.
 """
 import itertools
 
@@ -94,10 +104,16 @@ def _modes(T, mats, transpose):
     return T
 
 
+DEFAULT_READING = {"omega": "mean", "h": "param", "k1": "K", "mult": False}
+
+
 class Smoother:
     """L_l^{-1} on global free vectors of one level."""
 
-    def __init__(self, prob, level, dm, pcs, omegas, sigma_scale=5.0):
+    def __init__(self, prob, level, dm, pcs, omegas, sigma_scale=5.0, reading=None, lengths=None):
+        rd = dict(DEFAULT_READING)
+        rd.update(reading or {})
+        self.reading = rd
         self.p = p = prob.degree
         d = prob.dim
         nel = prob.nel(level)
@@ -106,36 +122,51 @@ class Smoother:
         self.pieces = []
         cache = {}
 
-        def one_d(e):
-            if e not in cache:
+        def hdir(k, c):
+            """h of patch k in direction c under the reading."""
+            h = 1.0 / float(nel[k][c])
+            if rd["h"] == "physical":
+                h *= lengths[k][c]
+            return h
+
+        def one_d(k, c):
+            e = int(nel[k][c])
+            sigma = sigma_scale / hdir(k, c) ** 2
+            key = (e, sigma)
+            if key not in cache:
                 Mi, Ki, C = interior_1d(p, e)
-                U, mu, _, _ = split_basis(Mi, Ki, C, sigma_scale * e * e)
-                cache[e] = (Mi, Ki, U, mu)
-            return cache[e]
+                U, mu, k0, _ = split_basis(Mi, Ki, C, sigma)
+                if rd["k1"] == "K+sigmaM":
+                    mu = mu.copy()
+                    mu[k0:] += sigma
+                cache[key] = (Mi, Ki, U, mu)
+            return cache[key]
 
         for pc in pcs:
             k = pc.owner
             adj = [a for a, _ in pc.adjacent]
-            om = float(np.mean([omegas[a] for a in adj]))
+            om = float(np.mean([omegas[a] for a in adj])) if rd["omega"] == "mean" else 1.0
+            if rd["mult"] and pc.kind != "interior":
+                om *= len(adj)
             if pc.kind == "interior":
-                ops = [one_d(int(nel[k][c])) for c in range(d)]
+                ops = [one_d(k, c) for c in range(d)]
                 Us = [o[2] for o in ops]
                 D = om * sum(np.meshgrid(*[o[3] for o in reversed(ops)], indexing="ij")[d - 1 - c]
                              for c in range(d))
                 self.pieces.append(("fd", pc.dofs, Us, D))
                 continue
-            hs = [1.0 / nel[a][c] for a, bd in pc.adjacent for c in bd]
+            hs = [hdir(a, c) for a, bd in pc.adjacent for c in bd]
             h = float(np.exp(np.mean(np.log(hs))))
             if pc.kind == "vertex":
                 self.pieces.append(("scalar", pc.dofs, om * (h / p) ** (d - 2)))
             elif pc.kind == "edge":
                 c = [c for c in range(d) if c not in pc.bdirs][0]
-                Mi, Ki, _, _ = one_d(int(nel[k][c]))
+                Mi, Ki, _, _ = one_d(k, c)
                 L = om * ((h / p) ** (d - 1) * Ki + (h / p) ** (d - 3) * Mi)
                 self.pieces.append(("dense", pc.dofs, sla.cho_factor(L), L))
             else:  # face, d == 3
                 tang = [c for c in range(d) if c not in pc.bdirs]
-                ops = [one_d(int(nel[k][c])) for c in tang]
+                ops = [one_d(k, c) for c in tang]
                 Us = [o[2] for o in ops]
                 mu0, mu1 = ops[0][3], ops[1][3]
                 D = om * (h / p) * (mu1[:, None] + mu0[None, :] + p * p / (h * h))

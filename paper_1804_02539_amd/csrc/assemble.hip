@@ -19,6 +19,7 @@
 // band[(row/256)*nb*256 + o*256 + row%256].
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
 #include <cstdint>
 
 #include "assemble_stages.hpp"
@@ -28,8 +29,14 @@ namespace igamg {
 
 namespace {
 
-// grid of at most 2^32 threads (every launch here stays far below)
+// one thread per item; the per-slab stages stay far below the 2^32 work-items
+// of a dispatch (the largest slab of a 48^3-element p=8 patch has about 2.6e8
+// direction-2 threads), and launch_slab checks it
 inline dim3 grid_for(int64_t tot) { return dim3((unsigned)((tot + 255) / 256)); }
+constexpr int64_t MAX_DISPATCH_ITEMS = ((int64_t)1 << 32) - 256;
+
+// grid-stride launches cap their grid at this many workgroups
+constexpr int64_t STRIDE_BLOCKS = (int64_t)1 << 20;
 
 template <int D>
 __global__ __launch_bounds__(256) void k_asm_metric(AsmPatch P, const double* __restrict__ tab, int e2,
@@ -77,39 +84,47 @@ template <int D>
 __global__ __launch_bounds__(256) void k_asm_mask(const PatchDev* __restrict__ pd, const int* __restrict__ bpatch,
                                                   const uint8_t* __restrict__ isfree, double* __restrict__ band,
                                                   int nbt, int p, int64_t tot) {
-  const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (t < tot) asm_mask_entry<D>(pd, bpatch, isfree, band, nbt, p, t);
+  // grid-stride: a whole level's band can hold more than 2^32 entries
+  const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+  for (int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; t < tot; t += stride)
+    asm_mask_entry<D>(pd, bpatch, isfree, band, nbt, p, t);
 }
 
 // the four launches of one slab; the direction-2 stage has degree P in 3D
 // and none in 2D
 template <int D, int P>
-void launch_slab(const AsmPatch& Pt, const double* tab, int e2, double* Gs, double* T1, double* T2, double* band,
-                 int nbt, int* flag, hipStream_t st) {
+hipError_t launch_slab(const AsmPatch& Pt, const double* tab, int e2, double* Gs, double* T1, double* T2,
+                       double* band, int nbt, int* flag, hipStream_t st) {
   constexpr int P2 = (D == 3) ? P : 0;
   size_t sz[3];
   asm_sizes(D, Pt, sz);
   const int64_t t0 = asm_dir0_threads(D, Pt), t1 = asm_dir1_threads(D, Pt), t2 = asm_dir2_threads(Pt);
+  if ((int64_t)sz[0] / (D * D) > MAX_DISPATCH_ITEMS || t0 > MAX_DISPATCH_ITEMS || t1 > MAX_DISPATCH_ITEMS ||
+      t2 > MAX_DISPATCH_ITEMS)
+    return hipErrorInvalidConfiguration;
   hipLaunchKernelGGL(k_asm_metric<D>, grid_for((int64_t)sz[0] / (D * D)), dim3(256), 0, st, Pt, tab, e2, Gs, flag);
   hipLaunchKernelGGL((k_asm_dir0<D, P>), grid_for(t0), dim3(256), 0, st, Pt, tab, Gs, T1, t0);
   hipLaunchKernelGGL((k_asm_dir1<D, P>), grid_for(t1), dim3(256), 0, st, Pt, tab, T1, T2, t1);
   hipLaunchKernelGGL((k_asm_dir2<D, P2>), grid_for(t2), dim3(256), 0, st, Pt, tab, e2, T2, band, nbt, t2);
+  return hipSuccess;
 }
 
 template <int D>
 hipError_t launch_slab_d(const AsmPatch& Pt, const double* tab, int e2, double* Gs, double* T1, double* T2,
                          double* band, int nbt, int* flag, hipStream_t st) {
+  hipError_t e = hipSuccess;
   switch (Pt.pc[0]) {
-    case 1: launch_slab<D, 1>(Pt, tab, e2, Gs, T1, T2, band, nbt, flag, st); break;
-    case 2: launch_slab<D, 2>(Pt, tab, e2, Gs, T1, T2, band, nbt, flag, st); break;
-    case 3: launch_slab<D, 3>(Pt, tab, e2, Gs, T1, T2, band, nbt, flag, st); break;
-    case 4: launch_slab<D, 4>(Pt, tab, e2, Gs, T1, T2, band, nbt, flag, st); break;
-    case 5: launch_slab<D, 5>(Pt, tab, e2, Gs, T1, T2, band, nbt, flag, st); break;
-    case 6: launch_slab<D, 6>(Pt, tab, e2, Gs, T1, T2, band, nbt, flag, st); break;
-    case 7: launch_slab<D, 7>(Pt, tab, e2, Gs, T1, T2, band, nbt, flag, st); break;
-    case 8: launch_slab<D, 8>(Pt, tab, e2, Gs, T1, T2, band, nbt, flag, st); break;
+    case 1: e = launch_slab<D, 1>(Pt, tab, e2, Gs, T1, T2, band, nbt, flag, st); break;
+    case 2: e = launch_slab<D, 2>(Pt, tab, e2, Gs, T1, T2, band, nbt, flag, st); break;
+    case 3: e = launch_slab<D, 3>(Pt, tab, e2, Gs, T1, T2, band, nbt, flag, st); break;
+    case 4: e = launch_slab<D, 4>(Pt, tab, e2, Gs, T1, T2, band, nbt, flag, st); break;
+    case 5: e = launch_slab<D, 5>(Pt, tab, e2, Gs, T1, T2, band, nbt, flag, st); break;
+    case 6: e = launch_slab<D, 6>(Pt, tab, e2, Gs, T1, T2, band, nbt, flag, st); break;
+    case 7: e = launch_slab<D, 7>(Pt, tab, e2, Gs, T1, T2, band, nbt, flag, st); break;
+    case 8: e = launch_slab<D, 8>(Pt, tab, e2, Gs, T1, T2, band, nbt, flag, st); break;
     default: return hipErrorInvalidValue;
   }
+  if (e != hipSuccess) return e;
   return hipGetLastError();
 }
 
@@ -128,10 +143,11 @@ void launch_asm_mask(int d, int p, const PatchDev* pd, const int* bpatch, const 
                      int nbt, int64_t NL, hipStream_t st) {
   const int64_t tot = NL * nbt;
   if (tot <= 0) return;
+  const dim3 grid((unsigned)std::min<int64_t>((tot + 255) / 256, STRIDE_BLOCKS));
   if (d == 2)
-    hipLaunchKernelGGL(k_asm_mask<2>, grid_for(tot), dim3(256), 0, st, pd, bpatch, isfree, band, nbt, p, tot);
+    hipLaunchKernelGGL(k_asm_mask<2>, grid, dim3(256), 0, st, pd, bpatch, isfree, band, nbt, p, tot);
   else
-    hipLaunchKernelGGL(k_asm_mask<3>, grid_for(tot), dim3(256), 0, st, pd, bpatch, isfree, band, nbt, p, tot);
+    hipLaunchKernelGGL(k_asm_mask<3>, grid, dim3(256), 0, st, pd, bpatch, isfree, band, nbt, p, tot);
 }
 
 }  // namespace igamg

@@ -1,7 +1,7 @@
 // Host-side univariate spline tools for the setup phase (Sec. 2: S_{p,h}(0,1)).
 //
 //  - open uniform knot vectors, span search, the non-zero B-splines of a span
-//    and their derivatives by the triangular recurrence tables;
+//    and their derivatives (Cox-de Boor recursion, de Boor's derivative formula);
 //  - Gauss-Legendre nodes by Newton iteration on the Legendre polynomial;
 //  - univariate mass and stiffness matrices by Gauss quadrature;
 //  - the embedding matrix between nested spaces by repeated single-knot
@@ -46,59 +46,66 @@ inline int find_span(const Knots& k, double x) {
 }
 
 // ders[r][j] = r-th derivative of B_{s-p+j} at x, r = 0..nd, j = 0..p.
+//
+// Values come from the Cox-de Boor recursion run over the degrees 0..p on the
+// span s: tab[q][i] holds B_{s-q+i,q}(x), the q+1 functions of degree q that do
+// not vanish there.  Derivatives use de Boor's derivative formula
+//   B'_{g,q} = q B_{g,q-1} / (t_{g+q} - t_g) - q B_{g+1,q-1} / (t_{g+q+1} - t_{g+1}),
+// applied r times to the unit coefficient vector of one degree-p function; the
+// resulting combination of degree p-r functions is read from the table.
 inline void span_ders(const Knots& k, int s, double x, int nd, std::vector<std::vector<double>>& ders) {
   const int p = k.p;
   const std::vector<double>& t = k.t;
-  std::vector<std::vector<double>> ndu(p + 1, std::vector<double>(p + 1, 0.0));
-  std::vector<double> left(p + 1), right(p + 1);
-  ndu[0][0] = 1.0;
-  for (int j = 1; j <= p; ++j) {
-    left[j] = x - t[s + 1 - j];
-    right[j] = t[s + j] - x;
-    double saved = 0.0;
-    for (int r = 0; r < j; ++r) {
-      ndu[j][r] = right[r + 1] + left[j - r];
-      double tmp = ndu[r][j - 1] / ndu[j][r];
-      ndu[r][j] = saved + right[r + 1] * tmp;
-      saved = left[j - r] * tmp;
+  std::vector<std::vector<double>> tab(p + 1);
+  tab[0].assign(1, 1.0);
+  for (int q = 1; q <= p; ++q) {
+    tab[q].assign(q + 1, 0.0);
+    for (int i = 0; i <= q; ++i) {
+      const int g = s - q + i;                       // B_{g,q}
+      double v = 0.0;
+      if (i >= 1) {                                  // B_{g,q-1} = tab[q-1][i-1]
+        const double den = t[g + q] - t[g];
+        if (den > 0.0) v += (x - t[g]) / den * tab[q - 1][i - 1];
+      }
+      if (i < q) {                                   // B_{g+1,q-1} = tab[q-1][i]
+        const double den = t[g + q + 1] - t[g + 1];
+        if (den > 0.0) v += (t[g + q + 1] - x) / den * tab[q - 1][i];
+      }
+      tab[q][i] = v;
     }
-    ndu[j][j] = saved;
   }
   ders.assign(nd + 1, std::vector<double>(p + 1, 0.0));
-  for (int j = 0; j <= p; ++j) ders[0][j] = ndu[j][p];
-  std::vector<std::vector<double>> a(2, std::vector<double>(p + 1, 0.0));
-  for (int r = 0; r <= p; ++r) {
-    int s1 = 0, s2 = 1;
-    a[0][0] = 1.0;
-    for (int kk = 1; kk <= nd; ++kk) {
-      double d = 0.0;
-      int rk = r - kk, pk = p - kk;
-      if (r >= kk) {
-        a[s2][0] = a[s1][0] / ndu[pk + 1][rk];
-        d = a[s2][0] * ndu[rk][pk];
+  for (int j = 0; j <= p; ++j) ders[0][j] = tab[p][j];
+  std::vector<double> c, cn;
+  for (int j = 0; j <= p; ++j) {
+    const int g0 = s - p + j;
+    c.assign(1, 1.0);                                // c[m]: coefficient of B_{g0+m, p-r}
+    for (int r = 1; r <= nd && r <= p; ++r) {
+      const int q = p - r + 1;                       // degree being differentiated
+      cn.assign(r + 1, 0.0);
+      for (int m = 0; m < r; ++m) {
+        const int g = g0 + m;
+        const double d0 = t[g + q] - t[g];
+        const double d1 = t[g + q + 1] - t[g + 1];
+        if (d0 > 0.0) cn[m] += q * c[m] / d0;
+        if (d1 > 0.0) cn[m + 1] -= q * c[m] / d1;
       }
-      int j1 = (rk >= -1) ? 1 : -rk;
-      int j2 = (r - 1 <= pk) ? kk - 1 : p - r;
-      for (int j = j1; j <= j2; ++j) {
-        a[s2][j] = (a[s1][j] - a[s1][j - 1]) / ndu[pk + 1][rk + j];
-        d += a[s2][j] * ndu[rk + j][pk];
+      c.swap(cn);
+      const int qd = p - r;
+      double v = 0.0;
+      for (int m = 0; m <= r; ++m) {
+        const int i = g0 + m - s + qd;               // position of B_{g0+m,qd} in tab[qd]
+        if (i >= 0 && i <= qd) v += c[m] * tab[qd][i];
       }
-      if (r <= pk) {
-        a[s2][kk] = -a[s1][kk - 1] / ndu[pk + 1][r];
-        d += a[s2][kk] * ndu[r][pk];
-      }
-      ders[kk][r] = d;
-      std::swap(s1, s2);
+      ders[r][j] = v;
     }
-  }
-  double fac = p;
-  for (int kk = 1; kk <= nd; ++kk) {
-    for (int j = 0; j <= p; ++j) ders[kk][j] *= fac;
-    fac *= (p - kk);
   }
 }
 
-// Gauss-Legendre nodes/weights on [a, b] (Newton on P_n from Chebyshev guesses).
+// Gauss-Legendre nodes and weights on [a, b]: Newton's method on the Legendre
+// polynomial P_n, evaluated by its three-term recurrence, started from
+// Tricomi's asymptotic guesses cos(pi (i + 3/4) / (n + 1/2)); the weights are
+// 2 / ((1 - z^2) P_n'(z)^2), scaled to [a, b].
 inline void gauss_legendre(int n, double a, double b, std::vector<double>& x, std::vector<double>& w) {
   x.assign(n, 0.0);
   w.assign(n, 0.0);
