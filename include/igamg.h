@@ -100,6 +100,15 @@ typedef struct {
                             sum-factorised Gauss quadrature, straight into the workspace; 1 on the host
                             and uploaded (level 0, which forms the coarse matrix, is always assembled
                             on the host) */
+  /* Readings of the smoother's constants, which the paper leaves to its
+   * references (Sec. 3) and to "spectrally equivalent up to geometry
+   * constants" (Sec. 2); the defaults are the library's reading:           */
+  int s1_sigma;           /* 0 (default): K on the complement S1 of the interior subspace
+                             corrected mass smoother; 1: K + sigma M                       */
+  int iface_multiplicity; /* 0 (default): face, edge and vertex operators as printed; 1: each
+                             times the number of patches adjacent to the piece             */
+  int physical_h;         /* 0 (default): h_c = 1/nel_c of the parameter domain; 1: the
+                             patch's mean physical length in direction c over nel_c        */
   int reserved[1];
 } igamg_options;
 

@@ -560,12 +560,38 @@ struct OneD {
   std::vector<double> mu;
 };
 
+// Mean physical length of each parameter direction: the average over (0,1)^d
+// of |dG/dxi_c| (8-point Gauss).
+static std::array<double, 3> patch_lengths(const ProblemH& P, int k) {
+  GeoEval ge = make_geo(P, k);
+  std::vector<double> x, w;
+  gauss_legendre(8, 0.0, 1.0, x, w);
+  for (int c = 0; c < P.d; ++c) ge.tables(c, x);
+  std::array<double, 3> len{1.0, 1.0, 1.0};
+  for (int c = 0; c < P.d; ++c) len[c] = 0.0;
+  const int n2 = (P.d == 3) ? 8 : 1;
+  for (int q2 = 0; q2 < n2; ++q2)
+    for (int q1 = 0; q1 < 8; ++q1)
+      for (int q0 = 0; q0 < 8; ++q0) {
+        double X[3], J[9];
+        ge.eval(q0, q1, q2, X, J);
+        const double wt = w[q0] * w[q1] * ((P.d == 3) ? w[q2] : 1.0);
+        for (int c = 0; c < P.d; ++c) {
+          double s = 0.0;
+          for (int i = 0; i < P.d; ++i) s += J[i * 3 + c] * J[i * 3 + c];
+          len[c] += wt * std::sqrt(s);
+        }
+      }
+  return len;
+}
+
 // Interior 1D space of S_{p,1/nel} (functions 1..n-2), the subspace of splines
 // whose even derivatives of order 2l (1 <= l, 2l < p) vanish at both ends, its
 // M-orthogonal complement, and the basis U = [M-orthonormal basis of the
 // subspace, M-orthonormal eigenvectors of K on the complement] with
-// mu = [sigma .., eigenvalues].
-static OneD one_d(int p, int nel, double sigma_scale) {
+// mu = [sigma .., eigenvalues] (eigenvalues + sigma when s1_sigma: the
+// operator K + sigma M on the complement).
+static OneD one_d(int p, int nel, double sigma, bool s1_sigma) {
   OneD o;
   Knots kn = open_uniform(p, nel);
   const int n = kn.n(), m = n - 2;
@@ -599,7 +625,6 @@ static OneD one_d(int p, int nel, double sigma_scale) {
     }
   int k0 = 0;
   Mat Z = null_space(C, r, m, &k0);
-  const double sigma = sigma_scale * (double)nel * nel;
   o.U.assign((size_t)m * m, 0.0);
   o.mu.assign(m, 0.0);
   // U0 = Z L0^{-T}, Z^T M Z = L0 L0^T
@@ -662,7 +687,7 @@ static OneD one_d(int p, int nel, double sigma_scale) {
         for (int i = 0; i < k1; ++i) s += Y[(size_t)a * k1 + i] * V[(size_t)i * k1 + j];
         o.U[(size_t)a * m + k0 + j] = s;
       }
-    for (int j = 0; j < k1; ++j) o.mu[k0 + j] = lam[j];
+    for (int j = 0; j < k1; ++j) o.mu[k0 + j] = lam[j] + (s1_sigma ? sigma : 0.0);
   }
   return o;
 }
@@ -753,26 +778,40 @@ static std::vector<PieceH> make_pieces(const ProblemH& P, const LevelH& L) {
 static void make_smoother(const ProblemH& P, const Options& O, LevelH& L) {
   const int d = P.d, p = P.p;
   std::vector<PieceH> pcs = make_pieces(P, L);
-  std::map<int, OneD> cache;
-  std::map<int, int64_t> Uoff, muoff;
+  // 1D factors by (element count, sigma): sigma depends on the patch only
+  // through h, which is 1/nel unless the physical-h reading is chosen
+  using Key = std::pair<int, double>;
+  std::map<Key, OneD> cache;
+  std::map<Key, int64_t> Uoff, muoff;
   L.fdmat.clear();
   // every U_c is stored followed by its transpose; dummy direction: U = U^T = [1], mu = [0]
   const int64_t dummyU = 0, dummyMu = 2;
   L.fdmat.push_back(1.0);
   L.fdmat.push_back(1.0);
   L.fdmat.push_back(0.0);
-  auto get1d = [&](int nel) -> const OneD& {
-    auto it = cache.find(nel);
+  // h of patch k in direction c
+  auto hdir = [&](int k, int c) -> double {
+    double h = 1.0 / (double)L.nel[k][c];
+    if (O.physical_h) h *= L.length[k][c];
+    return h;
+  };
+  auto key1d = [&](int k, int c) -> Key {
+    const double h = hdir(k, c);
+    return Key(L.nel[k][c], O.sigma_scale / (h * h));
+  };
+  auto get1d = [&](int k, int c) -> const OneD& {
+    const Key key = key1d(k, c);
+    auto it = cache.find(key);
     if (it == cache.end()) {
-      OneD o = one_d(p, nel, O.sigma_scale);
+      OneD o = one_d(p, key.first, key.second, O.s1_sigma != 0);
       if (o.m > MAX_FD) fail(IGAMG_EINVAL, "patch too fine for the FD smoother (n-2 > 84)");
-      Uoff[nel] = (int64_t)L.fdmat.size();
+      Uoff[key] = (int64_t)L.fdmat.size();
       L.fdmat.insert(L.fdmat.end(), o.U.begin(), o.U.end());
       for (int i = 0; i < o.m; ++i)
         for (int j = 0; j < o.m; ++j) L.fdmat.push_back(o.U[(size_t)j * o.m + i]);
-      muoff[nel] = (int64_t)L.fdmat.size();
+      muoff[key] = (int64_t)L.fdmat.size();
       L.fdmat.insert(L.fdmat.end(), o.mu.begin(), o.mu.end());
-      it = cache.emplace(nel, std::move(o)).first;
+      it = cache.emplace(key, std::move(o)).first;
     }
     return it->second;
   };
@@ -794,10 +833,10 @@ static void make_smoother(const ProblemH& P, const Options& O, LevelH& L) {
     it.stride[2] = (int64_t)n[0] * n[1];
     for (int c = 0; c < 3; ++c) {
       if (c < d) {
-        const OneD& o = get1d(L.nel[k][c]);
+        const OneD& o = get1d(k, c);
         it.m[c] = o.m;
-        it.U[c] = Uoff[L.nel[k][c]];
-        it.mu[c] = muoff[L.nel[k][c]];
+        it.U[c] = Uoff[key1d(k, c)];
+        it.mu[c] = muoff[key1d(k, c)];
         L.fd_maxm = std::max(L.fd_maxm, o.m);
       } else {
         it.m[c] = 1;
@@ -830,11 +869,12 @@ static void make_smoother(const ProblemH& P, const Options& O, LevelH& L) {
     for (const auto& a : pc.adj) {
       om += O.geometry_scaling ? L.omega[a.first] : 1.0;
       for (int c : a.second) {
-        lh += std::log(1.0 / L.nel[a.first][c]);
+        lh += std::log(hdir(a.first, c));
         ++nh;
       }
     }
     om /= (double)pc.adj.size();
+    if (O.iface_multiplicity) om *= (double)pc.adj.size();
     const double h = std::exp(lh / nh);
     const double hp = h / p;
     if (pc.kind == 1) {  // face: FD in the two free directions of the owner
@@ -843,10 +883,10 @@ static void make_smoother(const ProblemH& P, const Options& O, LevelH& L) {
       it.src_if = 1;
       it.base = seg;
       for (int j = 0; j < 2; ++j) {
-        const OneD& o = get1d(L.nel[k][pc.ft[j]]);
+        const OneD& o = get1d(k, pc.ft[j]);
         it.m[j] = o.m;
-        it.U[j] = Uoff[L.nel[k][pc.ft[j]]];
-        it.mu[j] = muoff[L.nel[k][pc.ft[j]]];
+        it.U[j] = Uoff[key1d(k, pc.ft[j])];
+        it.mu[j] = muoff[key1d(k, pc.ft[j])];
       }
       it.m[2] = 1;
       it.U[2] = dummyU;
@@ -869,7 +909,7 @@ static void make_smoother(const ProblemH& P, const Options& O, LevelH& L) {
       if (pc.kind == 3) {
         Lm[0] = om * std::pow(hp, d - 2);
       } else {
-        const OneD& o = get1d(L.nel[pc.owner][pc.ft[0]]);
+        const OneD& o = get1d(pc.owner, pc.ft[0]);
         if (o.m != m) fail(IGAMG_ETOPO, "internal: edge size mismatch");
         for (size_t i = 0; i < Lm.size(); ++i)
           Lm[i] = om * (std::pow(hp, d - 1) * o.Ki[i] + std::pow(hp, d - 3) * o.Mi[i]);
@@ -1018,9 +1058,16 @@ void build_topology(Hierarchy& H, bool with_numerics) {
   }
   if (H.lv[0].N == 0) fail(IGAMG_EINVAL, "no free degrees of freedom");
   std::vector<double> om(P.K, 1.0);
+  std::vector<std::array<double, 3>> len(P.K, std::array<double, 3>{1.0, 1.0, 1.0});
   if (with_numerics)
-    for (int k = 0; k < P.K; ++k) om[k] = patch_omega(P, k);
-  for (auto& L : H.lv) L.omega = om;
+    for (int k = 0; k < P.K; ++k) {
+      om[k] = patch_omega(P, k);
+      len[k] = patch_lengths(P, k);
+    }
+  for (auto& L : H.lv) {
+    L.omega = om;
+    L.length = len;
+  }
   for (int l = 1; l < P.levels; ++l) {
     make_smoother(P, H.opt, H.lv[l]);
     make_transfers(P, H.lv[l - 1], H.lv[l]);

@@ -37,6 +37,9 @@ struct Options {
   int coarse_factor = 0;   // 0 auto, 1 host, 2 device
   int autotune = 1;
   int assembly = 0;        // levels >= 1: 0 on the device when there is one, 1 on the host
+  int s1_sigma = 0;        // 1: K + sigma M on the complement S1 of the interior smoother
+  int iface_multiplicity = 0;  // 1: interface piece operators times their number of adjacent patches
+  int physical_h = 0;      // 1: h_c = (mean length of the c-th Jacobian column) / nel_c
 };
 
 // Error with an igamg return code.
@@ -76,6 +79,7 @@ struct LevelH {
   std::vector<double> tr_val;
   std::vector<PatchDev> pd;
   std::vector<double> omega;                 // per patch
+  std::vector<std::array<double, 3>> length; // per patch: mean |dG/dxi_c| over (0,1)^d
 };
 
 // A vector of doubles whose elements start uninitialised: the dense coarse

@@ -657,6 +657,12 @@ static void read_opts(const igamg_options* o, Options& O) {
   O.coarse_factor = o->coarse_factor;
   O.autotune = o->autotune;
   O.assembly = o->assembly;
+  O.s1_sigma = o->s1_sigma;
+  O.iface_multiplicity = o->iface_multiplicity;
+  O.physical_h = o->physical_h;
+  if (O.s1_sigma < 0 || O.s1_sigma > 1 || O.iface_multiplicity < 0 || O.iface_multiplicity > 1 || O.physical_h < 0 ||
+      O.physical_h > 1 || O.geometry_scaling < 0 || O.geometry_scaling > 1)
+    throw SetupError{IGAMG_EINVAL, "invalid options"};
   if (!(O.tau > 0) || !(O.sigma_scale > 0) || O.nu < 1 || O.nu > 8 || (O.mu != 1 && O.mu != 2) ||
       (O.precision != IGAMG_FP64 && O.precision != IGAMG_MIXED) || O.maxit < 1 || O.inner_maxit < 1 ||
       !(O.inner_tol > 0 && O.inner_tol < 1) || O.fd_mfma < 0 || O.fd_mfma > 2 || O.autotune < 0 || O.autotune > 1 ||

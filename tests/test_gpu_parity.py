@@ -32,6 +32,7 @@ CASES = {
     "cube2x2x2_p2_l3": lambda: W.cube_2x2x2_trilinear(p=2, levels=3),
     "fichera7_p2_l3": lambda: W.fichera(2, 3),
     "fichera448_p3_l1": lambda: W.fichera(3, 2, split=4),
+    "fichera448_p4_l1": lambda: W.fichera(4, 2, split=4),
     "box3x1_p1_l4": lambda: W.box_grid(2, [3, 1], 1, 2, 4, gdeg=1, dirichlet_sides=[0]),
     "single_patch_p5_l3": lambda: W.box_grid(2, [1, 1], 5, 2, 3, gdeg=1),
     "cube_p4_l3_neumann": lambda: W.box_grid(3, [2, 1, 1], 4, 1, 3, gdeg=1, dirichlet_sides=[0, 2]),
@@ -107,29 +108,74 @@ def test_wcycle_matches_oracle(torch_cuda):
     assert rel(S.vcycle(r).cpu().numpy(), H.vcycle(r)) < 1e-10
 
 
-@pytest.mark.parametrize("name", ["square2x2_p2", "square4x4_p4_l4", "cube2x2x2_p3_l4", "fichera7_p2_l3",
-                                  "fichera448_p3_l1"])
-def test_solve_matches_oracle(torch_cuda, name):
+SOLVE_CASES = ["square2x2_p2", "square4x4_p4_l4", "cube2x2x2_p3_l4", "fichera7_p2_l3", "fichera448_p3_l1",
+               "fichera448_p4_l1"]
+
+
+def _rhs(name, H, S):
     from oracle.multigrid import load_vector
-    _say(f"solve {name}")
     prob = CASES[name]()
-    H = oracle_for(name)
-    S = gpu_for(name)
     if prob.meta["source"][0] == "sine":
         f = load_vector(prob, H.finest)
         fg = S.load_vector(*prob.meta["source"][1:])
         assert rel(fg, f) < 1e-13
-    else:
-        f = W.random_rhs(H.finest.N, prob.meta["source"][1])
+        return f
+    return W.random_rhs(H.finest.N, prob.meta["source"][1])
+
+
+def _nrel(a, b):
+    return float(np.linalg.norm(np.asarray(a) - np.asarray(b)) / np.linalg.norm(np.asarray(b)))
+
+
+# Two PCG runs (Sec. 4) of exactly k iterations from u = 0 on the same
+# operator and preconditioner agree up to rounding.  In FP64 the cycle outputs
+# agree to about 1e-15 (the cycle tests); over k <= 30 iterations the iterates
+# drift apart by at most a few orders of magnitude more, so 1e-10 relative is
+# the bar for u after the same number of iterations.
+FIXED_K_TOL = 1e-10
+
+
+@pytest.mark.parametrize("name", SOLVE_CASES)
+def test_solve_matches_oracle(torch_cuda, name):
+    _say(f"solve {name}")
+    H = oracle_for(name)
+    S = gpu_for(name)
+    f = _rhs(name, H, S)
     u_ref, it_ref, _ = H.pcg(f, tol=1e-8)
     u, info = S.solve(f, tol=1e-8)
     u = u.cpu().numpy()
-    assert abs(info.iterations - it_ref) <= 1, (info.iterations, it_ref)
     res = np.linalg.norm(f - H.finest.apply(u)) / np.linalg.norm(f)
     assert res <= 1.0001e-8 and info.rel_residual <= 1e-8
     assert abs(res - info.rel_residual) <= 1e-3 * res + 1e-14
-    if info.iterations == it_ref:
-        assert rel(u, u_ref) < 1e-9
+    # the GPU solution against the oracle's iterate after the same number of
+    # iterations, whether or not the two stopping tests fired on the same one
+    u_same, _, _ = H.pcg(f, tol=0.0, maxit=info.iterations)
+    e_same = _nrel(u, u_same)
+    e_conv = _nrel(u, u_ref)
+    _say(f"  GPU {info.iterations} it, oracle {it_ref} it; |u - u_oracle(k)|/|u_oracle(k)| = {e_same:.2e}, "
+         f"against the oracle's converged u {e_conv:.2e}")
+    assert e_same < FIXED_K_TOL
+    assert abs(info.iterations - it_ref) <= 2, (info.iterations, it_ref)
+
+
+@pytest.mark.parametrize("name", SOLVE_CASES)
+def test_solve_fixed_iterations_match_oracle(torch_cuda, name):
+    """Both PCGs run exactly k iterations (tolerance 1e-300, cap k); the iterates
+    must agree to FIXED_K_TOL at k = 5 and at half the converged count."""
+    from paper_1804_02539_amd import igamg
+    H = oracle_for(name)
+    _, it_ref, _ = H.pcg(_rhs(name, H, gpu_for(name)), tol=1e-8)
+    for k in sorted({5, max(1, it_ref // 2)}):
+        S = igamg.Solver(CASES[name](), igamg.default_options(maxit=k))
+        f = _rhs(name, H, S)
+        u, info = S.solve(f, tol=1e-300, raise_on_error=False)
+        assert S.last_code == igamg.ENOCONV and info.iterations == k, (S.last_code, info.iterations)
+        u_k, _, hist = H.pcg(f, tol=0.0, maxit=k)
+        err = _nrel(u.cpu().numpy(), u_k)
+        _say(f"  {name} k={k}: |u - u_oracle|/|u_oracle| = {err:.2e} (residual {hist[-1]:.1e}, "
+             f"GPU {info.rel_residual:.1e})")
+        assert err < FIXED_K_TOL
+        assert abs(info.rel_residual - hist[-1]) <= 1e-6 * hist[-1]
 
 
 def test_full_size_square4x4(torch_cuda):

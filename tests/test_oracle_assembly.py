@@ -133,3 +133,85 @@ def test_jacobian_convention():
     _, J = geo.eval_grid([np.array([0.3]), np.array([0.6])])
     assert np.allclose(J[0, 0], [[2, 1], [0, 3]])
     assert abs(geometry.omega(geo) - 6 * np.trace(np.linalg.inv(J[0, 0]) @ np.linalg.inv(J[0, 0]).T) / 2) < 1e-13
+
+
+def _plain_patch_matrix(gdeg, ctrl, p, nel):
+    """A_k of Sec. 2 (the bilinear form a_k with the metric |det J| J^{-1} J^{-T})
+    summed the plain way: element by element, Gauss point by Gauss point, pair
+    of basis functions by pair.  Basis values, the geometry map and the Gauss
+    rule come from scipy and numpy, not from the oracle's own routines."""
+    import itertools
+    from scipy.interpolate import BSpline
+    d = len(nel)
+    knots = [np.r_[np.zeros(p), np.linspace(0.0, 1.0, e + 1), np.ones(p)] for e in nel]
+    nfun = [len(t) - p - 1 for t in knots]
+    ctrl = np.asarray(ctrl, dtype=float).reshape([g + 1 for g in reversed(gdeg)] + [d])
+    gk = [np.r_[np.zeros(g + 1), np.ones(g + 1)] for g in gdeg]
+
+    def basis(c, i, x, nu):
+        coef = np.zeros(nfun[c])
+        coef[i] = 1.0
+        return float(BSpline(knots[c], coef, p)(x, nu=nu))
+
+    def bern(c, a, x, nu):
+        coef = np.zeros(gdeg[c] + 1)
+        coef[a] = 1.0
+        return float(BSpline(gk[c], coef, gdeg[c])(x, nu=nu))
+
+    def jacobian(xi):
+        J = np.zeros((d, d))
+        for idx in itertools.product(*[range(g + 1) for g in gdeg]):
+            cp = ctrl[tuple(reversed(idx))]
+            for j in range(d):
+                w = 1.0
+                for c in range(d):
+                    w *= bern(c, idx[c], xi[c], 1 if c == j else 0)
+                J[:, j] += cp * w
+        return J
+
+    gx, gw = np.polynomial.legendre.leggauss(p + 1)
+    n_loc = int(np.prod(nfun))
+    A = np.zeros((n_loc, n_loc))
+    for el in itertools.product(*[range(e) for e in nel]):
+        lo = [el[c] / nel[c] for c in range(d)]
+        pts = [lo[c] + 0.5 * (gx + 1.0) / nel[c] for c in range(d)]
+        wts = [0.5 * gw / nel[c] for c in range(d)]
+        funs = [range(el[c], el[c] + p + 1) for c in range(d)]
+        for qi in itertools.product(*[range(p + 1) for _ in range(d)]):
+            xi = [pts[c][qi[c]] for c in range(d)]
+            w = np.prod([wts[c][qi[c]] for c in range(d)])
+            J = jacobian(xi)
+            Ji = np.linalg.inv(J)
+            G = abs(np.linalg.det(J)) * Ji @ Ji.T
+            grads = {}
+            for fi in itertools.product(*funs):
+                g = np.ones(d)
+                for a in range(d):
+                    for c in range(d):
+                        g[a] *= basis(c, fi[c], xi[c], 1 if c == a else 0)
+                row = 0
+                for c in reversed(range(d)):
+                    row = row * nfun[c] + fi[c]
+                grads[row] = g
+            for i, gi in grads.items():
+                for j, gj in grads.items():
+                    A[i, j] += w * gi @ G @ gj
+    return A
+
+
+@pytest.mark.parametrize("case", ["2d_p2", "2d_p3", "3d_p2"])
+def test_matrix_equals_plain_quadrature_loop(case):
+    # the sum-factorised element contraction of PatchOp.matrix() against the
+    # plain quadrature sum, on small curved patches
+    if case.startswith("2d"):
+        p = int(case[-1])
+        prob = W.square_4x4_bezier(p=p, nel0=2, levels=2, seed=11)
+        k, nel = 6, [2, 3]
+    else:
+        p = 2
+        prob = W.cube_2x2x2_trilinear(p=p, levels=2, seed=13)
+        k, nel = 7, [2, 1, 2]
+    op = PatchOp(prob.geo_degree[k], prob.geo_ctrl[k], p, nel)
+    ref = _plain_patch_matrix(prob.geo_degree[k], prob.geo_ctrl[k], p, nel)
+    A = op.matrix().toarray()
+    assert np.abs(A - ref).max() <= 1e-12 * np.abs(ref).max()

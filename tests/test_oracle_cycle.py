@@ -125,3 +125,46 @@ def test_fichera_iteration_count_near_paper():
     H = Hierarchy(prob)
     _, it, _ = H.pcg(load_vector(prob, H.finest))
     assert abs(it - paper) <= 0.3 * paper, (it, paper)
+
+
+def _dense_op(apply, n):
+    out = np.zeros((n, n))
+    for j in range(n):
+        e = np.zeros(n)
+        e[j] = 1.0
+        out[:, j] = apply(e)
+    return out
+
+
+@pytest.mark.parametrize("make,mu", [
+    (lambda: W.square_4x4_bezier(p=3, nel0=1, levels=2, seed=1), 1),
+    (lambda: W.cube_2x2x2_trilinear(p=2, nel0=1, levels=2), 1),
+    (lambda: W.unit_square_2x2(p=2, nel0=1, levels=3), 1),
+    (lambda: W.unit_square_2x2(p=2, nel0=1, levels=3), 2),
+])
+def test_cycle_error_propagation_identity(make, mu):
+    # Algorithm 1 from a zero initial guess gives u = B f with the error
+    # propagation I - B A = S (I - P C P^T A) S on every level, where
+    # S = I - tau L^{-1} A is one damped smoothing step (Sec. 3) and C is the
+    # coarse operator: A_0^{-1} on the level above the coarsest, otherwise
+    # the mu-fold recursive cycle, I - C A_{l-1} = (I - B_{l-1} A_{l-1})^mu.
+    # Built here from dense matrices; a dropped smoothing step, a factor tau
+    # on the coarse correction or a transposed transfer breaks it.
+    H = Hierarchy(make(), mu=mu)
+    tau = H.tau
+    A0 = H.levels[0].A.toarray()
+    C = np.linalg.inv(A0)
+    for l in range(1, len(H.levels)):
+        lev = H.levels[l]
+        n = lev.N
+        A = lev.A.toarray()
+        Linv = lev.smoother.dense_inverse()
+        P = H.P[l].toarray()
+        S = np.eye(n) - tau * Linv @ A
+        E = S @ (np.eye(n) - P @ C @ P.T @ A) @ S
+        Bl = _dense_op(lambda r: H.cycle(l, np.zeros(n), r), n)
+        ref = np.eye(n) - Bl @ A
+        assert np.abs(E - ref).max() <= 1e-10 * max(1.0, np.abs(ref).max()), l
+        # the coarse operator of the next level: mu cycles from zero
+        Em = np.linalg.matrix_power(np.eye(n) - Bl @ A, mu)
+        C = (np.eye(n) - Em) @ np.linalg.inv(A)
