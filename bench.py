@@ -333,7 +333,19 @@ def serving_full(n_requests, n_families, rate, seed, dev, precision="mixed"):
     return {"serving_full": out}
 
 
-def fichera_table(degrees, levels, dev):
+READINGS = {
+    "library": {},
+    "omega1": {"geometry_scaling": 0},
+    "s1sigma": {"s1_sigma": 1},
+    "mult": {"iface_multiplicity": 1},
+    "s1sigma_mult": {"s1_sigma": 1, "iface_multiplicity": 1},
+    "omega1_mult": {"geometry_scaling": 0, "iface_multiplicity": 1},
+    "omega1_s1sigma": {"geometry_scaling": 0, "s1_sigma": 1},
+    "physh": {"physical_h": 1},
+}
+
+
+def fichera_table(degrees, levels, dev, reading="library"):
     """FP64 PCG iteration counts on the Fichera corner with K=448 patches
     (Sec. 5: 7 unit cubes split into 4^3 patches each, 1 element per patch on
     the coarsest level, f = 75 pi^2 sin 5 pi x sin 5 pi y sin 5 pi z), beside
@@ -347,16 +359,16 @@ def fichera_table(degrees, levels, dev):
         for lev in levels:
             prob = W.fichera(p, lev + 1, split=4)
             t0 = time.perf_counter()
-            S = igamg.Solver(prob, device=dev)
+            S = igamg.Solver(prob, igamg.default_options(**READINGS[reading]), device=dev)
             setup = time.perf_counter() - t0
             f = torch.as_tensor(S.load_vector(75.0 * np.pi ** 2, 5.0), device=dev)
             u, info = S.solve(f, tol=1e-8)
             ref = paper.get(str(lev), {}).get(str(p))
-            rows.append({"p": p, "level": lev, "N": S.N, "N0": int(S.num_dofs(0)[0]),
+            rows.append({"p": p, "level": lev, "reading": reading, "N": S.N, "N0": int(S.num_dofs(0)[0]),
                          "iterations": info.iterations, "paper": ref, "converged": bool(info.converged),
                          "rel_residual": info.rel_residual, "setup_s": round(setup, 1),
                          "solve_ms": round(info.solve_ms, 1)})
-            log(f"fichera p={p} l={lev}: N={S.N}, {info.iterations} it (paper {ref}), setup {setup:.1f} s, "
+            log(f"fichera {reading} p={p} l={lev}: N={S.N}, {info.iterations} it (paper {ref}), setup {setup:.1f} s, "
                 f"solve {info.solve_ms:.0f} ms")
             del S, u, f
             torch.cuda.empty_cache()
@@ -386,6 +398,9 @@ def main():
                     help="instead of the benchmark line, print FP64 iteration counts on the Fichera corner "
                          "(K=448) for these degrees, e.g. 2,3,4, on the levels --fichera-levels")
     ap.add_argument("--fichera-levels", default="1,2,3,4")
+    ap.add_argument("--fichera-readings", default="library",
+                    help="comma-separated readings of the smoother constants for --fichera-table: "
+                         + ", ".join(READINGS))
     ap.add_argument("--fd-mfma", action="store_true",
                     help="also time the mixed solver with the smoother's FP32 mode products on the matrix cores")
     ap.add_argument("--copy-calibration", action="store_true",
@@ -408,7 +423,10 @@ def main():
     if a.fichera_table:
         degrees = [int(x) for x in a.fichera_table.split(",")]
         levels = [int(x) for x in a.fichera_levels.split(",")]
-        print(json.dumps(fichera_table(degrees, levels, dev)), flush=True)
+        out = {"fichera_K448": []}
+        for rd in a.fichera_readings.split(","):
+            out["fichera_K448"] += fichera_table(degrees, levels, dev, rd)["fichera_K448"]
+        print(json.dumps(out), flush=True)
         return
     if a.copy_calibration:
         x = torch.empty(64 << 20, dtype=torch.float32, device=dev)

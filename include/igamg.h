@@ -49,8 +49,14 @@ extern "C" {
  * Patch k maps (0,1)^dim onto Omega_k by one tensor-product Bezier element of
  * degree geo_degree[k*dim + c] in direction c; its control points are stored
  * x-fastest, each with `dim` coordinates, patch after patch in geo_ctrl.
- * Level l has nel0[k*dim + c] * 2^l uniform elements per patch and direction
- * and open knot vectors (maximal smoothness C^{p-1}), l = 0 .. levels-1.
+ * Level l has nel0[k*dim + c] * 2^l elements per patch and direction and
+ * open knot vectors (p+1 copies of each end, simple interior knots: maximal
+ * smoothness C^{p-1}, Sec. 2), l = 0 .. levels-1.  The coarsest breakpoints
+ * are uniform, or given in knots0: for patch k and direction c in that order
+ * (direction fastest), nel0[k*dim + c] + 1 values 0 = x_0 < ... < x_nel = 1;
+ * each refinement halves every span (Sec. 3).  Interfaces must match: the
+ * breakpoints of paired tangential directions agree (reversed where the
+ * orientation reverses the axis), else ETOPO.
  * Side s = 2*dir + end of a patch is where parameter `dir` equals `end`.
  * iface[5*i .. 5*i+4] = (patch a, side a, patch b, side b, orient): the
  * tangential axes (t0 < t1) of side a meet the axes (u0 < u1) of side b; bit 0
@@ -65,6 +71,7 @@ typedef struct {
   int npatch;             /* K >= 1                                         */
   int levels;             /* number of grid levels, >= 2                    */
   const int* nel0;        /* [npatch*dim] coarsest element counts, >= 1     */
+  const double* knots0;   /* NULL: uniform; else the coarsest breakpoints   */
   const int* geo_degree;  /* [npatch*dim] Bezier degree of each map, >= 1   */
   const double* geo_ctrl; /* control points, see above                      */
   int nif;                /* number of interfaces                           */

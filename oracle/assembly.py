@@ -26,13 +26,15 @@ from .geometry import BezierMap, metric
 
 
 class PatchOp:
-    def __init__(self, degrees_geo, ctrl, p, nel, nq=None):
+    def __init__(self, degrees_geo, ctrl, p, nel, nq=None, knots=None):
         self.d = len(nel)
         self.p = p
         self.nel = [int(e) for e in nel]
         self.geo = BezierMap(degrees_geo, ctrl)
         nq = p + 1 if nq is None else nq
-        self.knots = [bspline.open_uniform_knots(p, e) for e in self.nel]
+        if knots is None:
+            knots = [bspline.open_uniform_knots(p, e) for e in self.nel]
+        self.knots = [np.asarray(t, dtype=np.float64) for t in knots]
         self.n = [bspline.num_basis(t, p) for t in self.knots]
         self.quad = [bspline.span_quadrature(t, nq) for t in self.knots]
         self.B = [bspline.eval_basis(t, p, q[0]) for t, q in zip(self.knots, self.quad)]

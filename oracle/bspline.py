@@ -2,7 +2,8 @@
 
 Test infrastructure only (see ``oracle/__init__``).
 
-* open uniform knot vectors of maximal smoothness C^{p-1} (Sec. 2);
+* open knot vectors of maximal smoothness C^{p-1} (Sec. 2), uniform or with
+  given coarsest breakpoints, refined by halving every span (Sec. 3);
 * all B-splines and their derivatives by the Cox-de Boor recursion;
 * Gauss-Legendre quadrature per knot span;
 * univariate mass and stiffness matrices (the M_l, K_l of the edge and face
@@ -25,6 +26,27 @@ def open_uniform_knots(p, nel):
     """
     inner = np.arange(1, nel, dtype=np.float64) / nel
     return np.concatenate([np.zeros(p + 1), inner, np.ones(p + 1)])
+
+
+def open_knots(p, breaks):
+    """Open knot vector with the given breakpoints (0 = x_0 < ... < x_nel = 1)
+    as simple interior knots: maximal smoothness C^{p-1} (Sec. 2)."""
+    b = np.asarray(breaks, dtype=np.float64)
+    return np.concatenate([np.full(p, b[0]), b, np.full(p, b[-1])])
+
+
+def level_knots(prob, level, k, c):
+    """Knot vector of patch k in direction c on grid level ``level``: the
+    coarsest breakpoints (uniform unless the problem gives them) with every
+    span halved once per level (the uniform refinement of Sec. 3)."""
+    p = prob.degree
+    kn0 = getattr(prob, "knots0", None)
+    if kn0 is None:
+        return open_uniform_knots(p, int(prob.nel(level)[k][c]))
+    t = open_knots(p, kn0[k][c])
+    for _ in range(level):
+        t = insert_midpoints(t)
+    return t
 
 
 def insert_midpoints(knots):

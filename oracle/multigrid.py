@@ -31,7 +31,9 @@ class Level:
         self.dm = DofMap(prob, level)
         self.N = self.dm.N
         nel = prob.nel(level)
-        self.ops = [PatchOp(prob.geo_degree[k], prob.geo_ctrl[k], prob.degree, nel[k])
+        self.knots = [[bspline.level_knots(prob, level, k, c) for c in range(prob.dim)]
+                      for k in range(prob.npatch)]
+        self.ops = [PatchOp(prob.geo_degree[k], prob.geo_ctrl[k], prob.degree, nel[k], knots=self.knots[k])
                     for k in range(prob.npatch)]
         self.S = [self.dm.selection(k) for k in range(prob.npatch)]
         if explicit is None:
@@ -54,7 +56,7 @@ class Level:
     def set_reading(self, reading):
         """(Re)build the smoother under a reading of its constants (see oracle.smoother)."""
         self.smoother = Smoother(self.prob, self.level, self.dm, self.pieces, self.omegas,
-                                 self.sigma_scale, reading=reading, lengths=self.lengths)
+                                 self.sigma_scale, reading=reading, lengths=self.lengths, knots=self.knots)
 
     def apply(self, u):
         """A_l u (eq. of the linear system) on free dofs."""
@@ -85,8 +87,8 @@ def prolongation(prob, coarse, fine):
     for k in range(prob.npatch):
         Ps = []
         for c in range(prob.dim):
-            tc = bspline.open_uniform_knots(p, int(prob.nel(coarse.level)[k][c]))
-            tf = bspline.open_uniform_knots(p, int(prob.nel(fine.level)[k][c]))
+            tc = coarse.knots[k][c]
+            tf = fine.knots[k][c]
             Ps.append(sp.csr_matrix(bspline.embedding(tc, tf, p)))
         Pk = Ps[0]
         for Pc in Ps[1:]:

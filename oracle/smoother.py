@@ -47,9 +47,10 @@ import scipy.linalg as sla
 from . import bspline
 
 
-def interior_1d(p, nel):
-    """Knots, interior mass/stiffness (m x m, m = n-2) and the constraint rows."""
-    t = bspline.open_uniform_knots(p, nel)
+def interior_1d(p, t):
+    """Interior mass/stiffness (m x m, m = n-2) and the constraint rows of the
+    spline space on the knot vector t."""
+    t = np.asarray(t, dtype=np.float64)
     M, K = bspline.mass_stiffness(t, p)
     n = M.shape[0]
     Mi, Ki = M[1:n - 1, 1:n - 1], K[1:n - 1, 1:n - 1]
@@ -110,7 +111,7 @@ DEFAULT_READING = {"omega": "mean", "h": "param", "k1": "K", "mult": False}
 class Smoother:
     """L_l^{-1} on global free vectors of one level."""
 
-    def __init__(self, prob, level, dm, pcs, omegas, sigma_scale=5.0, reading=None, lengths=None):
+    def __init__(self, prob, level, dm, pcs, omegas, sigma_scale=5.0, reading=None, lengths=None, knots=None):
         rd = dict(DEFAULT_READING)
         rd.update(reading or {})
         self.reading = rd
@@ -122,19 +123,24 @@ class Smoother:
         self.pieces = []
         cache = {}
 
+        if knots is None:
+            knots = [[bspline.open_uniform_knots(p, int(nel[k][c])) for c in range(d)]
+                     for k in range(prob.npatch)]
+
         def hdir(k, c):
-            """h of patch k in direction c under the reading."""
-            h = 1.0 / float(nel[k][c])
+            """h of patch k in direction c under the reading: the smallest
+            span (1/nel on uniform knots)."""
+            h = float(np.min(np.diff(np.unique(knots[k][c]))))
             if rd["h"] == "physical":
                 h *= lengths[k][c]
             return h
 
         def one_d(k, c):
-            e = int(nel[k][c])
+            t = knots[k][c]
             sigma = sigma_scale / hdir(k, c) ** 2
-            key = (e, sigma)
+            key = (tuple(t), sigma)
             if key not in cache:
-                Mi, Ki, C = interior_1d(p, e)
+                Mi, Ki, C = interior_1d(p, t)
                 U, mu, k0, _ = split_basis(Mi, Ki, C, sigma)
                 if rd["k1"] == "K+sigmaM":
                     mu = mu.copy()

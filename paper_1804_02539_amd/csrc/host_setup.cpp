@@ -61,6 +61,20 @@ ProblemH read_problem(const void* cp) {
     for (double v : q.ctrl.back())
       if (!std::isfinite(v)) fail(IGAMG_EINVAL, "non-finite control point");
   }
+  q.brk0.assign((size_t)q.K * d, std::vector<double>());
+  if (P->knots0) {
+    size_t kp = 0;
+    for (int k = 0; k < q.K; ++k)
+      for (int c = 0; c < d; ++c) {
+        const int e = q.nel0[k * d + c];
+        std::vector<double> b(P->knots0 + kp, P->knots0 + kp + e + 1);
+        kp += (size_t)e + 1;
+        if (b.front() != 0.0 || b.back() != 1.0) fail(IGAMG_EINVAL, "knots0: breakpoints must run from 0 to 1");
+        for (int i = 0; i < e; ++i)
+          if (!std::isfinite(b[i + 1]) || !(b[i + 1] > b[i])) fail(IGAMG_EINVAL, "knots0: breakpoints must increase");
+        q.brk0[(size_t)k * d + c] = std::move(b);
+      }
+  }
   for (int b : q.bc)
     if (b != 0 && b != 1) fail(IGAMG_EINVAL, "bc entries must be 0 or 1");
   for (int i = 0; i < P->nif; ++i) {
@@ -97,18 +111,30 @@ static std::vector<int64_t> side_layer(const std::array<int, 3>& n, int s) {
   return out;
 }
 
+// Breakpoints of patch k in direction c on level l: uniform, or the given
+// coarsest ones with every span halved l times (Sec. 3, uniform refinement).
+static std::vector<double> level_breaks(const ProblemH& P, int k, int c, int l) {
+  const auto& b0 = P.brk0[(size_t)k * P.d + c];
+  if (b0.empty()) return uniform_breaks(P.nel0[k * P.d + c] << l);
+  std::vector<double> b = b0;
+  for (int i = 0; i < l; ++i) b = refine_breaks(b);
+  return b;
+}
+
 static void make_level_dofs(const ProblemH& P, LevelH& L) {
   const int d = P.d, p = P.p, K = P.K;
   L.n.resize(K);
   L.nel.resize(K);
   L.off.resize(K);
   L.rows.resize(K);
+  L.brk.assign((size_t)K * 3, std::vector<double>{0.0, 1.0});
   int64_t pos = 0;
   for (int k = 0; k < K; ++k) {
     for (int c = 0; c < 3; ++c) {
       if (c < d) {
         L.nel[k][c] = P.nel0[k * d + c] << L.l;
         L.n[k][c] = L.nel[k][c] + p;
+        L.brk[(size_t)k * 3 + c] = level_breaks(P, k, c, L.l);
       } else {
         L.nel[k][c] = 1;
         L.n[k][c] = 1;
@@ -146,6 +172,18 @@ static void make_level_dofs(const ProblemH& P, LevelH& L) {
     int u_of_t1 = swap ? tb[0] : tb[1];
     if (na[ta[0]] != nbs[u_of_t0] || na[ta[1]] != nbs[u_of_t1])
       fail(IGAMG_ETOPO, "interface sides do not match (element counts differ)");
+    // fully matching (Sec. 2): the breakpoints of paired directions agree,
+    // read backwards where the orientation reverses the axis
+    for (int j = 0; j < 2; ++j) {
+      if (ta[j] >= d) continue;
+      const auto& xa = L.brk[(size_t)a * 3 + ta[j]];
+      const auto& xb = L.brk[(size_t)b * 3 + (j == 0 ? u_of_t0 : u_of_t1)];
+      const bool rev = (o & (j == 0 ? 2 : 4)) != 0;
+      for (size_t i = 0; i < xa.size(); ++i) {
+        const double v = rev ? 1.0 - xb[xb.size() - 1 - i] : xb[i];
+        if (std::fabs(xa[i] - v) > 1e-12) fail(IGAMG_ETOPO, "interface sides do not match (knot vectors differ)");
+      }
+    }
     std::vector<int64_t> la = side_layer(na, sa), lb = side_layer(nbs, sb);
     const int n0a = na[ta[0]], n1a = na[ta[1]], n0b = nbs[tb[0]];
     for (int j1 = 0; j1 < n1a; ++j1)
@@ -309,7 +347,7 @@ struct Quad1D {
   std::vector<double> val, der;       // [(e*nq + q)*(pc+1) + l]
 };
 
-static Quad1D quad_1d(int p, int nel, bool dummy) {
+static Quad1D quad_1d(int p, const std::vector<double>& brk, bool dummy) {
   Quad1D Q;
   if (dummy) {
     Q.x = {0.0};
@@ -318,16 +356,17 @@ static Quad1D quad_1d(int p, int nel, bool dummy) {
     Q.der = {0.0};
     return Q;
   }
+  const int nel = (int)brk.size() - 1;
   Q.nel = nel;
   Q.nq = p + 1;
   Q.pc = p;
-  Knots kn = open_uniform(p, nel);
+  Knots kn = open_knots(p, brk);
   std::vector<double> gx, gw;
   std::vector<std::vector<double>> ders;
   Q.val.resize((size_t)nel * Q.nq * (p + 1));
   Q.der.resize((size_t)nel * Q.nq * (p + 1));
   for (int e = 0; e < nel; ++e) {
-    gauss_legendre(Q.nq, (double)e / nel, (double)(e + 1) / nel, gx, gw);
+    gauss_legendre(Q.nq, kn.lo(e), kn.hi(e), gx, gw);
     for (int q = 0; q < Q.nq; ++q) {
       Q.x.push_back(gx[q]);
       Q.w.push_back(gw[q]);
@@ -349,7 +388,7 @@ static void assemble_patch(const ProblemH& P, const LevelH& L, int k, double* ba
   const int d = P.d, p = P.p;
   const auto& n = L.n[k];
   Quad1D Q[3];
-  for (int c = 0; c < 3; ++c) Q[c] = quad_1d(p, L.nel[k][c], c >= d);
+  for (int c = 0; c < 3; ++c) Q[c] = quad_1d(p, L.brk[(size_t)k * 3 + c], c >= d);
   GeoEval ge = make_geo(P, k);
   for (int c = 0; c < d; ++c) ge.tables(c, Q[c].x);
   const int nb0 = 2 * p + 1, nb1 = 2 * p + 1, p2 = Q[2].pc, nb2 = 2 * p2 + 1;
@@ -531,7 +570,7 @@ void make_assembly_tables(const ProblemH& P, const LevelH& L, std::vector<AsmPat
     a.off = L.off[k];
     for (int c = 0; c < 3; ++c) {
       const bool dummy = c >= d;
-      const Quad1D Q = quad_1d(p, dummy ? 1 : L.nel[k][c], dummy);
+      const Quad1D Q = quad_1d(p, L.brk[(size_t)k * 3 + c], dummy);
       a.n[c] = L.n[k][c];
       a.nel[c] = dummy ? 1 : L.nel[k][c];
       a.pc[c] = Q.pc;
@@ -591,9 +630,9 @@ static std::array<double, 3> patch_lengths(const ProblemH& P, int k) {
 // subspace, M-orthonormal eigenvectors of K on the complement] with
 // mu = [sigma .., eigenvalues] (eigenvalues + sigma when s1_sigma: the
 // operator K + sigma M on the complement).
-static OneD one_d(int p, int nel, double sigma, bool s1_sigma) {
+static OneD one_d(int p, const std::vector<double>& brk, double sigma, bool s1_sigma) {
   OneD o;
-  Knots kn = open_uniform(p, nel);
+  Knots kn = open_knots(p, brk);
   const int n = kn.n(), m = n - 2;
   o.m = m;
   Mat M, K;
@@ -780,7 +819,7 @@ static void make_smoother(const ProblemH& P, const Options& O, LevelH& L) {
   std::vector<PieceH> pcs = make_pieces(P, L);
   // 1D factors by (element count, sigma): sigma depends on the patch only
   // through h, which is 1/nel unless the physical-h reading is chosen
-  using Key = std::pair<int, double>;
+  using Key = std::pair<std::vector<double>, double>;
   std::map<Key, OneD> cache;
   std::map<Key, int64_t> Uoff, muoff;
   L.fdmat.clear();
@@ -791,13 +830,15 @@ static void make_smoother(const ProblemH& P, const Options& O, LevelH& L) {
   L.fdmat.push_back(0.0);
   // h of patch k in direction c
   auto hdir = [&](int k, int c) -> double {
-    double h = 1.0 / (double)L.nel[k][c];
+    const auto& b = L.brk[(size_t)k * 3 + c];
+    double h = b[1] - b[0];
+    for (size_t i = 1; i + 1 < b.size(); ++i) h = std::min(h, b[i + 1] - b[i]);
     if (O.physical_h) h *= L.length[k][c];
     return h;
   };
   auto key1d = [&](int k, int c) -> Key {
     const double h = hdir(k, c);
-    return Key(L.nel[k][c], O.sigma_scale / (h * h));
+    return Key(L.brk[(size_t)k * 3 + c], O.sigma_scale / (h * h));
   };
   auto get1d = [&](int k, int c) -> const OneD& {
     const Key key = key1d(k, c);
@@ -932,16 +973,18 @@ static void make_smoother(const ProblemH& P, const Options& O, LevelH& L) {
 // ---------------------------------------------------------------------------
 static void make_transfers(const ProblemH& P, const LevelH& C, LevelH& F) {
   const int d = P.d, p = P.p;
-  std::map<int, std::vector<double>> Pm;   // nel_c -> P (n_f x n_c)
+  using Brk = std::vector<double>;
+  std::map<Brk, std::vector<double>> Pm;   // coarse breakpoints -> P (n_f x n_c)
   for (int k = 0; k < P.K; ++k)
     for (int c = 0; c < d; ++c) {
-      int e = C.nel[k][c];
-      if (!Pm.count(e)) Pm[e] = refinement_matrix(p, e);
+      const Brk& e = C.brk[(size_t)k * 3 + c];
+      if (!Pm.count(e)) Pm[e] = refinement_matrix(open_knots(p, e));
     }
   // widths
   int WP = 1, WR = 1;
   for (auto& kv : Pm) {
-    const int nc = kv.first + p, nf = 2 * kv.first + p;
+    const int ne = (int)kv.first.size() - 1;
+    const int nc = ne + p, nf = 2 * ne + p;
     const auto& M = kv.second;
     for (int i = 0; i < nf; ++i) {
       int lo = nc, hi = -1;
@@ -966,11 +1009,12 @@ static void make_transfers(const ProblemH& P, const LevelH& C, LevelH& F) {
   F.WR = WR;
   F.tr_idx.clear();
   F.tr_val.clear();
-  std::map<int, std::array<int64_t, 4>> tabs;  // nel_c -> (Pst, Pval, Rst, Rval)
-  auto build = [&](int e) {
+  std::map<Brk, std::array<int64_t, 4>> tabs;  // coarse breakpoints -> (Pst, Pval, Rst, Rval)
+  auto build = [&](const Brk& e) {
     if (tabs.count(e)) return tabs[e];
     std::array<int64_t, 4> t;
-    const int nc = e + p, nf = 2 * e + p;
+    const int ne = (int)e.size() - 1;
+    const int nc = ne + p, nf = 2 * ne + p;
     const auto& M = Pm[e];
     t[0] = (int64_t)F.tr_idx.size();
     t[1] = (int64_t)F.tr_val.size();
@@ -1005,7 +1049,7 @@ static void make_transfers(const ProblemH& P, const LevelH& C, LevelH& F) {
       pd.n[c] = F.n[k][c];
       pd.nc[c] = C.n[k][c];
       if (c < d) {
-        auto t = build(C.nel[k][c]);
+        auto t = build(C.brk[(size_t)k * 3 + c]);
         pd.Pst[c] = t[0];
         pd.Pval[c] = t[1];
         pd.Rst[c] = t[2];
@@ -1151,7 +1195,7 @@ std::vector<double> load_vector(const Hierarchy& H, double amp, double freq) {
   parallel_for(P.K, [&](int k) {
     const auto& n = L.n[k];
     Quad1D Q[3];
-    for (int c = 0; c < 3; ++c) Q[c] = quad_1d(p, L.nel[k][c], c >= d);
+    for (int c = 0; c < 3; ++c) Q[c] = quad_1d(p, L.brk[(size_t)k * 3 + c], c >= d);
     GeoEval ge = make_geo(P, k);
     for (int c = 0; c < d; ++c) ge.tables(c, Q[c].x);
     std::vector<double>& f = loc[k];

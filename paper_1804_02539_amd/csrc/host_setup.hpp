@@ -17,6 +17,7 @@ namespace igamg {
 struct ProblemH {
   int d = 2, p = 2, K = 1, levels = 2;
   std::vector<int> nel0;                  // K*d
+  std::vector<std::vector<double>> brk0;  // K*d coarsest breakpoints; empty = uniform
   std::vector<int> gdeg;                  // K*d
   std::vector<std::vector<double>> ctrl;  // per patch, prod(g+1)*d
   std::vector<std::array<int, 5>> iface;
@@ -52,6 +53,7 @@ struct SetupError {
 struct LevelH {
   int l = 0;
   std::vector<std::array<int, 3>> n, nel;   // per patch (unused dims: n = 1, nel = 1)
+  std::vector<std::vector<double>> brk;     // K*3 breakpoints per patch and direction (unused: {0, 1})
   std::vector<int64_t> off, rows;
   int64_t NL = 0;                            // padded local length
   std::vector<int64_t> gid;                  // NL entries: free id or -1

@@ -18,19 +18,44 @@ namespace igamg {
 struct Knots {
   int p = 0;
   int nel = 0;
-  std::vector<double> t;  // open, uniform
+  std::vector<double> t;  // open: p+1 copies of each end, simple interior knots
   int n() const { return (int)t.size() - p - 1; }
+  double lo(int e) const { return t[p + e]; }       // element e = [lo(e), hi(e)]
+  double hi(int e) const { return t[p + e + 1]; }
 };
 
-inline Knots open_uniform(int p, int nel) {
+// Open knot vector with the breakpoints 0 = brk[0] < ... < brk[nel] = 1 as
+// simple interior knots (maximal smoothness C^{p-1}).
+inline Knots open_knots(int p, const std::vector<double>& brk) {
   Knots k;
   k.p = p;
-  k.nel = nel;
-  for (int i = 0; i <= p; ++i) k.t.push_back(0.0);
-  for (int i = 1; i < nel; ++i) k.t.push_back((double)i / nel);
-  for (int i = 0; i <= p; ++i) k.t.push_back(1.0);
+  k.nel = (int)brk.size() - 1;
+  for (int i = 0; i < p; ++i) k.t.push_back(brk.front());
+  k.t.insert(k.t.end(), brk.begin(), brk.end());
+  for (int i = 0; i < p; ++i) k.t.push_back(brk.back());
   return k;
 }
+
+inline std::vector<double> uniform_breaks(int nel) {
+  std::vector<double> b(nel + 1);
+  for (int i = 0; i <= nel; ++i) b[i] = (double)i / nel;
+  b[nel] = 1.0;
+  return b;
+}
+
+// The breakpoints after one uniform refinement: the midpoint of every span.
+inline std::vector<double> refine_breaks(const std::vector<double>& b) {
+  std::vector<double> f;
+  f.reserve(2 * b.size() - 1);
+  for (size_t i = 0; i + 1 < b.size(); ++i) {
+    f.push_back(b[i]);
+    f.push_back(0.5 * (b[i] + b[i + 1]));
+  }
+  f.push_back(b.back());
+  return f;
+}
+
+inline Knots open_uniform(int p, int nel) { return open_knots(p, uniform_breaks(nel)); }
 
 // Index s with t[s] <= x < t[s+1], p <= s <= n-1 (x = 1 maps to the last span).
 inline int find_span(const Knots& k, double x) {
@@ -148,8 +173,7 @@ inline void mass_stiffness_1d(const Knots& k, std::vector<double>& M, std::vecto
   std::vector<double> gx, gw;
   std::vector<std::vector<double>> ders;
   for (int e = 0; e < k.nel; ++e) {
-    double a = (double)e / k.nel, b = (double)(e + 1) / k.nel;
-    gauss_legendre(p + 1, a, b, gx, gw);
+    gauss_legendre(p + 1, k.lo(e), k.hi(e), gx, gw);
     for (int q = 0; q <= p; ++q) {
       int s = find_span(k, gx[q]);
       span_ders(k, s, gx[q], 1, ders);
@@ -165,15 +189,15 @@ inline void mass_stiffness_1d(const Knots& k, std::vector<double>& M, std::vecto
 
 // Embedding S(coarse) -> S(fine) where fine = coarse with every span halved.
 // Returns P (n_f x n_c, row-major): fine coefficients = P * coarse coefficients.
-inline std::vector<double> refinement_matrix(int p, int nel_c) {
-  Knots cur = open_uniform(p, nel_c);
+// The midpoints are inserted one knot at a time by Boehm's rule.
+inline std::vector<double> refinement_matrix(const Knots& coarse) {
+  const int p = coarse.p, nel_c = coarse.nel;
+  Knots cur = coarse;
   int n = cur.n();
   std::vector<double> P((size_t)n * n, 0.0);
   for (int i = 0; i < n; ++i) P[(size_t)i * n + i] = 1.0;
-  int rows = n;
   for (int e = 0; e < nel_c; ++e) {
-    double xbar = (e + 0.5) / nel_c;
-    // insert xbar into cur (one knot): Boehm's rule
+    const double xbar = 0.5 * (coarse.lo(e) + coarse.hi(e));
     int s = find_span(cur, xbar);
     int m = cur.n();
     std::vector<double> Q((size_t)(m + 1) * n, 0.0);
@@ -191,9 +215,7 @@ inline std::vector<double> refinement_matrix(int p, int nel_c) {
     }
     cur.t.insert(cur.t.begin() + s + 1, xbar);
     P.swap(Q);
-    rows = m + 1;
   }
-  (void)rows;
   return P;  // (n_c + nel_c) x n_c
 }
 

@@ -36,6 +36,7 @@ class IgamgError(RuntimeError):
 class _Problem(ctypes.Structure):
     _fields_ = [("dim", ctypes.c_int), ("degree", ctypes.c_int), ("npatch", ctypes.c_int),
                 ("levels", ctypes.c_int), ("nel0", ctypes.POINTER(ctypes.c_int)),
+                ("knots0", ctypes.POINTER(ctypes.c_double)),
                 ("geo_degree", ctypes.POINTER(ctypes.c_int)),
                 ("geo_ctrl", ctypes.POINTER(ctypes.c_double)), ("nif", ctypes.c_int),
                 ("iface", ctypes.POINTER(ctypes.c_int)), ("bc", ctypes.POINTER(ctypes.c_int))]
@@ -132,9 +133,13 @@ class _CProblem:
         self.ctrl = prob.flat_ctrl()
         self.iface = i32(prob.iface) if len(prob.iface) else np.zeros(5, dtype=np.int32)
         self.bc = i32(prob.bc)
+        kn = prob.flat_knots0() if hasattr(prob, "flat_knots0") else None
+        self.knots0 = kn
         ip = lambda a: a.ctypes.data_as(ctypes.POINTER(ctypes.c_int))
+        dp = lambda a: a.ctypes.data_as(ctypes.POINTER(ctypes.c_double))
         self.s = _Problem(prob.dim, prob.degree, prob.npatch, prob.levels, ip(self.nel0),
-                          ip(self.gdeg), self.ctrl.ctypes.data_as(ctypes.POINTER(ctypes.c_double)),
+                          dp(kn) if kn is not None else ctypes.POINTER(ctypes.c_double)(),
+                          ip(self.gdeg), dp(self.ctrl),
                           int(len(prob.iface)), ip(self.iface), ip(self.bc))
 
 

@@ -19,7 +19,9 @@ Conventions shared by every consumer of a ``Problem``:
   t1;
 * bc[k, s] = 1 marks a homogeneous Dirichlet side, 0 a homogeneous Neumann one
   (ignored on interface sides);
-* level l has nel0 * 2**l elements per patch and direction, l = 0..levels-1.
+* level l has nel0 * 2**l elements per patch and direction, l = 0..levels-1;
+  the coarsest breakpoints are uniform unless ``knots0[k][c]`` gives them
+  (nel0[k][c] + 1 increasing values from 0 to 1).
 """
 from dataclasses import dataclass, field
 import itertools
@@ -39,6 +41,7 @@ class Problem:
     bc: np.ndarray            # (K, 2d) int32
     name: str = ""
     meta: dict = field(default_factory=dict)
+    knots0: list = None       # None, or K lists of d breakpoint arrays (coarsest level)
 
     @property
     def npatch(self):
@@ -46,6 +49,14 @@ class Problem:
 
     def nel(self, level):
         return self.nel0 * (2 ** level)
+
+    def flat_knots0(self):
+        """Breakpoints of every patch and direction, concatenated (direction
+        fastest), or None for uniform knots."""
+        if self.knots0 is None:
+            return None
+        return np.ascontiguousarray(np.concatenate([np.asarray(b, dtype=np.float64)
+                                                    for kk in self.knots0 for b in kk]))
 
     def flat_ctrl(self):
         return np.ascontiguousarray(np.concatenate([c.reshape(-1) for c in self.geo_ctrl]),
@@ -156,7 +167,51 @@ def perturb_interior_vertices_3d(prob, rel, rng):
     return prob
 
 
+def grade_slab_knots(prob, rel, rng):
+    """Non-uniform coarsest breakpoints for a ``box_grid`` problem: per
+    direction and slab, the interior breakpoints of the uniform grid are moved
+    by U[-rel, rel] times the span.  Patches of one slab share the vector, so
+    the interfaces stay fully matching."""
+    npp, pid = prob.meta["npp"], prob.meta["pid"]
+    slab = {}
+    for c in range(prob.dim):
+        for j in range(npp[c]):
+            k0 = next(k for idx, k in pid.items() if idx[c] == j)
+            e = int(prob.nel0[k0][c])
+            b = np.arange(e + 1, dtype=np.float64) / e
+            b[1:-1] += rng.uniform(-rel, rel, size=e - 1) / e
+            b[0], b[-1] = 0.0, 1.0
+            slab[(c, j)] = b
+    prob.knots0 = [[slab[(c, idx[c])] for c in range(prob.dim)]
+                   for idx, k in sorted(pid.items(), key=lambda t: t[1])]
+    return prob
+
+
 # --- the workloads ------------------------------------------------------------
+
+def graded_square_3x2(p=3, nel0=3, levels=3, seed=12):
+    """2D box (0,1.5)x(0,1) as 3x2 affine patches with seeded non-uniform
+    coarsest knot vectors (interior breakpoints moved by up to 30% of a span);
+    Dirichlet on x=0 and y=0, Neumann elsewhere; seeded U[-1,1] right-hand side."""
+    rng = np.random.default_rng(seed)
+    prob = box_grid(2, [3, 2], p, nel0, levels, gdeg=1, dirichlet_sides=[0, 2], extent=[1.5, 1.0],
+                    name="graded_square3x2")
+    grade_slab_knots(prob, 0.3, rng)
+    prob.meta["source"] = ("random", seed)
+    return prob
+
+
+def graded_cube_2x2x2(p=2, nel0=2, levels=3, seed=14):
+    """3D unit cube as 2x2x2 trilinear patches (interior vertex moved as in
+    the 3D cube workload) with seeded non-uniform coarsest knot vectors (up to
+    30% of a span); full Dirichlet; seeded U[-1,1] right-hand side."""
+    rng = np.random.default_rng(seed)
+    prob = box_grid(3, [2, 2, 2], p, nel0, levels, gdeg=1, name="graded_cube2x2x2")
+    perturb_vertex_3d(prob, [0.5, 0.5, 0.5], 0.05, rng)
+    grade_slab_knots(prob, 0.3, rng)
+    prob.meta["source"] = ("random", seed)
+    return prob
+
 
 def unit_square_2x2(p=2, nel0=2, levels=4):
     """2D unit square as 2x2 identity-scaled patches, full Dirichlet (f = 2 pi^2 sin sin)."""

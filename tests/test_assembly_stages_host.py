@@ -36,6 +36,8 @@ CASES = {
     "fichera7_p2_l3": lambda: W.fichera(2, 3),
     "cube_p4_neumann_l3": lambda: W.box_grid(3, [2, 1, 1], 4, 1, 3, gdeg=1, dirichlet_sides=[0, 2]),
     "box1x2_p8_l2": lambda: W.box_grid(2, [1, 2], 8, 1, 2, gdeg=1),
+    "graded_square3x2_p3_l3": lambda: W.graded_square_3x2(),
+    "graded_cube2x2x2_p2_l3": lambda: W.graded_cube_2x2x2(),
 }
 
 

@@ -36,6 +36,8 @@ CASES = {
     "box3x1_p1_l4": lambda: W.box_grid(2, [3, 1], 1, 2, 4, gdeg=1, dirichlet_sides=[0]),
     "single_patch_p5_l3": lambda: W.box_grid(2, [1, 1], 5, 2, 3, gdeg=1),
     "cube_p4_l3_neumann": lambda: W.box_grid(3, [2, 1, 1], 4, 1, 3, gdeg=1, dirichlet_sides=[0, 2]),
+    "graded_square3x2_p3_l3": lambda: W.graded_square_3x2(),
+    "graded_cube2x2x2_p2_l3": lambda: W.graded_cube_2x2x2(),
 }
 
 _ORACLE = {}
@@ -109,7 +111,7 @@ def test_wcycle_matches_oracle(torch_cuda):
 
 
 SOLVE_CASES = ["square2x2_p2", "square4x4_p4_l4", "cube2x2x2_p3_l4", "fichera7_p2_l3", "fichera448_p3_l1",
-               "fichera448_p4_l1"]
+               "fichera448_p4_l1", "graded_cube2x2x2_p2_l3"]
 
 
 def _rhs(name, H, S):

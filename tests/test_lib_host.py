@@ -34,6 +34,8 @@ def test_library_exports_every_declared_symbol():
     lambda: W.cube_2x2x2_trilinear(levels=3),
     lambda: W.fichera(2, 2),
     lambda: W.box_grid(2, [3, 1], 1, 2, 3, gdeg=1, dirichlet_sides=[0]),
+    lambda: W.graded_square_3x2(),
+    lambda: W.graded_cube_2x2x2(),
 ])
 def test_host_setup_equals_oracle(make):
     from oracle.multigrid import Hierarchy, load_vector
@@ -150,3 +152,29 @@ def test_piece_wider_than_the_smoother_kernels_is_rejected():
     rejected at setup (the fast-diagonalization kernels hold an 84 x 84 tile)."""
     prob = W.box_grid(2, [1, 1], 2, 2, 7, gdeg=1)      # 128 elements per direction at the finest level
     _expect(igamg.EINVAL, lambda: igamg.Solver(prob, host_only=True))
+
+
+def test_knots0_validation():
+    prob = W.graded_square_3x2()
+    s = igamg.Solver(prob, host_only=True)
+    assert s.N > 0
+    # breakpoints that do not increase, or do not run from 0 to 1
+    bad = W.graded_square_3x2()
+    bad.knots0[0][0] = bad.knots0[0][0][::-1].copy()
+    with pytest.raises(igamg.IgamgError) as e:
+        igamg.Solver(bad, host_only=True)
+    assert e.value.code == igamg.EINVAL
+    bad = W.graded_square_3x2()
+    bad.knots0[0][1] = bad.knots0[0][1] * 0.5
+    with pytest.raises(igamg.IgamgError) as e:
+        igamg.Solver(bad, host_only=True)
+    assert e.value.code == igamg.EINVAL
+    # the two sides of an interface with different breakpoints (Sec. 2:
+    # fully matching interfaces)
+    bad = W.graded_square_3x2()
+    b = bad.knots0[0][1].copy()
+    b[1] = 0.5 * (b[1] + b[2])
+    bad.knots0[0][1] = b
+    with pytest.raises(igamg.IgamgError) as e:
+        igamg.Solver(bad, host_only=True)
+    assert e.value.code == igamg.ETOPO

@@ -103,3 +103,34 @@ def test_embedding(p):
     col = P[:, p]          # support [t_p, t_{2p+1}] = [0, (p+1)/8]: uniform knots
     nz = col[np.abs(col) > 1e-14]
     assert np.allclose(nz, [comb(p + 1, j) / 2 ** p for j in range(p + 2)], atol=1e-14)
+
+
+def _graded_breaks(nel, seed):
+    r = np.random.default_rng(seed)
+    b = np.arange(nel + 1, dtype=np.float64) / nel
+    b[1:-1] += r.uniform(-0.3, 0.3, size=nel - 1) / nel
+    return b
+
+
+@pytest.mark.parametrize("p", [1, 2, 3, 5])
+def test_nonuniform_knots_partition_integrals_and_embedding(p):
+    # explicit coarsest breakpoints (Sec. 2 allows any open knot vector of
+    # maximal smoothness): partition of unity, the closed-form integrals
+    # int B_i = (t_{i+p+1} - t_i) / (p+1), and the refinement identity
+    # B_fine P = B_coarse when every span is halved
+    tc = bspline.open_knots(p, _graded_breaks(5, p))
+    assert len(tc) == 5 + 1 + 2 * p
+    x = np.concatenate([rng.random(60), [0.0, 1.0]])
+    B = bspline.eval_basis(tc, p, x)
+    assert np.allclose(B.sum(axis=1), 1.0, atol=1e-14)
+    M, _ = bspline.mass_stiffness(tc, p)
+    n = bspline.num_basis(tc, p)
+    integrals = np.array([(tc[i + p + 1] - tc[i]) / (p + 1) for i in range(n)])
+    assert np.allclose(M.sum(axis=1), integrals, atol=1e-14)
+    tf = bspline.insert_midpoints(tc)
+    spans_c = np.diff(np.unique(tc))
+    spans_f = np.diff(np.unique(tf))
+    assert np.allclose(spans_f, np.repeat(spans_c / 2, 2), atol=1e-15)
+    P = bspline.embedding(tc, tf, p)
+    assert np.allclose(bspline.eval_basis(tf, p, x) @ P, B, atol=1e-12)
+    assert np.allclose(P.sum(axis=1), 1.0, atol=1e-13)

@@ -13,7 +13,7 @@ rng = np.random.default_rng(7)
 
 @pytest.mark.parametrize("p,nel", [(2, 8), (3, 2), (3, 8), (4, 4), (5, 2), (5, 16), (6, 3), (6, 8)])
 def test_split_basis_orthonormality_and_subspace(p, nel):
-    Mi, Ki, C = interior_1d(p, nel)
+    Mi, Ki, C = interior_1d(p, bspline.open_uniform_knots(p, nel))
     sigma = 5.0 * nel * nel
     U, mu, k0, Z = split_basis(Mi, Ki, C, sigma)
     m = Mi.shape[0]
@@ -41,7 +41,7 @@ def test_split_basis_orthonormality_and_subspace(p, nel):
 def test_fd_equals_literal_additive_sum(dims):
     Mis, Kis, Cs, sig, Us, mus = [], [], [], [], [], []
     for p, nel in dims:
-        Mi, Ki, C = interior_1d(p, nel)
+        Mi, Ki, C = interior_1d(p, bspline.open_uniform_knots(p, nel))
         s = 5.0 * nel * nel
         U, mu, _, _ = split_basis(Mi, Ki, C, s)
         Mis.append(Mi); Kis.append(Ki); Cs.append(C); sig.append(s); Us.append(U); mus.append(mu)
@@ -65,7 +65,7 @@ def test_fd_equals_literal_additive_sum(dims):
 
 def test_fd_independent_of_basis_within_subspace():
     p, nel = 5, 8
-    Mi, Ki, C = interior_1d(p, nel)
+    Mi, Ki, C = interior_1d(p, bspline.open_uniform_knots(p, nel))
     U, mu, k0, _ = split_basis(Mi, Ki, C, 5.0 * nel * nel)
     Q, _ = np.linalg.qr(rng.standard_normal((k0, k0)))
     U2 = U.copy()
@@ -82,7 +82,7 @@ def test_null_space_rank_gap():
     # window (the oracle cuts at 1e-10, a Gram-matrix route needs ~1e-5) agrees
     for p in range(2, 9):
         for nel in [1, 2, 3, 4, 5, 6, 8, 12, 16, 24, 32, 48, 64, 96]:
-            Mi, Ki, C = interior_1d(p, nel)
+            Mi, Ki, C = interior_1d(p, bspline.open_uniform_knots(p, nel))
             if C.shape[0] == 0:
                 continue
             s = np.linalg.svd(C / np.linalg.norm(C, axis=1, keepdims=True), compute_uv=False)
