@@ -116,7 +116,10 @@ typedef struct {
                              times the number of patches adjacent to the piece             */
   int physical_h;         /* 0 (default): h_c = 1/nel_c of the parameter domain; 1: the
                              patch's mean physical length in direction c over nel_c        */
-  int reserved[1];
+  int iface_direct;       /* 0 (default): the edge and vertex smoothers of Sec. 3, (h/p)^{d-1} K
+                             + (h/p)^{d-3} M and (h/p)^{d-2}; 1: the exact restriction of A_l
+                             to each edge and vertex, solved directly (the variant Sec. 3
+                             cites from its reference)                                    */
 } igamg_options;
 
 #define IGAMG_FP64 0
@@ -255,7 +258,8 @@ int igamg_export(igamg_handle h, int what, int level, double* out, int64_t* rows
  * igamg_profile_read synchronises the stream of the last recorded launch and
  * returns, per level l, the launch count, the summed kernel time in ms (timing
  * events attached to each dispatch, so the time is the kernel's own) and the
- * algorithmic bytes moved (rows * s ((2p+1)^d + vectors), s = 8 or 4 bytes);
+ * algorithmic bytes moved (rows * s (nbh + vectors), s = 8 or 4 bytes, nbh =
+ * ((2p+1)^d + 1)/2 the stored planes of the symmetric half-band);
  * arrays have 2*levels entries: [l] for FP64 launches, [levels + l] for FP32
  * launches of a mixed-precision handle.  Then it clears the record.          */
 int igamg_profile(igamg_handle h, int enable);

@@ -56,7 +56,21 @@ class Level:
     def set_reading(self, reading):
         """(Re)build the smoother under a reading of its constants (see oracle.smoother)."""
         self.smoother = Smoother(self.prob, self.level, self.dm, self.pieces, self.omegas,
-                                 self.sigma_scale, reading=reading, lengths=self.lengths, knots=self.knots)
+                                 self.sigma_scale, reading=reading, lengths=self.lengths, knots=self.knots,
+                                 restrict=self.restricted)
+
+    def restricted(self, dofs):
+        """The restriction A_l[dofs, dofs] of the level's matrix to a set of
+        free dofs (dense)."""
+        dofs = np.asarray(dofs)
+        if self.A is not None:
+            return self.A[dofs][:, dofs].toarray()
+        out = np.zeros((len(dofs), len(dofs)))
+        for j, g in enumerate(dofs):
+            e = np.zeros(self.N)
+            e[g] = 1.0
+            out[:, j] = self.apply(e)[dofs]
+        return out
 
     def apply(self, u):
         """A_l u (eq. of the linear system) on free dofs."""

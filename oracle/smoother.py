@@ -37,7 +37,11 @@ readings' iteration counts with the paper's Fichera table, Sec. 5):
 * k1 = "K+sigmaM": the operator on S1 is K + sigma M instead of K (the
   eigenvalues on the S1 columns become lambda + sigma);
 * mult = True: every interface piece operator is multiplied by the number of
-  patches adjacent to it.
+  patches adjacent to it;
+* edges = "direct": the edge and vertex operators are the restriction of the
+  level's matrix A_l to the piece, solved exactly (the direct solvers that
+  Sec. 3 attributes to its reference [Takacs:2017]), instead of the
+  approximations (h/p)^{d-1} K + (h/p)^{d-3} M and (h/p)^{d-2}.
 """
 import itertools
 
@@ -105,13 +109,14 @@ def _modes(T, mats, transpose):
     return T
 
 
-DEFAULT_READING = {"omega": "mean", "h": "param", "k1": "K", "mult": False}
+DEFAULT_READING = {"omega": "mean", "h": "param", "k1": "K", "mult": False, "edges": "approx"}
 
 
 class Smoother:
     """L_l^{-1} on global free vectors of one level."""
 
-    def __init__(self, prob, level, dm, pcs, omegas, sigma_scale=5.0, reading=None, lengths=None, knots=None):
+    def __init__(self, prob, level, dm, pcs, omegas, sigma_scale=5.0, reading=None, lengths=None, knots=None,
+                 restrict=None):
         rd = dict(DEFAULT_READING)
         rd.update(reading or {})
         self.reading = rd
@@ -163,6 +168,10 @@ class Smoother:
                 continue
             hs = [hdir(a, c) for a, bd in pc.adjacent for c in bd]
             h = float(np.exp(np.mean(np.log(hs))))
+            if pc.kind in ("vertex", "edge") and rd["edges"] == "direct":
+                L = restrict(pc.dofs)
+                self.pieces.append(("dense", pc.dofs, sla.cho_factor(L), L))
+                continue
             if pc.kind == "vertex":
                 self.pieces.append(("scalar", pc.dofs, om * (h / p) ** (d - 2)))
             elif pc.kind == "edge":

@@ -4,7 +4,8 @@
 //   Gs[ab][q2][q1][q0]           ab = a*D + b, q2 local to the element slab
 //   T1[ab][q2][q1][o0][i0]
 //   T2[g][q2][i1][o1][o0][i0]     g = 2*(a == 2) + (b == 2)  (one group in 2D)
-//   band[(row/256)*nbt*256 + o*256 + row%256], o = o0 + nb*(o1 + nb*o2)
+//   band[(row/256)*nbt*256 + plane*256 + row%256]: the symmetric half-band of
+//   layout.hpp, plane = band_half_plane(o0, L), L = o1 + nb*o2
 // 1D tables: val/der[(e*nq + q)*(pc+1) + l] is basis function e + l (value or
 // derivative) at Gauss point q of element e.
 #pragma once
@@ -227,9 +228,12 @@ IGAMG_HD inline void asm_dir2_entry(const AsmPatch& P, const double* tab, int e2
 #pragma unroll
         for (int q = 0; q < NQ2; ++q) acc += Fs[q * W + l] * Ft[q * W + lp] * v[g][q];
       }
-      const int64_t row = P.off + i0 + (int64_t)n0 * (i1 + (int64_t)n1 * (e2 + l));
-      const int o = o0 + nb * (o1 + nb * (lp - l + P2));
-      band[((row >> 8) * nbt + o) * 256 + (row & 255)] += acc;
+      // only the upper half is stored (the lower half is its transpose)
+      const int plane = band_half_plane(D, p, o0, o1 + nb * (lp - l + P2));
+      if (plane >= 0) {
+        const int64_t row = P.off + i0 + (int64_t)n0 * (i1 + (int64_t)n1 * (e2 + l));
+        band[((row >> 8) * nbt + plane) * 256 + (row & 255)] += acc;
+      }
     }
 }
 
@@ -240,7 +244,7 @@ IGAMG_HD inline void asm_mask_entry(const PatchDev* pd, const int* bpatch, const
                                     int nbt, int p, int64_t t) {
   const int rr = (int)(t & 255);
   const int64_t bo = t >> 8;
-  const int o = (int)(bo % nbt);
+  const int plane = (int)(bo % nbt);
   const int64_t blk = bo / nbt;
   const int k = bpatch[blk];
   if (k < 0) return;
@@ -250,8 +254,17 @@ IGAMG_HD inline void asm_mask_entry(const PatchDev* pd, const int* bpatch, const
   if (r < 0 || r >= P.rows) return;
   const int n0 = P.n[0], n1 = P.n[1], n2 = P.n[2];
   const int i0 = (int)(r % n0), i1 = (int)((r / n0) % n1), i2 = (int)(r / ((int64_t)n0 * n1));
-  const int nb = 2 * p + 1, p2 = (D == 3) ? p : 0;
-  const int j0 = i0 + o % nb - p, j1 = i1 + (o / nb) % nb - p, j2 = i2 + o / (nb * nb) - p2;
+  const int nb = 2 * p + 1, p2 = (D == 3) ? p : 0, lc = (band_lines(D, p) - 1) / 2;
+  // the index-form offset of the stored plane (layout.hpp)
+  int o0, L;
+  if (plane <= p) {
+    o0 = plane + p;
+    L = lc;
+  } else {
+    o0 = (plane - p - 1) % nb;
+    L = lc + 1 + (plane - p - 1) / nb;
+  }
+  const int j0 = i0 + o0 - p, j1 = i1 + L % nb - p, j2 = i2 + ((D == 3) ? L / nb : 0) - p2;
   bool zero = j0 < 0 || j0 >= n0 || j1 < 0 || j1 >= n1 || j2 < 0 || j2 >= n2 || !isfree[row];
   if (!zero) zero = !isfree[P.off + j0 + (int64_t)n0 * (j1 + (int64_t)n1 * j2)];
   if (zero) band[t] = 0.0;

@@ -814,6 +814,76 @@ static std::vector<PieceH> make_pieces(const ProblemH& P, const LevelH& L) {
   return out;
 }
 
+// L^{-1} = W^T W (W = the inverse Cholesky factor) of an SPD m x m matrix,
+// written to pool[at .. at + m*m)
+static void store_spd_inverse(Mat Lm, int m, std::vector<double>& pool, int64_t at) {
+  if (!cholesky(Lm, m)) fail(IGAMG_ENOTSPD, "internal: edge or vertex operator not SPD");
+  Mat W = lower_inverse(Lm, m);
+  if (pool.size() < (size_t)at + (size_t)m * m) pool.resize((size_t)at + (size_t)m * m);
+  for (int i = 0; i < m; ++i)
+    for (int j = 0; j < m; ++j) {
+      double s = 0.0;
+      for (int a = std::max(i, j); a < m; ++a) s += W[(size_t)a * m + i] * W[(size_t)a * m + j];
+      pool[(size_t)at + (size_t)i * m + j] = s;
+    }
+}
+
+// Gather list of one edge or vertex piece for its exact restriction
+// A_l[g, g]: entry (i, j) sums, over the patches holding copies x of g_i and
+// y of g_j, the coupling of x with y, read from the symmetric half-band at
+// (row x, plane of the offset y - x) or, for an offset of the lower half, at
+// (row y, plane of x - y).
+static void add_direct_gather(const ProblemH& P, LevelH& L, const std::vector<int64_t>& g) {
+  const int d = P.d, p = P.p, nb = 2 * p + 1, lc = (band_lines(d, p) - 1) / 2;
+  if (L.dg_ptr.empty()) L.dg_ptr.push_back(0);
+  auto tensor = [&](int64_t x, int k, int t[3]) {
+    const auto& n = L.n[k];
+    const int64_t r = x - L.off[k];
+    t[0] = (int)(r % n[0]);
+    t[1] = (int)((r / n[0]) % n[1]);
+    t[2] = (int)(r / ((int64_t)n[0] * n[1]));
+  };
+  for (int64_t gi : g)
+    for (int64_t gj : g) {
+      for (int64_t ci = L.gptr[gi]; ci < L.gptr[gi + 1]; ++ci)
+        for (int64_t cj = L.gptr[gj]; cj < L.gptr[gj + 1]; ++cj) {
+          const int64_t x = L.gidx[ci], y = L.gidx[cj];
+          const int k = patch_of(L, x);
+          if (patch_of(L, y) != k) continue;
+          int a[3], b[3], o[3] = {0, 0, 0};
+          tensor(x, k, a);
+          tensor(y, k, b);
+          bool near = true;
+          for (int c = 0; c < d; ++c) {
+            o[c] = b[c] - a[c] + p;
+            near = near && o[c] >= 0 && o[c] < nb;
+          }
+          if (!near) continue;
+          const int line = o[1] + (d == 3 ? nb * o[2] : 0);
+          const int pl = band_half_plane(d, p, o[0], line);
+          if (pl >= 0) {
+            L.dg_row.push_back(x);
+            L.dg_plane.push_back(pl);
+          } else {
+            L.dg_row.push_back(y);
+            L.dg_plane.push_back(band_half_plane(d, p, 2 * p - o[0], 2 * lc - line));
+          }
+        }
+      L.dg_ptr.push_back((int64_t)L.dg_row.size());
+    }
+}
+
+void finish_direct_pieces(LevelH& L, const std::vector<double>& vals) {
+  size_t e = 0;
+  for (size_t q = 0; q < L.dense.size(); ++q) {
+    if (!L.direct[q]) continue;
+    const int m = L.dense[q].m;
+    Mat Lm(vals.begin() + e, vals.begin() + e + (size_t)m * m);
+    e += (size_t)m * m;
+    store_spd_inverse(Lm, m, L.densemat, L.dense[q].Linv);
+  }
+}
+
 static void make_smoother(const ProblemH& P, const Options& O, LevelH& L) {
   const int d = P.d, p = P.p;
   std::vector<PieceH> pcs = make_pieces(P, L);
@@ -859,6 +929,10 @@ static void make_smoother(const ProblemH& P, const Options& O, LevelH& L) {
   L.fd.clear();
   L.dense.clear();
   L.densemat.clear();
+  L.direct.clear();
+  L.dg_ptr.clear();
+  L.dg_row.clear();
+  L.dg_plane.clear();
   L.fdscr = 0;
   L.fd_maxm = 1;
   // interiors first
@@ -946,6 +1020,16 @@ static void make_smoother(const ProblemH& P, const Options& O, LevelH& L) {
       dp.m = (int)pc.g.size();
       dp.Linv = (int64_t)L.densemat.size();
       const int m = dp.m;
+      if (O.iface_direct) {
+        // the exact restriction of A_l to the piece: its entries are gathered
+        // from the assembled band once it exists (finish_direct_pieces)
+        add_direct_gather(P, L, pc.g);
+        L.direct.push_back(1);
+        L.densemat.resize(L.densemat.size() + (size_t)m * m, 0.0);
+        L.dense.push_back(dp);
+        continue;
+      }
+      L.direct.push_back(0);
       Mat Lm((size_t)m * m, 0.0);
       if (pc.kind == 3) {
         Lm[0] = om * std::pow(hp, d - 2);
@@ -955,14 +1039,7 @@ static void make_smoother(const ProblemH& P, const Options& O, LevelH& L) {
         for (size_t i = 0; i < Lm.size(); ++i)
           Lm[i] = om * (std::pow(hp, d - 1) * o.Ki[i] + std::pow(hp, d - 3) * o.Mi[i]);
       }
-      if (!cholesky(Lm, m)) fail(IGAMG_ENOTSPD, "internal: edge operator not SPD");
-      Mat W = lower_inverse(Lm, m);  // L^{-1}; inverse = W^T W
-      for (int i = 0; i < m; ++i)
-        for (int j = 0; j < m; ++j) {
-          double s = 0.0;
-          for (int a = std::max(i, j); a < m; ++a) s += W[(size_t)a * m + i] * W[(size_t)a * m + j];
-          L.densemat.push_back(s);
-        }
+      store_spd_inverse(Lm, m, L.densemat, dp.Linv);
       L.dense.push_back(dp);
     }
   }
@@ -1127,6 +1204,20 @@ void build_all(Hierarchy& H, bool device) {
   for (int l = 0; l < nasm; ++l) {
     assemble_level(P, H.lv[l]);
     setup_progress("assembled level", l);
+    LevelH& L = H.lv[l];
+    if (l > 0 && !L.dg_row.empty()) {
+      // exact edge and vertex pieces from the host band (full storage: the
+      // half-band plane of offset (o0, line) is the full offset o0 + nb*line)
+      const int p = P.p, nb = 2 * p + 1, lc = (band_lines(P.d, p) - 1) / 2;
+      std::vector<double> vals(L.dg_ptr.size() - 1, 0.0);
+      for (size_t e = 0; e + 1 < L.dg_ptr.size(); ++e)
+        for (int64_t c = L.dg_ptr[e]; c < L.dg_ptr[e + 1]; ++c) {
+          const int pl = L.dg_plane[c];
+          const int full = pl <= p ? (pl + p) + nb * lc : (pl - p - 1) % nb + nb * (lc + 1 + (pl - p - 1) / nb);
+          vals[e] += L.band[(size_t)full * L.NL + L.dg_row[c]];
+        }
+      finish_direct_pieces(L, vals);
+    }
   }
   // coarse matrix (dense, free dofs of level 0) and its inverse Cholesky factor
   LevelH& L0 = H.lv[0];

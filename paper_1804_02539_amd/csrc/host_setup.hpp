@@ -41,6 +41,7 @@ struct Options {
   int s1_sigma = 0;        // 1: K + sigma M on the complement S1 of the interior smoother
   int iface_multiplicity = 0;  // 1: interface piece operators times their number of adjacent patches
   int physical_h = 0;      // 1: h_c = (mean length of the c-th Jacobian column) / nel_c
+  int iface_direct = 0;    // 1: edges and vertices solved with the exact restriction of A_l
 };
 
 // Error with an igamg return code.
@@ -75,6 +76,12 @@ struct LevelH {
   int fd_maxm = 1;
   std::vector<DensePiece> dense;
   std::vector<double> densemat;
+  // exact edge and vertex pieces (options.iface_direct): direct[q] = 1 for
+  // dense piece q whose m*m entries (piece by piece, row-major) gather the
+  // half-band entries (dg_row, dg_plane)[dg_ptr[e] .. dg_ptr[e+1])
+  std::vector<char> direct;
+  std::vector<int64_t> dg_ptr, dg_row;
+  std::vector<int> dg_plane;
   // transfers from level l-1 (empty for l = 0)
   int WP = 0, WR = 0;
   std::vector<int64_t> tr_idx;
@@ -126,6 +133,9 @@ void build_topology(Hierarchy& H, bool with_numerics);
 // Everything (assembly, smoothers, transfers, coarse factor).  Levels >= 1
 // are left unassembled when they will be assembled on the device.
 void build_all(Hierarchy& H, bool device);
+// Inverts the exact edge and vertex pieces of a level from their gathered
+// entries (vals[e] for the entries listed by dg_ptr) into densemat.
+void finish_direct_pieces(LevelH& L, const std::vector<double>& vals);
 // Whether levels >= 1 are assembled on the device.
 inline bool assemble_on_device(const Options& o, bool device) { return device && o.assembly == 0; }
 // Quadrature, basis and geometry tables of every patch of level L for device

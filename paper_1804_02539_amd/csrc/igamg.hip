@@ -48,7 +48,7 @@ struct LevelData {
 
 struct DevLevel {
   int64_t NL = 0, N = 0, rows = 0;
-  int nb = 0, nfd = 0, nfd_int = 0, ndense = 0, WP = 0, WR = 0, fd_maxm = 1, max_dense = 1;
+  int nb = 0, nbh = 0, nfd = 0, nfd_int = 0, ndense = 0, WP = 0, WR = 0, fd_maxm = 1, max_dense = 1;
   int mfma_grid = 1;
   int* bpatch = nullptr;
   PatchDev* pd = nullptr;
@@ -118,6 +118,10 @@ struct igamg_ctx {
   // det J sign flags, a level's tables, one element slab's intermediates
   int* asm_flag = nullptr;
   double *asm_tab = nullptr, *asm_gs = nullptr, *asm_t1 = nullptr, *asm_t2 = nullptr;
+  // setup-only gather lists of the exact edge and vertex pieces
+  int64_t *dg_ptr = nullptr, *dg_row = nullptr;
+  int* dg_plane = nullptr;
+  double* dg_out = nullptr;
   double* cb = nullptr;
   int64_t N0 = 0;
   PcgVecs<double> v64;
@@ -150,7 +154,7 @@ static void plan_level_data(Bump& b, const LevelH& L, DevLevel& D, LevelData<T>&
   X.f = b.take<T>(L.NL);
   X.w = b.take<T>(L.NL);
   if (!solver_level) return;
-  X.band = b.take<T>((size_t)D.nb * L.NL);
+  X.band = b.take<T>((size_t)D.nbh * L.NL);
   X.fdmat = b.take<T>(L.fdmat.size());
   X.densemat = b.take<T>(L.densemat.size());
   X.tr_val = b.take<T>(L.tr_val.size());
@@ -184,6 +188,7 @@ static size_t plan(igamg_ctx& C, char* base) {
     int nb = 1;
     for (int c = 0; c < H.prob.d; ++c) nb *= 2 * H.prob.p + 1;
     D.nb = nb;
+    D.nbh = band_half_planes(H.prob.d, H.prob.p);
     D.bpatch = b.take<int>(L.bpatch.size());
     D.pd = b.take<PatchDev>(L.pd.size());
     D.isfree = b.take<uint8_t>(L.NL);
@@ -247,6 +252,18 @@ static size_t plan(igamg_ctx& C, char* base) {
     C.asm_gs = b.take<double>(std::max(sz_max[0], sz_max[2]));
     C.asm_t2 = C.asm_gs;
     C.asm_t1 = b.take<double>(sz_max[1]);
+    size_t ne = 0, nc = 0;
+    for (size_t l = 1; l < H.lv.size(); ++l)
+      if (!H.lv[l].dg_ptr.empty()) {
+        ne = std::max(ne, H.lv[l].dg_ptr.size());
+        nc = std::max(nc, H.lv[l].dg_row.size());
+      }
+    if (ne > 0) {
+      C.dg_ptr = b.take<int64_t>(ne);
+      C.dg_row = b.take<int64_t>(nc);
+      C.dg_plane = b.take<int>(nc);
+      C.dg_out = b.take<double>(ne);
+    }
   }
   return std::max(b.pos, scratch_end) + 256;
 }
@@ -350,9 +367,9 @@ static void device_assemble(igamg_ctx& C, size_t l, hipStream_t st) {
   HIP_OK(hipMemsetAsync(C.asm_flag, 0, (size_t)K * sizeof(int), st));
   for (int k = 0; k < K; ++k)
     for (int e2 = 0; e2 < pt[k].nel[2]; ++e2)
-      HIP_OK(launch_asm_slab(d, pt[k], C.asm_tab, e2, C.asm_gs, C.asm_t1, C.asm_t2, D.d64.band, D.nb, C.asm_flag + k,
+      HIP_OK(launch_asm_slab(d, pt[k], C.asm_tab, e2, C.asm_gs, C.asm_t1, C.asm_t2, D.d64.band, D.nbh, C.asm_flag + k,
                              st));
-  launch_asm_mask(d, H.prob.p, D.pd, D.bpatch, D.isfree, D.d64.band, D.nb, D.NL, st);
+  launch_asm_mask(d, H.prob.p, D.pd, D.bpatch, D.isfree, D.d64.band, D.nbh, D.NL, st);
   HIP_OK(hipGetLastError());
   std::vector<int> flags(K, 0);
   HIP_OK(hipMemcpyAsync(flags.data(), C.asm_flag, (size_t)K * sizeof(int), hipMemcpyDeviceToHost, st));
@@ -360,7 +377,7 @@ static void device_assemble(igamg_ctx& C, size_t l, hipStream_t st) {
   for (int k = 0; k < K; ++k)
     if ((flags[k] & 4) || ((flags[k] & 1) && (flags[k] & 2)))
       throw SetupError{IGAMG_EGEOM, "patch " + std::to_string(k) + ": det J vanishes or changes sign"};
-  if (C.mixed) launch_to_f32(D.d32.band, D.d64.band, (int64_t)D.nb * D.NL, st);
+  if (C.mixed) launch_to_f32(D.d32.band, D.d64.band, (int64_t)D.nbh * D.NL, st);
   HIP_OK(hipStreamSynchronize(st));
   setup_progress("assembled on the device: level", (double)l);
 }
@@ -404,15 +421,34 @@ static void upload(igamg_ctx& C, hipStream_t st) {
     if (l == 0) continue;
     if (assemble_on_device(H.opt, true)) {
       device_assemble(C, l, st);
+      if (!L.dg_row.empty()) {
+        // exact edge and vertex pieces: gather their entries from the band
+        const int64_t ne = (int64_t)L.dg_ptr.size() - 1;
+        up(C.dg_ptr, L.dg_ptr, st);
+        up(C.dg_row, L.dg_row, st);
+        up(C.dg_plane, L.dg_plane, st);
+        launch_band_gather(D.d64.band, D.nbh, C.dg_ptr, C.dg_row, C.dg_plane, ne, C.dg_out, st);
+        HIP_OK(hipGetLastError());
+        std::vector<double> vals(ne);
+        HIP_OK(hipMemcpyAsync(vals.data(), C.dg_out, ne * sizeof(double), hipMemcpyDeviceToHost, st));
+        HIP_OK(hipStreamSynchronize(st));
+        finish_direct_pieces(L, vals);
+      }
     } else {
-      // tiled coefficient-major: the (2p+1)^d planes of each 256-row block are
-      // contiguous, band[(row/256)*nb*256 + o*256 + row%256]
-      std::vector<double> tiled(L.band.size());
+      // tiled symmetric half-band (layout.hpp): the stored planes of each
+      // 256-row block are contiguous, band[(row/256)*nbh*256 + plane*256 + row%256];
+      // plane P+1+(L-LC-1)*NB+o0 (or o0-P on the centre line) is the full
+      // band's offset o0 + NB*L
+      const int p = H.prob.p, nb1 = 2 * p + 1, lc = (band_lines(H.prob.d, p) - 1) / 2;
+      std::vector<int> full_of(D.nbh);
+      for (int pl = 0; pl < D.nbh; ++pl)
+        full_of[pl] = pl <= p ? (pl + p) + nb1 * lc : (pl - p - 1) % nb1 + nb1 * (lc + 1 + (pl - p - 1) / nb1);
+      std::vector<double> tiled((size_t)D.nbh * L.NL);
       const int64_t nblk = L.NL / ROW_ALIGN;
       for (int64_t bk = 0; bk < nblk; ++bk)
-        for (int o = 0; o < D.nb; ++o)
-          std::memcpy(&tiled[((size_t)bk * D.nb + o) * ROW_ALIGN], &L.band[(size_t)o * L.NL + bk * ROW_ALIGN],
-                      ROW_ALIGN * sizeof(double));
+        for (int pl = 0; pl < D.nbh; ++pl)
+          std::memcpy(&tiled[((size_t)bk * D.nbh + pl) * ROW_ALIGN],
+                      &L.band[(size_t)full_of[pl] * L.NL + bk * ROW_ALIGN], ROW_ALIGN * sizeof(double));
       up(D.d64.band, tiled, st);
       if (C.mixed) up(D.d32.band, to_float(tiled), st);
       std::vector<double>().swap(L.band);
@@ -459,7 +495,7 @@ static void band_op(igamg_ctx& C, int l, const T* u, const T* f, T* r, bool resi
   }
   igamg_ctx::Rec rc;
   rc.level = l + (sizeof(T) == 4 ? (int)C.dl.size() : 0);
-  rc.bytes = (double)D.rows * sizeof(T) * ((double)D.nb + (resid ? 3 : 2));
+  rc.bytes = (double)D.rows * sizeof(T) * ((double)D.nbh + (resid ? 3 : 2));
   rc.a = next_event(C);
   rc.b = next_event(C);
   HIP_OK(launch_band<T>(C.d, C.p, band, u, f, r, D.bpatch, D.pd, D.NL, resid, st, rc.a, rc.b));
@@ -660,8 +696,10 @@ static void read_opts(const igamg_options* o, Options& O) {
   O.s1_sigma = o->s1_sigma;
   O.iface_multiplicity = o->iface_multiplicity;
   O.physical_h = o->physical_h;
+  O.iface_direct = o->iface_direct;
   if (O.s1_sigma < 0 || O.s1_sigma > 1 || O.iface_multiplicity < 0 || O.iface_multiplicity > 1 || O.physical_h < 0 ||
-      O.physical_h > 1 || O.geometry_scaling < 0 || O.geometry_scaling > 1)
+      O.physical_h > 1 || O.geometry_scaling < 0 || O.geometry_scaling > 1 || O.iface_direct < 0 ||
+      O.iface_direct > 1)
     throw SetupError{IGAMG_EINVAL, "invalid options"};
   if (!(O.tau > 0) || !(O.sigma_scale > 0) || O.nu < 1 || O.nu > 8 || (O.mu != 1 && O.mu != 2) ||
       (O.precision != IGAMG_FP64 && O.precision != IGAMG_MIXED) || O.maxit < 1 || O.inner_maxit < 1 ||

@@ -23,22 +23,77 @@ namespace igamg {
 // ---------------------------------------------------------------------------
 // banded stiffness apply: r = f - A u  (RESID) or r = A u   (Sec. 4: A_{l,k}
 // applied patch by patch to accumulated u gives a distributed result).
-// The band is tiled: the (2P+1)^D planes of each 256-row block are contiguous.
+// The band holds the upper half of each symmetric patch matrix (layout.hpp):
+// a row reads its own stored planes, and each coupling of the lower half from
+// the row it couples to (A[i][i+d] = A[i+d][i], d < 0), at the plane of the
+// negated offset.  Each coefficient is fetched from HBM once and read twice;
+// the second read finds it in the caches (the mirrored rows lie at most
+// P (n0 n1 + n0 + 1) rows back).
 // A workgroup takes a strip of 64 rows (one row per lane); its 4 waves split
-// the stencil lines (o1, o2) between them (the single planes, for 2D FP64)
-// and add their partial sums in LDS,
-// so a launch has 4 x (rows / 256) x 4 waves to hide HBM latency with.  Each
-// wave reads every band plane of its lines as one coalesced 64-entry segment.
+// the stencil lines (o1, o2) between them (the single stencil entries, in
+// 2D) and add their partial sums in LDS, so a launch has 4 x (rows / 256) x 4
+// waves to hide HBM latency with.  Every band read of a wave, own or
+// mirrored, is a run of 64 consecutive rows of one plane: one coalesced
+// segment, two where it crosses a 256-row tile.
 // ---------------------------------------------------------------------------
 constexpr int BAND_STRIP = 64;
 
-template <int P, int W, typename TB, typename TV>
-__device__ __forceinline__ TV band_planes_2d(const TB* __restrict__ bp, const TV* __restrict__ ub, const int* c0,
-                                             const int* c1) {
-  constexpr int NB = 2 * P + 1;
+// Band entry `plane` of row gg (global) in the tiled half-band.
+template <int NBH, typename TB>
+__device__ __forceinline__ TB band_at(const TB* __restrict__ band, int64_t gg, int plane) {
+  return band[((gg >> 8) * NBH + plane) * ROW_ALIGN + (gg & (ROW_ALIGN - 1))];
+}
+
+// The lower-half couplings of one stencil line L <= LC (index form) for row
+// rl: the rows rl + d of the patch (a row outside the patch couples nothing),
+// read at the planes of the negated offsets.
+template <int D, int P, typename TB, typename TV>
+__device__ __forceinline__ TV band_mirror_line(const TB* __restrict__ band, const TV* __restrict__ ub, int64_t off,
+                                               int64_t rows, int64_t rl, int64_t dl, int L, int o0_end) {
+  constexpr int NB = 2 * P + 1, NLINE = band_lines(D, P), LC = (NLINE - 1) / 2;
+  constexpr int NBH = band_half_planes(D, P);
+  // plane of the negated offset (2P - o0, line 2 LC - L): pbase - o0
+  const int pbase = (L < LC) ? P + 1 + (LC - L - 1) * NB + 2 * P : P;
+  const int64_t r0 = rl + dl - P;
   TV s = 0;
 #pragma unroll
-  for (int o = W; o < NB * NB; o += 4) s += (TV)bp[o * ROW_ALIGN] * ub[c1[o / NB] + c0[o % NB]];
+  for (int o0 = 0; o0 < NB; ++o0) {
+    if (o0 < o0_end) {
+      const int64_t rr = r0 + o0;
+      const bool in = rr >= 0 && rr < rows;
+      const int64_t rc = in ? rr : rl;
+      const TV v = (TV)band_at<NBH>(band, off + rc, pbase - o0) * ub[rc];
+      s += in ? v : (TV)0;
+    }
+  }
+  return s;
+}
+
+// 2D: the NB^2 stencil entries are dealt to the 4 waves one by one (entry t
+// to wave t mod 4); the wave index is a template argument so every entry's
+// offsets are compile-time constants.
+template <int P, int W, typename TB, typename TV>
+__device__ __forceinline__ TV band_entries_2d(const TB* __restrict__ band, const TV* __restrict__ ub, int64_t off,
+                                              int64_t rows, int64_t g, int64_t rl, const int* c0, const int* c1,
+                                              int n0) {
+  constexpr int NB = 2 * P + 1, LC = P, NBH = band_half_planes(2, P);
+  TV s = 0;
+#pragma unroll
+  for (int t = W; t < NB * NB; t += 4) {
+    const int o0 = t % NB, L = t / NB;
+    const int pl = band_half_plane(2, P, o0, L);
+    if (pl >= 0) {
+      s += (TV)band_at<NBH>(band, g, pl) * ub[c1[L] + c0[o0]];
+    } else {
+      // lower half: row rl + d, plane of the negated offset
+      const int pn = band_half_plane(2, P, 2 * P - o0, 2 * LC - L);
+      const int64_t rr = rl + (int64_t)(L - P) * n0 + (o0 - P);
+      const bool in = rr >= 0 && rr < rows;
+      const int64_t rc = in ? rr : rl;
+      const TV v = (TV)band_at<NBH>(band, off + rc, pn) * ub[rc];
+      s += in ? v : (TV)0;
+    }
+  }
   return s;
 }
 
@@ -47,8 +102,9 @@ __global__ __launch_bounds__(256) void k_band(const TB* __restrict__ band, const
                                               const TV* __restrict__ f, TV* __restrict__ r,
                                               const int* __restrict__ bpatch, const PatchDev* __restrict__ pd) {
   constexpr int NB = 2 * P + 1;
-  constexpr int NLINE = (D == 2) ? NB : NB * NB;        // stencil lines (o1, o2)
-  constexpr int NBT = NLINE * NB;
+  constexpr int NLINE = band_lines(D, P);                 // stencil lines (o1, o2)
+  constexpr int LC = (NLINE - 1) / 2;
+  constexpr int NBH = band_half_planes(D, P);
   __shared__ TV part[3][BAND_STRIP];
   const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
   const int64_t g = (int64_t)blockIdx.x * BAND_STRIP + lane;
@@ -60,6 +116,7 @@ __global__ __launch_bounds__(256) void k_band(const TB* __restrict__ band, const
   const int64_t rl0 = g - off;
   const bool valid = rl0 < rows;
   const int64_t rl = valid ? rl0 : rows - 1;             // padding lanes compute a real row, never store
+  const int64_t gr = off + rl;
   const int n0 = pd[k].n[0], n1 = pd[k].n[1], n2 = pd[k].n[2];
   const int i0 = (int)(rl % n0);
   const int64_t t = rl / n0;
@@ -69,33 +126,41 @@ __global__ __launch_bounds__(256) void k_band(const TB* __restrict__ band, const
 #pragma unroll
   for (int o = 0; o < NB; ++o) c0[o] = min(max(i0 + o - P, 0), n0 - 1);
   const TV* ub = u + off;
-  const TB* bp = band + tile * NBT * ROW_ALIGN + (g - tile * ROW_ALIGN);
   const int64_t pl = (int64_t)n0 * n1;
   TV s = 0;
-  if constexpr (D == 2 && sizeof(TB) == 8) {
-    // 2D FP64: the (2P+1)^2 planes are dealt to the 4 waves one by one (plane
-    // o to wave o mod 4), which balances 2P+1 lines far better than whole
-    // lines (measured faster for double; for float the line split is faster);
-    // the wave index is a template argument so every plane's offsets stay
-    // compile-time register indices
+  if constexpr (D == 2) {
     int c1[NB];
 #pragma unroll
     for (int o = 0; o < NB; ++o) c1[o] = min(max(i1 + o - P, 0), n1 - 1) * n0;
     switch (w) {
-      case 0: s = band_planes_2d<P, 0, TB, TV>(bp, ub, c0, c1); break;
-      case 1: s = band_planes_2d<P, 1, TB, TV>(bp, ub, c0, c1); break;
-      case 2: s = band_planes_2d<P, 2, TB, TV>(bp, ub, c0, c1); break;
-      default: s = band_planes_2d<P, 3, TB, TV>(bp, ub, c0, c1); break;
+      case 0: s = band_entries_2d<P, 0, TB, TV>(band, ub, off, rows, gr, rl, c0, c1, n0); break;
+      case 1: s = band_entries_2d<P, 1, TB, TV>(band, ub, off, rows, gr, rl, c0, c1, n0); break;
+      case 2: s = band_entries_2d<P, 2, TB, TV>(band, ub, off, rows, gr, rl, c0, c1, n0); break;
+      default: s = band_entries_2d<P, 3, TB, TV>(band, ub, off, rows, gr, rl, c0, c1, n0); break;
     }
   } else {
+    const TB* bt = band + (gr >> 8) * NBH * ROW_ALIGN + (gr & (ROW_ALIGN - 1));
     for (int L = w; L < NLINE; L += 4) {
       const int o1 = L % NB, o2 = L / NB;
-      int64_t base = (int64_t)min(max(i1 + o1 - P, 0), n1 - 1) * n0;
-      if constexpr (D == 3) base += (int64_t)min(max(i2 + o2 - P, 0), n2 - 1) * pl;
-      const TV* ur = ub + base;
-      const TB* bq = bp + (int64_t)L * NB * ROW_ALIGN;
+      if (L >= LC) {
+        // upper half (and the centre line's o0 >= P): this row's own planes;
+        // out-of-patch columns hold zeros, so their u index is only clamped
+        const int64_t base = (int64_t)min(max(i1 + o1 - P, 0), n1 - 1) * n0 +
+                             (int64_t)min(max(i2 + o2 - P, 0), n2 - 1) * pl;
+        const TV* ur = ub + base;
+        if (L > LC) {
+          const TB* bq = bt + (int64_t)(P + 1 + (L - LC - 1) * NB) * ROW_ALIGN;
 #pragma unroll
-      for (int o0 = 0; o0 < NB; ++o0) s += (TV)bq[o0 * ROW_ALIGN] * ur[c0[o0]];
+          for (int o0 = 0; o0 < NB; ++o0) s += (TV)bq[o0 * ROW_ALIGN] * ur[c0[o0]];
+        } else {
+#pragma unroll
+          for (int o0 = P; o0 < NB; ++o0) s += (TV)bt[(o0 - P) * ROW_ALIGN] * ur[c0[o0]];
+        }
+      }
+      if (L <= LC) {
+        const int64_t dl = (int64_t)(o1 - P) * n0 + (int64_t)(o2 - P) * pl;
+        s += band_mirror_line<D, P, TB, TV>(band, ub, off, rows, rl, dl, L, L == LC ? P : NB);
+      }
     }
   }
   if (w > 0) part[w - 1][lane] = s;
@@ -640,6 +705,29 @@ void launch_mirror_lower(double* A, int64_t n, hipStream_t st) {
   if (tot <= 0) return;
   const int64_t blocks = std::min<int64_t>((tot + 255) / 256, (int64_t)1 << 20);
   hipLaunchKernelGGL(k_mirror_lower, dim3((unsigned)blocks), dim3(256), 0, st, A, n);
+}
+
+// the exact edge and vertex pieces' entries: sums of listed half-band
+// entries (setup only; one thread per entry, the list order fixes the sum)
+__global__ __launch_bounds__(256) void k_band_gather(const double* __restrict__ band, int nbh,
+                                                     const int64_t* __restrict__ ptr, const int64_t* __restrict__ row,
+                                                     const int* __restrict__ plane, int64_t ne,
+                                                     double* __restrict__ out) {
+  const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (e >= ne) return;
+  double s = 0.0;
+  for (int64_t c = ptr[e]; c < ptr[e + 1]; ++c) {
+    const int64_t g = row[c];
+    s += band[((g >> 8) * nbh + plane[c]) * ROW_ALIGN + (g & (ROW_ALIGN - 1))];
+  }
+  out[e] = s;
+}
+
+void launch_band_gather(const double* band, int nbh, const int64_t* ptr, const int64_t* row, const int* plane,
+                        int64_t ne, double* out, hipStream_t st) {
+  if (ne <= 0) return;
+  hipLaunchKernelGGL(k_band_gather, dim3((unsigned)((ne + 255) / 256)), dim3(256), 0, st, band, nbh, ptr, row, plane,
+                     ne, out);
 }
 
 // A[i + i n] = v for i < n

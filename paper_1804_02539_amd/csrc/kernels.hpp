@@ -84,6 +84,9 @@ void launch_to_f32(float* y, const double* x, int64_t n, hipStream_t st);
 // device assembly (assemble.hip): doubles of one element slab's metric (Gs),
 // direction-0 (T1) and direction-1 (T2) intermediates of a patch
 void asm_slab_sizes(int d, const AsmPatch& P, size_t out[3]);
+// out[e] = sum of the half-band entries (row[c], plane[c]), c in [ptr[e], ptr[e+1])
+void launch_band_gather(const double* band, int nbh, const int64_t* ptr, const int64_t* row, const int* plane,
+                        int64_t ne, double* out, hipStream_t st);
 // adds slab e2's contribution of patch P to the tiled FP64 band (nbt =
 // (2p+1)^d coefficients per row); ORs the sign bits of det J into *flag
 hipError_t launch_asm_slab(int d, const AsmPatch& P, const double* tab, int e2, double* Gs, double* T1, double* T2,

@@ -14,6 +14,26 @@ constexpr int ROW_ALIGN = 256;   // patch block alignment (entries) and apply bl
 constexpr int MAX_P = 8;         // highest spline degree with a compiled apply kernel
 constexpr int MAX_FD = 84;       // largest 1D interior size handled by the FD kernels (LDS: L^2 + 1024 doubles)
 
+// Symmetric half-band storage of the banded patch matrices.  An offset of the
+// (2P+1)^D stencil is written in index form (o0, o1, o2), o_c in [0, 2P]
+// (actual offset o_c - P); its stencil line is L = o1 + NB*o2 (2D: L = o1),
+// NB = 2P+1, and the centre line LC = (NLINE-1)/2 holds the diagonal.  Only
+// the offsets whose linear displacement in the patch is >= 0 are stored:
+//   centre line, o0 = P..2P:    plane o0 - P      (plane 0: the diagonal)
+//   lines L > LC (all o0):      plane P + 1 + (L - LC - 1)*NB + o0
+// The other half follows from symmetry, A[i][i+d] = A[i+d][i]: row i reads
+// it from row i+d at the plane of the negated offset.  Per 256-row tile the
+// band_half_planes(D, P) planes are contiguous:
+//   band[(row/256)*nbh*256 + plane*256 + row%256].
+constexpr int band_lines(int d, int p) { return d == 2 ? 2 * p + 1 : (2 * p + 1) * (2 * p + 1); }
+constexpr int band_half_planes(int d, int p) { return p + 1 + (band_lines(d, p) - 1) / 2 * (2 * p + 1); }
+// plane of index-form offset (o0, line L), or -1 for an offset of the lower half
+constexpr int band_half_plane(int d, int p, int o0, int L) {
+  return L == (band_lines(d, p) - 1) / 2 ? (o0 >= p ? o0 - p : -1)
+         : L > (band_lines(d, p) - 1) / 2 ? p + 1 + (L - (band_lines(d, p) - 1) / 2 - 1) * (2 * p + 1) + o0
+                                          : -1;
+}
+
 // One patch on one level l (coarse data refers to level l-1).
 struct PatchDev {
   int n[3];          // local functions per direction at level l (1 for unused directions)

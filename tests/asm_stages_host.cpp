@@ -65,8 +65,8 @@ extern "C" int asm_stages_vs_host(const void* cprob, double* rel, int* flags) {
       std::vector<AsmPatch> pt;
       std::vector<double> tab;
       make_assembly_tables(P, L, pt, tab);
-      int nbt = 1;
-      for (int c = 0; c < P.d; ++c) nbt *= 2 * P.p + 1;
+      const int nbt = band_half_planes(P.d, P.p);   // the stored (upper) planes
+      const int nb1 = 2 * P.p + 1, lc = (band_lines(P.d, P.p) - 1) / 2;
       std::vector<double> band((size_t)nbt * L.NL, 0.0);
       for (int k = 0; k < P.K; ++k)
         for (int e2 = 0; e2 < pt[k].nel[2]; ++e2) {
@@ -84,9 +84,12 @@ extern "C" int asm_stages_vs_host(const void* cprob, double* rel, int* flags) {
       }
       double mx = 0.0, df = 0.0;
       for (int64_t row = 0; row < L.NL; ++row)
-        for (int o = 0; o < nbt; ++o) {
-          const double h = L.band[(size_t)o * L.NL + row];
-          const double g = band[((row >> 8) * nbt + o) * 256 + (row & 255)];
+        for (int pl = 0; pl < nbt; ++pl) {
+          // the host band keeps every offset o0 + nb*L (L = o1 + nb*o2)
+          const int o0 = pl <= P.p ? pl + P.p : (pl - P.p - 1) % nb1;
+          const int L1 = pl <= P.p ? lc : lc + 1 + (pl - P.p - 1) / nb1;
+          const double h = L.band[(size_t)(o0 + nb1 * L1) * L.NL + row];
+          const double g = band[((row >> 8) * nbt + pl) * 256 + (row & 255)];
           mx = std::max(mx, std::fabs(h));
           df = std::max(df, std::fabs(h - g));
         }

@@ -269,3 +269,34 @@ def test_mixed_solve_reaches_fp64_tolerance(torch_cuda, name, fd_mfma):
     # the FP64 handle of the same problem still gives the oracle's result
     u64, info64 = gpu_for(name).solve(f, tol=1e-8)
     assert abs(info64.iterations - it_ref) <= 1
+
+
+# readings of the smoother constants: library option -> oracle reading
+READING_OPTS = {
+    "omega1": ({"geometry_scaling": 0}, {"omega": "one"}),
+    "s1sigma": ({"s1_sigma": 1}, {"k1": "K+sigmaM"}),
+    "mult": ({"iface_multiplicity": 1}, {"mult": True}),
+    "physh": ({"physical_h": 1}, {"h": "physical"}),
+    "direct": ({"iface_direct": 1}, {"edges": "direct"}),
+    "direct_hostasm": ({"iface_direct": 1, "assembly": 1}, {"edges": "direct"}),
+}
+
+
+@pytest.mark.parametrize("reading", list(READING_OPTS))
+@pytest.mark.parametrize("name", ["fichera7_p2_l3", "cube2x2x2_p3_l4", "square4x4_p3_l3_nel1",
+                                  "graded_cube2x2x2_p2_l3"])
+def test_smoother_readings_match_oracle(torch_cuda, reading, name):
+    from oracle.multigrid import Hierarchy
+    from paper_1804_02539_amd import igamg
+    lib_opts, orc = READING_OPTS[reading]
+    _say(f"reading {reading} {name}")
+    prob = CASES[name]()
+    H = Hierarchy(prob, reading=orc)
+    S = igamg.Solver(prob, igamg.default_options(**lib_opts))
+    rng = np.random.default_rng(8)
+    for l in range(1, len(H.levels)):
+        x = rng.standard_normal(H.levels[l].N)
+        y = S.operator(igamg.OP_SMOOTHER, l, x).cpu().numpy()
+        assert rel(y, H.levels[l].smoother.apply(x)) < 1e-11, l
+    r = rng.standard_normal(H.finest.N)
+    assert rel(S.vcycle(r).cpu().numpy(), H.vcycle(r)) < 1e-10

@@ -90,3 +90,30 @@ def test_null_space_rank_gap():
             big = s[s > 1e-10 * s[0]]
             assert small.size == 0 or small.max() < 1e-13 * s[0]
             assert big.min() > 1e-4 * s[0]
+
+
+@pytest.mark.parametrize("make", [lambda: __import__("paper_1804_02539_amd.workloads", fromlist=["x"]).fichera(2, 3),
+                                  lambda: __import__("paper_1804_02539_amd.workloads", fromlist=["x"]).square_4x4_bezier(p=3, levels=3)])
+def test_direct_edge_and_vertex_pieces_solve_the_restriction(make):
+    # the variant of Sec. 3 (its reference's direct solvers): on an edge or a
+    # vertex T the smoother solves A_l[T, T] z_T = r_T exactly.  Checked with
+    # the patch-wise matrix-free apply of the level (not the matrix the
+    # smoother sliced), on a vector supported on one piece.
+    from oracle.multigrid import Hierarchy
+    prob = make()
+    H = Hierarchy(prob, reading={"edges": "direct"})
+    lev = H.finest
+    kinds = {"edge": 0, "vertex": 0}
+    for pc in lev.pieces:
+        if pc.kind not in kinds or kinds[pc.kind] >= 3:
+            continue
+        kinds[pc.kind] += 1
+        r = np.zeros(lev.N)
+        r[pc.dofs] = rng.standard_normal(len(pc.dofs))
+        z = lev.smoother.apply(r)
+        assert np.count_nonzero(z) <= len(pc.dofs)
+        Az = np.zeros(lev.N)
+        for S, op in zip(lev.S, lev.ops):
+            Az += S @ op.apply(S.T @ z)
+        assert np.abs(Az[pc.dofs] - r[pc.dofs]).max() <= 1e-10 * np.abs(r).max()
+    assert kinds["edge"] > 0 and kinds["vertex"] > 0
