@@ -333,14 +333,15 @@ def serving_full(n_requests, n_families, rate, seed, dev, precision="mixed"):
     return {"serving_full": out}
 
 
+# readings of the smoother's constants, as options on top of the library's
+# default (omega = 1, K + sigma M on S1)
 READINGS = {
     "library": {},
-    "omega1": {"geometry_scaling": 0},
-    "s1sigma": {"s1_sigma": 1},
+    "s1_K": {"s1_sigma": 0},
+    "omega_mean": {"geometry_scaling": 1},
+    "omega_mean_s1_K": {"geometry_scaling": 1, "s1_sigma": 0},
     "mult": {"iface_multiplicity": 1},
-    "s1sigma_mult": {"s1_sigma": 1, "iface_multiplicity": 1},
-    "omega1_mult": {"geometry_scaling": 0, "iface_multiplicity": 1},
-    "omega1_s1sigma": {"geometry_scaling": 0, "s1_sigma": 1},
+    "direct": {"iface_direct": 1},
     "physh": {"physical_h": 1},
 }
 

@@ -80,7 +80,9 @@ typedef struct {
 } igamg_problem;
 
 /* Solver parameters; igamg_default_options() gives the paper's choice
- * (Sec. 5): tau = 0.25, sigma = 5 h^-2, 1+1 smoothing, V-cycle.             */
+ * (Sec. 5): tau = 0.25, sigma = 5 h^-2, 1+1 smoothing, V-cycle; the readings
+ * of the smoother's constants that reproduce the paper's Fichera iteration
+ * table (geometry_scaling = 0, s1_sigma = 1).                               */
 typedef struct {
   double tau;            /* smoothing damping                                */
   double sigma_scale;    /* sigma = sigma_scale * h^-2 in the interior smoother */
@@ -89,7 +91,9 @@ typedef struct {
   int precision;         /* IGAMG_FP64, or IGAMG_MIXED (FP32 inner solve inside FP64
                             iterative refinement)                          */
   int maxit;             /* iteration cap of igamg_solve                    */
-  int geometry_scaling;  /* 1: scale piece operators by the patch's mean metric trace */
+  int geometry_scaling;  /* 0 (default): piece operators in parameter-domain units, as the
+                            paper's Fichera iteration table indicates; 1: each scaled by
+                            the patch's mean |det J| tr(J^{-1} J^{-T}) / d                  */
   int inner_maxit;       /* mixed: inner PCG iteration cap per refinement step (100) */
   double inner_tol;      /* mixed: the largest reduction an inner FP32 solve is asked for (1e-4) */
   int graphs;            /* 1: replay each PCG iteration as HIP graphs (default); 0: direct launches */
@@ -110,8 +114,8 @@ typedef struct {
   /* Readings of the smoother's constants, which the paper leaves to its
    * references (Sec. 3) and to "spectrally equivalent up to geometry
    * constants" (Sec. 2); the defaults are the library's reading:           */
-  int s1_sigma;           /* 0 (default): K on the complement S1 of the interior subspace
-                             corrected mass smoother; 1: K + sigma M                       */
+  int s1_sigma;           /* 1 (default): K + sigma M on the complement S1 of the interior
+                             subspace corrected mass smoother; 0: K                        */
   int iface_multiplicity; /* 0 (default): face, edge and vertex operators as printed; 1: each
                              times the number of patches adjacent to the piece             */
   int physical_h;         /* 0 (default): h_c = 1/nel_c of the parameter domain; 1: the

@@ -6,19 +6,21 @@ L^{-1} = sum_T P_T L_T^{-1} P_T^T over the pieces T (patch interiors, faces,
 edges, vertices), P_T the indicator of the piece's dofs.
 
 Interior pieces: the subspace-corrected mass smoother, which the paper takes
-from its reference [HT:2016] without restating it.  Reading used here (parity
-unpinned against the paper; pinned only by self-consistency):
+from its reference [HT:2016] without restating it.  Reading used here:
 
 * per direction c, on the 1D space of interior functions (indices 1..n-2,
   vanishing at both ends), the subspace
   S~ = {u : the even derivatives of order 2l, 1 <= l, 2l < p, vanish at 0 and 1}
   and its M-orthogonal complement S1;
-* on S~ the 1D operator is sigma_c M (sigma_c = 5 h_c^{-2}, h_c = 1/nel_c, the
-  value sigma = h^{-2}/0.2 of Sec. 5), on S1 it is K;
+* on S~ the 1D operator is sigma_c M (sigma_c = 5 h_c^{-2}, h_c the smallest
+  knot span, 1/nel_c on uniform knots: the value sigma = h^{-2}/0.2 of Sec. 5),
+  on S1 it is K + sigma_c M;
 * the d-variate piece operators L_alpha = sum_c (x)_{j != c} M_{alpha_j} (x) Khat_{c,alpha_c}
-  over the 2^d products of these subspaces, times the geometry factor omega_k;
+  over the 2^d products of these subspaces, all in parameter-domain units
+  (no geometry factor: omega = 1);
 * applied as (x)U_c D^{-1} (x)U_c^T, where U_c = [M-orthonormal basis of S~,
-  M-orthonormal eigenvectors of K on S1] and D = omega * sum_c mu_c.  The
+  M-orthonormal eigenvectors of K on S1] and D = omega * sum_c mu_c, with
+  mu = sigma on the S~ columns and lambda + sigma on the S1 columns.  The
   tests check this against the literal sum over alpha.
 
 Faces (3D): the operator (h/p)(Kcal + p^2 h^{-2} Mcal) of Sec. 3 with Kcal
@@ -26,16 +28,23 @@ replaced by the same subspace-corrected construction in the two tangential
 directions: D = omega (h/p)(mu_t0 + mu_t1 + p^2/h^2).
 Edges: L_T = omega ((h/p)^{d-1} K + (h/p)^{d-3} M) on the edge-interior
 functions, solved exactly.  Vertices: L_T = omega (h/p)^{d-2}.
-h for an interface piece is the geometric mean of 1/nel over the adjacent
-patches' normal directions; omega is the mean of the adjacent patches' omega.
+h for an interface piece is the geometric mean of the adjacent patches' h in
+their normal directions.
 
-Other readings, selected by the ``reading`` argument (used to compare the
-readings' iteration counts with the paper's Fichera table, Sec. 5):
-* omega = "one": no geometry factor (omega = 1 for every piece);
+The constants (omega, the operator on S1, h, multiplicities) are readings:
+the paper leaves them to its references and to "spectrally equivalent up to
+geometry constants" (Sec. 2).  The default was chosen by the PCG iteration
+counts on the Fichera corner with 448 patches, l = 1..4, p = 2..4, against the
+paper's table (Sec. 5): omega = 1 is the only reading whose counts grow with
+l as the paper's do (p = 2: 33, 32, 39, 44 against 30, 33, 39, 44), and
+K + sigma M on S1 brings p = 3 closest (27, 32, 37, 43 against 31, 32, 38,
+44).  The alternatives stay selectable through the ``reading`` argument:
+* omega = "mean": every piece operator times omega_k, the parameter-domain
+  mean of |det J| tr(J^{-1} J^{-T}) / d (averaged over the adjacent patches
+  for an interface piece);
 * h = "physical": h_c = (mean length of the patch's c-th Jacobian column)/nel_c
-  instead of the parameter-domain 1/nel_c, in sigma and in the interface formulas;
-* k1 = "K+sigmaM": the operator on S1 is K + sigma M instead of K (the
-  eigenvalues on the S1 columns become lambda + sigma);
+  instead of the parameter-domain span, in sigma and in the interface formulas;
+* k1 = "K": the operator on S1 is K (eigenvalues lambda on the S1 columns);
 * mult = True: every interface piece operator is multiplied by the number of
   patches adjacent to it;
 * edges = "direct": the edge and vertex operators are the restriction of the
@@ -109,7 +118,7 @@ def _modes(T, mats, transpose):
     return T
 
 
-DEFAULT_READING = {"omega": "mean", "h": "param", "k1": "K", "mult": False, "edges": "approx"}
+DEFAULT_READING = {"omega": "one", "h": "param", "k1": "K+sigmaM", "mult": False, "edges": "approx"}
 
 
 class Smoother:

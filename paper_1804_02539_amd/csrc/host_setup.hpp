@@ -30,7 +30,7 @@ constexpr int64_t COARSE_HOST_MAX = 3000;
 
 struct Options {
   double tau = 0.25, sigma_scale = 5.0;
-  int nu = 1, mu = 1, precision = 0, maxit = 500, geometry_scaling = 1;
+  int nu = 1, mu = 1, precision = 0, maxit = 500, geometry_scaling = 0;
   int inner_maxit = 100;
   double inner_tol = 1e-4;
   int graphs = 1;
@@ -38,7 +38,7 @@ struct Options {
   int coarse_factor = 0;   // 0 auto, 1 host, 2 device
   int autotune = 1;
   int assembly = 0;        // levels >= 1: 0 on the device when there is one, 1 on the host
-  int s1_sigma = 0;        // 1: K + sigma M on the complement S1 of the interior smoother
+  int s1_sigma = 1;        // 1: K + sigma M on the complement S1 of the interior smoother, 0: K
   int iface_multiplicity = 0;  // 1: interface piece operators times their number of adjacent patches
   int physical_h = 0;      // 1: h_c = (mean length of the c-th Jacobian column) / nel_c
   int iface_direct = 0;    // 1: edges and vertices solved with the exact restriction of A_l

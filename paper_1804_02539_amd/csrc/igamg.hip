@@ -1212,7 +1212,8 @@ void igamg_default_options(igamg_options* o) {
   o->mu = 1;
   o->precision = IGAMG_FP64;
   o->maxit = 500;
-  o->geometry_scaling = 1;
+  o->geometry_scaling = 0;
+  o->s1_sigma = 1;
   o->inner_maxit = 100;
   o->inner_tol = 1e-4;
   o->graphs = 1;

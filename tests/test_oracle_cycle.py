@@ -116,15 +116,16 @@ def test_iteration_counts_flat_in_h_and_p():
 
 
 @pytest.mark.slow
-def test_fichera_iteration_count_near_paper():
-    # soft pin: level 1, p = 2 of the paper's 3D table (K = 448); the smoother's
-    # constants are a reading, so agreement within 30% is what is asserted
+@pytest.mark.parametrize("p", [2, 3])
+def test_fichera_iteration_count_near_paper(p):
+    # level 1 of the paper's 3D table (K = 448), with the default reading of
+    # the smoother's constants (chosen to reproduce that table): within 15%
     with open(os.path.join(GOLD, "iteration_counts.json")) as fh:
-        paper = json.load(fh)["fichera_K448"]["1"]["2"]
-    prob = W.fichera(2, 2, split=4)
+        paper = json.load(fh)["fichera_K448"]["1"][str(p)]
+    prob = W.fichera(p, 2, split=4)
     H = Hierarchy(prob)
     _, it, _ = H.pcg(load_vector(prob, H.finest))
-    assert abs(it - paper) <= 0.3 * paper, (it, paper)
+    assert abs(it - paper) <= 0.15 * paper, (it, paper)
 
 
 def _dense_op(apply, n):
