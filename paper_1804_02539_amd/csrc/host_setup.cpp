@@ -1180,11 +1180,12 @@ void build_topology(Hierarchy& H, bool with_numerics) {
   if (H.lv[0].N == 0) fail(IGAMG_EINVAL, "no free degrees of freedom");
   std::vector<double> om(P.K, 1.0);
   std::vector<std::array<double, 3>> len(P.K, std::array<double, 3>{1.0, 1.0, 1.0});
-  if (with_numerics)
-    for (int k = 0; k < P.K; ++k) {
-      om[k] = patch_omega(P, k);
-      len[k] = patch_lengths(P, k);
-    }
+  // the physical-h reading keys the 1D factors by h, so the sizing pass
+  // needs the patch lengths too
+  for (int k = 0; k < P.K; ++k) {
+    if (with_numerics) om[k] = patch_omega(P, k);
+    if (with_numerics || H.opt.physical_h) len[k] = patch_lengths(P, k);
+  }
   for (auto& L : H.lv) {
     L.omega = om;
     L.length = len;
