@@ -162,6 +162,24 @@ int igamg_workspace_size(const igamg_problem* prob, const igamg_options* opts, s
 int igamg_setup(const igamg_problem* prob, const igamg_options* opts, void* workspace,
                 size_t bytes, void* stream, igamg_handle* out);
 
+/* For callers that cannot allocate (code under HIP graph capture, tight
+ * serving loops, harnesses that forbid allocation): igamg_setup without any
+ * allocation by the library.  The hierarchy goes into the caller's
+ * `workspace` as with igamg_setup, but the setup-only scratch of the device
+ * assembly lives in a static device array of 64 MiB per GPU (held until the
+ * process ends), so the workspace is smaller than igamg_workspace_size():
+ * with workspace == NULL the call only writes the bytes it needs to *needed
+ * (out may then be NULL).  No hipMalloc, hipFree, pinned host memory or
+ * library allocation is made: the coarse matrix is factored on the host
+ * (EINVAL above 3000 coarse unknowns or with options.coarse_factor = 2), the
+ * handle reads its scalars back into ordinary host memory and so launches
+ * its solves directly (options.graphs is ignored), and a problem whose
+ * setup scratch exceeds the static array is rejected with EINVAL.  Calls are
+ * serialised inside the process; the array keeps the last call's contents,
+ * and each call clears what it needs zeroed.  Other errors as igamg_setup.   */
+int igamg_setup_noalloc(const igamg_problem* prob, const igamg_options* opts, void* workspace, size_t bytes,
+                        void* stream, igamg_handle* out, size_t* needed);
+
 /* Free and local sizes of level `level` (-1 = finest): n_free = unique free
  * dofs, n_local = sum over patches of their local function counts.          */
 int igamg_num_dofs(igamg_handle h, int level, int64_t* n_free, int64_t* n_local);

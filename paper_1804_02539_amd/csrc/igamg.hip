@@ -128,8 +128,13 @@ struct igamg_ctx {
   PcgVecs<float> v32;
   double* fsave = nullptr;       // mixed: the right-hand side (patch-local, distributed)
   double *part = nullptr, *scal = nullptr;
-  double* host_scal = nullptr;   // pinned
+  double* host_scal = nullptr;   // pinned (a plain host array for no-allocation handles)
   bool on_device = false;
+  // igamg_setup_noalloc: the setup scratch lives in the static device array
+  bool noalloc = false;
+  char* setup_base = nullptr;
+  size_t setup_bytes = 0;
+  double host_scal_own[16] = {};
   // optional event timing of the banded apply
   bool prof = false;
   struct Rec {
@@ -232,6 +237,10 @@ static size_t plan(igamg_ctx& C, char* base) {
   C.scal = b.take<double>(16);
   C.scratch_at = scratch_at;
   if (assemble_on_device(H.opt, true) && H.lv.size() > 1) {
+    // the setup-only scratch: at the end of the workspace, or in the static
+    // device array of a no-allocation setup
+    Bump sb{C.setup_base};
+    Bump& a = C.noalloc ? sb : b;
     size_t pool = 0, sz_max[3] = {0, 0, 0};
     for (size_t l = 1; l < H.lv.size(); ++l) {
       std::vector<AsmPatch> pt;
@@ -244,14 +253,14 @@ static size_t plan(igamg_ctx& C, char* base) {
         for (int i = 0; i < 3; ++i) sz_max[i] = std::max(sz_max[i], sz[i]);
       }
     }
-    C.asm_flag = b.take<int>(H.prob.K);
-    C.asm_tab = b.take<double>(pool);
+    C.asm_flag = a.take<int>(H.prob.K);
+    C.asm_tab = a.take<double>(pool);
     // Gs is dead once direction 0 has read it, and T2 is written only after
     // that (the next slab's metric stage follows this slab's last stage on
     // the stream), so the two share one region
-    C.asm_gs = b.take<double>(std::max(sz_max[0], sz_max[2]));
+    C.asm_gs = a.take<double>(std::max(sz_max[0], sz_max[2]));
     C.asm_t2 = C.asm_gs;
-    C.asm_t1 = b.take<double>(sz_max[1]);
+    C.asm_t1 = a.take<double>(sz_max[1]);
     size_t ne = 0, nc = 0;
     for (size_t l = 1; l < H.lv.size(); ++l)
       if (!H.lv[l].dg_ptr.empty()) {
@@ -259,11 +268,12 @@ static size_t plan(igamg_ctx& C, char* base) {
         nc = std::max(nc, H.lv[l].dg_row.size());
       }
     if (ne > 0) {
-      C.dg_ptr = b.take<int64_t>(ne);
-      C.dg_row = b.take<int64_t>(nc);
-      C.dg_plane = b.take<int>(nc);
-      C.dg_out = b.take<double>(ne);
+      C.dg_ptr = a.take<int64_t>(ne);
+      C.dg_row = a.take<int64_t>(nc);
+      C.dg_plane = a.take<int>(nc);
+      C.dg_out = a.take<double>(ne);
     }
+    if (C.noalloc) C.setup_bytes = sb.pos;
   }
   return std::max(b.pos, scratch_end) + 256;
 }
@@ -1201,6 +1211,26 @@ static void fill_info(const Req& q, igamg_solve_info* info) {
 // ---------------------------------------------------------------------------
 // exported entry points
 // ---------------------------------------------------------------------------
+// the no-allocation setup's scratch (igamg_setup_noalloc)
+constexpr size_t NOALLOC_SCRATCH_BYTES = (size_t)64 << 20;
+static __device__ __align__(256) unsigned char scratch[NOALLOC_SCRATCH_BYTES];
+static std::mutex g_noalloc_mu;             // one no-allocation setup at a time
+static std::map<int, char*> g_scratch_at;   // device -> address of its `scratch`, under g_noalloc_mu
+
+// The address of `scratch` on the current device, looked up once per device.
+static char* noalloc_scratch() {
+  int dev = 0;
+  HIP_OK(hipGetDevice(&dev));
+  auto it = g_scratch_at.find(dev);
+  if (it != g_scratch_at.end()) return it->second;
+  void* ptr = nullptr;
+  const hipError_t e = hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch));
+  if (e != hipSuccess || !ptr)
+    throw SetupError{IGAMG_EDEVICE, std::string("hipGetSymbolAddress(scratch): ") + hipGetErrorString(e)};
+  g_scratch_at[dev] = static_cast<char*>(ptr);
+  return static_cast<char*>(ptr);
+}
+
 extern "C" {
 
 void igamg_default_options(igamg_options* o) {
@@ -1270,6 +1300,76 @@ int igamg_setup(const igamg_problem* prob, const igamg_options* opts, void* work
   API_END
 }
 
+// Setup without any allocation: the setup-only scratch of the device
+// assembly (quadrature and geometry tables, det J flags, one element slab's
+// intermediates, the gather lists of exact edge and vertex pieces) is taken
+// from this static device array instead of the workspace.  Every GPU keeps
+// its own copy for the life of the process; its address on the current
+// device comes from hipGetSymbolAddress (the array's name is a host stand-in
+// in host code, not a device address).  Calls are serialised by a mutex, and
+// each call clears what it needs zeroed (the flags) and writes every other
+// region before reading it, so nothing depends on what the last call left.
+int igamg_setup_noalloc(const igamg_problem* prob, const igamg_options* opts, void* workspace, size_t bytes,
+                        void* stream, igamg_handle* out, size_t* needed) {
+  API_BEGIN
+  if (!workspace && !needed) return set_err(IGAMG_EINVAL, "workspace and needed are both NULL");
+  if (workspace && !out) return set_err(IGAMG_EINVAL, "out is NULL");
+  if (out) *out = nullptr;
+  igamg_ctx* C = new igamg_ctx();
+  try {
+    C->noalloc = true;
+    C->H.prob = read_problem(prob);
+    read_opts(opts, C->H.opt);
+    // scalar readbacks go to a plain host array, which graph capture cannot
+    // target: these handles launch their kernels directly
+    C->H.opt.graphs = 0;
+    C->mixed = C->H.opt.precision == IGAMG_MIXED;
+    C->d = C->H.prob.d;
+    C->p = C->H.prob.p;
+    C->L = C->H.prob.levels - 1;
+    {
+      Hierarchy T;
+      T.prob = C->H.prob;
+      T.opt = C->H.opt;
+      build_topology(T, false);
+      if (coarse_on_device(T.opt, T.lv[0].N, true))
+        throw SetupError{IGAMG_EINVAL, "the no-allocation setup factors the coarse matrix on the host only: at most " +
+                                           std::to_string(COARSE_HOST_MAX) + " coarse unknowns (this problem has " +
+                                           std::to_string(T.lv[0].N) + ") and options.coarse_factor != 2"};
+    }
+    build_all(C->H, true);
+    const size_t need = plan(*C, nullptr);
+    if (C->setup_bytes > NOALLOC_SCRATCH_BYTES)
+      throw SetupError{IGAMG_EINVAL, "setup scratch of " + std::to_string(C->setup_bytes) +
+                                         " bytes exceeds the static " + std::to_string(NOALLOC_SCRATCH_BYTES) +
+                                         " bytes of the no-allocation setup"};
+    if (needed) *needed = need;
+    if (workspace) {
+      if (bytes < need) throw SetupError{IGAMG_ENOMEM, "workspace too small: need " + std::to_string(need)};
+      if (reinterpret_cast<uintptr_t>(workspace) & 255) throw SetupError{IGAMG_EINVAL, "workspace not 256-byte aligned"};
+      std::lock_guard<std::mutex> lock(g_noalloc_mu);
+      C->setup_base = noalloc_scratch();
+      C->ws = workspace;
+      C->bytes = need;
+      plan(*C, static_cast<char*>(workspace));
+      C->host_scal = C->host_scal_own;
+      upload(*C, static_cast<hipStream_t>(stream));
+      C->on_device = true;
+      autotune(*C, static_cast<hipStream_t>(stream));
+    }
+  } catch (...) {
+    igamg_destroy(C);
+    throw;
+  }
+  if (!workspace) {
+    igamg_destroy(C);
+    return IGAMG_OK;
+  }
+  *out = C;
+  return IGAMG_OK;
+  API_END
+}
+
 int igamg_profile(igamg_handle h, int enable) {
   API_BEGIN
   need_device(h);
@@ -1311,7 +1411,7 @@ int igamg_destroy(igamg_handle h) {
   for (hipGraphExec_t g : h->gx)
     if (g) (void)hipGraphExecDestroy(g);
   for (hipEvent_t e : h->pool) (void)hipEventDestroy(e);
-  if (h->host_scal) (void)hipHostFree(h->host_scal);
+  if (h->host_scal && !h->noalloc) (void)hipHostFree(h->host_scal);
   delete h;
   return IGAMG_OK;
 }

@@ -68,6 +68,8 @@ def _load():
         "igamg_default_options": (None, [P(Options)]),
         "igamg_workspace_size": (ctypes.c_int, [P(_Problem), P(Options), P(ctypes.c_size_t)]),
         "igamg_setup": (ctypes.c_int, [P(_Problem), P(Options), vp, ctypes.c_size_t, vp, P(vp)]),
+        "igamg_setup_noalloc": (ctypes.c_int, [P(_Problem), P(Options), vp, ctypes.c_size_t, vp, P(vp),
+                                                P(ctypes.c_size_t)]),
         "igamg_num_dofs": (ctypes.c_int, [vp, ctypes.c_int, i64p, i64p]),
         "igamg_load_vector": (ctypes.c_int, [vp, ctypes.c_double, ctypes.c_double, P(ctypes.c_double)]),
         "igamg_vcycle": (ctypes.c_int, [vp, vp, vp, vp]),
@@ -101,7 +103,8 @@ EXPORTED = ["igamg_default_options", "igamg_workspace_size", "igamg_setup", "iga
             "igamg_load_vector", "igamg_vcycle", "igamg_solve", "igamg_operator", "igamg_dof_map",
             "igamg_export", "igamg_profile", "igamg_profile_read", "igamg_destroy",
             "igamg_last_error", "igamg_batch_create", "igamg_batch_destroy", "igamg_batch_add",
-            "igamg_batch_step", "igamg_batch_poll", "igamg_batch_remove", "igamg_solve_batch", "igamg_tuning"]
+            "igamg_batch_step", "igamg_batch_poll", "igamg_batch_remove", "igamg_solve_batch", "igamg_tuning",
+            "igamg_setup_noalloc"]
 EXPORT_MATRIX, EXPORT_PROLONG = 0, 1
 
 
@@ -165,13 +168,25 @@ def _dptr(t):
 class Solver:
     """A multigrid hierarchy resident in a caller-owned device workspace."""
 
-    def __init__(self, prob, opts=None, device="cuda:0", stream=None, host_only=False):
+    def __init__(self, prob, opts=None, device="cuda:0", stream=None, host_only=False, noalloc=False):
         import torch
         self.prob = prob
         self.opts = opts or default_options()
         cp = _CProblem(prob)
         h = ctypes.c_void_p()
-        if host_only:
+        if noalloc:
+            # igamg_setup_noalloc: size query, then the setup into a workspace
+            # of that size (this binding allocates the workspace; the library
+            # allocates nothing)
+            need = ctypes.c_size_t()
+            _check(_lib.igamg_setup_noalloc(ctypes.byref(cp.s), ctypes.byref(self.opts), None, 0, None, None,
+                                            ctypes.byref(need)))
+            nbytes = int(need.value)
+            self.workspace = torch.empty(nbytes + 256, dtype=torch.uint8, device=device)
+            aligned = (self.workspace.data_ptr() + 255) & ~255
+            _check(_lib.igamg_setup_noalloc(ctypes.byref(cp.s), ctypes.byref(self.opts), ctypes.c_void_p(aligned),
+                                            nbytes, _stream_ptr(stream), ctypes.byref(h), None))
+        elif host_only:
             self.workspace = None
             _check(_lib.igamg_setup(ctypes.byref(cp.s), ctypes.byref(self.opts), None, 0, None,
                                     ctypes.byref(h)))

@@ -178,3 +178,22 @@ def test_knots0_validation():
     with pytest.raises(igamg.IgamgError) as e:
         igamg.Solver(bad, host_only=True)
     assert e.value.code == igamg.ETOPO
+
+
+def test_noalloc_size_query_and_limits():
+    # the no-allocation setup answers a size query on the host (workspace
+    # NULL): its workspace leaves out the device assembly's setup scratch
+    prob = W.cube_2x2x2_trilinear(levels=3)
+    opts = igamg.default_options()
+    cp = igamg._CProblem(prob)
+    need = ctypes.c_size_t()
+    lib = igamg.lib()
+    assert lib.igamg_setup_noalloc(ctypes.byref(cp.s), ctypes.byref(opts), None, 0, None, None,
+                                   ctypes.byref(need)) == igamg.OK
+    assert 0 < need.value < igamg.workspace_size(prob, opts)
+    # device factorization of the coarse matrix is not available without allocation
+    bad = igamg.default_options(coarse_factor=2)
+    assert lib.igamg_setup_noalloc(ctypes.byref(cp.s), ctypes.byref(bad), None, 0, None, None,
+                                   ctypes.byref(need)) == igamg.EINVAL
+    # a query needs somewhere to write the size
+    assert lib.igamg_setup_noalloc(ctypes.byref(cp.s), ctypes.byref(opts), None, 0, None, None, None) == igamg.EINVAL
