@@ -98,8 +98,11 @@ typedef struct {
   double inner_tol;      /* mixed: the largest reduction an inner FP32 solve is asked for (1e-4) */
   int graphs;            /* 1: replay each PCG iteration as HIP graphs (default); 0: direct launches */
   int fd_mfma;           /* FP32 fast-diagonalization mode products (mixed precision): 0 (default) as the
-                            autotuner chooses, 1 always on the matrix cores (v_mfma_f32_16x16x4f32),
-                            2 always vector FMAs */
+                            autotuner chooses among vector FMAs and FP32 matrix cores, 1 always on the
+                            matrix cores (v_mfma_f32_16x16x4f32: FUSED on levels of 2D tensors, MFMA
+                            otherwise), 2 always vector FMAs, 3 always on the matrix cores with the
+                            operands rounded to bfloat16 (v_mfma_f32_16x16x16bf16_1k, FP32
+                            accumulation) */
   int coarse_factor;     /* factorization of the dense coarse matrix: 0 (default) on the host up to
                             3000 coarse unknowns and on the device (rocSOLVER Cholesky, then the
                             inverse by blocked solves against I, in the workspace) above; 1 always on
@@ -280,8 +283,9 @@ int igamg_export(igamg_handle h, int what, int level, double* out, int64_t* rows
  * igamg_profile_read synchronises the stream of the last recorded launch and
  * returns, per level l, the launch count, the summed kernel time in ms (timing
  * events attached to each dispatch, so the time is the kernel's own) and the
- * algorithmic bytes moved (rows * s (nbh + vectors), s = 8 or 4 bytes, nbh =
- * ((2p+1)^d + 1)/2 the stored planes of the symmetric half-band);
+ * algorithmic bytes moved (rows * s (planes + vectors): FP64, s = 8 and the
+ * ((2p+1)^d + 1)/2 stored planes of the symmetric half band; FP32, s = 4 and
+ * all (2p+1)^d planes);
  * arrays have 2*levels entries: [l] for FP64 launches, [levels + l] for FP32
  * launches of a mixed-precision handle.  Then it clears the record.          */
 int igamg_profile(igamg_handle h, int enable);
@@ -291,6 +295,12 @@ int igamg_profile_read(igamg_handle h, int64_t* launches, double* ms, double* by
 #define IGAMG_FD_VEC8 0   /* vector FMAs, chunks of 8 columns per workgroup     */
 #define IGAMG_FD_VEC4 1   /* vector FMAs, chunks of 4 columns per workgroup     */
 #define IGAMG_FD_MFMA 2   /* FP32 only: 16x16x4 matrix-core tiles, 8 columns    */
+#define IGAMG_FD_FUSED 3  /* FP32 only, levels whose items are all 2D tensors: one
+                             launch per smoothing, each item in LDS through the four
+                             mode products on the matrix cores                     */
+#define IGAMG_FD_MFMA_BF16 4 /* FP32 solves: the matrix-core products (FUSED on 2D
+                             levels, MFMA otherwise) with operands rounded to
+                             bfloat16, FP32 accumulation; only by options.fd_mfma = 3 */
 
 /* The smoother variant level `level` (>= 1) uses in FP64 (fp32 = 0) or in
  * the FP32 inner solves (fp32 = 1).  With options.autotune = 1 setup times

@@ -159,7 +159,8 @@ static void plan_level_data(Bump& b, const LevelH& L, DevLevel& D, LevelData<T>&
   X.f = b.take<T>(L.NL);
   X.w = b.take<T>(L.NL);
   if (!solver_level) return;
-  X.band = b.take<T>((size_t)D.nbh * L.NL);
+  // FP64: the symmetric half band; FP32: the full band
+  X.band = b.take<T>((size_t)(sizeof(T) == 8 ? D.nbh : D.nb) * L.NL);
   X.fdmat = b.take<T>(L.fdmat.size());
   X.densemat = b.take<T>(L.densemat.size());
   X.tr_val = b.take<T>(L.tr_val.size());
@@ -387,7 +388,7 @@ static void device_assemble(igamg_ctx& C, size_t l, hipStream_t st) {
   for (int k = 0; k < K; ++k)
     if ((flags[k] & 4) || ((flags[k] & 1) && (flags[k] & 2)))
       throw SetupError{IGAMG_EGEOM, "patch " + std::to_string(k) + ": det J vanishes or changes sign"};
-  if (C.mixed) launch_to_f32(D.d32.band, D.d64.band, (int64_t)D.nbh * D.NL, st);
+  if (C.mixed) launch_band_half_to_full(d, H.prob.p, D.d32.band, D.d64.band, D.bpatch, D.pd, D.NL, st);
   HIP_OK(hipStreamSynchronize(st));
   setup_progress("assembled on the device: level", (double)l);
 }
@@ -460,7 +461,15 @@ static void upload(igamg_ctx& C, hipStream_t st) {
           std::memcpy(&tiled[((size_t)bk * D.nbh + pl) * ROW_ALIGN],
                       &L.band[(size_t)full_of[pl] * L.NL + bk * ROW_ALIGN], ROW_ALIGN * sizeof(double));
       up(D.d64.band, tiled, st);
-      if (C.mixed) up(D.d32.band, to_float(tiled), st);
+      if (C.mixed) {
+        // the FP32 copy keeps every plane, band[(row/256)*nb*256 + o*256 + row%256]
+        std::vector<float> full32((size_t)D.nb * L.NL);
+        for (int64_t bk = 0; bk < nblk; ++bk)
+          for (int o = 0; o < D.nb; ++o)
+            for (int r = 0; r < ROW_ALIGN; ++r)
+              full32[((size_t)bk * D.nb + o) * ROW_ALIGN + r] = (float)L.band[(size_t)o * L.NL + bk * ROW_ALIGN + r];
+        up(D.d32.band, full32, st);
+      }
       std::vector<double>().swap(L.band);
       setup_progress("uploaded band of level", (double)l);
     }
@@ -505,7 +514,7 @@ static void band_op(igamg_ctx& C, int l, const T* u, const T* f, T* r, bool resi
   }
   igamg_ctx::Rec rc;
   rc.level = l + (sizeof(T) == 4 ? (int)C.dl.size() : 0);
-  rc.bytes = (double)D.rows * sizeof(T) * ((double)D.nbh + (resid ? 3 : 2));
+  rc.bytes = (double)D.rows * sizeof(T) * ((double)(sizeof(T) == 8 ? D.nbh : D.nb) + (resid ? 3 : 2));
   rc.a = next_event(C);
   rc.b = next_event(C);
   HIP_OK(launch_band<T>(C.d, C.p, band, u, f, r, D.bpatch, D.pd, D.NL, resid, st, rc.a, rc.b));
@@ -522,15 +531,22 @@ static void smoother_apply(igamg_ctx& C, int l, const T* src, T* u, bool add, do
   LevelData<T>& X = dat<T>(D);
   const int variant = D.fdv[std::is_same<T, float>::value ? 1 : 0];
   if constexpr (std::is_same<T, float>::value) {
-    if (variant == IGAMG_FD_MFMA) {
+    const bool bf16 = variant == IGAMG_FD_MFMA_BF16;
+    if ((variant == IGAMG_FD_FUSED || bf16) && D.max_m2 == 1) {
+      // every item is a 2D tensor: one launch, each item held in LDS
+      launch_fd2_fused(D.fd, D.nfd, D.ndense, fd2_fused_lds(D.fd_maxm, D.max_dense), D.dense, X.densemat, X.fdmat,
+                       src, u, D.if_ptr, D.if_idx, tau, add, bf16, st);
+      return;
+    }
+    if (variant == IGAMG_FD_MFMA || variant == IGAMG_FD_FUSED || bf16) {
       // FP32: forward and inverse mode products on the matrix cores
       const size_t lds = std::max(fd_mfma_lds(D.fd_maxm), fd_dense_lds(D.max_dense, sizeof(T)));
       launch_fd_fwd_mfma(D.fd, D.nfd, D.ndense, D.mfma_grid, lds, D.dense, X.densemat, X.fdmat, src, u, D.if_ptr,
-                         D.if_idx, X.scr, tau, add, st);
+                         D.if_idx, X.scr, tau, add, bf16, st);
       if (C.d == 3 && D.nfd_int > 0 && D.max_m2 > 1)
         launch_fd_mid<T>(D.fd, D.nfd_int, D.mid_grid, fd_mid_lds(D.fd_maxm, sizeof(T)), X.fdmat, X.scr, st);
       launch_fd_inv_mfma(D.fd, D.nfd, D.mfma_grid, fd_mfma_lds(D.fd_maxm), X.fdmat, u, D.if_ptr, D.if_idx, X.scr,
-                         tau, add, st);
+                         tau, add, bf16, st);
       return;
     }
   }
@@ -713,7 +729,7 @@ static void read_opts(const igamg_options* o, Options& O) {
     throw SetupError{IGAMG_EINVAL, "invalid options"};
   if (!(O.tau > 0) || !(O.sigma_scale > 0) || O.nu < 1 || O.nu > 8 || (O.mu != 1 && O.mu != 2) ||
       (O.precision != IGAMG_FP64 && O.precision != IGAMG_MIXED) || O.maxit < 1 || O.inner_maxit < 1 ||
-      !(O.inner_tol > 0 && O.inner_tol < 1) || O.fd_mfma < 0 || O.fd_mfma > 2 || O.autotune < 0 || O.autotune > 1 ||
+      !(O.inner_tol > 0 && O.inner_tol < 1) || O.fd_mfma < 0 || O.fd_mfma > 3 || O.autotune < 0 || O.autotune > 1 ||
       O.coarse_factor < 0 || O.coarse_factor > 2 || O.assembly < 0 || O.assembly > 1)
     throw SetupError{IGAMG_EINVAL, "invalid options"};
 }
@@ -766,7 +782,7 @@ void tune_load_locked() {
     const size_t colon = text.find(':', end);
     if (colon == std::string::npos) break;
     const int v = std::atoi(text.c_str() + colon + 1);
-    if (v >= IGAMG_FD_VEC8 && v <= IGAMG_FD_MFMA) g_tune[key] = v;
+    if (v >= IGAMG_FD_VEC8 && v <= IGAMG_FD_FUSED) g_tune[key] = v;
     pos = text.find_first_of(",}", colon);
     if (pos == std::string::npos) break;
   }
@@ -823,8 +839,9 @@ static void tune_level(igamg_ctx& C, int l, hipStream_t st) {
   DevLevel& D = C.dl[l];
   int& v = D.fdv[fp32 ? 1 : 0];
   const Options& O = C.H.opt;
-  if (fp32 && O.fd_mfma == 1) { v = IGAMG_FD_MFMA; return; }
+  if (fp32 && O.fd_mfma == 1) { v = D.max_m2 == 1 ? IGAMG_FD_FUSED : IGAMG_FD_MFMA; return; }
   if (fp32 && O.fd_mfma == 2) { v = IGAMG_FD_VEC8; return; }
+  if (fp32 && O.fd_mfma == 3) { v = IGAMG_FD_MFMA_BF16; return; }
   if (!O.autotune || D.nfd + D.ndense == 0) { v = IGAMG_FD_VEC8; return; }
   const std::string key = tune_key(C, l, fp32);
   {
@@ -835,6 +852,7 @@ static void tune_level(igamg_ctx& C, int l, hipStream_t st) {
   }
   std::vector<int> cand{IGAMG_FD_VEC8, IGAMG_FD_VEC4};
   if (fp32) cand.push_back(IGAMG_FD_MFMA);
+  if (fp32 && D.max_m2 == 1) cand.push_back(IGAMG_FD_FUSED);
   int best = IGAMG_FD_VEC8;
   double best_ms = 1e300;
   for (int c : cand) {

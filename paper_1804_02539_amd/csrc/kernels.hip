@@ -23,7 +23,8 @@ namespace igamg {
 // ---------------------------------------------------------------------------
 // banded stiffness apply: r = f - A u  (RESID) or r = A u   (Sec. 4: A_{l,k}
 // applied patch by patch to accumulated u gives a distributed result).
-// The band holds the upper half of each symmetric patch matrix (layout.hpp):
+// FP64 (k_band_half): the band holds the upper half of each symmetric patch
+// matrix (layout.hpp):
 // a row reads its own stored planes, and each coupling of the lower half from
 // the row it couples to (A[i][i+d] = A[i+d][i], d < 0), at the plane of the
 // negated offset.  Each coefficient is fetched from HBM once and read twice;
@@ -98,9 +99,9 @@ __device__ __forceinline__ TV band_entries_2d(const TB* __restrict__ band, const
 }
 
 template <int D, int P, bool RESID, typename TB, typename TV>
-__global__ __launch_bounds__(256) void k_band(const TB* __restrict__ band, const TV* __restrict__ u,
-                                              const TV* __restrict__ f, TV* __restrict__ r,
-                                              const int* __restrict__ bpatch, const PatchDev* __restrict__ pd) {
+__global__ __launch_bounds__(256) void k_band_half(const TB* __restrict__ band, const TV* __restrict__ u,
+                                                   const TV* __restrict__ f, TV* __restrict__ r,
+                                                   const int* __restrict__ bpatch, const PatchDev* __restrict__ pd) {
   constexpr int NB = 2 * P + 1;
   constexpr int NLINE = band_lines(D, P);                 // stencil lines (o1, o2)
   constexpr int LC = (NLINE - 1) / 2;
@@ -171,21 +172,155 @@ __global__ __launch_bounds__(256) void k_band(const TB* __restrict__ band, const
   }
 }
 
+// The full band (all (2P+1)^D planes per row, the layout of the FP32 copy):
+// each row reads its own planes only.  2D FP64 deals single planes to the
+// waves (plane o to wave o mod 4), everything else whole stencil lines.
+template <int P, int W, typename TB, typename TV>
+__device__ __forceinline__ TV band_planes_2d(const TB* __restrict__ bp, const TV* __restrict__ ub, const int* c0,
+                                             const int* c1) {
+  constexpr int NB = 2 * P + 1;
+  TV s = 0;
+#pragma unroll
+  for (int o = W; o < NB * NB; o += 4) s += (TV)bp[o * ROW_ALIGN] * ub[c1[o / NB] + c0[o % NB]];
+  return s;
+}
+
+template <int D, int P, bool RESID, typename TB, typename TV>
+__global__ __launch_bounds__(256) void k_band_full(const TB* __restrict__ band, const TV* __restrict__ u,
+                                                   const TV* __restrict__ f, TV* __restrict__ r,
+                                                   const int* __restrict__ bpatch, const PatchDev* __restrict__ pd) {
+  constexpr int NB = 2 * P + 1;
+  constexpr int NLINE = (D == 2) ? NB : NB * NB;        // stencil lines (o1, o2)
+  constexpr int NBT = NLINE * NB;
+  __shared__ TV part[3][BAND_STRIP];
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+  const int64_t g = (int64_t)blockIdx.x * BAND_STRIP + lane;
+  const int64_t tile = g / ROW_ALIGN;                    // the same for the whole workgroup
+  const int k = bpatch[tile];
+  if (k < 0) return;                                     // uniform: a padding tile
+  const int64_t off = pd[k].off;
+  const int64_t rows = pd[k].rows;
+  const int64_t rl0 = g - off;
+  const bool valid = rl0 < rows;
+  const int64_t rl = valid ? rl0 : rows - 1;             // padding lanes compute a real row, never store
+  const int n0 = pd[k].n[0], n1 = pd[k].n[1], n2 = pd[k].n[2];
+  const int i0 = (int)(rl % n0);
+  const int64_t t = rl / n0;
+  const int i1 = (int)(t % n1);
+  const int i2 = (int)(t / n1);
+  int c0[NB];
+#pragma unroll
+  for (int o = 0; o < NB; ++o) c0[o] = min(max(i0 + o - P, 0), n0 - 1);
+  const TV* ub = u + off;
+  const TB* bp = band + tile * NBT * ROW_ALIGN + (g - tile * ROW_ALIGN);
+  const int64_t pl = (int64_t)n0 * n1;
+  TV s = 0;
+  if constexpr (D == 2 && sizeof(TB) == 8) {
+    int c1[NB];
+#pragma unroll
+    for (int o = 0; o < NB; ++o) c1[o] = min(max(i1 + o - P, 0), n1 - 1) * n0;
+    switch (w) {
+      case 0: s = band_planes_2d<P, 0, TB, TV>(bp, ub, c0, c1); break;
+      case 1: s = band_planes_2d<P, 1, TB, TV>(bp, ub, c0, c1); break;
+      case 2: s = band_planes_2d<P, 2, TB, TV>(bp, ub, c0, c1); break;
+      default: s = band_planes_2d<P, 3, TB, TV>(bp, ub, c0, c1); break;
+    }
+  } else {
+    for (int L = w; L < NLINE; L += 4) {
+      const int o1 = L % NB, o2 = L / NB;
+      int64_t base = (int64_t)min(max(i1 + o1 - P, 0), n1 - 1) * n0;
+      if constexpr (D == 3) base += (int64_t)min(max(i2 + o2 - P, 0), n2 - 1) * pl;
+      const TV* ur = ub + base;
+      const TB* bq = bp + (int64_t)L * NB * ROW_ALIGN;
+#pragma unroll
+      for (int o0 = 0; o0 < NB; ++o0) s += (TV)bq[o0 * ROW_ALIGN] * ur[c0[o0]];
+    }
+  }
+  if (w > 0) part[w - 1][lane] = s;
+  __syncthreads();
+  if (w == 0 && valid) {
+    s += part[0][lane] + part[1][lane] + part[2][lane];
+    if constexpr (RESID) r[g] = f[g] - s; else r[g] = s;
+  }
+}
+
+// The FP32 full band from the FP64 half band: entry (row, o) of the full
+// band is the stored plane of o at the row, or, for an offset of the lower
+// half, the stored plane of -o at row + d(o) (zero outside the patch).
+template <int D>
+__global__ __launch_bounds__(256) void k_band_half_to_full(float* __restrict__ full, const double* __restrict__ half,
+                                                           const int* __restrict__ bpatch,
+                                                           const PatchDev* __restrict__ pd, int p, int64_t tot) {
+  const int nb = 2 * p + 1, nline = (D == 2) ? nb : nb * nb, nbt = nline * nb, lc = (nline - 1) / 2;
+  const int nbh = band_half_planes(D, p);
+  const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+  for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < tot; e += stride) {
+    const int64_t blk = e / ((int64_t)nbt * ROW_ALIGN);
+    const int o = (int)((e / ROW_ALIGN) % nbt);
+    const int64_t row = blk * ROW_ALIGN + (e % ROW_ALIGN);
+    const int k = bpatch[blk];
+    float v = 0.f;
+    if (k >= 0) {
+      const int o0 = o % nb, L = o / nb;
+      const int pl = band_half_plane(D, p, o0, L);
+      if (pl >= 0) {
+        v = (float)half[((row >> 8) * nbh + pl) * ROW_ALIGN + (row & (ROW_ALIGN - 1))];
+      } else {
+        const PatchDev& P = pd[k];
+        const int o1 = L % nb, o2 = (D == 3) ? L / nb : p;
+        const int64_t d = (int64_t)(o0 - p) + (int64_t)(o1 - p) * P.n[0] + (int64_t)(o2 - p) * P.n[0] * P.n[1];
+        const int64_t rr = row - P.off + d;
+        if (row - P.off < P.rows && rr >= 0 && rr < P.rows) {
+          const int64_t g2 = P.off + rr;
+          const int pn = band_half_plane(D, p, 2 * p - o0, 2 * lc - L);
+          v = (float)half[((g2 >> 8) * nbh + pn) * ROW_ALIGN + (g2 & (ROW_ALIGN - 1))];
+        }
+      }
+    }
+    full[e] = v;
+  }
+}
+
+void launch_band_half_to_full(int d, int p, float* full, const double* half, const int* bpatch, const PatchDev* pd,
+                              int64_t NL, hipStream_t st) {
+  int nbt = 1;
+  for (int c = 0; c < d; ++c) nbt *= 2 * p + 1;
+  const int64_t tot = (int64_t)nbt * NL;
+  if (tot <= 0) return;
+  const dim3 grid((unsigned)std::min<int64_t>((tot + 255) / 256, (int64_t)1 << 20));
+  if (d == 2)
+    hipLaunchKernelGGL(k_band_half_to_full<2>, grid, dim3(256), 0, st, full, half, bpatch, pd, p, tot);
+  else
+    hipLaunchKernelGGL(k_band_half_to_full<3>, grid, dim3(256), 0, st, full, half, bpatch, pd, p, tot);
+}
+
 template <int D, int P, typename T>
 static hipError_t launch_band_dp(const T* band, const T* u, const T* f, T* r, const int* bpatch, const PatchDev* pd,
                                  int64_t NL, bool resid, hipStream_t st, hipEvent_t ev0, hipEvent_t ev1) {
   dim3 grid((unsigned)(NL / BAND_STRIP)), block(256);
-  const void* fn = resid ? reinterpret_cast<const void*>(&k_band<D, P, true, T, T>)
-                         : reinterpret_cast<const void*>(&k_band<D, P, false, T, T>);
+  // FP64: the symmetric half band; FP32: the full band (faster at FP32,
+  // where the mirrored reads of the half band cost more than they save)
+  constexpr bool HALF = sizeof(T) == 8;
+  const void* fn = HALF ? (resid ? reinterpret_cast<const void*>(&k_band_half<D, P, true, T, T>)
+                                 : reinterpret_cast<const void*>(&k_band_half<D, P, false, T, T>))
+                        : (resid ? reinterpret_cast<const void*>(&k_band_full<D, P, true, T, T>)
+                                 : reinterpret_cast<const void*>(&k_band_full<D, P, false, T, T>));
   if (ev0) {
     // timed launch: the events take the dispatch's own start and end stamps
     void* args[] = {(void*)&band, (void*)&u, (void*)&f, (void*)&r, (void*)&bpatch, (void*)&pd};
     return hipExtLaunchKernel(fn, grid, block, args, 0, st, ev0, ev1, 0);
   }
-  if (resid)
-    hipLaunchKernelGGL((k_band<D, P, true, T, T>), grid, block, 0, st, band, u, f, r, bpatch, pd);
-  else
-    hipLaunchKernelGGL((k_band<D, P, false, T, T>), grid, block, 0, st, band, u, f, r, bpatch, pd);
+  if (resid) {
+    if constexpr (HALF)
+      hipLaunchKernelGGL((k_band_half<D, P, true, T, T>), grid, block, 0, st, band, u, f, r, bpatch, pd);
+    else
+      hipLaunchKernelGGL((k_band_full<D, P, true, T, T>), grid, block, 0, st, band, u, f, r, bpatch, pd);
+  } else {
+    if constexpr (HALF)
+      hipLaunchKernelGGL((k_band_half<D, P, false, T, T>), grid, block, 0, st, band, u, f, r, bpatch, pd);
+    else
+      hipLaunchKernelGGL((k_band_full<D, P, false, T, T>), grid, block, 0, st, band, u, f, r, bpatch, pd);
+  }
   return hipSuccess;
 }
 
@@ -430,6 +565,15 @@ static_assert(4 * FDM_TILES * 16 >= MAX_FD, "row tiles per wave");
 
 __device__ __forceinline__ int fdm_up(int x, int q) { return (x + q - 1) / q * q; }
 
+typedef short fd_s4 __attribute__((ext_vector_type(4)));
+
+// float to bfloat16, rounded to nearest even (the operands are finite)
+__device__ __forceinline__ short fd_bf16(float x) {
+  unsigned int v = __float_as_uint(x);
+  v += 0x7fffu + ((v >> 16) & 1u);
+  return (short)(v >> 16);
+}
+
 __device__ __forceinline__ void fdm_chunk(const FDItem& it, int& z, int& c0, int& nc) {
   const int nch = (it.m[1] + FDM_CW - 1) / FDM_CW;
   z = blockIdx.x / nch;
@@ -439,21 +583,44 @@ __device__ __forceinline__ void fdm_chunk(const FDItem& it, int& z, int& c0, int
 
 // acc[t] = (A B) rows 16 (w + 4 t) .. of the (mp x kp) A (column-major, leading
 // dimension mp) times the (kp x 16) B (row-major), for the tiles of wave w
+// With BF16 the operands are rounded to bfloat16 and kp must be a multiple
+// of 16 (v_mfma_f32_16x16x16bf16_1k: lane l holds k = 4 (l / 16) .. + 3).
+template <bool BF16>
 __device__ __forceinline__ void fdm_product(const float* A, int mp, const float* B, int kp, fd_f4* acc) {
   const int l = threadIdx.x & 63, w = threadIdx.x >> 6;
   const int li = l & 15, lk = l >> 4;
 #pragma unroll
   for (int t = 0; t < FDM_TILES; ++t) acc[t] = fd_f4{0.f, 0.f, 0.f, 0.f};
-  for (int ks = 0; ks < kp; ks += 4) {
-    const float b = B[(ks + lk) * FDM_N + li];
+  if constexpr (BF16) {
+    for (int ks = 0; ks < kp; ks += 16) {
+      const int k = ks + 4 * lk;
+      fd_s4 b;
 #pragma unroll
-    for (int t = 0; t < FDM_TILES; ++t) {
-      const int mt = w + 4 * t;
-      if (mt * 16 < mp) acc[t] = __builtin_amdgcn_mfma_f32_16x16x4f32(A[(mt * 16 + li) + mp * (ks + lk)], b, acc[t], 0, 0, 0);
+      for (int q = 0; q < 4; ++q) b[q] = fd_bf16(B[(k + q) * FDM_N + li]);
+#pragma unroll
+      for (int t = 0; t < FDM_TILES; ++t) {
+        const int mt = w + 4 * t;
+        if (mt * 16 < mp) {
+          fd_s4 a;
+#pragma unroll
+          for (int q = 0; q < 4; ++q) a[q] = fd_bf16(A[(mt * 16 + li) + mp * (k + q)]);
+          acc[t] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(a, b, acc[t], 0, 0, 0);
+        }
+      }
+    }
+  } else {
+    for (int ks = 0; ks < kp; ks += 4) {
+      const float b = B[(ks + lk) * FDM_N + li];
+#pragma unroll
+      for (int t = 0; t < FDM_TILES; ++t) {
+        const int mt = w + 4 * t;
+        if (mt * 16 < mp) acc[t] = __builtin_amdgcn_mfma_f32_16x16x4f32(A[(mt * 16 + li) + mp * (ks + lk)], b, acc[t], 0, 0, 0);
+      }
     }
   }
 }
 
+template <bool BF16>
 __global__ __launch_bounds__(256) void k_fd_fwd_mfma(const FDItem* __restrict__ items, int nitems,
                                                      const DensePiece* __restrict__ dense,
                                                      const float* __restrict__ densemat, const float* __restrict__ mat,
@@ -473,7 +640,8 @@ __global__ __launch_bounds__(256) void k_fd_fwd_mfma(const FDItem* __restrict__ 
   int z, c0, nc;
   fdm_chunk(it, z, c0, nc);
   if (z >= it.m[2]) return;
-  const int m0p = fdm_up(m0, 16), m1k = fdm_up(m1, 4), m0k = fdm_up(m0, 4);
+  const int kq = BF16 ? 16 : 4;
+  const int m0p = fdm_up(m0, 16), m1k = fdm_up(m1, kq), m0k = fdm_up(m0, kq);
   float* X = lds;                                   // X[j + m0p b]; later U0 as A[a + m0p k] = U0[k, a]
   float* C = lds + max(m0p * m1k, m0p * m0k);       // U1[k, c0 + c] as C[k 16 + c]; later V[i 16 + c]
   const int64_t zoff = (int64_t)z * it.stride[2];
@@ -498,7 +666,7 @@ __global__ __launch_bounds__(256) void k_fd_fwd_mfma(const FDItem* __restrict__ 
   }
   __syncthreads();
   fd_f4 acc[FDM_TILES];
-  fdm_product(X, m0p, C, m1k, acc);                  // V = X U1[:, chunk]
+  fdm_product<BF16>(X, m0p, C, m1k, acc);            // V = X U1[:, chunk]
   __syncthreads();
   const int l = threadIdx.x & 63, w = threadIdx.x >> 6;
   const int li = l & 15, lr = 4 * (l >> 4);
@@ -513,7 +681,7 @@ __global__ __launch_bounds__(256) void k_fd_fwd_mfma(const FDItem* __restrict__ 
     X[t] = (a < m0 && k < m0) ? U0[(int64_t)k * m0 + a] : 0.f;
   }
   __syncthreads();
-  fdm_product(X, m0p, C, m0k, acc);                  // Y = U0^T V
+  fdm_product<BF16>(X, m0p, C, m0k, acc);            // Y = U0^T V
   const float* mu0 = mat + it.mu[0];
   const float* mu1 = mat + it.mu[1];
   const float mu2 = mat[it.mu[2]];
@@ -535,6 +703,7 @@ __global__ __launch_bounds__(256) void k_fd_fwd_mfma(const FDItem* __restrict__ 
   }
 }
 
+template <bool BF16>
 __global__ __launch_bounds__(256) void k_fd_inv_mfma(const FDItem* __restrict__ items, const float* __restrict__ mat,
                                                      float* __restrict__ u, const int64_t* __restrict__ if_ptr,
                                                      const int64_t* __restrict__ if_idx, const float* __restrict__ scr,
@@ -546,7 +715,8 @@ __global__ __launch_bounds__(256) void k_fd_inv_mfma(const FDItem* __restrict__ 
   int z, c0, nc;
   fdm_chunk(it, z, c0, nc);
   if (z >= it.m[2]) return;
-  const int m0p = fdm_up(m0, 16), m1k = fdm_up(m1, 4), m0k = fdm_up(m0, 4);
+  const int kq = BF16 ? 16 : 4;
+  const int m0p = fdm_up(m0, 16), m1k = fdm_up(m1, kq), m0k = fdm_up(m0, kq);
   float* X = lds;                                   // Y[j + m0p b]; later U0 as A[a + m0p k] = U0[a, k]
   float* C = lds + max(m0p * m1k, m0p * m0k);       // U1[c0 + c, k] as C[k 16 + c]; later V[i 16 + c]
   const float* S = scr + it.scr + (int64_t)z * m0 * m1;
@@ -562,7 +732,7 @@ __global__ __launch_bounds__(256) void k_fd_inv_mfma(const FDItem* __restrict__ 
   }
   __syncthreads();
   fd_f4 acc[FDM_TILES];
-  fdm_product(X, m0p, C, m1k, acc);                  // V = Y U1^T[:, chunk]
+  fdm_product<BF16>(X, m0p, C, m1k, acc);            // V = Y U1^T[:, chunk]
   __syncthreads();
   const int l = threadIdx.x & 63, w = threadIdx.x >> 6;
   const int li = l & 15, lr = 4 * (l >> 4);
@@ -577,7 +747,7 @@ __global__ __launch_bounds__(256) void k_fd_inv_mfma(const FDItem* __restrict__ 
     X[t] = (a < m0 && k < m0) ? U0T[(int64_t)k * m0 + a] : 0.f;
   }
   __syncthreads();
-  fdm_product(X, m0p, C, m0k, acc);                  // Z = U0 V
+  fdm_product<BF16>(X, m0p, C, m0k, acc);            // Z = U0 V
   const int64_t zoff = (int64_t)z * it.stride[2];
 #pragma unroll
   for (int t = 0; t < FDM_TILES; ++t) {
@@ -600,6 +770,175 @@ __global__ __launch_bounds__(256) void k_fd_inv_mfma(const FDItem* __restrict__ 
       }
     }
   }
+}
+
+// ---------------------------------------------------------------------------
+// One launch per smoothing for 2D tensors (2D patch interiors, 3D faces): a
+// workgroup owns one item and keeps it in LDS through all four mode products,
+// D^{-1} and the damped update (Sec. 3, the subspace corrected mass smoother
+// in fast-diagonalization form):
+//   T = X U1,  Y = U0^T T,  Y /= D,  T = Y U1^T,  Z = U0 T,  u += tau Z
+// Every product runs on the matrix cores over 16x16 output tiles: FP32
+// operands with v_mfma_f32_16x16x4f32, or operands rounded to bfloat16 (FP32
+// accumulation) with v_mfma_f32_16x16x16bf16_1k.  Matrices sit in LDS
+// row-major, zero-padded to multiples of 16, with an odd leading dimension
+// p + 1 so that the 16 rows a wave reads at once fall into distinct banks.
+// The dense pieces (edges, vertices) take the workgroups after the items.
+// ---------------------------------------------------------------------------
+// C (Mp x Np) = A (Mp x Kp) B (Kp x Np), all in LDS; A(i, k) = A[i lda + k]
+// or, with TA, A[k lda + i]; B(k, j) = B[k ldb + j] or, with TB, B[j ldb + k].
+// Tile t of the (Mp/16) x (Np/16) output goes to wave t mod 4; each wave
+// runs two tiles side by side so their accumulation chains interleave.
+template <bool TA, bool TB, bool BF16>
+__device__ __forceinline__ void fd2_mm(const float* A, int lda, const float* B, int ldb, float* C, int ldc, int Mp,
+                                       int Np, int Kp) {
+  const int l = threadIdx.x & 63, w = threadIdx.x >> 6;
+  const int li = l & 15, lk = l >> 4;
+  const int tn = Np / 16, nt = (Mp / 16) * tn;
+  auto a_at = [&](int i, int k) { return TA ? A[k * lda + i] : A[i * lda + k]; };
+  auto b_at = [&](int k, int j) { return TB ? B[j * ldb + k] : B[k * ldb + j]; };
+  for (int t0 = w; t0 < nt; t0 += 8) {
+    const int t1 = t0 + 4;
+    const bool two = t1 < nt;
+    const int r0 = (t0 / tn) * 16 + li, c0 = (t0 % tn) * 16 + li;
+    const int r1 = two ? (t1 / tn) * 16 + li : r0, c1 = two ? (t1 % tn) * 16 + li : c0;
+    fd_f4 acc0 = {0.f, 0.f, 0.f, 0.f}, acc1 = {0.f, 0.f, 0.f, 0.f};
+    if constexpr (BF16) {
+      for (int ks = 0; ks < Kp; ks += 16) {
+        const int k = ks + 4 * lk;
+        fd_s4 a0, b0, a1, b1;
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+          a0[q] = fd_bf16(a_at(r0, k + q));
+          b0[q] = fd_bf16(b_at(k + q, c0));
+          a1[q] = fd_bf16(a_at(r1, k + q));
+          b1[q] = fd_bf16(b_at(k + q, c1));
+        }
+        acc0 = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(a0, b0, acc0, 0, 0, 0);
+        if (two) acc1 = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(a1, b1, acc1, 0, 0, 0);
+      }
+    } else {
+      for (int ks = 0; ks < Kp; ks += 4) {
+        const int k = ks + lk;
+        acc0 = __builtin_amdgcn_mfma_f32_16x16x4f32(a_at(r0, k), b_at(k, c0), acc0, 0, 0, 0);
+        if (two) acc1 = __builtin_amdgcn_mfma_f32_16x16x4f32(a_at(r1, k), b_at(k, c1), acc1, 0, 0, 0);
+      }
+    }
+    // lane l holds rows 4 (l / 16) + q of the tile, column l % 16
+    const int rr0 = (t0 / tn) * 16 + 4 * lk, rr1 = (t1 / tn) * 16 + 4 * lk;
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+      C[(rr0 + q) * ldc + c0] = acc0[q];
+      if (two) C[(rr1 + q) * ldc + c1] = acc1[q];
+    }
+  }
+}
+
+template <bool BF16>
+__global__ __launch_bounds__(256) void k_fd2_fused(const FDItem* __restrict__ items, int nitems,
+                                                   const DensePiece* __restrict__ dense,
+                                                   const float* __restrict__ densemat, const float* __restrict__ mat,
+                                                   const float* __restrict__ src, float* __restrict__ u,
+                                                   const int64_t* __restrict__ if_ptr,
+                                                   const int64_t* __restrict__ if_idx, float tau, int add) {
+  DYN_LDS(float, lds);
+  const int y = blockIdx.x;
+  if (y >= nitems) {
+    fd_dense_piece(dense[y - nitems], densemat, src, u, if_ptr, if_idx, tau, add, lds);
+    return;
+  }
+  const FDItem it = items[y];
+  const int m0 = it.m[0], m1 = it.m[1];
+  const int p0 = (m0 + 15) / 16 * 16, p1 = (m1 + 15) / 16 * 16;
+  const int l0 = p0 + 1, l1 = p1 + 1;          // leading dimensions
+  float* X = lds;                              // p0 x p1, ld l1: X, then Y, then Z
+  float* T = X + p0 * l1;                      // p0 x p1, ld l1
+  float* U0 = T + p0 * l1;                     // p0 x p0, ld l0: U0(i, a)
+  float* U1 = U0 + p0 * l0;                    // p1 x p1, ld l1: U1(j, b)
+  const float* g0 = mat + it.U[0];
+  const float* g1 = mat + it.U[1];
+  for (int t = threadIdx.x; t < p0 * p1; t += blockDim.x) {
+    const int i = t / p1, j = t % p1;
+    float v = 0.f;
+    if (i < m0 && j < m1) {
+      if (it.src_if) {
+        const int64_t e = it.base + i + (int64_t)m0 * j;   // face tensors are stored i fastest
+        for (int64_t c = if_ptr[e]; c < if_ptr[e + 1]; ++c) v += src[if_idx[c]];
+      } else {
+        v = src[it.base + i * it.stride[0] + j * it.stride[1]];
+      }
+    }
+    X[i * l1 + j] = v;
+  }
+  for (int t = threadIdx.x; t < p0 * p0; t += blockDim.x) {
+    const int i = t / p0, a = t % p0;
+    U0[i * l0 + a] = (i < m0 && a < m0) ? g0[(int64_t)i * m0 + a] : 0.f;
+  }
+  for (int t = threadIdx.x; t < p1 * p1; t += blockDim.x) {
+    const int j = t / p1, b = t % p1;
+    U1[j * l1 + b] = (j < m1 && b < m1) ? g1[(int64_t)j * m1 + b] : 0.f;
+  }
+  __syncthreads();
+  fd2_mm<false, false, BF16>(X, l1, U1, l1, T, l1, p0, p1, p1);    // T = X U1
+  __syncthreads();
+  fd2_mm<true, false, BF16>(U0, l0, T, l1, X, l1, p0, p1, p0);     // Y = U0^T T
+  __syncthreads();
+  const float* mu0 = mat + it.mu[0];
+  const float* mu1 = mat + it.mu[1];
+  const float mu2 = mat[it.mu[2]];
+  for (int t = threadIdx.x; t < p0 * p1; t += blockDim.x) {
+    const int a = t / p1, b = t % p1;
+    X[a * l1 + b] = (a < m0 && b < m1) ? X[a * l1 + b] / ((float)it.pref * (mu0[a] + mu1[b] + mu2 + (float)it.extra))
+                                       : 0.f;
+  }
+  __syncthreads();
+  fd2_mm<false, true, BF16>(X, l1, U1, l1, T, l1, p0, p1, p1);     // T = Y U1^T
+  __syncthreads();
+  fd2_mm<false, false, BF16>(U0, l0, T, l1, X, l1, p0, p1, p0);    // Z = U0 T
+  __syncthreads();
+  for (int t = threadIdx.x; t < m0 * m1; t += blockDim.x) {
+    const int i = t % m0, j = t / m0;
+    const float v = tau * X[i * l1 + j];
+    if (it.src_if) {
+      const int64_t e = it.base + i + (int64_t)m0 * j;
+      for (int64_t c = if_ptr[e]; c < if_ptr[e + 1]; ++c) {
+        const int64_t x = if_idx[c];
+        u[x] = add ? u[x] + v : v;
+      }
+    } else {
+      const int64_t x = it.base + i * it.stride[0] + j * it.stride[1];
+      u[x] = add ? u[x] + v : v;
+    }
+  }
+}
+
+size_t fd2_fused_lds(int maxm, int max_dense) {
+  const size_t p = (size_t)(maxm + 15) / 16 * 16;
+  const size_t items = (3 * p * (p + 1) + p * (p + 1)) * sizeof(float);
+  const size_t pieces = ((size_t)max_dense * max_dense + max_dense) * sizeof(float) + 64;
+  return std::max(items, pieces);
+}
+
+void launch_fd2_fused(const FDItem* items, int nitems, int ndense, size_t lds, const DensePiece* dense,
+                      const float* densemat, const float* mat, const float* src, float* u, const int64_t* if_ptr,
+                      const int64_t* if_idx, double tau, bool add, bool bf16, hipStream_t st) {
+  const int n = nitems + ndense;
+  if (n <= 0) return;
+  // up to 146 KB of LDS per workgroup (of the 160 KB a CU has)
+  static const bool attr = [] {
+    (void)hipFuncSetAttribute(reinterpret_cast<const void*>(&k_fd2_fused<false>),
+                              hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024);
+    (void)hipFuncSetAttribute(reinterpret_cast<const void*>(&k_fd2_fused<true>),
+                              hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024);
+    return true;
+  }();
+  (void)attr;
+  if (bf16)
+    hipLaunchKernelGGL(k_fd2_fused<true>, dim3(n), dim3(256), lds, st, items, nitems, dense, densemat, mat, src, u,
+                       if_ptr, if_idx, (float)tau, (int)add);
+  else
+    hipLaunchKernelGGL(k_fd2_fused<false>, dim3(n), dim3(256), lds, st, items, nitems, dense, densemat, mat, src, u,
+                       if_ptr, if_idx, (float)tau, (int)add);
 }
 
 // Middle direction of 3D patch interiors, in place on the compact scratch
@@ -661,6 +1000,7 @@ __global__ __launch_bounds__(256) void k_fd_mid(const FDItem* __restrict__ items
 }
 
 size_t fd_mfma_lds(int maxm) {
+  // K padded to 16 (enough for both precisions)
   const size_t mp = (size_t)(maxm + 15) / 16 * 16;
   return (mp * mp + (size_t)FDM_N * mp) * sizeof(float) + 64;
 }
@@ -673,19 +1013,27 @@ int fd_mfma_grid(const FDItem* items, int nitems) {
 
 void launch_fd_fwd_mfma(const FDItem* items, int nitems, int ndense, int gridx, size_t lds, const DensePiece* dense,
                         const float* densemat, const float* mat, const float* src, float* u, const int64_t* if_ptr,
-                        const int64_t* if_idx, float* scr, double tau, bool add, hipStream_t st) {
+                        const int64_t* if_idx, float* scr, double tau, bool add, bool bf16, hipStream_t st) {
   const int ny = nitems + ndense;
   if (ny <= 0) return;
-  hipLaunchKernelGGL(k_fd_fwd_mfma, dim3(gridx, ny), dim3(256), lds, st, items, nitems, dense, densemat, mat, src, u,
-                     if_ptr, if_idx, scr, (float)tau, (int)add);
+  if (bf16)
+    hipLaunchKernelGGL(k_fd_fwd_mfma<true>, dim3(gridx, ny), dim3(256), lds, st, items, nitems, dense, densemat, mat,
+                       src, u, if_ptr, if_idx, scr, (float)tau, (int)add);
+  else
+    hipLaunchKernelGGL(k_fd_fwd_mfma<false>, dim3(gridx, ny), dim3(256), lds, st, items, nitems, dense, densemat, mat,
+                       src, u, if_ptr, if_idx, scr, (float)tau, (int)add);
 }
 
 void launch_fd_inv_mfma(const FDItem* items, int nitems, int gridx, size_t lds, const float* mat, float* u,
                         const int64_t* if_ptr, const int64_t* if_idx, const float* scr, double tau, bool add,
-                        hipStream_t st) {
+                        bool bf16, hipStream_t st) {
   if (nitems <= 0) return;
-  hipLaunchKernelGGL(k_fd_inv_mfma, dim3(gridx, nitems), dim3(256), lds, st, items, mat, u, if_ptr, if_idx, scr,
-                     (float)tau, (int)add);
+  if (bf16)
+    hipLaunchKernelGGL(k_fd_inv_mfma<true>, dim3(gridx, nitems), dim3(256), lds, st, items, mat, u, if_ptr, if_idx,
+                       scr, (float)tau, (int)add);
+  else
+    hipLaunchKernelGGL(k_fd_inv_mfma<false>, dim3(gridx, nitems), dim3(256), lds, st, items, mat, u, if_ptr, if_idx,
+                       scr, (float)tau, (int)add);
 }
 
 // A[j + i n] = A[i + j n] for i > j: the column-major lower triangle copied

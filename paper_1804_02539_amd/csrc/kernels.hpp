@@ -32,15 +32,22 @@ template <typename T>
 void launch_fd_fwd(const FDItem* items, int nitems, int ndense, int gridx, size_t lds, const DensePiece* dense,
                    const T* densemat, const T* mat, const T* src, T* u, const int64_t* if_ptr, const int64_t* if_idx,
                    T* scr, double tau, bool add, int rb, hipStream_t st);
-// FP32 forward/inverse products on the matrix cores (16-column chunks)
+// FP32 forward/inverse products on the matrix cores (16-column chunks), with
+// FP32 operands or operands rounded to bfloat16 (FP32 accumulation)
 size_t fd_mfma_lds(int maxm);
+// One launch per smoothing for 2D tensors (2D interiors, 3D faces) and the
+// dense pieces: items[0 .. nitems) must all have m[2] == 1, every m <= MAX_FD.
+size_t fd2_fused_lds(int maxm, int max_dense);
+void launch_fd2_fused(const FDItem* items, int nitems, int ndense, size_t lds, const DensePiece* dense,
+                      const float* densemat, const float* mat, const float* src, float* u, const int64_t* if_ptr,
+                      const int64_t* if_idx, double tau, bool add, bool bf16, hipStream_t st);
 int fd_mfma_grid(const FDItem* items, int nitems);
 void launch_fd_fwd_mfma(const FDItem* items, int nitems, int ndense, int gridx, size_t lds, const DensePiece* dense,
                         const float* densemat, const float* mat, const float* src, float* u, const int64_t* if_ptr,
-                        const int64_t* if_idx, float* scr, double tau, bool add, hipStream_t st);
+                        const int64_t* if_idx, float* scr, double tau, bool add, bool bf16, hipStream_t st);
 void launch_fd_inv_mfma(const FDItem* items, int nitems, int gridx, size_t lds, const float* mat, float* u,
                         const int64_t* if_ptr, const int64_t* if_idx, const float* scr, double tau, bool add,
-                        hipStream_t st);
+                        bool bf16, hipStream_t st);
 template <typename T>
 void launch_fd_mid(const FDItem* items, int nitems, int gridx, size_t lds, const T* mat, T* scr, hipStream_t st);
 template <typename T>
@@ -84,6 +91,9 @@ void launch_to_f32(float* y, const double* x, int64_t n, hipStream_t st);
 // device assembly (assemble.hip): doubles of one element slab's metric (Gs),
 // direction-0 (T1) and direction-1 (T2) intermediates of a patch
 void asm_slab_sizes(int d, const AsmPatch& P, size_t out[3]);
+// FP32 full band (all (2p+1)^d planes per tile) from the FP64 symmetric half band
+void launch_band_half_to_full(int d, int p, float* full, const double* half, const int* bpatch, const PatchDev* pd,
+                              int64_t NL, hipStream_t st);
 // out[e] = sum of the half-band entries (row[c], plane[c]), c in [ptr[e], ptr[e+1])
 void launch_band_gather(const double* band, int nbh, const int64_t* ptr, const int64_t* row, const int* plane,
                         int64_t ne, double* out, hipStream_t st);

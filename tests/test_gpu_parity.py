@@ -133,22 +133,25 @@ def _nrel(a, b):
 # operator and preconditioner agree up to rounding.  For most problems the
 # library's and the oracle's iterates agree to 1e-10 relative, the bar.  Where
 # the PCG amplifies rounding more than that, the bar comes from the oracle
-# itself: every output of its cycle is perturbed elementwise by a relative
-# amount as large as the measured difference between the library's cycle and
-# the oracle's on a random vector (at least 2^-52); ten times the largest
-# move of the oracle's iterate (and of its residual) over three seeds is then
-# what two correct FP64 runs of the same PCG may differ by.
+# itself.  The library's cycle and coarse solve are compared with the
+# oracle's on random vectors (relative max-norm differences e_cyc and e_crs,
+# at least 2^-52).  The oracle's PCG is then rerun with every output of its
+# coarse solve and of its cycle perturbed elementwise by relative amounts of
+# those sizes (three seeds); ten times the largest move of its iterate (and of
+# its residual) is what two correct FP64 runs of the same PCG may differ by.
 FIXED_K_TOL = 1e-10
 
 
-def _perturbed_pcg(H, f, k, seed, eps):
+def _perturbed_pcg(H, f, k, seed, e_cyc, e_crs):
     rng = np.random.default_rng(seed)
-    cycle = H.vcycle
-    H.vcycle = lambda r: (lambda z: z * (1.0 + eps * rng.uniform(-1.0, 1.0, z.shape)))(cycle(r))
+    cycle, coarse = H.vcycle, H.coarse_solve
+    H.coarse_solve = lambda r: (lambda z: z * (1.0 + e_crs * rng.uniform(-1.0, 1.0, z.shape)))(coarse(r))
+    H.vcycle = lambda r: (lambda z: z * (1.0 + e_cyc * rng.uniform(-1.0, 1.0, z.shape)))(cycle(r))
     try:
         u, _, hist = H.pcg(f, tol=0.0, maxit=k)
     finally:
         del H.vcycle
+        del H.coarse_solve
     return u, hist[-1]
 
 
@@ -156,14 +159,22 @@ def _bar(H, S, f, k, u_k, res_k, err):
     """(bar for u, bar for the final relative residual, sensitivity or None):
     the fixed bars, or the measured rounding sensitivity of the oracle's PCG
     after k iterations (computed only when err exceeds FIXED_K_TOL)."""
+    from paper_1804_02539_amd import igamg
     if err < FIXED_K_TOL:
         return FIXED_K_TOL, 1e-6 * res_k, None
-    r = np.random.default_rng(11).standard_normal(H.finest.N)
+    rng = np.random.default_rng(11)
+    r = rng.standard_normal(H.finest.N)
     zc = H.vcycle(r)
-    eps = max(2.0 ** -52, float(np.abs(S.vcycle(r).cpu().numpy() - zc).max() / np.abs(zc).max()))
-    runs = [_perturbed_pcg(H, f, k, s, eps) for s in range(3)]
+    e_cyc = max(2.0 ** -52, float(np.abs(S.vcycle(r).cpu().numpy() - zc).max() / np.abs(zc).max()))
+    r0 = rng.standard_normal(H.levels[0].N)
+    z0 = H.coarse_solve(r0)
+    e_crs = max(2.0 ** -52, float(np.abs(S.operator(igamg.OP_COARSE, 0, r0).cpu().numpy() - z0).max()
+                                  / np.abs(z0).max()))
+    runs = [_perturbed_pcg(H, f, k, s, e_cyc, e_crs) for s in range(3)]
     sens = max(_nrel(u, u_k) for u, _ in runs)
     sens_r = max(abs(rr - res_k) for _, rr in runs)
+    _say(f"  measured differences: cycle {e_cyc:.1e}, coarse solve {e_crs:.1e}; oracle PCG sensitivity "
+         f"{sens:.1e} (u), {sens_r:.1e} (residual)")
     return max(FIXED_K_TOL, 10.0 * sens), max(1e-6 * res_k, 10.0 * sens_r), sens
 
 
@@ -278,7 +289,8 @@ def test_fp32_cycle_close_to_oracle(torch_cuda, name, fd_mfma):
 
 @pytest.mark.parametrize("name,fd_mfma", [("square2x2_p2", 0), ("square4x4_p4_l4", 0), ("cube2x2x2_p3_l4", 0),
                                           ("fichera7_p2_l3", 0), ("square4x4_p4_l4", 1), ("fichera7_p2_l3", 1),
-                                          ("cube2x2x2_p3_l4", 2)])
+                                          ("cube2x2x2_p3_l4", 2), ("square4x4_p4_l4", 3), ("cube2x2x2_p3_l4", 3),
+                                          ("fichera7_p2_l3", 3)])
 def test_mixed_solve_reaches_fp64_tolerance(torch_cuda, name, fd_mfma):
     from oracle.multigrid import load_vector
     from paper_1804_02539_amd import igamg
@@ -333,3 +345,23 @@ def test_smoother_readings_match_oracle(torch_cuda, reading, name):
         assert rel(y, H.levels[l].smoother.apply(x)) < 1e-11, l
     r = rng.standard_normal(H.finest.N)
     assert rel(S.vcycle(r).cpu().numpy(), H.vcycle(r)) < 1e-10
+
+
+@pytest.mark.parametrize("name", ["square4x4_p4_l4", "square2x2_p2", "cube2x2x2_p3_l4", "fichera7_p2_l3",
+                                  "single_patch_p5_l3"])
+def test_bf16_smoother_cycle_error_stated(torch_cuda, name):
+    """The FP32 cycle with the smoother's mode products in bfloat16 (FP32
+    accumulation) against the oracle's FP64 cycle: the error is stated; it
+    is bfloat16 rounding (2^-9 per operand), nothing larger."""
+    from paper_1804_02539_amd import igamg
+    H = oracle_for(name)
+    S = gpu_for(name, precision=igamg.MIXED, fd_mfma=3)
+    r = np.random.default_rng(7).standard_normal(H.finest.N)
+    z = S.operator(igamg.OP_CYCLE_FP32, -1, r).cpu().numpy()
+    err = rel(z, H.vcycle(r))
+    S32 = gpu_for(name, precision=igamg.MIXED, fd_mfma=1)
+    e32 = rel(S32.operator(igamg.OP_CYCLE_FP32, -1, r).cpu().numpy(), H.vcycle(r))
+    _say(f"bf16 cycle {name}: rel err {err:.2e} against the FP64 oracle (FP32 matrix cores {e32:.2e}); "
+         f"finest variant {igamg.FD_NAMES[S.tuning(-1, True)]}")
+    assert S.tuning(-1, True) == igamg.FD_MFMA_BF16
+    assert err < 3e-2
