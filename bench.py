@@ -103,6 +103,53 @@ def _cpu_model():
     return "unknown"
 
 
+def traffic_summary(workload, fetch_csv, write_csv, fetch_cmd, write_cmd):
+    """HBM bytes per launch of the finest-level banded apply from two
+    rocprofv3 --pmc runs of the same bench command with --copy-calibration
+    (FETCH_SIZE, then WRITE_SIZE; csv output).  Each counter is scaled by what
+    it reads for the 256 MiB device copy of the calibration; the finest level
+    is the band launch with the largest grid.  Written beside the kernel
+    source hash, so that bench.py reports it only for the kernels measured."""
+    import csv
+    copy_bytes = 256 << 20
+
+    def read(path, counter):
+        rows = []
+        with open(path) as fh:
+            for r in csv.DictReader(fh):
+                if r.get("Counter_Name") == counter:
+                    rows.append((r["Kernel_Name"], int(r["Grid_Size"]), float(r["Counter_Value"])))
+        copies = [v for n, g, v in rows if "copyBuffer" in n]
+        if not copies:
+            raise SystemExit(f"{path}: no copy-calibration dispatch")
+        out = {"copy_kib": max(copies)}
+        for prec, key, typ in (("fp64", "k_band_half", "double"), ("mixed", "k_band_full", "float")):
+            band = [(g, v) for n, g, v in rows if key in n and typ in n]
+            if not band:
+                continue
+            gmax = max(g for g, _ in band)
+            vals = [v for g, v in band if g == gmax]
+            out[prec] = (sum(vals) / len(vals), len(vals))
+        return out
+
+    fe, wr = read(fetch_csv, "FETCH_SIZE"), read(write_csv, "WRITE_SIZE")
+    fs, ws = copy_bytes / (fe["copy_kib"] * 1024.0), copy_bytes / (wr["copy_kib"] * 1024.0)
+    res = {"kernel_sha": kernel_sha(),
+           "kernel_sha_covers": "the banded kernels' section of kernels.hip and layout.hpp",
+           "workload": workload, "copy_bytes": copy_bytes,
+           "fetch_copy_kib": fe["copy_kib"], "fetch_scale": fs, "fetch_command": fetch_cmd,
+           "write_copy_kib": wr["copy_kib"], "write_scale": ws, "write_command": write_cmd}
+    for prec in ("fp64", "mixed"):
+        if prec in fe and prec in wr:
+            res[prec] = {"fetch_kib_per_launch": fe[prec][0], "fetch_launches": fe[prec][1],
+                         "write_kib_per_launch": wr[prec][0], "write_launches": wr[prec][1],
+                         "hbm_bytes_per_launch": 1024.0 * (fe[prec][0] * fs + wr[prec][0] * ws)}
+    path = os.path.join(ROOT, "profiles", f"band_apply_{workload}_traffic.json")
+    with open(path, "w") as fh:
+        json.dump(res, fh, indent=1)
+    return res
+
+
 def cpu_baseline(prob, rhs, min_seconds=10.0, max_solves=50):
     """The oracle's PCG solve of the same workload on the host (setup
     excluded), repeated until about min_seconds of solving have elapsed."""
@@ -407,9 +454,18 @@ def main():
     ap.add_argument("--copy-calibration", action="store_true",
                     help="first fill and copy a 256 MiB buffer: dispatches of known size against "
                          "which hardware byte counters are scaled")
+    ap.add_argument("--traffic-summary", nargs=2, metavar=("FETCH_CSV", "WRITE_CSV"),
+                    help="instead of the benchmark line, write profiles/band_apply_<workload>_traffic.json from the "
+                         "counter_collection.csv files of two rocprofv3 --pmc runs (FETCH_SIZE, WRITE_SIZE)")
+    ap.add_argument("--traffic-commands", nargs=2, default=["", ""], metavar=("FETCH_CMD", "WRITE_CMD"),
+                    help="the two rocprofv3 commands, recorded in the summary")
     ap.add_argument("--serve-requests", type=int, default=96)
     ap.add_argument("--serve-families", type=int, default=12)
     a = ap.parse_args()
+    if a.traffic_summary:
+        print(json.dumps(traffic_summary(a.workload, a.traffic_summary[0], a.traffic_summary[1],
+                                         a.traffic_commands[0], a.traffic_commands[1])))
+        return
     if a.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print("bench.py measures one GPU only: the library has no multi-GPU path "
               "(sharding patches across GPUs is described, not implemented)", file=sys.stderr)
