@@ -450,7 +450,8 @@ def main():
                     help="comma-separated readings of the smoother constants for --fichera-table: "
                          + ", ".join(READINGS))
     ap.add_argument("--fd-mfma", action="store_true",
-                    help="also time the mixed solver with the smoother's FP32 mode products on the matrix cores")
+                    help="also time the mixed solver with the smoother's mode products on the matrix cores, with "
+                         "FP32 operands (fd_mfma = 1) and with bfloat16 operands (fd_mfma = 3)")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="first fill and copy a 256 MiB buffer: dispatches of known size against "
                          "which hardware byte counters are scaled")
@@ -506,6 +507,8 @@ def main():
         if a.fd_mfma:
             _, runs["mixed_fd_mfma"] = run(a.workload, prob, "mixed", a.steps, a.warmup, dev, fd_mfma=1,
                                            profile_steps=a.profile_steps)
+            _, runs["mixed_fd_bf16"] = run(a.workload, prob, "mixed", a.steps, a.warmup, dev, fd_mfma=3,
+                                           profile_steps=a.profile_steps)
         rhs_cpu = rhs_for(prob, S)
         del S
         torch.cuda.empty_cache()
@@ -542,7 +545,8 @@ def main():
     if "fp64" in runs and "mixed" in runs:
         out["speedup_mixed_vs_fp64"] = runs["mixed"]["value"] / runs["fp64"]["value"]
     if "mixed_fd_mfma" in runs and "mixed" in runs:
-        out["mixed_fd_mfma_vs_vector"] = runs["mixed_fd_mfma"]["value"] / runs["mixed"]["value"]
+        out["mixed_fd_mfma_vs_default"] = runs["mixed_fd_mfma"]["value"] / runs["mixed"]["value"]
+        out["mixed_fd_bf16_vs_default"] = runs["mixed_fd_bf16"]["value"] / runs["mixed"]["value"]
     secondary = {}
     for wname in [w for w in a.secondary.split(",") if w and w != a.workload]:
         sprob = make_problem(wname)
