@@ -118,7 +118,8 @@ def traffic_summary(workload, fetch_csv, write_csv, fetch_cmd, write_cmd):
         with open(path) as fh:
             for r in csv.DictReader(fh):
                 if r.get("Counter_Name") == counter:
-                    rows.append((r["Kernel_Name"], int(r["Grid_Size"]), float(r["Counter_Value"])))
+                    grid = r.get("Grid_Size", r.get("Grid_Size_X", "0"))
+                    rows.append((r["Kernel_Name"], int(grid), float(r["Counter_Value"])))
         copies = [v for n, g, v in rows if "copyBuffer" in n]
         if not copies:
             raise SystemExit(f"{path}: no copy-calibration dispatch")

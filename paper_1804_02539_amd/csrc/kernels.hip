@@ -98,17 +98,18 @@ __device__ __forceinline__ TV band_entries_2d(const TB* __restrict__ band, const
   return s;
 }
 
+// strip bx of 64 rows (the body of one workgroup of k_band_half)
 template <int D, int P, bool RESID, typename TB, typename TV>
-__global__ __launch_bounds__(256) void k_band_half(const TB* __restrict__ band, const TV* __restrict__ u,
-                                                   const TV* __restrict__ f, TV* __restrict__ r,
-                                                   const int* __restrict__ bpatch, const PatchDev* __restrict__ pd) {
+__device__ __forceinline__ void band_half_strip(int64_t bx, const TB* __restrict__ band, const TV* __restrict__ u,
+                                                const TV* __restrict__ f, TV* __restrict__ r,
+                                                const int* __restrict__ bpatch, const PatchDev* __restrict__ pd) {
   constexpr int NB = 2 * P + 1;
   constexpr int NLINE = band_lines(D, P);                 // stencil lines (o1, o2)
   constexpr int LC = (NLINE - 1) / 2;
   constexpr int NBH = band_half_planes(D, P);
   __shared__ TV part[3][BAND_STRIP];
   const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
-  const int64_t g = (int64_t)blockIdx.x * BAND_STRIP + lane;
+  const int64_t g = bx * BAND_STRIP + lane;
   const int64_t tile = g / ROW_ALIGN;                    // the same for the whole workgroup
   const int k = bpatch[tile];
   if (k < 0) return;                                     // uniform: a padding tile
@@ -172,6 +173,13 @@ __global__ __launch_bounds__(256) void k_band_half(const TB* __restrict__ band, 
   }
 }
 
+template <int D, int P, bool RESID, typename TB, typename TV>
+__global__ __launch_bounds__(256) void k_band_half(const TB* __restrict__ band, const TV* __restrict__ u,
+                                                   const TV* __restrict__ f, TV* __restrict__ r,
+                                                   const int* __restrict__ bpatch, const PatchDev* __restrict__ pd) {
+  band_half_strip<D, P, RESID, TB, TV>(blockIdx.x, band, u, f, r, bpatch, pd);
+}
+
 // The full band (all (2P+1)^D planes per row, the layout of the FP32 copy):
 // each row reads its own planes only.  2D FP64 deals single planes to the
 // waves (plane o to wave o mod 4), everything else whole stencil lines.
@@ -186,15 +194,15 @@ __device__ __forceinline__ TV band_planes_2d(const TB* __restrict__ bp, const TV
 }
 
 template <int D, int P, bool RESID, typename TB, typename TV>
-__global__ __launch_bounds__(256) void k_band_full(const TB* __restrict__ band, const TV* __restrict__ u,
-                                                   const TV* __restrict__ f, TV* __restrict__ r,
-                                                   const int* __restrict__ bpatch, const PatchDev* __restrict__ pd) {
+__device__ __forceinline__ void band_full_strip(int64_t bx, const TB* __restrict__ band, const TV* __restrict__ u,
+                                                const TV* __restrict__ f, TV* __restrict__ r,
+                                                const int* __restrict__ bpatch, const PatchDev* __restrict__ pd) {
   constexpr int NB = 2 * P + 1;
   constexpr int NLINE = (D == 2) ? NB : NB * NB;        // stencil lines (o1, o2)
   constexpr int NBT = NLINE * NB;
   __shared__ TV part[3][BAND_STRIP];
   const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
-  const int64_t g = (int64_t)blockIdx.x * BAND_STRIP + lane;
+  const int64_t g = bx * BAND_STRIP + lane;
   const int64_t tile = g / ROW_ALIGN;                    // the same for the whole workgroup
   const int k = bpatch[tile];
   if (k < 0) return;                                     // uniform: a padding tile
@@ -242,6 +250,13 @@ __global__ __launch_bounds__(256) void k_band_full(const TB* __restrict__ band, 
     s += part[0][lane] + part[1][lane] + part[2][lane];
     if constexpr (RESID) r[g] = f[g] - s; else r[g] = s;
   }
+}
+
+template <int D, int P, bool RESID, typename TB, typename TV>
+__global__ __launch_bounds__(256) void k_band_full(const TB* __restrict__ band, const TV* __restrict__ u,
+                                                   const TV* __restrict__ f, TV* __restrict__ r,
+                                                   const int* __restrict__ bpatch, const PatchDev* __restrict__ pd) {
+  band_full_strip<D, P, RESID, TB, TV>(blockIdx.x, band, u, f, r, bpatch, pd);
 }
 
 // The FP32 full band from the FP64 half band: entry (row, o) of the full
@@ -357,10 +372,10 @@ static_assert(256 / MAX_FD >= 3 && (FD_RB + 2) / 3 <= FD_RPT, "chunk columns per
 
 // A chunk is rb <= FD_RB columns (second tensor index) of one z-slab, so that the
 // results of a chunk are whole columns, contiguous in memory.
-__device__ __forceinline__ void fd_chunk(const FDItem& it, int rb, int& z, int& c0, int& nc) {
+__device__ __forceinline__ void fd_chunk(const FDItem& it, int rb, int bx, int& z, int& c0, int& nc) {
   const int nch = (it.m[1] + rb - 1) / rb;
-  z = blockIdx.x / nch;
-  c0 = (blockIdx.x - z * nch) * rb;
+  z = bx / nch;
+  c0 = (bx - z * nch) * rb;
   nc = min(rb, it.m[1] - c0);
 }
 
@@ -429,24 +444,25 @@ __device__ void fd_dense_piece(const DensePiece pc, const T* __restrict__ densem
   }
 }
 
+// block (bx, by) of the forward launch (by >= nitems: dense piece by - nitems)
 template <typename T>
-__global__ __launch_bounds__(256) void k_fd_fwd(const FDItem* __restrict__ items, int nitems,
-                                                const DensePiece* __restrict__ dense,
-                                                const T* __restrict__ densemat, const T* __restrict__ mat,
-                                                const T* __restrict__ src, T* __restrict__ u,
-                                                const int64_t* __restrict__ if_ptr, const int64_t* __restrict__ if_idx,
-                                                T* __restrict__ scr, T tau, int add, int rb) {
+__device__ __forceinline__ void fd_fwd_block(int bx, int by, const FDItem* __restrict__ items, int nitems,
+                                             const DensePiece* __restrict__ dense, const T* __restrict__ densemat,
+                                             const T* __restrict__ mat, const T* __restrict__ src,
+                                             T* __restrict__ u, const int64_t* __restrict__ if_ptr,
+                                             const int64_t* __restrict__ if_idx, T* __restrict__ scr, T tau, int add,
+                                             int rb) {
   DYN_LDS(T, lds);
-  const int y = blockIdx.y;
+  const int y = by;
   if (y >= nitems) {
-    if (blockIdx.x == 0) fd_dense_piece(dense[y - nitems], densemat, src, u, if_ptr, if_idx, tau, add, lds);
+    if (bx == 0) fd_dense_piece(dense[y - nitems], densemat, src, u, if_ptr, if_idx, tau, add, lds);
     return;
   }
   // Y[:, c0 + c] = U0^T (X U1[:, c0 + c]) for the chunk's columns
   const FDItem it = items[y];
   const int m0 = it.m[0], m1 = it.m[1];
   int z, c0, nc;
-  fd_chunk(it, rb, z, c0, nc);
+  fd_chunk(it, rb, bx, z, c0, nc);
   if (z >= it.m[2]) return;
   const int n = m0 * m1;
   T* X = lds;                        // X[j + m0 b]; later U0[j m0 + a]
@@ -498,16 +514,28 @@ __global__ __launch_bounds__(256) void k_fd_fwd(const FDItem* __restrict__ items
 }
 
 template <typename T>
-__global__ __launch_bounds__(256) void k_fd_inv(const FDItem* __restrict__ items, const T* __restrict__ mat,
-                                                T* __restrict__ u, const int64_t* __restrict__ if_ptr,
-                                                const int64_t* __restrict__ if_idx, const T* __restrict__ scr, T tau,
-                                                int add, int rb) {
+__global__ __launch_bounds__(256) void k_fd_fwd(const FDItem* __restrict__ items, int nitems,
+                                                const DensePiece* __restrict__ dense,
+                                                const T* __restrict__ densemat, const T* __restrict__ mat,
+                                                const T* __restrict__ src, T* __restrict__ u,
+                                                const int64_t* __restrict__ if_ptr, const int64_t* __restrict__ if_idx,
+                                                T* __restrict__ scr, T tau, int add, int rb) {
+  fd_fwd_block<T>(blockIdx.x, blockIdx.y, items, nitems, dense, densemat, mat, src, u, if_ptr, if_idx, scr, tau, add,
+                  rb);
+}
+
+// block (bx, by) of the inverse launch
+template <typename T>
+__device__ __forceinline__ void fd_inv_block(int bx, int by, const FDItem* __restrict__ items,
+                                             const T* __restrict__ mat, T* __restrict__ u,
+                                             const int64_t* __restrict__ if_ptr, const int64_t* __restrict__ if_idx,
+                                             const T* __restrict__ scr, T tau, int add, int rb) {
   // Z[:, c0 + c] = U0 (Y U1^T[:, c0 + c]) for the chunk's columns
   DYN_LDS(T, lds);
-  const FDItem it = items[blockIdx.y];
+  const FDItem it = items[by];
   const int m0 = it.m[0], m1 = it.m[1];
   int z, c0, nc;
-  fd_chunk(it, rb, z, c0, nc);
+  fd_chunk(it, rb, bx, z, c0, nc);
   if (z >= it.m[2]) return;
   const int n = m0 * m1;
   T* Y = lds;                        // Y[j + m0 b]; later U0^T[j m0 + a]
@@ -546,6 +574,14 @@ __global__ __launch_bounds__(256) void k_fd_inv(const FDItem* __restrict__ items
       u[x] = add ? u[x] + v : v;
     }
   }
+}
+
+template <typename T>
+__global__ __launch_bounds__(256) void k_fd_inv(const FDItem* __restrict__ items, const T* __restrict__ mat,
+                                                T* __restrict__ u, const int64_t* __restrict__ if_ptr,
+                                                const int64_t* __restrict__ if_idx, const T* __restrict__ scr, T tau,
+                                                int add, int rb) {
+  fd_inv_block<T>(blockIdx.x, blockIdx.y, items, mat, u, if_ptr, if_idx, scr, tau, add, rb);
 }
 
 // ---------------------------------------------------------------------------
@@ -946,16 +982,16 @@ void launch_fd2_fused(const FDItem* items, int nitems, int ndense, size_t lds, c
 __device__ __forceinline__ int fd_mid_lines(int L) { return max(1, min(64, 512 / L)); }
 
 template <typename T>
-__global__ __launch_bounds__(256) void k_fd_mid(const FDItem* __restrict__ items, const T* __restrict__ mat,
-                                                T* __restrict__ scr) {
+__device__ __forceinline__ void fd_mid_block(int bx, int by, const FDItem* __restrict__ items,
+                                             const T* __restrict__ mat, T* __restrict__ scr) {
   DYN_LDS(T, lds);
-  const FDItem it = items[blockIdx.y];
+  const FDItem it = items[by];
   const int L = it.m[2];
   if (L <= 1) return;
   const int m0 = it.m[0];
   const int64_t lines = (int64_t)m0 * it.m[1];
   const int LB = fd_mid_lines(L);
-  const int64_t line0 = (int64_t)blockIdx.x * LB;
+  const int64_t line0 = (int64_t)bx * LB;
   if (line0 >= lines) return;
   const int nl = (int)min((int64_t)LB, lines - line0);
   T* sU = lds;
@@ -997,6 +1033,12 @@ __global__ __launch_bounds__(256) void k_fd_mid(const FDItem* __restrict__ items
     const int j = t / nl, line = t - j * nl;
     S[line0 + line + j * plane] = sx[line * L + j];
   }
+}
+
+template <typename T>
+__global__ __launch_bounds__(256) void k_fd_mid(const FDItem* __restrict__ items, const T* __restrict__ mat,
+                                                T* __restrict__ scr) {
+  fd_mid_block<T>(blockIdx.x, blockIdx.y, items, mat, scr);
 }
 
 size_t fd_mfma_lds(int maxm) {
@@ -1143,11 +1185,10 @@ void launch_fd_inv(const FDItem* items, int nitems, int gridx, size_t lds, const
 // accumulated, P^T distributed to distributed vectors)
 // ---------------------------------------------------------------------------
 template <int D, int WR, typename T>
-__global__ __launch_bounds__(256) void k_restrict(const T* __restrict__ rf, T* __restrict__ rc,
-                                                  const PatchDev* __restrict__ pd, const int* __restrict__ bpatch_c,
-                                                  const int64_t* __restrict__ tidx, const T* __restrict__ tval,
-                                                  const uint8_t* __restrict__ isfree_c) {
-  const int b = blockIdx.x;
+__device__ __forceinline__ void restrict_block(int64_t b, const T* __restrict__ rf, T* __restrict__ rc,
+                                               const PatchDev* __restrict__ pd, const int* __restrict__ bpatch_c,
+                                               const int64_t* __restrict__ tidx, const T* __restrict__ tval,
+                                               const uint8_t* __restrict__ isfree_c) {
   const int k = bpatch_c[b];
   if (k < 0) return;
   const PatchDev& P = pd[k];
@@ -1196,13 +1237,19 @@ __global__ __launch_bounds__(256) void k_restrict(const T* __restrict__ rf, T* _
   rc[g] = s;
 }
 
+template <int D, int WR, typename T>
+__global__ __launch_bounds__(256) void k_restrict(const T* __restrict__ rf, T* __restrict__ rc,
+                                                  const PatchDev* __restrict__ pd, const int* __restrict__ bpatch_c,
+                                                  const int64_t* __restrict__ tidx, const T* __restrict__ tval,
+                                                  const uint8_t* __restrict__ isfree_c) {
+  restrict_block<D, WR, T>(blockIdx.x, rf, rc, pd, bpatch_c, tidx, tval, isfree_c);
+}
+
 template <int D, int WP, typename T>
-__global__ __launch_bounds__(256) void k_prolong_add(const T* __restrict__ uc, T* __restrict__ uf,
-                                                     const PatchDev* __restrict__ pd,
-                                                     const int* __restrict__ bpatch_f,
-                                                     const int64_t* __restrict__ tidx, const T* __restrict__ tval,
-                                                     const uint8_t* __restrict__ isfree_f) {
-  const int b = blockIdx.x;
+__device__ __forceinline__ void prolong_block(int64_t b, const T* __restrict__ uc, T* __restrict__ uf,
+                                              const PatchDev* __restrict__ pd, const int* __restrict__ bpatch_f,
+                                              const int64_t* __restrict__ tidx, const T* __restrict__ tval,
+                                              const uint8_t* __restrict__ isfree_f) {
   const int k = bpatch_f[b];
   if (k < 0) return;
   const PatchDev& P = pd[k];
@@ -1244,6 +1291,15 @@ __global__ __launch_bounds__(256) void k_prolong_add(const T* __restrict__ uc, T
     }
   }
   uf[g] += s;
+}
+
+template <int D, int WP, typename T>
+__global__ __launch_bounds__(256) void k_prolong_add(const T* __restrict__ uc, T* __restrict__ uf,
+                                                     const PatchDev* __restrict__ pd,
+                                                     const int* __restrict__ bpatch_f,
+                                                     const int64_t* __restrict__ tidx, const T* __restrict__ tval,
+                                                     const uint8_t* __restrict__ isfree_f) {
+  prolong_block<D, WP, T>(blockIdx.x, uc, uf, pd, bpatch_f, tidx, tval, isfree_f);
 }
 
 template <int D, typename T>
@@ -1297,14 +1353,21 @@ void launch_prolong_add(int d, const T* uc, T* uf, const PatchDev* pd, const int
 // every copy
 // ---------------------------------------------------------------------------
 template <typename TL, typename TG>
-__global__ __launch_bounds__(256) void k_gather_dist(const TL* __restrict__ loc, TG* __restrict__ glob,
-                                                     const int64_t* __restrict__ ptr,
-                                                     const int64_t* __restrict__ idx, int64_t n) {
-  const int64_t g = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+__device__ __forceinline__ void gather_dist_block(int64_t bx, const TL* __restrict__ loc, TG* __restrict__ glob,
+                                                  const int64_t* __restrict__ ptr, const int64_t* __restrict__ idx,
+                                                  int64_t n) {
+  const int64_t g = bx * blockDim.x + threadIdx.x;
   if (g >= n) return;
   double s = 0.0;
   for (int64_t c = ptr[g]; c < ptr[g + 1]; ++c) s += (double)loc[idx[c]];
   glob[g] = (TG)s;
+}
+
+template <typename TL, typename TG>
+__global__ __launch_bounds__(256) void k_gather_dist(const TL* __restrict__ loc, TG* __restrict__ glob,
+                                                     const int64_t* __restrict__ ptr,
+                                                     const int64_t* __restrict__ idx, int64_t n) {
+  gather_dist_block<TL, TG>(blockIdx.x, loc, glob, ptr, idx, n);
 }
 
 __global__ __launch_bounds__(256) void k_gather_acc(const double* __restrict__ loc, double* __restrict__ glob,
@@ -1357,11 +1420,12 @@ void launch_scatter(const double* glob, double* loc, const int64_t* ptr, const i
 // x = A_0^{-1} b (dense FP64, n x n row-major), one wavefront per row; x_i goes
 // to every local copy of coarse dof i (the restriction chi of the coarse solve)
 template <typename T>
-__global__ __launch_bounds__(256) void k_coarse_gemv(const double* __restrict__ Ainv, const double* __restrict__ b,
-                                                     T* __restrict__ u0, const int64_t* __restrict__ ptr,
-                                                     const int64_t* __restrict__ idx, int n) {
+__device__ __forceinline__ void coarse_gemv_block(int64_t bx, const double* __restrict__ Ainv,
+                                                  const double* __restrict__ b, T* __restrict__ u0,
+                                                  const int64_t* __restrict__ ptr, const int64_t* __restrict__ idx,
+                                                  int n) {
   const int lane = threadIdx.x & 63;
-  const int row = blockIdx.x * 4 + (threadIdx.x >> 6);
+  const int row = (int)(bx * 4 + (threadIdx.x >> 6));
   if (row >= n) return;
   const double* ar = Ainv + (int64_t)row * n;
   double s = 0.0;
@@ -1373,12 +1437,179 @@ __global__ __launch_bounds__(256) void k_coarse_gemv(const double* __restrict__ 
 }
 
 template <typename T>
+__global__ __launch_bounds__(256) void k_coarse_gemv(const double* __restrict__ Ainv, const double* __restrict__ b,
+                                                     T* __restrict__ u0, const int64_t* __restrict__ ptr,
+                                                     const int64_t* __restrict__ idx, int n) {
+  coarse_gemv_block<T>(blockIdx.x, Ainv, b, u0, ptr, idx, n);
+}
+
+template <typename T>
 void launch_coarse(const double* Ainv, const T* f0, double* b, T* u0, const int64_t* ptr, const int64_t* idx, int n,
                    hipStream_t st) {
   hipLaunchKernelGGL((k_gather_dist<T, double>), dim3((unsigned)((n + 255) / 256)), dim3(256), 0, st, f0, b, ptr, idx,
                      (int64_t)n);
   hipLaunchKernelGGL(k_coarse_gemv<T>, dim3((n + 3) / 4), dim3(256), 0, st, Ainv, b, u0, ptr, idx, n);
 }
+
+// ---------------------------------------------------------------------------
+// The coarse levels of a cycle in one persistent launch.  The phases of the
+// cycle below a level (smoothing products, residuals, transfers, the coarse
+// solve) form one work list; a workgroup takes the next ticket, waits until
+// every item of the previous phase has finished (a completion counter per
+// phase), runs its item with the same body as the separate launch would,
+// and counts it done.  Tickets are taken in order, so every item a
+// workgroup waits for was taken before by a running workgroup that is not
+// itself waiting on a later ticket: the list always drains, whatever number
+// of workgroups is resident (no co-residency assumption, no grid barrier).
+// The counters are at agent scope with release/acquire fences, so results
+// written on one XCD are seen on another.  ctr[0] is the ticket counter,
+// ctr[1 + k] the completed items of phase k, ctr[1 + nph] an overflow flag
+// set if a wait ever exceeded its (very large) spin bound.
+// ---------------------------------------------------------------------------
+template <int D, int P, typename T>
+__device__ __forceinline__ void tail_item(const Phase& ph, int64_t t) {
+  const int bx = (int)(t % ph.gx), by = (int)(t / ph.gx);
+  const void* const* a = ph.a;
+  switch (ph.kind) {
+    case PH_BAND: {
+      const T* band = static_cast<const T*>(a[0]);
+      const T* u = static_cast<const T*>(a[1]);
+      const T* f = static_cast<const T*>(a[2]);
+      T* r = const_cast<T*>(static_cast<const T*>(a[3]));
+      const int* bp = static_cast<const int*>(a[4]);
+      const PatchDev* pd = static_cast<const PatchDev*>(a[5]);
+      if constexpr (sizeof(T) == 8) {
+        if (ph.resid) band_half_strip<D, P, true, T, T>(t, band, u, f, r, bp, pd);
+        else band_half_strip<D, P, false, T, T>(t, band, u, f, r, bp, pd);
+      } else {
+        if (ph.resid) band_full_strip<D, P, true, T, T>(t, band, u, f, r, bp, pd);
+        else band_full_strip<D, P, false, T, T>(t, band, u, f, r, bp, pd);
+      }
+      break;
+    }
+    case PH_FD_FWD:
+      fd_fwd_block<T>(bx, by, static_cast<const FDItem*>(a[0]), ph.nitems, static_cast<const DensePiece*>(a[1]),
+                      static_cast<const T*>(a[2]), static_cast<const T*>(a[3]), static_cast<const T*>(a[4]),
+                      const_cast<T*>(static_cast<const T*>(a[5])), static_cast<const int64_t*>(a[6]),
+                      static_cast<const int64_t*>(a[7]), const_cast<T*>(static_cast<const T*>(a[8])), (T)ph.tau,
+                      ph.add, ph.rb);
+      break;
+    case PH_FD_MID:
+      fd_mid_block<T>(bx, by, static_cast<const FDItem*>(a[0]), static_cast<const T*>(a[1]),
+                      const_cast<T*>(static_cast<const T*>(a[2])));
+      break;
+    case PH_FD_INV:
+      fd_inv_block<T>(bx, by, static_cast<const FDItem*>(a[0]), static_cast<const T*>(a[1]),
+                      const_cast<T*>(static_cast<const T*>(a[2])), static_cast<const int64_t*>(a[3]),
+                      static_cast<const int64_t*>(a[4]), static_cast<const T*>(a[5]), (T)ph.tau, ph.add, ph.rb);
+      break;
+    case PH_RESTRICT:
+    case PH_PROLONG: {
+      const T* x = static_cast<const T*>(a[0]);
+      T* y = const_cast<T*>(static_cast<const T*>(a[1]));
+      const PatchDev* pd = static_cast<const PatchDev*>(a[2]);
+      const int* bp = static_cast<const int*>(a[3]);
+      const int64_t* ti = static_cast<const int64_t*>(a[4]);
+      const T* tv = static_cast<const T*>(a[5]);
+      const uint8_t* fr = static_cast<const uint8_t*>(a[6]);
+      // table widths run up to P + 2
+#define IGAMG_TAIL_W(W)                                                              \
+  case W:                                                                            \
+    if (ph.kind == PH_RESTRICT) restrict_block<D, W, T>(t, x, y, pd, bp, ti, tv, fr); \
+    else prolong_block<D, W, T>(t, x, y, pd, bp, ti, tv, fr);                        \
+    break;
+      switch (ph.w) {
+        IGAMG_TAIL_W(1) IGAMG_TAIL_W(2) IGAMG_TAIL_W(3) IGAMG_TAIL_W(4) IGAMG_TAIL_W(5)
+        IGAMG_TAIL_W(6) IGAMG_TAIL_W(7) IGAMG_TAIL_W(8) IGAMG_TAIL_W(9) IGAMG_TAIL_W(10)
+        default: break;
+      }
+#undef IGAMG_TAIL_W
+      break;
+    }
+    case PH_GATHER:
+      gather_dist_block<T, double>(t, static_cast<const T*>(a[0]), const_cast<double*>(static_cast<const double*>(a[1])),
+                                   static_cast<const int64_t*>(a[2]), static_cast<const int64_t*>(a[3]), ph.len);
+      break;
+    case PH_GEMV:
+      coarse_gemv_block<T>(t, static_cast<const double*>(a[0]), static_cast<const double*>(a[1]),
+                           const_cast<T*>(static_cast<const T*>(a[2])), static_cast<const int64_t*>(a[3]),
+                           static_cast<const int64_t*>(a[4]), (int)ph.len);
+      break;
+    default:
+      break;
+  }
+}
+
+constexpr unsigned TAIL_SPIN_LIMIT = 1u << 26;   // about a second of polling; never reached when the list drains
+
+template <int D, int P, typename T>
+__global__ __launch_bounds__(256) void k_cycle_tail(const Phase* __restrict__ prog, int nph, int64_t total,
+                                                    unsigned long long* __restrict__ ctr) {
+  __shared__ int64_t s_ticket;
+  int ph = 0, ready = 0;   // phases < ready are known complete
+  for (;;) {
+    if (threadIdx.x == 0) s_ticket = (int64_t)atomicAdd(&ctr[0], 1ull);
+    __syncthreads();
+    const int64_t t = s_ticket;
+    __syncthreads();                      // s_ticket is read by every thread before it changes
+    if (t >= total) break;
+    while (ph + 1 < nph && t >= prog[ph + 1].first) ++ph;
+    if (ph > 0 && ready < ph) {
+      if (threadIdx.x == 0) {
+        const unsigned long long need = (unsigned long long)prog[ph - 1].n;
+        unsigned spins = 0;
+        while (__hip_atomic_load(&ctr[ph], __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT) < need) {
+          __builtin_amdgcn_s_sleep(1);
+          if (++spins > TAIL_SPIN_LIMIT) {
+            __hip_atomic_store(&ctr[1 + nph], 1ull, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            break;
+          }
+        }
+      }
+      __syncthreads();
+      __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
+      ready = ph;
+    }
+    tail_item<D, P, T>(prog[ph], t - prog[ph].first);
+    __syncthreads();
+    if (threadIdx.x == 0) {
+      __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
+      atomicAdd(&ctr[1 + ph], 1ull);
+    }
+  }
+}
+
+// zero the counters of one launch (a kernel, so that graphs may hold it)
+__global__ __launch_bounds__(64) void k_tail_reset(unsigned long long* __restrict__ ctr, int n) {
+  for (int i = threadIdx.x; i < n; i += blockDim.x) ctr[i] = 0ull;
+}
+
+size_t cycle_tail_lds(int maxm, int max_dense, size_t elem) {
+  return std::max({fd_slab_lds(maxm, elem), fd_dense_lds(max_dense, elem), fd_mid_lds(maxm, elem)});
+}
+
+template <typename T>
+hipError_t launch_cycle_tail(int d, int p, const Phase* prog, int nph, int64_t total, unsigned long long* ctr,
+                             int grid, size_t lds, hipStream_t st) {
+  if (total <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_tail_reset, dim3(1), dim3(64), 0, st, ctr, nph + 2);
+#define IGAMG_TAIL_CASE(DD, PP)                                                                          \
+  if (d == DD && p == PP) {                                                                              \
+    hipLaunchKernelGGL((k_cycle_tail<DD, PP, T>), dim3(grid), dim3(256), lds, st, prog, nph, total, ctr); \
+    return hipGetLastError();                                                                            \
+  }
+  IGAMG_TAIL_CASE(2, 1) IGAMG_TAIL_CASE(2, 2) IGAMG_TAIL_CASE(2, 3) IGAMG_TAIL_CASE(2, 4)
+  IGAMG_TAIL_CASE(2, 5) IGAMG_TAIL_CASE(2, 6) IGAMG_TAIL_CASE(2, 7) IGAMG_TAIL_CASE(2, 8)
+  IGAMG_TAIL_CASE(3, 1) IGAMG_TAIL_CASE(3, 2) IGAMG_TAIL_CASE(3, 3) IGAMG_TAIL_CASE(3, 4)
+  IGAMG_TAIL_CASE(3, 5) IGAMG_TAIL_CASE(3, 6) IGAMG_TAIL_CASE(3, 7) IGAMG_TAIL_CASE(3, 8)
+#undef IGAMG_TAIL_CASE
+  return hipErrorInvalidValue;
+}
+
+template hipError_t launch_cycle_tail<double>(int, int, const Phase*, int, int64_t, unsigned long long*, int, size_t,
+                                              hipStream_t);
+template hipError_t launch_cycle_tail<float>(int, int, const Phase*, int, int64_t, unsigned long long*, int, size_t,
+                                             hipStream_t);
 
 // ---------------------------------------------------------------------------
 // vector kernels of the PCG loop (deterministic two-stage reductions in FP64)

@@ -91,6 +91,14 @@ void launch_to_f32(float* y, const double* x, int64_t n, hipStream_t st);
 // device assembly (assemble.hip): doubles of one element slab's metric (Gs),
 // direction-0 (T1) and direction-1 (T2) intermediates of a patch
 void asm_slab_sizes(int d, const AsmPatch& P, size_t out[3]);
+// The coarse levels of a cycle as one persistent launch over a work list of
+// phases (prog, nph entries, total items), preceded by a one-workgroup reset
+// of the nph + 2 counters at ctr (ticket, one completion count per phase,
+// overflow flag).
+size_t cycle_tail_lds(int maxm, int max_dense, size_t elem);
+template <typename T>
+hipError_t launch_cycle_tail(int d, int p, const Phase* prog, int nph, int64_t total, unsigned long long* ctr,
+                             int grid, size_t lds, hipStream_t st);
 // FP32 full band (all (2p+1)^d planes per tile) from the FP64 symmetric half band
 void launch_band_half_to_full(int d, int p, float* full, const double* half, const int* bpatch, const PatchDev* pd,
                               int64_t NL, hipStream_t st);

@@ -62,6 +62,29 @@ struct FDItem {
   double extra;
 };
 
+// One phase of the persistent coarse cycle (k_cycle_tail): `n` work items,
+// item t is block (t % gx, t / gx) of the launch the phase replaces, and its
+// tickets are first .. first + n - 1.  Pointers and scalars by kind:
+//   BAND      a: band, u, f, r, bpatch, pd;                        resid
+//   FD_FWD    a: items, dense, densemat, mat, src, u, if_ptr, if_idx, scr;  nitems, tau, add, rb
+//   FD_MID    a: items, mat, scr
+//   FD_INV    a: items, mat, u, if_ptr, if_idx, scr;               tau, add, rb
+//   RESTRICT  a: rf, rc, pd, bpatch_c, tidx, tval, isfree_c;       w
+//   PROLONG   a: uc, uf, pd, bpatch_f, tidx, tval, isfree_f;       w
+//   GATHER    a: loc, glob (double), ptr, idx;                     len
+//   GEMV      a: Ainv, b, u0, ptr, idx;                            len
+enum PhaseKind : int { PH_BAND = 0, PH_FD_FWD, PH_FD_MID, PH_FD_INV, PH_RESTRICT, PH_PROLONG, PH_GATHER, PH_GEMV };
+struct Phase {
+  int kind;
+  int gx;
+  int64_t n;
+  int64_t first;
+  int resid, add, w, nitems, rb, pad;
+  int64_t len;
+  double tau;
+  const void* a[10];
+};
+
 // A piece applied by a dense inverse (edges, vertices).
 struct DensePiece {
   int64_t seg;       // first entry in the interface vector
