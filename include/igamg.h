@@ -127,6 +127,9 @@ typedef struct {
                              + (h/p)^{d-3} M and (h/p)^{d-2}; 1: the exact restriction of A_l
                              to each edge and vertex, solved directly (the variant Sec. 3
                              cites from its reference)                                    */
+  int persistent;         /* 1: the levels of at most 65536 local rows below the finest run as one
+                             persistent launch per cycle (a work list of the cycle's phases,
+                             V-cycle only); 0 (default): one launch per kernel               */
 } igamg_options;
 
 #define IGAMG_FP64 0

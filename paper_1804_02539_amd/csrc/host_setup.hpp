@@ -42,6 +42,7 @@ struct Options {
   int iface_multiplicity = 0;  // 1: interface piece operators times their number of adjacent patches
   int physical_h = 0;      // 1: h_c = (mean length of the c-th Jacobian column) / nel_c
   int iface_direct = 0;    // 1: edges and vertices solved with the exact restriction of A_l
+  int persistent = 0;      // 1: the coarse levels of each cycle as one persistent launch
 };
 
 // Error with an igamg return code.

@@ -123,6 +123,15 @@ struct igamg_ctx {
   int* dg_plane = nullptr;
   double* dg_out = nullptr;
   double* cb = nullptr;
+  // the coarse levels of a cycle as one persistent launch (options.persistent)
+  struct Tail {
+    int level = 0, nph = 0, grid = 0;
+    int64_t total = 0;
+    size_t lds = 0;
+    Phase* prog = nullptr;
+    unsigned long long* ctr = nullptr;
+    std::vector<Phase> host;
+  } tail[2];   // [0] FP64, [1] FP32
   int64_t N0 = 0;
   PcgVecs<double> v64;
   PcgVecs<float> v32;
@@ -165,6 +174,147 @@ static void plan_level_data(Bump& b, const LevelH& L, DevLevel& D, LevelData<T>&
   X.densemat = b.take<T>(L.densemat.size());
   X.tr_val = b.take<T>(L.tr_val.size());
   X.scr = b.take<T>(L.fdscr);
+}
+
+// Rows up to which a level belongs to the persistent coarse cycle: below
+// this size a level's kernels are launch-bound.
+constexpr int64_t TAIL_MAX_ROWS = 1 << 16;
+
+// The work list of cycle(Lp) from a zero guess (Algorithm 1 with mu = 1) over
+// the levels 1..Lp, Lp the largest level below the finest whose levels are
+// all at most TAIL_MAX_ROWS rows: smoothing products, residuals, transfers
+// and the coarse solve, in the order the separate launches run them.  Needs
+// the level data planned (pointers are null in the sizing pass).
+template <typename T>
+static void tail_program(igamg_ctx& C, igamg_ctx::Tail& tl) {
+  const Options& O = C.H.opt;
+  if (!O.persistent || O.mu != 1 || C.dl.size() < 3) return;
+  int Lp = 0;
+  for (int l = 1; l + 1 < (int)C.dl.size() && C.dl[l].NL <= TAIL_MAX_ROWS; ++l) Lp = l;
+  if (Lp < 1) return;
+  std::vector<Phase>& prog = tl.host;
+  int64_t total = 0;
+  auto push = [&](Phase ph) {
+    if (ph.n <= 0) return;
+    ph.first = total;
+    total += ph.n;
+    prog.push_back(ph);
+  };
+  auto band = [&](int l) {
+    DevLevel& D = C.dl[l];
+    LevelData<T>& X = dat<T>(D);
+    Phase ph{};
+    ph.kind = PH_BAND;
+    ph.gx = 1;
+    ph.n = D.NL / 64;
+    ph.resid = 1;
+    const void* a[] = {X.band, X.u, X.f, X.w, D.bpatch, D.pd};
+    for (int i = 0; i < 6; ++i) ph.a[i] = a[i];
+    push(ph);
+  };
+  auto smooth = [&](int l, const T* src, bool add) {
+    DevLevel& D = C.dl[l];
+    LevelData<T>& X = dat<T>(D);
+    Phase ph{};
+    ph.kind = PH_FD_FWD;
+    ph.gx = D.slab_grid;
+    ph.n = (int64_t)D.slab_grid * (D.nfd + D.ndense);
+    ph.nitems = D.nfd;
+    ph.tau = O.tau;
+    ph.add = add;
+    ph.rb = 8;
+    const void* a[] = {D.fd, D.dense, X.densemat, X.fdmat, src, X.u, D.if_ptr, D.if_idx, X.scr};
+    for (int i = 0; i < 9; ++i) ph.a[i] = a[i];
+    push(ph);
+    if (C.d == 3 && D.nfd_int > 0 && D.max_m2 > 1) {
+      Phase m{};
+      m.kind = PH_FD_MID;
+      m.gx = D.mid_grid;
+      m.n = (int64_t)D.mid_grid * D.nfd_int;
+      m.a[0] = D.fd;
+      m.a[1] = X.fdmat;
+      m.a[2] = X.scr;
+      push(m);
+    }
+    Phase v{};
+    v.kind = PH_FD_INV;
+    v.gx = D.slab_grid;
+    v.n = (int64_t)D.slab_grid * D.nfd;
+    v.tau = O.tau;
+    v.add = add;
+    v.rb = 8;
+    const void* b2[] = {D.fd, X.fdmat, X.u, D.if_ptr, D.if_idx, X.scr};
+    for (int i = 0; i < 6; ++i) v.a[i] = b2[i];
+    push(v);
+  };
+  for (int l = Lp; l >= 1; --l) {
+    DevLevel& F = C.dl[l];
+    DevLevel& Cc = C.dl[l - 1];
+    LevelData<T>& X = dat<T>(F);
+    LevelData<T>& Xc = dat<T>(Cc);
+    for (int i = 0; i < O.nu; ++i) {
+      if (i == 0) {
+        smooth(l, X.f, false);
+      } else {
+        band(l);
+        smooth(l, X.w, true);
+      }
+    }
+    band(l);
+    Phase r{};
+    r.kind = PH_RESTRICT;
+    r.gx = 1;
+    r.n = Cc.NL / ROW_ALIGN;
+    r.w = F.WR;
+    const void* a[] = {X.w, Xc.f, F.pd, Cc.bpatch, F.tr_idx, X.tr_val, Cc.isfree};
+    for (int i = 0; i < 7; ++i) r.a[i] = a[i];
+    push(r);
+  }
+  {
+    DevLevel& D0 = C.dl[0];
+    LevelData<T>& X0 = dat<T>(D0);
+    Phase g{};
+    g.kind = PH_GATHER;
+    g.gx = 1;
+    g.len = C.N0;
+    g.n = (C.N0 + 255) / 256;
+    const void* a[] = {X0.f, C.cb, D0.gptr, D0.gidx};
+    for (int i = 0; i < 4; ++i) g.a[i] = a[i];
+    push(g);
+    Phase m{};
+    m.kind = PH_GEMV;
+    m.gx = 1;
+    m.len = C.N0;
+    m.n = (C.N0 + 3) / 4;
+    const void* b2[] = {C.Ainv, C.cb, X0.u, D0.gptr, D0.gidx};
+    for (int i = 0; i < 5; ++i) m.a[i] = b2[i];
+    push(m);
+  }
+  for (int l = 1; l <= Lp; ++l) {
+    DevLevel& F = C.dl[l];
+    DevLevel& Cc = C.dl[l - 1];
+    LevelData<T>& X = dat<T>(F);
+    LevelData<T>& Xc = dat<T>(Cc);
+    Phase pr{};
+    pr.kind = PH_PROLONG;
+    pr.gx = 1;
+    pr.n = F.NL / ROW_ALIGN;
+    pr.w = F.WP;
+    const void* a[] = {Xc.u, X.u, F.pd, F.bpatch, F.tr_idx, X.tr_val, F.isfree};
+    for (int i = 0; i < 7; ++i) pr.a[i] = a[i];
+    push(pr);
+    for (int i = 0; i < O.nu; ++i) {
+      band(l);
+      smooth(l, X.w, true);
+    }
+  }
+  tl.level = Lp;
+  tl.nph = (int)prog.size();
+  tl.total = total;
+  tl.grid = 512;
+  tl.lds = 0;
+  for (int l = 1; l <= Lp; ++l)
+    tl.lds = std::max(tl.lds, cycle_tail_lds(C.dl[l].fd_maxm, C.dl[l].max_dense, sizeof(T)));
 }
 
 static size_t plan(igamg_ctx& C, char* base) {
@@ -233,6 +383,16 @@ static size_t plan(igamg_ctx& C, char* base) {
     C.v32.p = b.take<float>(NLf);
     C.v32.q = b.take<float>(NLf);
     C.fsave = b.take<double>(NLf);
+  }
+  for (int prec = 0; prec < (C.mixed ? 2 : 1); ++prec) {
+    igamg_ctx::Tail& tl = C.tail[prec];
+    tl = igamg_ctx::Tail{};
+    if (prec == 0) tail_program<double>(C, tl);
+    else tail_program<float>(C, tl);
+    if (tl.nph > 0) {
+      tl.prog = b.take<Phase>(tl.host.size());
+      tl.ctr = b.take<unsigned long long>(tl.host.size() + 2);
+    }
   }
   C.part = b.take<double>(2 * RED_BLOCKS);
   C.scal = b.take<double>(16);
@@ -487,6 +647,8 @@ static void upload(igamg_ctx& C, hipStream_t st) {
       up(D.d32.tr_val, to_float(L.tr_val), st);
     }
   }
+  for (auto& tl : C.tail)
+    if (tl.nph > 0) up(tl.prog, tl.host, st);
   // the bands are large and no longer needed on the host
   for (auto& L : H.lv) std::vector<double>().swap(L.band);
   std::vector<double>().swap(H.Ainv);
@@ -585,6 +747,12 @@ static void prolong_add(igamg_ctx& C, int l, const T* uc, T* uf, hipStream_t st)
 // Algorithm 1 on level l >= 1 with u_l, f_l in dat<T>(dl[l]).u / .f
 template <typename T>
 static void cycle(igamg_ctx& C, int l, bool zero_init, hipStream_t st) {
+  const igamg_ctx::Tail& tl = C.tail[std::is_same<T, float>::value ? 1 : 0];
+  if (tl.nph > 0 && l == tl.level && zero_init) {
+    // the whole cycle from here down, in one persistent launch
+    HIP_OK(launch_cycle_tail<T>(C.d, C.p, tl.prog, tl.nph, tl.total, tl.ctr, tl.grid, tl.lds, st));
+    return;
+  }
   LevelData<T>& X = dat<T>(C.dl[l]);
   LevelData<T>& Xc = dat<T>(C.dl[l - 1]);
   const Options& O = C.H.opt;
@@ -723,9 +891,10 @@ static void read_opts(const igamg_options* o, Options& O) {
   O.iface_multiplicity = o->iface_multiplicity;
   O.physical_h = o->physical_h;
   O.iface_direct = o->iface_direct;
+  O.persistent = o->persistent;
   if (O.s1_sigma < 0 || O.s1_sigma > 1 || O.iface_multiplicity < 0 || O.iface_multiplicity > 1 || O.physical_h < 0 ||
       O.physical_h > 1 || O.geometry_scaling < 0 || O.geometry_scaling > 1 || O.iface_direct < 0 ||
-      O.iface_direct > 1)
+      O.iface_direct > 1 || O.persistent < 0 || O.persistent > 1)
     throw SetupError{IGAMG_EINVAL, "invalid options"};
   if (!(O.tau > 0) || !(O.sigma_scale > 0) || O.nu < 1 || O.nu > 8 || (O.mu != 1 && O.mu != 2) ||
       (O.precision != IGAMG_FP64 && O.precision != IGAMG_MIXED) || O.maxit < 1 || O.inner_maxit < 1 ||
