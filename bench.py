@@ -212,14 +212,16 @@ def log(msg):
     print(f"[bench] {msg}", file=sys.stderr, flush=True)
 
 
-def run(workload, prob, precision, steps, warmup, dev, fd_mfma=0, profile_steps=3):
+def run(workload, prob, precision, steps, warmup, dev, fd_mfma=0, profile_steps=3, persistent=0):
     import torch
     from paper_1804_02539_amd import igamg
-    opts = igamg.default_options(precision=igamg.MIXED if precision == "mixed" else igamg.FP64, fd_mfma=fd_mfma)
+    opts = igamg.default_options(precision=igamg.MIXED if precision == "mixed" else igamg.FP64, fd_mfma=fd_mfma,
+                                 persistent=persistent)
     t0 = time.perf_counter()
     S = igamg.Solver(prob, opts, device=dev)
     setup_s = time.perf_counter() - t0
-    log(f"{workload} {precision}{' fd_mfma' if fd_mfma else ''}: setup {setup_s:.1f} s, N = {S.N}")
+    log(f"{workload} {precision}{' fd_mfma' if fd_mfma else ''}{' persistent' if persistent else ''}: "
+        f"setup {setup_s:.1f} s, N = {S.N}")
     f = torch.as_tensor(rhs_for(prob, S), device=dev)
     u = torch.empty_like(f)
     stream = torch.cuda.current_stream()
@@ -453,6 +455,8 @@ def main():
     ap.add_argument("--fd-mfma", action="store_true",
                     help="also time the mixed solver with the smoother's mode products on the matrix cores, with "
                          "FP32 operands (fd_mfma = 1) and with bfloat16 operands (fd_mfma = 3)")
+    ap.add_argument("--persistent", action="store_true",
+                    help="also time every solve with the persistent coarse cycle (options.persistent = 1)")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="first fill and copy a 256 MiB buffer: dispatches of known size against "
                          "which hardware byte counters are scaled")
@@ -502,6 +506,9 @@ def main():
         rhs_cpu = rhs_for(prob, S)
         del S
         torch.cuda.empty_cache()
+        if a.persistent:
+            _, runs["fp64_persistent"] = run(a.workload, prob, "fp64", a.steps, a.warmup, dev, persistent=1,
+                                             profile_steps=a.profile_steps)
     if a.precision in ("both", "mixed"):
         S, runs["mixed"] = run(a.workload, prob, "mixed", a.steps, a.warmup, dev, profile_steps=a.profile_steps)
         N_free, N_local = S.N, S.N_local
@@ -510,6 +517,9 @@ def main():
                                            profile_steps=a.profile_steps)
             _, runs["mixed_fd_bf16"] = run(a.workload, prob, "mixed", a.steps, a.warmup, dev, fd_mfma=3,
                                            profile_steps=a.profile_steps)
+        if a.persistent:
+            _, runs["mixed_persistent"] = run(a.workload, prob, "mixed", a.steps, a.warmup, dev, persistent=1,
+                                              profile_steps=a.profile_steps)
         rhs_cpu = rhs_for(prob, S)
         del S
         torch.cuda.empty_cache()
@@ -548,6 +558,9 @@ def main():
     if "mixed_fd_mfma" in runs and "mixed" in runs:
         out["mixed_fd_mfma_vs_default"] = runs["mixed_fd_mfma"]["value"] / runs["mixed"]["value"]
         out["mixed_fd_bf16_vs_default"] = runs["mixed_fd_bf16"]["value"] / runs["mixed"]["value"]
+    for prec in ("fp64", "mixed"):
+        if f"{prec}_persistent" in runs and prec in runs:
+            out[f"{prec}_persistent_vs_default"] = runs[f"{prec}_persistent"]["value"] / runs[prec]["value"]
     secondary = {}
     for wname in [w for w in a.secondary.split(",") if w and w != a.workload]:
         sprob = make_problem(wname)

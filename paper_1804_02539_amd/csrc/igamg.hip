@@ -179,6 +179,8 @@ static void plan_level_data(Bump& b, const LevelH& L, DevLevel& D, LevelData<T>&
 // Rows up to which a level belongs to the persistent coarse cycle: below
 // this size a level's kernels are launch-bound.
 constexpr int64_t TAIL_MAX_ROWS = 1 << 16;
+// workgroups of the persistent launch
+constexpr int TAIL_GRID = 128;
 
 // The work list of cycle(Lp) from a zero guess (Algorithm 1 with mu = 1) over
 // the levels 1..Lp, Lp the largest level below the finest whose levels are
@@ -194,10 +196,13 @@ static void tail_program(igamg_ctx& C, igamg_ctx::Tail& tl) {
   if (Lp < 1) return;
   std::vector<Phase>& prog = tl.host;
   int64_t total = 0;
+  // a phase has at most TAIL_GRID tickets, as many as the launch has workgroups
   auto push = [&](Phase ph) {
     if (ph.n <= 0) return;
+    ph.chunk = (ph.n + TAIL_GRID - 1) / TAIL_GRID;
+    ph.ntk = (ph.n + ph.chunk - 1) / ph.chunk;
     ph.first = total;
-    total += ph.n;
+    total += ph.ntk;
     prog.push_back(ph);
   };
   auto band = [&](int l) {
@@ -311,10 +316,11 @@ static void tail_program(igamg_ctx& C, igamg_ctx::Tail& tl) {
   tl.level = Lp;
   tl.nph = (int)prog.size();
   tl.total = total;
-  tl.grid = 512;
+  tl.grid = TAIL_GRID;
   tl.lds = 0;
   for (int l = 1; l <= Lp; ++l)
     tl.lds = std::max(tl.lds, cycle_tail_lds(C.dl[l].fd_maxm, C.dl[l].max_dense, sizeof(T)));
+  if (tl.lds > 64 * 1024) tl = igamg_ctx::Tail{};   // pieces too large for one workgroup's default LDS
 }
 
 static size_t plan(igamg_ctx& C, char* base) {
@@ -389,10 +395,16 @@ static size_t plan(igamg_ctx& C, char* base) {
     tl = igamg_ctx::Tail{};
     if (prec == 0) tail_program<double>(C, tl);
     else tail_program<float>(C, tl);
-    if (tl.nph > 0) {
-      tl.prog = b.take<Phase>(tl.host.size());
-      tl.ctr = b.take<unsigned long long>(tl.host.size() + 2);
+    // reserved by a bound that does not depend on the level data, which the
+    // sizing pass has not filled in: per level nu pre- and post-smoothing
+    // steps of at most 4 phases, a residual, a restriction and a
+    // prolongation; the coarse gather and product
+    const int max_phases = (H.opt.persistent && H.opt.mu == 1) ? (int)C.dl.size() * (3 + 8 * H.opt.nu) + 2 : 0;
+    if (max_phases > 0) {
+      tl.prog = b.take<Phase>((size_t)max_phases);
+      tl.ctr = b.take<unsigned long long>((size_t)max_phases + 2);
     }
+    if (tl.nph > max_phases) tl = igamg_ctx::Tail{};
   }
   C.part = b.take<double>(2 * RED_BLOCKS);
   C.scal = b.take<double>(16);

@@ -1454,17 +1454,19 @@ void launch_coarse(const double* Ainv, const T* f0, double* b, T* u0, const int6
 // ---------------------------------------------------------------------------
 // The coarse levels of a cycle in one persistent launch.  The phases of the
 // cycle below a level (smoothing products, residuals, transfers, the coarse
-// solve) form one work list; a workgroup takes the next ticket, waits until
-// every item of the previous phase has finished (a completion counter per
-// phase), runs its item with the same body as the separate launch would,
-// and counts it done.  Tickets are taken in order, so every item a
-// workgroup waits for was taken before by a running workgroup that is not
-// itself waiting on a later ticket: the list always drains, whatever number
-// of workgroups is resident (no co-residency assumption, no grid barrier).
-// The counters are at agent scope with release/acquire fences, so results
-// written on one XCD are seen on another.  ctr[0] is the ticket counter,
-// ctr[1 + k] the completed items of phase k, ctr[1 + nph] an overflow flag
-// set if a wait ever exceeded its (very large) spin bound.
+// solve) form one work list; a workgroup takes the next ticket (a run of
+// consecutive items of one phase), waits until every ticket of the previous
+// phase has finished (a completion counter per phase), runs its items with
+// the same bodies as the separate launches would, and counts the ticket
+// done.  Tickets are taken in order, so every ticket a workgroup waits for
+// was taken before by a running workgroup that is not itself waiting on a
+// later ticket: the list always drains, whatever number of workgroups is
+// resident (no co-residency assumption, no grid barrier).  The counters are
+// at agent scope with release/acquire fences, so results written on one XCD
+// are seen on another; the wait polls with relaxed loads and acquires once,
+// since an acquire invalidates the L2 of the waiting XCD.  ctr[0] is the
+// ticket counter, ctr[1 + k] the finished tickets of phase k, ctr[1 + nph]
+// an overflow flag set if a wait ever exceeded its (very large) spin bound.
 // ---------------------------------------------------------------------------
 template <int D, int P, typename T>
 __device__ __forceinline__ void tail_item(const Phase& ph, int64_t t) {
@@ -1540,7 +1542,7 @@ __device__ __forceinline__ void tail_item(const Phase& ph, int64_t t) {
   }
 }
 
-constexpr unsigned TAIL_SPIN_LIMIT = 1u << 26;   // about a second of polling; never reached when the list drains
+constexpr unsigned TAIL_SPIN_LIMIT = 1u << 22;   // seconds of polling; a phase takes microseconds
 
 template <int D, int P, typename T>
 __global__ __launch_bounds__(256) void k_cycle_tail(const Phase* __restrict__ prog, int nph, int64_t total,
@@ -1556,26 +1558,32 @@ __global__ __launch_bounds__(256) void k_cycle_tail(const Phase* __restrict__ pr
     while (ph + 1 < nph && t >= prog[ph + 1].first) ++ph;
     if (ph > 0 && ready < ph) {
       if (threadIdx.x == 0) {
-        const unsigned long long need = (unsigned long long)prog[ph - 1].n;
+        const unsigned long long need = (unsigned long long)prog[ph - 1].ntk;
         unsigned spins = 0;
-        while (__hip_atomic_load(&ctr[ph], __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT) < need) {
+        while (__hip_atomic_load(&ctr[ph], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) < need) {
           __builtin_amdgcn_s_sleep(1);
           if (++spins > TAIL_SPIN_LIMIT) {
             __hip_atomic_store(&ctr[1 + nph], 1ull, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
             break;
           }
         }
+        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
       }
       __syncthreads();
-      __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
       ready = ph;
     }
-    tail_item<D, P, T>(prog[ph], t - prog[ph].first);
-    __syncthreads();
-    if (threadIdx.x == 0) {
-      __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
-      atomicAdd(&ctr[1 + ph], 1ull);
+    const Phase& P_ = prog[ph];
+    const int64_t i0 = (t - P_.first) * P_.chunk;
+    const int64_t i1 = i0 + P_.chunk < P_.n ? i0 + P_.chunk : P_.n;
+    for (int64_t i = i0; i < i1; ++i) {
+      if (i > i0) __syncthreads();         // the item bodies reuse the LDS
+      tail_item<D, P, T>(P_, i);
     }
+    // every wave makes its own stores visible at agent scope before the
+    // workgroup counts the ticket done
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
+    __syncthreads();
+    if (threadIdx.x == 0) atomicAdd(&ctr[1 + ph], 1ull);
   }
 }
 

@@ -63,8 +63,9 @@ struct FDItem {
 };
 
 // One phase of the persistent coarse cycle (k_cycle_tail): `n` work items,
-// item t is block (t % gx, t / gx) of the launch the phase replaces, and its
-// tickets are first .. first + n - 1.  Pointers and scalars by kind:
+// item t is block (t % gx, t / gx) of the launch the phase replaces; ticket
+// first + j covers items j*chunk .. min(n, (j+1)*chunk) - 1, ntk tickets in
+// all.  Pointers and scalars by kind:
 //   BAND      a: band, u, f, r, bpatch, pd;                        resid
 //   FD_FWD    a: items, dense, densemat, mat, src, u, if_ptr, if_idx, scr;  nitems, tau, add, rb
 //   FD_MID    a: items, mat, scr
@@ -79,6 +80,8 @@ struct Phase {
   int gx;
   int64_t n;
   int64_t first;
+  int64_t ntk;
+  int64_t chunk;
   int resid, add, w, nitems, rb, pad;
   int64_t len;
   double tau;
