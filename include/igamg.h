@@ -104,9 +104,9 @@ typedef struct {
                             operands rounded to bfloat16 (v_mfma_f32_16x16x16bf16_1k, FP32
                             accumulation) */
   int coarse_factor;     /* factorization of the dense coarse matrix: 0 (default) on the host up to
-                            3000 coarse unknowns and on the device (rocSOLVER Cholesky, then the
-                            inverse by blocked solves against I, in the workspace) above; 1 always on
-                            the host; 2 always on the device; at most 100000 coarse unknowns */
+                            3000 coarse unknowns and on the device (the library's tiled Cholesky
+                            factorization and inversion, in the workspace) above; 1 always on the
+                            host; 2 always on the device; at most 100000 coarse unknowns */
   int autotune;          /* 1 (default): at setup, time the smoother variants of every level and
                             precision on the device and keep the fastest (igamg_tuning); 0: vector
                             FMAs with 8-column chunks */
@@ -157,9 +157,9 @@ int igamg_workspace_size(const igamg_problem* prob, const igamg_options* opts, s
  * on `stream`.  By default (options.assembly) the levels above the coarsest
  * are assembled on the device, directly into the workspace, with a part of
  * the workspace as scratch.  Coarse problems factored on the device (see
- * options.coarse_factor) are factored there by rocSOLVER, which gets a part of
- * the workspace as scratch; then the smoother variants are autotuned (see
- * igamg_tuning).  Synchronises the stream before returning.  The handle
+ * options.coarse_factor) are factored and inverted there by the library's own
+ * kernels, with a part of the workspace as scratch; then the smoother
+ * variants are autotuned (see igamg_tuning).  Synchronises the stream before returning.  The handle
  * keeps host copies of nothing large; the workspace must outlive it.
  * IGAMG_VERBOSE set in the environment prints one line per setup phase.
  * With workspace == NULL the handle stays on the host (for igamg_export and
@@ -176,8 +176,8 @@ int igamg_setup(const igamg_problem* prob, const igamg_options* opts, void* work
  * process ends), so the workspace is smaller than igamg_workspace_size():
  * with workspace == NULL the call only writes the bytes it needs to *needed
  * (out may then be NULL).  No hipMalloc, hipFree, pinned host memory or
- * library allocation is made: the coarse matrix is factored on the host
- * (EINVAL above 3000 coarse unknowns or with options.coarse_factor = 2), the
+ * library allocation is made (the coarse matrix is factored as
+ * options.coarse_factor says, on the device in the workspace), the
  * handle reads its scalars back into ordinary host memory and so launches
  * its solves directly (options.graphs is ignored), and a problem whose
  * setup scratch exceeds the static array is rejected with EINVAL.  Calls are

@@ -29,7 +29,7 @@ def build():
     os.makedirs(BUILD, exist_ok=True)
     objs = []
     procs = []
-    for src in ["kernels.hip", "assemble.hip", "igamg.hip"]:
+    for src in ["kernels.hip", "assemble.hip", "coarse.hip", "igamg.hip"]:
         obj = os.path.join(BUILD, src + ".o")
         cmd = [HIPCC] + HIP_FLAGS + ["-c", os.path.join(CSRC, src), "-o", obj]
         print(" ".join(cmd), flush=True)
@@ -45,7 +45,7 @@ def build():
             raise SystemExit("compilation failed")
     tmp = LIB + ".tmp"
     run([HIPCC, "-shared", "-fPIC", f"--offload-arch={ARCH}", "-o", tmp] + objs +
-        ["-pthread", "-L/opt/rocm/lib", "-lrocsolver", "-lrocblas"])
+        ["-pthread"])
     os.replace(tmp, LIB)
     return LIB
 

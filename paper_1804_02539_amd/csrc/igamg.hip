@@ -4,8 +4,6 @@
 // Every step of the cycle runs in the kernels of kernels.hip; the host only
 // sequences launches on the caller's stream.
 #include <hip/hip_runtime.h>
-#include <rocblas/rocblas.h>
-#include <rocsolver/rocsolver.h>
 
 #include <chrono>
 #include <cmath>
@@ -94,25 +92,20 @@ struct Bump {
 
 }  // namespace
 
-// rocSOLVER scratch for the device Cholesky and inverse of an n x n coarse
-// matrix (measured: 1.15 n^2 doubles at n = 30056), with margin
-// device coarse factorization: the factor (n x n, column-major, padded to 256
-// bytes) followed by rocBLAS's workspace, a quarter of the factor's size plus
-// 256 MiB (the inverse is formed in column blocks narrow enough to fit it)
-static size_t coarse_factor_bytes(int64_t n) { return ((size_t)n * (size_t)n * sizeof(double) + 255) & ~(size_t)255; }
-static size_t coarse_ws_bytes(int64_t n) {
-  return coarse_factor_bytes(n) + (size_t)(0.25 * 8.0 * (double)n * (double)n) + ((size_t)256 << 20);
-}
+// scratch of the device coarse factorization: the factor and the inverse
+// factor, each in packed lower tiles
+static size_t coarse_ws_bytes(int64_t n) { return 2 * (size_t)coarse_packed_entries(n) * sizeof(double); }
 
 struct igamg_ctx {
   Hierarchy H;
   int d = 2, p = 2, L = 1;
   bool mixed = false;
   std::vector<DevLevel> dl;
-  double* Ainv = nullptr;
-  void* coarse_ws = nullptr;      // rocSOLVER scratch (device coarse factorization only; overlaps level data)
+  double* Ainv = nullptr;          // A_0^{-1}, packed lower tiles
+  double* cpart = nullptr;         // partial products of the coarse solve (coarse_tiles(N0)^2 * 64)
+  void* coarse_ws = nullptr;       // device coarse factorization scratch (overlaps level data)
   size_t coarse_ws_bytes = 0;
-  int64_t* coarse_info = nullptr;
+  int* coarse_info = nullptr;
   size_t scratch_at = 0;          // workspace offset where the level data (and that scratch) begins
   // device assembly scratch (setup only; after the level data): per-patch
   // det J sign flags, a level's tables, one element slab's intermediates
@@ -286,14 +279,23 @@ static void tail_program(igamg_ctx& C, igamg_ctx::Tail& tl) {
     const void* a[] = {X0.f, C.cb, D0.gptr, D0.gidx};
     for (int i = 0; i < 4; ++i) g.a[i] = a[i];
     push(g);
+    const int64_t Tc = coarse_tiles(C.N0);
     Phase m{};
-    m.kind = PH_GEMV;
+    m.kind = PH_CTILES;
     m.gx = 1;
     m.len = C.N0;
-    m.n = (C.N0 + 3) / 4;
-    const void* b2[] = {C.Ainv, C.cb, X0.u, D0.gptr, D0.gidx};
-    for (int i = 0; i < 5; ++i) m.a[i] = b2[i];
+    m.n = Tc * (Tc + 1) / 2;
+    const void* b2[] = {C.Ainv, C.cb, C.cpart};
+    for (int i = 0; i < 3; ++i) m.a[i] = b2[i];
     push(m);
+    Phase r{};
+    r.kind = PH_CREDUCE;
+    r.gx = 1;
+    r.len = C.N0;
+    r.n = (C.N0 + 255) / 256;
+    const void* b3[] = {C.cpart, X0.u, D0.gptr, D0.gidx};
+    for (int i = 0; i < 4; ++i) r.a[i] = b3[i];
+    push(r);
   }
   for (int l = 1; l <= Lp; ++l) {
     DevLevel& F = C.dl[l];
@@ -327,14 +329,15 @@ static size_t plan(igamg_ctx& C, char* base) {
   Bump b{base};
   const Hierarchy& H = C.H;
   // the coarse inverse first: a device factorization uses the space after it,
-  // which the level data occupies later, as rocSOLVER's scratch
+  // which the level data occupies later, as its scratch
   C.N0 = H.lv[0].N;
-  C.Ainv = b.take<double>((size_t)C.N0 * C.N0);
+  C.Ainv = b.take<double>((size_t)coarse_packed_entries(C.N0));
+  C.cpart = b.take<double>((size_t)(coarse_tiles(C.N0) * coarse_tiles(C.N0) * COARSE_TILE));
   C.cb = b.take<double>(C.N0);
   const size_t scratch_at = (b.pos + 255) & ~size_t(255);
   size_t scratch_end = 0;
   if (coarse_on_device(H.opt, C.N0, true)) {
-    C.coarse_info = reinterpret_cast<int64_t*>(base ? base + scratch_at : nullptr);
+    C.coarse_info = reinterpret_cast<int*>(base ? base + scratch_at : nullptr);
     C.coarse_ws = base ? base + scratch_at + 256 : nullptr;
     C.coarse_ws_bytes = coarse_ws_bytes(C.N0);
     scratch_end = scratch_at + 256 + C.coarse_ws_bytes;
@@ -398,8 +401,8 @@ static size_t plan(igamg_ctx& C, char* base) {
     // reserved by a bound that does not depend on the level data, which the
     // sizing pass has not filled in: per level nu pre- and post-smoothing
     // steps of at most 4 phases, a residual, a restriction and a
-    // prolongation; the coarse gather and product
-    const int max_phases = (H.opt.persistent && H.opt.mu == 1) ? (int)C.dl.size() * (3 + 8 * H.opt.nu) + 2 : 0;
+    // prolongation; the coarse gather, tile products and sums
+    const int max_phases = (H.opt.persistent && H.opt.mu == 1) ? (int)C.dl.size() * (3 + 8 * H.opt.nu) + 3 : 0;
     if (max_phases > 0) {
       tl.prog = b.take<Phase>((size_t)max_phases);
       tl.ctr = b.take<unsigned long long>((size_t)max_phases + 2);
@@ -461,78 +464,46 @@ static void up(T* dst, const std::vector<T, Alloc>& src, hipStream_t st) {
 
 static std::vector<float> to_float(const std::vector<double>& v) { return std::vector<float>(v.begin(), v.end()); }
 
-// The exact coarse solver of large coarse problems (Sec. 4): Cholesky
-// A_0 = L L^T by rocSOLVER on the device, then A_0^{-1} = L^{-T} L^{-1} by
-// solving L L^T X = I in blocks of columns.  The 64-bit (ILP64) entry points
-// are used throughout: the 32-bit ones take n and lda as 32-bit integers, and
-// A_0 of a coarse grid with more than 46,340 unknowns has more than 2^31
-// entries.  A_0 and L live at the start of the scratch region (which the level
-// data occupies later), rocBLAS's workspace after them, and the inverse is
-// formed in place of the identity in its own region, so nothing is allocated.
-// One device factorization at a time per process: two of them running at
-// once from two threads (separate rocBLAS handles, streams and workspaces)
-// returned non-positive-definite factors for matrices that factor correctly
-// alone, in half of the overlapping setups measured.  Graph captures take the
-// same lock (request_graph).
-static std::mutex g_factor_mu;
-
-static void factor_coarse_on_device(igamg_ctx& C, hipStream_t st) {
-  std::lock_guard<std::mutex> factor_lock(g_factor_mu);
-  struct Handle {
-    rocblas_handle h = nullptr;
-    ~Handle() {
-      if (h) (void)rocblas_destroy_handle(h);
+// A symmetric n x n matrix (full, row-major) in packed lower tiles
+// (layout.hpp), padding rows and columns zero with `pad` on the diagonal.
+static DenseBuf pack_coarse_tiles(const double* A, int64_t n, double pad) {
+  const int64_t T = coarse_tiles(n);
+  DenseBuf out((size_t)coarse_packed_entries(n));
+  for (int64_t I = 0; I < T; ++I)
+    for (int64_t J = 0; J <= I; ++J) {
+      double* t = out.data() + coarse_tile_at(I, J);
+      for (int r = 0; r < COARSE_TILE; ++r) {
+        const int64_t i = I * COARSE_TILE + r;
+        for (int c = 0; c < COARSE_TILE; ++c) {
+          const int64_t j = J * COARSE_TILE + c;
+          t[r * COARSE_TILE + c] = (i < n && j < n) ? A[i * n + j] : (i == j ? pad : 0.0);
+        }
+      }
     }
-  } H;
-  auto ok = [](rocblas_status s, const char* what) {
-    if (s != rocblas_status_success)
-      throw SetupError{IGAMG_EDEVICE, std::string(what) + ": " + rocblas_status_to_string(s)};
-  };
+  return out;
+}
+
+// The exact coarse solver of large coarse problems (Sec. 4): A_0^{-1} formed
+// on the device by the library's own tiled Cholesky factorization and
+// inversion (coarse.hip) in the scratch region, which the level data
+// occupies later.  No library handle, allocation or lock is involved.
+static void factor_coarse_on_device(igamg_ctx& C, hipStream_t st) {
   const int64_t n = C.N0;
-  double* Lf = static_cast<double*>(C.coarse_ws);
-  const size_t lbytes = coarse_factor_bytes(n);
-  char* ws = static_cast<char*>(C.coarse_ws) + lbytes;
-  const size_t ws_bytes = C.coarse_ws_bytes - lbytes;
-  ok(rocblas_create_handle(&H.h), "rocblas_create_handle");
-  ok(rocblas_set_stream(H.h, st), "rocblas_set_stream");
-  auto query = [&](int64_t k) {
-    size_t need = 0;
-    ok(rocblas_start_device_memory_size_query(H.h), "rocblas_start_device_memory_size_query");
-    if (k == 0)
-      (void)rocsolver_dpotrf_64(H.h, rocblas_fill_lower, n, Lf, n, C.coarse_info);
-    else
-      (void)rocsolver_dpotrs_64(H.h, rocblas_fill_lower, n, k, Lf, n, C.Ainv, n);
-    ok(rocblas_stop_device_memory_size_query(H.h, &need), "rocblas_stop_device_memory_size_query");
-    return need;
-  };
-  const size_t need_f = query(0);
-  if (need_f > ws_bytes)
-    throw SetupError{IGAMG_ENOMEM, "coarse factorization needs " + std::to_string(need_f) + " bytes of workspace"};
-  int64_t kb = std::min<int64_t>(n, 8192);
-  while (kb > 64 && query(kb) > ws_bytes) kb /= 2;
-  if (query(kb) > ws_bytes)
-    throw SetupError{IGAMG_ENOMEM, "coarse inverse needs " + std::to_string(query(kb)) + " bytes of workspace"};
-  ok(rocblas_set_workspace(H.h, ws, ws_bytes), "rocblas_set_workspace");
-  int64_t info = 0;
-  ok(rocsolver_dpotrf_64(H.h, rocblas_fill_lower, n, Lf, n, C.coarse_info), "rocsolver_dpotrf_64");
+  double* Lt = static_cast<double*>(C.coarse_ws);
+  double* Yt = Lt + coarse_packed_entries(n);
+  {
+    const DenseBuf packed = pack_coarse_tiles(C.H.A0.data(), n, 1.0);
+    up(Lt, packed, st);
+  }
+  coarse_inverse(Lt, Yt, C.Ainv, n, C.coarse_info, st);
+  HIP_OK(hipGetLastError());
+  int info = 0;
   HIP_OK(hipMemcpyAsync(&info, C.coarse_info, sizeof(info), hipMemcpyDeviceToHost, st));
   HIP_OK(hipStreamSynchronize(st));
   if (info != 0)
-    throw SetupError{IGAMG_ENOTSPD, "coarse matrix is not positive definite (is any side Dirichlet?)"};
-  setup_progress("coarse Cholesky factor on the device; unknowns", (double)n);
-  launch_set_diagonal(C.Ainv, n, 1.0, st);   // the region is zero: now the identity
-  for (int64_t c0 = 0; c0 < n; c0 += kb) {
-    const int64_t k = std::min(kb, n - c0);
-    ok(rocsolver_dpotrs_64(H.h, rocblas_fill_lower, n, k, Lf, n, C.Ainv + c0 * n, n), "rocsolver_dpotrs_64");
-    if (n > 20000) {   // large inverses take minutes: one progress line per block
-      HIP_OK(hipStreamSynchronize(st));
-      setup_progress("coarse inverse, columns done", (double)(c0 + k));
-    }
-  }
-  // column j of the result is A_0^{-1} e_j; copying the lower triangle over the
-  // upper one makes the stored inverse exactly symmetric
-  launch_mirror_lower(C.Ainv, n, st);
-  HIP_OK(hipStreamSynchronize(st));
+    throw SetupError{IGAMG_ENOTSPD, "coarse matrix is not positive definite (pivot " + std::to_string(info) +
+                                        "; is any side Dirichlet?)"};
+  setup_progress("coarse inverse on the device; unknowns", (double)n);
 }
 
 // Assembles level l's banded patch matrices on the device, straight into its
@@ -569,29 +540,13 @@ static void upload(igamg_ctx& C, hipStream_t st) {
   Hierarchy& H = C.H;
   HIP_OK(hipMemsetAsync(C.ws, 0, C.bytes, st));
   if (!H.A0.empty()) {
-    // Under serving load (other setups and solves on the device), a device
-    // factorization of a matrix that factors correctly alone was measured to
-    // report an indefinite matrix about once in 280 setups; the cause is not
-    // identified.  The matrix is therefore uploaded and factored once more
-    // before ENOTSPD is reported (the failed attempt left the inverse region
-    // untouched: potrf stops before it is written).
-    for (int attempt = 0;; ++attempt) {
-      up(static_cast<double*>(C.coarse_ws), H.A0, st);
-      try {
-        factor_coarse_on_device(C, st);
-        break;
-      } catch (const SetupError& e) {
-        if (e.code != IGAMG_ENOTSPD || attempt == 1) throw;
-        setup_progress("device factorization reported an indefinite matrix; factoring again, unknowns", (double)C.N0);
-      }
-    }
+    factor_coarse_on_device(C, st);
     DenseBuf().swap(H.A0);
     // the scratch was lent from the level data: zero it again
     HIP_OK(hipMemsetAsync(static_cast<char*>(C.ws) + C.scratch_at, 0, C.bytes - C.scratch_at, st));
     HIP_OK(hipStreamSynchronize(st));
-    setup_progress("coarse matrix factored on the device; unknowns", (double)C.N0);
   } else {
-    up(C.Ainv, H.Ainv, st);
+    up(C.Ainv, pack_coarse_tiles(H.Ainv.data(), C.N0, 0.0), st);
   }
   for (size_t l = 0; l < H.lv.size(); ++l) {
     LevelH& L = H.lv[l];
@@ -740,7 +695,7 @@ static void smoother_apply(igamg_ctx& C, int l, const T* src, T* u, bool add, do
 template <typename T>
 static void coarse_solve(igamg_ctx& C, const T* f0, T* u0, hipStream_t st) {
   DevLevel& D = C.dl[0];
-  launch_coarse<T>(C.Ainv, f0, C.cb, u0, D.gptr, D.gidx, (int)C.N0, st);
+  launch_coarse<T>(C.Ainv, f0, C.cb, C.cpart, u0, D.gptr, D.gidx, C.N0, st);
 }
 
 template <typename T>
@@ -1135,15 +1090,10 @@ static void body(Req& q, int which, hipStream_t st) {
 // The PCG bodies of one hierarchy, captured once as graphs.  A body touches
 // only its own hierarchy's memory, so the same graph serves every batch the
 // hierarchy ever joins, whatever the other members are.
-// The hierarchy's graph of body `which`, captured on first use; nullptr
-// while a device factorization runs in another thread (rocBLAS can issue work
-// on the legacy stream, which invalidates any capture in progress), and the
-// caller then launches the body directly.
+// The hierarchy's graph of body `which`, captured on first use.
 static hipGraphExec_t request_graph(igamg_batch_ctx& B, Req& q, int which) {
   igamg_ctx& C = *q.C;
   if (!C.gx[which]) {
-    std::unique_lock<std::mutex> no_factorization(g_factor_mu, std::try_to_lock);
-    if (!no_factorization.owns_lock()) return nullptr;
     hipGraph_t g = nullptr;
     HIP_OK(hipStreamBeginCapture(B.ds, hipStreamCaptureModeThreadLocal));
     body(q, which, B.ds);
@@ -1162,17 +1112,9 @@ static void run_bodies(igamg_batch_ctx& B, const std::vector<int>& set, int whic
     return;
   }
   // one graph per hierarchy, each on a branch stream of its own: requests
-  // joining or leaving the batch cost no capture; a request whose graph
-  // cannot be captured yet runs its body directly, before the fork
+  // joining or leaving the batch cost no capture
   std::vector<hipGraphExec_t> gs;
-  for (int i : set) {
-    hipGraphExec_t g = request_graph(B, B.reqs[i], which);
-    if (g)
-      gs.push_back(g);
-    else
-      body(B.reqs[i], which, B.ds);
-  }
-  if (gs.empty()) return;
+  for (int i : set) gs.push_back(request_graph(B, B.reqs[i], which));
   if (gs.size() == 1) {
     HIP_OK(hipGraphLaunch(gs[0], B.ds));
     return;
@@ -1526,16 +1468,6 @@ int igamg_setup_noalloc(const igamg_problem* prob, const igamg_options* opts, vo
     C->d = C->H.prob.d;
     C->p = C->H.prob.p;
     C->L = C->H.prob.levels - 1;
-    {
-      Hierarchy T;
-      T.prob = C->H.prob;
-      T.opt = C->H.opt;
-      build_topology(T, false);
-      if (coarse_on_device(T.opt, T.lv[0].N, true))
-        throw SetupError{IGAMG_EINVAL, "the no-allocation setup factors the coarse matrix on the host only: at most " +
-                                           std::to_string(COARSE_HOST_MAX) + " coarse unknowns (this problem has " +
-                                           std::to_string(T.lv[0].N) + ") and options.coarse_factor != 2"};
-    }
     build_all(C->H, true);
     const size_t need = plan(*C, nullptr);
     if (C->setup_bytes > NOALLOC_SCRATCH_BYTES)

@@ -1078,25 +1078,6 @@ void launch_fd_inv_mfma(const FDItem* items, int nitems, int gridx, size_t lds, 
                        scr, (float)tau, (int)add);
 }
 
-// A[j + i n] = A[i + j n] for i > j: the column-major lower triangle copied
-// to the upper one (a symmetric matrix reads the same in either order); a
-// grid-stride loop, since n^2 may exceed what one dispatch can index
-__global__ __launch_bounds__(256) void k_mirror_lower(double* __restrict__ A, int64_t n) {
-  const int64_t tot = n * n;
-  const int64_t stride = (int64_t)gridDim.x * blockDim.x;
-  for (int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; t < tot; t += stride) {
-    const int64_t i = t % n, j = t / n;
-    if (i > j) A[j + i * n] = A[i + j * n];
-  }
-}
-
-void launch_mirror_lower(double* A, int64_t n, hipStream_t st) {
-  const int64_t tot = n * n;
-  if (tot <= 0) return;
-  const int64_t blocks = std::min<int64_t>((tot + 255) / 256, (int64_t)1 << 20);
-  hipLaunchKernelGGL(k_mirror_lower, dim3((unsigned)blocks), dim3(256), 0, st, A, n);
-}
-
 // the exact edge and vertex pieces' entries: sums of listed half-band
 // entries (setup only; one thread per entry, the list order fixes the sum)
 __global__ __launch_bounds__(256) void k_band_gather(const double* __restrict__ band, int nbh,
@@ -1118,17 +1099,6 @@ void launch_band_gather(const double* band, int nbh, const int64_t* ptr, const i
   if (ne <= 0) return;
   hipLaunchKernelGGL(k_band_gather, dim3((unsigned)((ne + 255) / 256)), dim3(256), 0, st, band, nbh, ptr, row, plane,
                      ne, out);
-}
-
-// A[i + i n] = v for i < n
-__global__ __launch_bounds__(256) void k_set_diagonal(double* __restrict__ A, int64_t n, double v) {
-  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (i < n) A[i + i * n] = v;
-}
-
-void launch_set_diagonal(double* A, int64_t n, double v, hipStream_t st) {
-  if (n <= 0) return;
-  hipLaunchKernelGGL(k_set_diagonal, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, st, A, n, v);
 }
 
 size_t fd_dense_lds(int maxm, size_t elem) { return ((size_t)maxm * maxm + maxm) * elem + 64; }
@@ -1417,38 +1387,122 @@ void launch_scatter(const double* glob, double* loc, const int64_t* ptr, const i
     hipLaunchKernelGGL(k_scatter_acc, grid, dim3(256), 0, st, glob, loc, ptr, idx, n);
 }
 
-// x = A_0^{-1} b (dense FP64, n x n row-major), one wavefront per row; x_i goes
-// to every local copy of coarse dof i (the restriction chi of the coarse solve)
+// x = A_0^{-1} b with the symmetric inverse in packed lower tiles (each
+// stored tile read once).  Tile (I, J), J < I, gives its product with b_J to
+// block row I and its transpose's product with b_I to block row J; a
+// diagonal tile (both triangles stored) gives only the first.  The partial
+// results go to part[(R * T + X) * 64 + r] for block row R and the other
+// block index X (each slot written by exactly one tile), and the second pass
+// sums the T slots of each row in a fixed order: the result does not depend
+// on the order in which tiles run.  Row i of x then goes to every local copy
+// of coarse dof i (the restriction chi of the coarse solve).
+__device__ __forceinline__ void tri_index(int64_t t, int64_t& a, int64_t& b) {
+  int64_t x = (int64_t)((sqrt(8.0 * (double)t + 1.0) - 1.0) * 0.5);
+  while (x * (x + 1) / 2 > t) --x;
+  while ((x + 1) * (x + 2) / 2 <= t) ++x;
+  a = x;
+  b = t - x * (x + 1) / 2;
+}
+
+// Sums v[0..2H) over the 64 lanes of a wavefront by halving: at each step a
+// lane keeps one half of its values (the upper if `lane & off`), adds the
+// partner's copy of that half and passes the other half on.  Returns the
+// full sum of value index `row` (written), equal on the four lanes that
+// differ only in bits 0 and 1.
+template <int H>
+__device__ __forceinline__ double lane_transpose_sum(const double (&v)[2 * H], int lane, int& row) {
+  double k[H];
+  const bool up = lane & (2 * H * 2);   // offsets 32, 16, 8, 4 for H = 8, 4, 2, 1
+#pragma unroll
+  for (int i = 0; i < H; ++i) {
+    const double give = up ? v[i] : v[H + i];
+    k[i] = (up ? v[H + i] : v[i]) + __shfl_xor(give, 2 * H * 2, 64);
+  }
+  row += up ? H : 0;
+  if constexpr (H == 1) {
+    double s = k[0];
+    s += __shfl_xor(s, 1, 64);
+    s += __shfl_xor(s, 2, 64);
+    return s;
+  } else {
+    return lane_transpose_sum<H / 2>(k, lane, row);
+  }
+}
+
+__device__ __forceinline__ void coarse_tiles_block(int64_t bx, const double* __restrict__ Ainv,
+                                                   const double* __restrict__ b, double* __restrict__ part,
+                                                   int64_t n) {
+  constexpr int CT = COARSE_TILE;
+  __shared__ double s_bj[CT], s_bi[CT], s_red[4][CT];
+  int64_t I, J;
+  tri_index(bx, I, J);
+  const int64_t T = coarse_tiles(n);
+  const int c = threadIdx.x & (CT - 1), g = threadIdx.x >> 6;
+  if (threadIdx.x < CT) {
+    const int64_t j = J * CT + threadIdx.x;
+    s_bj[threadIdx.x] = j < n ? b[j] : 0.0;
+  } else if (threadIdx.x < 2 * CT) {
+    const int64_t i = I * CT + threadIdx.x - CT;
+    s_bi[threadIdx.x - CT] = i < n ? b[i] : 0.0;
+  }
+  __syncthreads();
+  // wavefront g holds rows 16 g .. 16 g + 15 of the tile, lane c column c
+  const double* tile = Ainv + coarse_tile_at(I, J);
+  double v[16];
+#pragma unroll
+  for (int i = 0; i < 16; ++i) v[i] = tile[(g * 16 + i) * CT + c];
+  const double bj = s_bj[c];
+  double colsum = 0.0, pr[16];
+#pragma unroll
+  for (int i = 0; i < 16; ++i) {
+    pr[i] = v[i] * bj;
+    colsum += v[i] * s_bi[g * 16 + i];
+  }
+  s_red[g][c] = colsum;
+  int row = 0;
+  const double rs = lane_transpose_sum<8>(pr, c, row);
+  if ((c & 3) == 0) part[(I * T + J) * CT + g * 16 + row] = rs;
+  __syncthreads();
+  if (I != J && threadIdx.x < CT)
+    part[(J * T + I) * CT + threadIdx.x] = (s_red[0][threadIdx.x] + s_red[1][threadIdx.x]) +
+                                           (s_red[2][threadIdx.x] + s_red[3][threadIdx.x]);
+}
+
 template <typename T>
-__device__ __forceinline__ void coarse_gemv_block(int64_t bx, const double* __restrict__ Ainv,
-                                                  const double* __restrict__ b, T* __restrict__ u0,
-                                                  const int64_t* __restrict__ ptr, const int64_t* __restrict__ idx,
-                                                  int n) {
-  const int lane = threadIdx.x & 63;
-  const int row = (int)(bx * 4 + (threadIdx.x >> 6));
+__device__ __forceinline__ void coarse_reduce_block(int64_t bx, const double* __restrict__ part, T* __restrict__ u0,
+                                                    const int64_t* __restrict__ ptr, const int64_t* __restrict__ idx,
+                                                    int64_t n) {
+  const int64_t row = bx * 256 + threadIdx.x;
   if (row >= n) return;
-  const double* ar = Ainv + (int64_t)row * n;
+  const int64_t Tn = coarse_tiles(n);
+  const int64_t R = row / COARSE_TILE, r = row % COARSE_TILE;
+  const double* pr = part + R * Tn * COARSE_TILE + r;
   double s = 0.0;
-  for (int j = lane; j < n; j += 64) s += ar[j] * b[j];
-  for (int o = 32; o > 0; o >>= 1) s += __shfl_down(s, o, 64);
-  const int64_t c0 = ptr[row], c1 = ptr[row + 1];
-  s = __shfl(s, 0, 64);
-  for (int64_t c = c0 + lane; c < c1; c += 64) u0[idx[c]] = (T)s;
+  for (int64_t x = 0; x < Tn; ++x) s += pr[x * COARSE_TILE];
+  for (int64_t c = ptr[row]; c < ptr[row + 1]; ++c) u0[idx[c]] = (T)s;
+}
+
+__global__ __launch_bounds__(256) void k_coarse_tiles(const double* __restrict__ Ainv, const double* __restrict__ b,
+                                                      double* __restrict__ part, int64_t n) {
+  coarse_tiles_block(blockIdx.x, Ainv, b, part, n);
 }
 
 template <typename T>
-__global__ __launch_bounds__(256) void k_coarse_gemv(const double* __restrict__ Ainv, const double* __restrict__ b,
-                                                     T* __restrict__ u0, const int64_t* __restrict__ ptr,
-                                                     const int64_t* __restrict__ idx, int n) {
-  coarse_gemv_block<T>(blockIdx.x, Ainv, b, u0, ptr, idx, n);
+__global__ __launch_bounds__(256) void k_coarse_reduce(const double* __restrict__ part, T* __restrict__ u0,
+                                                       const int64_t* __restrict__ ptr,
+                                                       const int64_t* __restrict__ idx, int64_t n) {
+  coarse_reduce_block<T>(blockIdx.x, part, u0, ptr, idx, n);
 }
 
 template <typename T>
-void launch_coarse(const double* Ainv, const T* f0, double* b, T* u0, const int64_t* ptr, const int64_t* idx, int n,
-                   hipStream_t st) {
+void launch_coarse(const double* Ainv, const T* f0, double* b, double* part, T* u0, const int64_t* ptr,
+                   const int64_t* idx, int64_t n, hipStream_t st) {
+  if (n <= 0) return;
+  const int64_t Tn = coarse_tiles(n);
   hipLaunchKernelGGL((k_gather_dist<T, double>), dim3((unsigned)((n + 255) / 256)), dim3(256), 0, st, f0, b, ptr, idx,
-                     (int64_t)n);
-  hipLaunchKernelGGL(k_coarse_gemv<T>, dim3((n + 3) / 4), dim3(256), 0, st, Ainv, b, u0, ptr, idx, n);
+                     n);
+  hipLaunchKernelGGL(k_coarse_tiles, dim3((unsigned)(Tn * (Tn + 1) / 2)), dim3(256), 0, st, Ainv, b, part, n);
+  hipLaunchKernelGGL(k_coarse_reduce<T>, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, st, part, u0, ptr, idx, n);
 }
 
 // ---------------------------------------------------------------------------
@@ -1532,10 +1586,13 @@ __device__ __forceinline__ void tail_item(const Phase& ph, int64_t t) {
       gather_dist_block<T, double>(t, static_cast<const T*>(a[0]), const_cast<double*>(static_cast<const double*>(a[1])),
                                    static_cast<const int64_t*>(a[2]), static_cast<const int64_t*>(a[3]), ph.len);
       break;
-    case PH_GEMV:
-      coarse_gemv_block<T>(t, static_cast<const double*>(a[0]), static_cast<const double*>(a[1]),
-                           const_cast<T*>(static_cast<const T*>(a[2])), static_cast<const int64_t*>(a[3]),
-                           static_cast<const int64_t*>(a[4]), (int)ph.len);
+    case PH_CTILES:
+      coarse_tiles_block(t, static_cast<const double*>(a[0]), static_cast<const double*>(a[1]),
+                         const_cast<double*>(static_cast<const double*>(a[2])), ph.len);
+      break;
+    case PH_CREDUCE:
+      coarse_reduce_block<T>(t, static_cast<const double*>(a[0]), const_cast<T*>(static_cast<const T*>(a[1])),
+                             static_cast<const int64_t*>(a[2]), static_cast<const int64_t*>(a[3]), ph.len);
       break;
     default:
       break;
@@ -1840,8 +1897,8 @@ void launch_add_f32(double* x, const float* d, int64_t n, hipStream_t st) {
                                    int, const uint8_t*, hipStream_t);                                                  \
   template void launch_prolong_add<T>(int, const T*, T*, const PatchDev*, const int*, int64_t, const int64_t*,         \
                                       const T*, int, const uint8_t*, hipStream_t);                                     \
-  template void launch_coarse<T>(const double*, const T*, double*, T*, const int64_t*, const int64_t*, int,            \
-                                 hipStream_t);                                                                         \
+  template void launch_coarse<T>(const double*, const T*, double*, double*, T*, const int64_t*, const int64_t*,       \
+                                 int64_t, hipStream_t);                                                                \
   template void launch_dot<T>(const T*, const T*, int64_t, double*, double*, int, int, hipStream_t);                   \
   template void launch_dot2_flex<T>(const T*, const T*, const T*, int64_t, double*, double*, hipStream_t);             \
   template void launch_norm2_dist<T>(T*, const int64_t*, const int64_t*, int64_t, double*, double*, int, bool,        \

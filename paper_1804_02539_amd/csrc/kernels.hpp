@@ -66,8 +66,14 @@ void launch_gather(const double* loc, double* glob, const int64_t* ptr, const in
 void launch_scatter(const double* glob, double* loc, const int64_t* ptr, const int64_t* idx, int64_t n, bool dist,
                     hipStream_t st);
 template <typename T>
-void launch_coarse(const double* Ainv, const T* f0, double* b, T* u0, const int64_t* ptr, const int64_t* idx, int n,
-                   hipStream_t st);
+void launch_coarse(const double* Ainv, const T* f0, double* b, double* part, T* u0, const int64_t* ptr,
+                   const int64_t* idx, int64_t n, hipStream_t st);
+// A_0^{-1} of the dense SPD coarse matrix in packed lower tiles (layout.hpp):
+// Lt holds A_0 on entry (identity padding) and its Cholesky factor on exit,
+// Yt (zero on entry) the inverse factor L^{-1}, Ainv (zero on entry) the
+// inverse.  *info (zero on entry) gets 1 + the first column whose pivot is
+// not positive and finite.  Stream-ordered, no allocation, no library.
+void coarse_inverse(double* Lt, double* Yt, double* Ainv, int64_t n, int* info, hipStream_t st);
 
 template <typename T>
 void launch_dot(const T* a, const T* b, int64_t n, double* part, double* scal, int slot, int op, hipStream_t st);
@@ -84,8 +90,6 @@ template <typename T>
 void launch_fill(T* x, int64_t n, double v, hipStream_t st);
 template <typename T>
 void launch_copy(T* y, const T* x, int64_t n, hipStream_t st);
-void launch_mirror_lower(double* A, int64_t n, hipStream_t st);
-void launch_set_diagonal(double* A, int64_t n, double v, hipStream_t st);
 void launch_to_f32(float* y, const double* x, int64_t n, hipStream_t st);
 
 // device assembly (assemble.hip): doubles of one element slab's metric (Gs),

@@ -73,8 +73,11 @@ struct FDItem {
 //   RESTRICT  a: rf, rc, pd, bpatch_c, tidx, tval, isfree_c;       w
 //   PROLONG   a: uc, uf, pd, bpatch_f, tidx, tval, isfree_f;       w
 //   GATHER    a: loc, glob (double), ptr, idx;                     len
-//   GEMV      a: Ainv, b, u0, ptr, idx;                            len
-enum PhaseKind : int { PH_BAND = 0, PH_FD_FWD, PH_FD_MID, PH_FD_INV, PH_RESTRICT, PH_PROLONG, PH_GATHER, PH_GEMV };
+//   CTILES    a: Ainv (packed tiles), b, part;                     len
+//   CREDUCE   a: part, u0, ptr, idx;                               len
+enum PhaseKind : int {
+  PH_BAND = 0, PH_FD_FWD, PH_FD_MID, PH_FD_INV, PH_RESTRICT, PH_PROLONG, PH_GATHER, PH_CTILES, PH_CREDUCE
+};
 struct Phase {
   int kind;
   int gx;
@@ -87,6 +90,18 @@ struct Phase {
   double tau;
   const void* a[10];
 };
+
+// The dense coarse inverse A_0^{-1} (and the Cholesky factor it is formed
+// from) in packed lower tiles: n is padded to T = ceil(n / COARSE_TILE) tiles
+// per side, tile (I, J), J <= I, holds rows COARSE_TILE*I .. and columns
+// COARSE_TILE*J .. row-major at entry coarse_tile_at(I, J).  Diagonal tiles
+// hold both triangles; padding rows and columns hold the identity.
+constexpr int COARSE_TILE = 64;
+constexpr int64_t coarse_tiles(int64_t n) { return (n + COARSE_TILE - 1) / COARSE_TILE; }
+constexpr int64_t coarse_tile_at(int64_t I, int64_t J) {
+  return (I * (I + 1) / 2 + J) * (int64_t)COARSE_TILE * COARSE_TILE;
+}
+constexpr int64_t coarse_packed_entries(int64_t n) { return coarse_tile_at(coarse_tiles(n), 0); }
 
 // A piece applied by a dense inverse (edges, vertices).
 struct DensePiece {

@@ -125,7 +125,7 @@ def test_largest_degree_matches_oracle(torch_cuda):
 
 def test_singular_coarse_matrix_on_the_device_reports_enotspd(torch_cuda):
     # no Dirichlet side: the coarse matrix is singular; the device
-    # factorization (forced here) reports it, after its one refactorization
+    # factorization (forced here) reports it
     from paper_1804_02539_amd import igamg
     from paper_1804_02539_amd import workloads as W
     bad = W.box_grid(2, [2, 1], 2, 1, 2, gdeg=1, dirichlet_sides=[])
