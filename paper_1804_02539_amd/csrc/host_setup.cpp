@@ -914,8 +914,10 @@ static void make_smoother(const ProblemH& P, const Options& O, LevelH& L) {
     const Key key = key1d(k, c);
     auto it = cache.find(key);
     if (it == cache.end()) {
+      // interior functions: n - 2 = nel + p - 2 (checked before the eigenproblem)
+      if ((int64_t)key.first.size() - 1 + p - 2 > MAX_FD)
+        fail(IGAMG_EINVAL, "patch too fine for the FD smoother (n-2 > " + std::to_string(MAX_FD) + ")");
       OneD o = one_d(p, key.first, key.second, O.s1_sigma != 0);
-      if (o.m > MAX_FD) fail(IGAMG_EINVAL, "patch too fine for the FD smoother (n-2 > 84)");
       Uoff[key] = (int64_t)L.fdmat.size();
       L.fdmat.insert(L.fdmat.end(), o.U.begin(), o.U.end());
       for (int i = 0; i < o.m; ++i)

@@ -975,9 +975,12 @@ static void tune_level(igamg_ctx& C, int l, hipStream_t st) {
   DevLevel& D = C.dl[l];
   int& v = D.fdv[fp32 ? 1 : 0];
   const Options& O = C.H.opt;
-  if (fp32 && O.fd_mfma == 1) { v = D.max_m2 == 1 ? IGAMG_FD_FUSED : IGAMG_FD_MFMA; return; }
+  // the matrix-core variants stage whole tensors in LDS: sides up to FD_LDS_M
+  const bool mfma_ok = D.fd_maxm <= FD_LDS_M && D.max_dense <= FD_LDS_M;
+  if (fp32 && O.fd_mfma == 1 && mfma_ok) { v = D.max_m2 == 1 ? IGAMG_FD_FUSED : IGAMG_FD_MFMA; return; }
   if (fp32 && O.fd_mfma == 2) { v = IGAMG_FD_VEC8; return; }
-  if (fp32 && O.fd_mfma == 3) { v = IGAMG_FD_MFMA_BF16; return; }
+  if (fp32 && O.fd_mfma == 3 && mfma_ok) { v = IGAMG_FD_MFMA_BF16; return; }
+  if (fp32 && O.fd_mfma != 0 && !mfma_ok) { v = IGAMG_FD_VEC8; return; }
   if (!O.autotune || D.nfd + D.ndense == 0) { v = IGAMG_FD_VEC8; return; }
   const std::string key = tune_key(C, l, fp32);
   {
@@ -987,8 +990,8 @@ static void tune_level(igamg_ctx& C, int l, hipStream_t st) {
     if (it != g_tune.end()) { v = it->second; return; }
   }
   std::vector<int> cand{IGAMG_FD_VEC8, IGAMG_FD_VEC4};
-  if (fp32) cand.push_back(IGAMG_FD_MFMA);
-  if (fp32 && D.max_m2 == 1) cand.push_back(IGAMG_FD_FUSED);
+  if (fp32 && mfma_ok) cand.push_back(IGAMG_FD_MFMA);
+  if (fp32 && mfma_ok && D.max_m2 == 1) cand.push_back(IGAMG_FD_FUSED);
   int best = IGAMG_FD_VEC8;
   double best_ms = 1e300;
   for (int c : cand) {

@@ -366,9 +366,11 @@ hipError_t launch_band(int d, int p, const T* band, const T* u, const T* f, T* r
 // ---------------------------------------------------------------------------
 constexpr int FD_RB = 8;   // widest chunk; also the column stride of the LDS tile C
 // columns of a chunk per thread: a 256-thread block has 256 / m0 >= 3 row
-// groups for m0 <= MAX_FD, so 8 columns need at most 3 per thread
+// groups for m0 <= FD_LDS_M, so 8 columns need at most 3 per thread; larger
+// tensors (m0 <= MAX_FD: at least one group) take up to all 8
 constexpr int FD_RPT = 3;
-static_assert(256 / MAX_FD >= 3 && (FD_RB + 2) / 3 <= FD_RPT, "chunk columns per thread");
+static_assert(256 / FD_LDS_M >= 3 && (FD_RB + 2) / 3 <= FD_RPT, "chunk columns per thread");
+static_assert(256 / MAX_FD >= 1, "one row per thread");
 
 // A chunk is rb <= FD_RB columns (second tensor index) of one z-slab, so that the
 // results of a chunk are whole columns, contiguous in memory.
@@ -394,23 +396,29 @@ struct FdLanes {
   }
 };
 
-// acc[i] = sum_b A[j + m0 b] C[b * FD_RB + c_i]  (A column-major m0 x k, C: k x FD_RB)
-template <typename T>
-__device__ __forceinline__ void fd_rows_times_chunk(const T* A, const T* C, int m0, int k, const FdLanes& L, int nc,
-                                                    T* acc) {
-  int cc[FD_RPT];
+// acc[i] = sum_b A(j, b) C[b * FD_RB + c_i]  (C: k x FD_RB in LDS), with
+// A(j, b) = A[j + m0 b] (column-major, LDS or memory) or given by `at`
+template <int RPT, typename T, typename F>
+__device__ __forceinline__ void fd_rows_times_chunk_f(F at, const T* C, int k, const FdLanes& L, int nc, T* acc) {
+  int cc[RPT];
 #pragma unroll
-  for (int i = 0; i < FD_RPT; ++i) {
+  for (int i = 0; i < RPT; ++i) {
     cc[i] = min(L.a0 + i, nc - 1);
     acc[i] = 0;
   }
   if (!L.act) return;
 #pragma unroll 8
   for (int b = 0; b < k; ++b) {
-    const T x = A[L.j + m0 * b];
+    const T x = at(L.j, b);
 #pragma unroll
-    for (int i = 0; i < FD_RPT; ++i) acc[i] += x * C[b * FD_RB + cc[i]];
+    for (int i = 0; i < RPT; ++i) acc[i] += x * C[b * FD_RB + cc[i]];
   }
+}
+
+template <typename T>
+__device__ __forceinline__ void fd_rows_times_chunk(const T* A, const T* C, int m0, int k, const FdLanes& L, int nc,
+                                                    T* acc) {
+  fd_rows_times_chunk_f<FD_RPT>([=](int j, int b) { return A[j + m0 * b]; }, C, k, L, nc, acc);
 }
 
 // Dense piece (edge or vertex): gather the residual over all copies (Sigma),
@@ -421,10 +429,12 @@ __device__ void fd_dense_piece(const DensePiece pc, const T* __restrict__ densem
                                T* __restrict__ u, const int64_t* __restrict__ if_ptr,
                                const int64_t* __restrict__ if_idx, T tau, int add, T* lds) {
   const int m = pc.m;
-  T* sA = lds;             // L^{-1}, row-major m x m
-  T* sr = lds + m * m;     // gathered residual
+  const bool big = m > FD_LDS_M;   // L^{-1} read from memory
+  T* sA = lds;                     // L^{-1}, row-major m x m
+  T* sr = lds + (big ? 0 : m * m); // gathered residual
   const T* A = densemat + pc.Linv;
-  for (int t = threadIdx.x; t < m * m; t += blockDim.x) sA[t] = A[t];
+  if (!big)
+    for (int t = threadIdx.x; t < m * m; t += blockDim.x) sA[t] = A[t];
   for (int j = threadIdx.x; j < m; j += blockDim.x) {
     T v = 0;
     for (int64_t c = if_ptr[pc.seg + j]; c < if_ptr[pc.seg + j + 1]; ++c) v += src[if_idx[c]];
@@ -433,7 +443,7 @@ __device__ void fd_dense_piece(const DensePiece pc, const T* __restrict__ densem
   __syncthreads();
   for (int k = threadIdx.x; k < m; k += blockDim.x) {
     T zz = 0;
-    const T* ar = sA + k * m;
+    const T* ar = (big ? A : sA) + k * m;
 #pragma unroll 8
     for (int j = 0; j < m; ++j) zz += ar[j] * sr[j];
     zz *= tau;
@@ -465,39 +475,67 @@ __device__ __forceinline__ void fd_fwd_block(int bx, int by, const FDItem* __res
   fd_chunk(it, rb, bx, z, c0, nc);
   if (z >= it.m[2]) return;
   const int n = m0 * m1;
-  T* X = lds;                        // X[j + m0 b]; later U0[j m0 + a]
-  T* C = lds + max(n, m0 * m0);      // U1[b, c0 + c] as C[b FD_RB + c]; later V[j FD_RB + c]
   const int64_t zoff = (int64_t)z * it.stride[2];
   const T* U0 = mat + it.U[0];
   const T* U1 = mat + it.U[1];
-  if (it.src_if) {
-    for (int t = threadIdx.x; t < n; t += blockDim.x) {
-      const int64_t e = it.base + t;  // face tensors are stored j fastest
-      T v = 0;
-      for (int64_t c = if_ptr[e]; c < if_ptr[e + 1]; ++c) v += src[if_idx[c]];
-      X[t] = v;
-    }
-  } else {
-    for (int t = threadIdx.x; t < n; t += blockDim.x) {
-      const int j = t % m0, b = t / m0;
-      X[t] = src[it.base + j * it.stride[0] + b * it.stride[1] + zoff];
-    }
-  }
-  for (int t = threadIdx.x; t < m1 * FD_RB; t += blockDim.x) {
-    const int c = t % FD_RB, b = t / FD_RB;
-    C[t] = c < nc ? U1[(int64_t)b * m1 + c0 + c] : (T)0;
-  }
-  __syncthreads();
   const FdLanes L(m0, nc);
-  T acc[FD_RPT];
-  fd_rows_times_chunk(X, C, m0, m1, L, nc, acc);     // V[j, c] = sum_b X[j, b] U1[b, c0 + c]
-  __syncthreads();
-  for (int i = 0; i < L.na; ++i) C[L.j * FD_RB + L.a0 + i] = acc[i];
-  for (int t = threadIdx.x; t < m0 * m0; t += blockDim.x) X[t] = U0[t];
-  __syncthreads();
-  // Y[a, c] = sum_j U0[j, a] V[j, c]: row a is this thread's j; U0 is read as
-  // U0[j m0 + a] = column-major access of U0^T, hence the same helper
-  fd_rows_times_chunk(X, C, m0, m0, L, nc, acc);
+  T acc[FD_RB];
+  if (max(m0, m1) > FD_LDS_M) {
+    // large tensor: X and U0 read from memory (coalesced along j), only the
+    // chunk of U1 and the intermediate V staged in LDS
+    T* C = lds;                      // U1[b, c0 + c] as C[b FD_RB + c]
+    T* V = lds + m1 * FD_RB;         // V[j FD_RB + c]
+    for (int t = threadIdx.x; t < m1 * FD_RB; t += blockDim.x) {
+      const int c = t % FD_RB, b = t / FD_RB;
+      C[t] = c < nc ? U1[(int64_t)b * m1 + c0 + c] : (T)0;
+    }
+    __syncthreads();
+    if (it.src_if)
+      fd_rows_times_chunk_f<FD_RB>(
+          [=](int j, int b) {
+            const int64_t e = it.base + j + (int64_t)m0 * b;
+            T v = 0;
+            for (int64_t c = if_ptr[e]; c < if_ptr[e + 1]; ++c) v += src[if_idx[c]];
+            return v;
+          },
+          C, m1, L, nc, acc);
+    else
+      fd_rows_times_chunk_f<FD_RB>(
+          [=](int j, int b) { return src[it.base + j * it.stride[0] + b * it.stride[1] + zoff]; }, C, m1, L, nc,
+          acc);
+    for (int i = 0; i < L.na; ++i) V[L.j * FD_RB + L.a0 + i] = acc[i];
+    __syncthreads();
+    fd_rows_times_chunk_f<FD_RB>([=](int j, int b) { return U0[j + (int64_t)m0 * b]; }, V, m0, L, nc, acc);
+  } else {
+    T* X = lds;                        // X[j + m0 b]; later U0[j m0 + a]
+    T* C = lds + max(n, m0 * m0);      // U1[b, c0 + c] as C[b FD_RB + c]; later V[j FD_RB + c]
+    if (it.src_if) {
+      for (int t = threadIdx.x; t < n; t += blockDim.x) {
+        const int64_t e = it.base + t;  // face tensors are stored j fastest
+        T v = 0;
+        for (int64_t c = if_ptr[e]; c < if_ptr[e + 1]; ++c) v += src[if_idx[c]];
+        X[t] = v;
+      }
+    } else {
+      for (int t = threadIdx.x; t < n; t += blockDim.x) {
+        const int j = t % m0, b = t / m0;
+        X[t] = src[it.base + j * it.stride[0] + b * it.stride[1] + zoff];
+      }
+    }
+    for (int t = threadIdx.x; t < m1 * FD_RB; t += blockDim.x) {
+      const int c = t % FD_RB, b = t / FD_RB;
+      C[t] = c < nc ? U1[(int64_t)b * m1 + c0 + c] : (T)0;
+    }
+    __syncthreads();
+    fd_rows_times_chunk(X, C, m0, m1, L, nc, acc);     // V[j, c] = sum_b X[j, b] U1[b, c0 + c]
+    __syncthreads();
+    for (int i = 0; i < L.na; ++i) C[L.j * FD_RB + L.a0 + i] = acc[i];
+    for (int t = threadIdx.x; t < m0 * m0; t += blockDim.x) X[t] = U0[t];
+    __syncthreads();
+    // Y[a, c] = sum_j U0[j, a] V[j, c]: row a is this thread's j; U0 is read as
+    // U0[j m0 + a] = column-major access of U0^T, hence the same helper
+    fd_rows_times_chunk(X, C, m0, m0, L, nc, acc);
+  }
   if (!L.act) return;
   const T* mu0 = mat + it.mu[0];
   const T* mu1 = mat + it.mu[1];
@@ -538,25 +576,40 @@ __device__ __forceinline__ void fd_inv_block(int bx, int by, const FDItem* __res
   fd_chunk(it, rb, bx, z, c0, nc);
   if (z >= it.m[2]) return;
   const int n = m0 * m1;
-  T* Y = lds;                        // Y[j + m0 b]; later U0^T[j m0 + a]
-  T* C = lds + max(n, m0 * m0);      // U1[c0 + c, b] as C[b FD_RB + c]; later V[j FD_RB + c]
   const T* S = scr + it.scr + (int64_t)z * n;
   const T* U0T = mat + it.U[0] + (int64_t)m0 * m0;
   const T* U1T = mat + it.U[1] + (int64_t)m1 * m1;
-  for (int t = threadIdx.x; t < n; t += blockDim.x) Y[t] = S[t];
-  for (int t = threadIdx.x; t < m1 * FD_RB; t += blockDim.x) {
-    const int c = t % FD_RB, b = t / FD_RB;
-    C[t] = c < nc ? U1T[(int64_t)b * m1 + c0 + c] : (T)0;
-  }
-  __syncthreads();
   const FdLanes L(m0, nc);
-  T acc[FD_RPT];
-  fd_rows_times_chunk(Y, C, m0, m1, L, nc, acc);     // V[j, c] = sum_b Y[j, b] U1[c0 + c, b]
-  __syncthreads();
-  for (int i = 0; i < L.na; ++i) C[L.j * FD_RB + L.a0 + i] = acc[i];
-  for (int t = threadIdx.x; t < m0 * m0; t += blockDim.x) Y[t] = U0T[t];
-  __syncthreads();
-  fd_rows_times_chunk(Y, C, m0, m0, L, nc, acc);     // Z[a, c] = sum_j U0[a, j] V[j, c]
+  T acc[FD_RB];
+  if (max(m0, m1) > FD_LDS_M) {
+    // large tensor: Y and U0^T read from memory, the chunk and V in LDS
+    T* C = lds;                      // U1[c0 + c, b] as C[b FD_RB + c]
+    T* V = lds + m1 * FD_RB;         // V[j FD_RB + c]
+    for (int t = threadIdx.x; t < m1 * FD_RB; t += blockDim.x) {
+      const int c = t % FD_RB, b = t / FD_RB;
+      C[t] = c < nc ? U1T[(int64_t)b * m1 + c0 + c] : (T)0;
+    }
+    __syncthreads();
+    fd_rows_times_chunk_f<FD_RB>([=](int j, int b) { return S[j + (int64_t)m0 * b]; }, C, m1, L, nc, acc);
+    for (int i = 0; i < L.na; ++i) V[L.j * FD_RB + L.a0 + i] = acc[i];
+    __syncthreads();
+    fd_rows_times_chunk_f<FD_RB>([=](int j, int b) { return U0T[j + (int64_t)m0 * b]; }, V, m0, L, nc, acc);
+  } else {
+    T* Y = lds;                        // Y[j + m0 b]; later U0^T[j m0 + a]
+    T* C = lds + max(n, m0 * m0);      // U1[c0 + c, b] as C[b FD_RB + c]; later V[j FD_RB + c]
+    for (int t = threadIdx.x; t < n; t += blockDim.x) Y[t] = S[t];
+    for (int t = threadIdx.x; t < m1 * FD_RB; t += blockDim.x) {
+      const int c = t % FD_RB, b = t / FD_RB;
+      C[t] = c < nc ? U1T[(int64_t)b * m1 + c0 + c] : (T)0;
+    }
+    __syncthreads();
+    fd_rows_times_chunk(Y, C, m0, m1, L, nc, acc);     // V[j, c] = sum_b Y[j, b] U1[c0 + c, b]
+    __syncthreads();
+    for (int i = 0; i < L.na; ++i) C[L.j * FD_RB + L.a0 + i] = acc[i];
+    for (int t = threadIdx.x; t < m0 * m0; t += blockDim.x) Y[t] = U0T[t];
+    __syncthreads();
+    fd_rows_times_chunk(Y, C, m0, m0, L, nc, acc);     // Z[a, c] = sum_j U0[a, j] V[j, c]
+  }
   if (!L.act) return;
   const int64_t zoff = (int64_t)z * it.stride[2];
   const int a = L.j;
@@ -596,8 +649,8 @@ __global__ __launch_bounds__(256) void k_fd_inv(const FDItem* __restrict__ items
 typedef float fd_f4 __attribute__((ext_vector_type(4)));
 constexpr int FDM_N = 16;          // MFMA tile width
 constexpr int FDM_CW = 8;          // columns per chunk (<= FDM_N; the rest of the tile is zero)
-constexpr int FDM_TILES = 2;       // output row tiles per wave (4 waves x 2 x 16 >= 96 >= MAX_FD rows)
-static_assert(4 * FDM_TILES * 16 >= MAX_FD, "row tiles per wave");
+constexpr int FDM_TILES = 2;       // output row tiles per wave (4 waves x 2 x 16 >= 96 >= FD_LDS_M rows)
+static_assert(4 * FDM_TILES * 16 >= FD_LDS_M, "row tiles per wave");
 
 __device__ __forceinline__ int fdm_up(int x, int q) { return (x + q - 1) / q * q; }
 
@@ -994,11 +1047,13 @@ __device__ __forceinline__ void fd_mid_block(int bx, int by, const FDItem* __res
   const int64_t line0 = (int64_t)bx * LB;
   if (line0 >= lines) return;
   const int nl = (int)min((int64_t)LB, lines - line0);
-  T* sU = lds;
-  T* sx = lds + L * L;
-  T* sy = sx + LB * L;
   const T* U = mat + it.U[2];
-  for (int i = threadIdx.x; i < L * L; i += blockDim.x) sU[i] = U[i];
+  const bool big = L > FD_LDS_M;     // U read from memory
+  T* sx = lds + (big ? 0 : L * L);
+  T* sy = sx + LB * L;
+  const T* sU = big ? U : lds;
+  if (!big)
+    for (int i = threadIdx.x; i < L * L; i += blockDim.x) lds[i] = U[i];
   T* S = scr + it.scr;
   const int64_t plane = lines;
   const int total = nl * L;
@@ -1101,8 +1156,16 @@ void launch_band_gather(const double* band, int nbh, const int64_t* ptr, const i
                      ne, out);
 }
 
-size_t fd_dense_lds(int maxm, size_t elem) { return ((size_t)maxm * maxm + maxm) * elem + 64; }
-size_t fd_slab_lds(int maxm, size_t elem) { return ((size_t)maxm * maxm + (size_t)FD_RB * maxm) * elem + 64; }
+// LDS of the vector FD kernels for tensors of sides up to maxm: those up to
+// FD_LDS_M staged whole, larger ones only their chunk and intermediate
+size_t fd_dense_lds(int maxm, size_t elem) {
+  const size_t s = (size_t)std::min(maxm, FD_LDS_M);
+  return std::max(s * s + s, (size_t)maxm) * elem + 64;
+}
+size_t fd_slab_lds(int maxm, size_t elem) {
+  const size_t s = (size_t)std::min(maxm, FD_LDS_M);
+  return std::max(s * s + (size_t)FD_RB * s, (size_t)(2 * FD_RB) * maxm) * elem + 64;
+}
 
 int fd_slab_grid(const FDItem* items, int nitems, int rb) {
   int g = 1;
@@ -1121,8 +1184,8 @@ int fd_mid_grid(const FDItem* items, int nitems) {
 }
 
 size_t fd_mid_lds(int maxm, size_t elem) {
-  const size_t L = (size_t)maxm;
-  return (L * L + 2 * std::max<size_t>(512, L)) * elem + 64;
+  const size_t s = (size_t)std::min(maxm, FD_LDS_M);
+  return (s * s + 2 * std::max<size_t>(512, (size_t)maxm)) * elem + 64;
 }
 
 template <typename T>

@@ -12,7 +12,9 @@ namespace igamg {
 
 constexpr int ROW_ALIGN = 256;   // patch block alignment (entries) and apply block size
 constexpr int MAX_P = 8;         // highest spline degree with a compiled apply kernel
-constexpr int MAX_FD = 84;       // largest 1D interior size handled by the FD kernels (LDS: L^2 + 1024 doubles)
+constexpr int MAX_FD = 256;      // largest 1D interior size handled by the FD kernels (one thread per row)
+constexpr int FD_LDS_M = 84;     // largest 1D interior size whose tensors the FD kernels stage in LDS
+                                 // (L^2 + 1024 doubles); larger ones read their operands from memory
 
 // Symmetric half-band storage of the banded patch matrices.  An offset of the
 // (2P+1)^D stencil is written in index form (o0, o1, o2), o_c in [0, 2P]

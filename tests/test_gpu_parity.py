@@ -38,6 +38,13 @@ CASES = {
     "cube_p4_l3_neumann": lambda: W.box_grid(3, [2, 1, 1], 4, 1, 3, gdeg=1, dirichlet_sides=[0, 2]),
     "graded_square3x2_p3_l3": lambda: W.graded_square_3x2(),
     "graded_cube2x2x2_p2_l3": lambda: W.graded_cube_2x2x2(),
+    # patches finer than the FD kernels stage in LDS (88 interior functions
+    # along a direction on the finest level): the kernels read those
+    # tensors' operands from memory
+    "fine_square_p2_m88": lambda: W.box_grid(2, [1, 1], 2, 11, 4, gdeg=1),
+    "fine_cube_z_p2_m88": lambda: W.box_grid(3, [2, 2, 1], 2, [[2, 2], [2, 2], [11]], 4, gdeg=1),
+    "fine_cube_x_p2_m88": lambda: W.box_grid(3, [1, 1, 2], 2, [[11], [2], [2, 2]], 4, gdeg=1,
+                                             dirichlet_sides=[0, 2, 4]),
 }
 
 _ORACLE = {}
@@ -271,7 +278,7 @@ def test_full_size_cube_sampled(torch_cuda):
 
 @pytest.mark.parametrize("fd_mfma", [1, 2])
 @pytest.mark.parametrize("name", ["square4x4_p4_l4", "cube2x2x2_p3_l4", "fichera7_p2_l3", "cube_p4_l3_neumann",
-                                  "single_patch_p5_l3"])
+                                  "single_patch_p5_l3", "fine_square_p2_m88", "fine_cube_z_p2_m88"])
 def test_fp32_cycle_close_to_oracle(torch_cuda, name, fd_mfma):
     """The FP32 cycle (FP32 bands, smoothers, transfers; FP64 coarse solve)
     against the oracle's FP64 cycle: FP32 rounding only.  fd_mfma = 1 runs the

@@ -148,9 +148,13 @@ def test_binding_loads_a_single_hip_runtime():
 
 
 def test_piece_wider_than_the_smoother_kernels_is_rejected():
-    """Patches with more than 84 interior functions in a direction are
-    rejected at setup (the fast-diagonalization kernels hold an 84 x 84 tile)."""
-    prob = W.box_grid(2, [1, 1], 2, 2, 7, gdeg=1)      # 128 elements per direction at the finest level
+    """Patches with more than 256 interior functions in a direction are
+    rejected at setup (the fast-diagonalization kernels give each row of a
+    tensor one thread of a 256-thread workgroup); 128 elements per direction
+    (the paper's finest per-patch resolution, l = 7) are accepted."""
+    ok = W.box_grid(2, [1, 1], 2, 2, 7, gdeg=1)        # 128 elements per direction at the finest level
+    assert igamg.Solver(ok, host_only=True).N == 128 * 128
+    prob = W.box_grid(2, [1, 1], 2, 2, 9, gdeg=1)      # 512 elements per direction
     _expect(igamg.EINVAL, lambda: igamg.Solver(prob, host_only=True))
 
 
