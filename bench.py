@@ -124,7 +124,7 @@ def traffic_summary(workload, fetch_csv, write_csv, fetch_cmd, write_cmd):
         if not copies:
             raise SystemExit(f"{path}: no copy-calibration dispatch")
         out = {"copy_kib": max(copies)}
-        for prec, key, typ in (("fp64", "k_band_half", "double"), ("mixed", "k_band_full", "float")):
+        for prec, key, typ in (("fp64", "k_band_half<", "double"), ("mixed", "k_band_full<", "float")):
             band = [(g, v) for n, g, v in rows if key in n and typ in n]
             if not band:
                 continue

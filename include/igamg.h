@@ -204,7 +204,8 @@ int igamg_vcycle(igamg_handle h, const double* r, double* z, void* stream);
  * ||f - A u||_2 <= tol ||f||_2 (Sec. 5).  With precision IGAMG_MIXED, FP64
  * iterative refinement around FP32 PCG solves: the residual f - A u and the
  * update u += d are FP64 (FP64 band), each correction d is an FP32 PCG solve
- * (FP32 bands, smoothers, transfers; the coarse solve stays FP64) that
+ * (FP32 bands, smoothers, transfers; the coarse solve reads A_0^{-1} rounded
+ * to FP32 and sums in FP64) that
  * reduces its residual by max(inner_tol, tol / (2 r)), r the outer relative
  * residual before it (the last correction aims just past tol instead of a
  * whole further inner_tol), and `maxit` caps the inner iterations summed.  rhs and u: device vectors of

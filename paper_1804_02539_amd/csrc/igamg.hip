@@ -102,6 +102,7 @@ struct igamg_ctx {
   bool mixed = false;
   std::vector<DevLevel> dl;
   double* Ainv = nullptr;          // A_0^{-1}, packed lower tiles
+  float* Ainv32 = nullptr;         // the same rounded to FP32, for the FP32 cycle (mixed precision)
   double* cpart = nullptr;         // partial products of the coarse solve (coarse_tiles(N0)^2 * 64)
   void* coarse_ws = nullptr;       // device coarse factorization scratch (overlaps level data)
   size_t coarse_ws_bytes = 0;
@@ -167,6 +168,12 @@ static void plan_level_data(Bump& b, const LevelH& L, DevLevel& D, LevelData<T>&
   X.densemat = b.take<T>(L.densemat.size());
   X.tr_val = b.take<T>(L.tr_val.size());
   X.scr = b.take<T>(L.fdscr);
+}
+
+template <typename T>
+static const T* coarse_inverse_of(const igamg_ctx& C) {
+  if constexpr (std::is_same<T, float>::value) return C.Ainv32;
+  else return C.Ainv;
 }
 
 // Rows up to which a level belongs to the persistent coarse cycle: below
@@ -285,7 +292,7 @@ static void tail_program(igamg_ctx& C, igamg_ctx::Tail& tl) {
     m.gx = 1;
     m.len = C.N0;
     m.n = Tc * (Tc + 1) / 2;
-    const void* b2[] = {C.Ainv, C.cb, C.cpart};
+    const void* b2[] = {coarse_inverse_of<T>(C), C.cb, C.cpart};
     for (int i = 0; i < 3; ++i) m.a[i] = b2[i];
     push(m);
     Phase r{};
@@ -332,6 +339,7 @@ static size_t plan(igamg_ctx& C, char* base) {
   // which the level data occupies later, as its scratch
   C.N0 = H.lv[0].N;
   C.Ainv = b.take<double>((size_t)coarse_packed_entries(C.N0));
+  C.Ainv32 = C.mixed ? b.take<float>((size_t)coarse_packed_entries(C.N0)) : nullptr;
   C.cpart = b.take<double>((size_t)(coarse_tiles(C.N0) * coarse_tiles(C.N0) * COARSE_TILE));
   C.cb = b.take<double>(C.N0);
   const size_t scratch_at = (b.pos + 255) & ~size_t(255);
@@ -548,6 +556,7 @@ static void upload(igamg_ctx& C, hipStream_t st) {
   } else {
     up(C.Ainv, pack_coarse_tiles(H.Ainv.data(), C.N0, 0.0), st);
   }
+  if (C.mixed) launch_to_float(C.Ainv, C.Ainv32, coarse_packed_entries(C.N0), st);
   for (size_t l = 0; l < H.lv.size(); ++l) {
     LevelH& L = H.lv[l];
     DevLevel& D = C.dl[l];
@@ -695,7 +704,7 @@ static void smoother_apply(igamg_ctx& C, int l, const T* src, T* u, bool add, do
 template <typename T>
 static void coarse_solve(igamg_ctx& C, const T* f0, T* u0, hipStream_t st) {
   DevLevel& D = C.dl[0];
-  launch_coarse<T>(C.Ainv, f0, C.cb, C.cpart, u0, D.gptr, D.gidx, C.N0, st);
+  launch_coarse<T>(coarse_inverse_of<T>(C), f0, C.cb, C.cpart, u0, D.gptr, D.gidx, C.N0, st);
 }
 
 template <typename T>

@@ -1492,7 +1492,8 @@ __device__ __forceinline__ double lane_transpose_sum(const double (&v)[2 * H], i
   }
 }
 
-__device__ __forceinline__ void coarse_tiles_block(int64_t bx, const double* __restrict__ Ainv,
+template <typename M>
+__device__ __forceinline__ void coarse_tiles_block(int64_t bx, const M* __restrict__ Ainv,
                                                    const double* __restrict__ b, double* __restrict__ part,
                                                    int64_t n) {
   constexpr int CT = COARSE_TILE;
@@ -1510,10 +1511,10 @@ __device__ __forceinline__ void coarse_tiles_block(int64_t bx, const double* __r
   }
   __syncthreads();
   // wavefront g holds rows 16 g .. 16 g + 15 of the tile, lane c column c
-  const double* tile = Ainv + coarse_tile_at(I, J);
+  const M* tile = Ainv + coarse_tile_at(I, J);
   double v[16];
 #pragma unroll
-  for (int i = 0; i < 16; ++i) v[i] = tile[(g * 16 + i) * CT + c];
+  for (int i = 0; i < 16; ++i) v[i] = (double)tile[(g * 16 + i) * CT + c];
   const double bj = s_bj[c];
   double colsum = 0.0, pr[16];
 #pragma unroll
@@ -1545,9 +1546,21 @@ __device__ __forceinline__ void coarse_reduce_block(int64_t bx, const double* __
   for (int64_t c = ptr[row]; c < ptr[row + 1]; ++c) u0[idx[c]] = (T)s;
 }
 
-__global__ __launch_bounds__(256) void k_coarse_tiles(const double* __restrict__ Ainv, const double* __restrict__ b,
+template <typename M>
+__global__ __launch_bounds__(256) void k_coarse_tiles(const M* __restrict__ Ainv, const double* __restrict__ b,
                                                       double* __restrict__ part, int64_t n) {
-  coarse_tiles_block(blockIdx.x, Ainv, b, part, n);
+  coarse_tiles_block<M>(blockIdx.x, Ainv, b, part, n);
+}
+
+__global__ __launch_bounds__(256) void k_to_float(const double* __restrict__ x, float* __restrict__ y, int64_t n) {
+  const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += stride) y[i] = (float)x[i];
+}
+
+void launch_to_float(const double* x, float* y, int64_t n, hipStream_t st) {
+  if (n <= 0) return;
+  const int64_t blocks = std::min<int64_t>((n + 255) / 256, (int64_t)1 << 16);
+  hipLaunchKernelGGL(k_to_float, dim3((unsigned)blocks), dim3(256), 0, st, x, y, n);
 }
 
 template <typename T>
@@ -1558,13 +1571,13 @@ __global__ __launch_bounds__(256) void k_coarse_reduce(const double* __restrict_
 }
 
 template <typename T>
-void launch_coarse(const double* Ainv, const T* f0, double* b, double* part, T* u0, const int64_t* ptr,
+void launch_coarse(const T* Ainv, const T* f0, double* b, double* part, T* u0, const int64_t* ptr,
                    const int64_t* idx, int64_t n, hipStream_t st) {
   if (n <= 0) return;
   const int64_t Tn = coarse_tiles(n);
   hipLaunchKernelGGL((k_gather_dist<T, double>), dim3((unsigned)((n + 255) / 256)), dim3(256), 0, st, f0, b, ptr, idx,
                      n);
-  hipLaunchKernelGGL(k_coarse_tiles, dim3((unsigned)(Tn * (Tn + 1) / 2)), dim3(256), 0, st, Ainv, b, part, n);
+  hipLaunchKernelGGL(k_coarse_tiles<T>, dim3((unsigned)(Tn * (Tn + 1) / 2)), dim3(256), 0, st, Ainv, b, part, n);
   hipLaunchKernelGGL(k_coarse_reduce<T>, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, st, part, u0, ptr, idx, n);
 }
 
@@ -1650,7 +1663,7 @@ __device__ __forceinline__ void tail_item(const Phase& ph, int64_t t) {
                                    static_cast<const int64_t*>(a[2]), static_cast<const int64_t*>(a[3]), ph.len);
       break;
     case PH_CTILES:
-      coarse_tiles_block(t, static_cast<const double*>(a[0]), static_cast<const double*>(a[1]),
+      coarse_tiles_block<T>(t, static_cast<const T*>(a[0]), static_cast<const double*>(a[1]),
                          const_cast<double*>(static_cast<const double*>(a[2])), ph.len);
       break;
     case PH_CREDUCE:
@@ -1960,7 +1973,7 @@ void launch_add_f32(double* x, const float* d, int64_t n, hipStream_t st) {
                                    int, const uint8_t*, hipStream_t);                                                  \
   template void launch_prolong_add<T>(int, const T*, T*, const PatchDev*, const int*, int64_t, const int64_t*,         \
                                       const T*, int, const uint8_t*, hipStream_t);                                     \
-  template void launch_coarse<T>(const double*, const T*, double*, double*, T*, const int64_t*, const int64_t*,       \
+  template void launch_coarse<T>(const T*, const T*, double*, double*, T*, const int64_t*, const int64_t*,            \
                                  int64_t, hipStream_t);                                                                \
   template void launch_dot<T>(const T*, const T*, int64_t, double*, double*, int, int, hipStream_t);                   \
   template void launch_dot2_flex<T>(const T*, const T*, const T*, int64_t, double*, double*, hipStream_t);             \

@@ -66,8 +66,9 @@ void launch_gather(const double* loc, double* glob, const int64_t* ptr, const in
 void launch_scatter(const double* glob, double* loc, const int64_t* ptr, const int64_t* idx, int64_t n, bool dist,
                     hipStream_t st);
 template <typename T>
-void launch_coarse(const double* Ainv, const T* f0, double* b, double* part, T* u0, const int64_t* ptr,
+void launch_coarse(const T* Ainv, const T* f0, double* b, double* part, T* u0, const int64_t* ptr,
                    const int64_t* idx, int64_t n, hipStream_t st);
+void launch_to_float(const double* x, float* y, int64_t n, hipStream_t st);
 // A_0^{-1} of the dense SPD coarse matrix in packed lower tiles (layout.hpp):
 // Lt holds A_0 on entry (identity padding) and its Cholesky factor on exit,
 // Yt (zero on entry) the inverse factor L^{-1}, Ainv (zero on entry) the

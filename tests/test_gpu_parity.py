@@ -280,7 +280,7 @@ def test_full_size_cube_sampled(torch_cuda):
 @pytest.mark.parametrize("name", ["square4x4_p4_l4", "cube2x2x2_p3_l4", "fichera7_p2_l3", "cube_p4_l3_neumann",
                                   "single_patch_p5_l3", "fine_square_p2_m88", "fine_cube_z_p2_m88"])
 def test_fp32_cycle_close_to_oracle(torch_cuda, name, fd_mfma):
-    """The FP32 cycle (FP32 bands, smoothers, transfers; FP64 coarse solve)
+    """The FP32 cycle (FP32 bands, smoothers, transfers; FP32 coarse inverse)
     against the oracle's FP64 cycle: FP32 rounding only.  fd_mfma = 1 runs the
     smoother's mode products on the matrix cores, 2 on vector FMAs."""
     from paper_1804_02539_amd import igamg
