@@ -6,6 +6,7 @@
 #define IGAMG_HD
 #include <algorithm>
 #include <cmath>
+#include <cstdio>
 #include <cstring>
 #include <vector>
 
@@ -142,5 +143,36 @@ extern "C" long coarse_dense_vs_serial(const void* cprob) {
     return diff;
   } catch (const SetupError&) {
     return -2;
+  }
+}
+
+// Work-items of the largest single dispatch the device assembly of this
+// problem makes (per element slab: metric, direction 0, 1 and 2 stages), over
+// every level >= 1; the mask stage is a grid-stride loop with a capped grid.
+// Returns -1 on a setup error.
+extern "C" long long asm_max_dispatch_items(const void* cprob) {
+  try {
+    Hierarchy H;
+    H.prob = read_problem(cprob);
+    build_topology(H, false);
+    const ProblemH& P = H.prob;
+    long long worst = 0;
+    for (size_t l = 1; l < H.lv.size(); ++l) {
+      std::vector<AsmPatch> pt;
+      std::vector<double> tab;
+      make_assembly_tables(P, H.lv[l], pt, tab);
+      for (int k = 0; k < P.K; ++k) {
+        size_t sz[3];
+        asm_sizes(P.d, pt[k], sz);
+        worst = std::max<long long>(worst, (long long)(sz[0] / (size_t)(P.d * P.d)));
+        worst = std::max<long long>(worst, asm_dir0_threads(P.d, pt[k]));
+        worst = std::max<long long>(worst, asm_dir1_threads(P.d, pt[k]));
+        worst = std::max<long long>(worst, asm_dir2_threads(pt[k]));
+      }
+    }
+    return worst;
+  } catch (const SetupError& e) {
+    std::fprintf(stderr, "asm_max_dispatch_items: %s\n", e.msg.c_str());
+    return -1;
   }
 }

@@ -27,6 +27,7 @@ def stages(tmp_path_factory):
     lib = ctypes.CDLL(out)
     lib.asm_stages_vs_host.restype = ctypes.c_int
     lib.coarse_dense_vs_serial.restype = ctypes.c_long
+    lib.asm_max_dispatch_items.restype = ctypes.c_longlong
     return lib
 
 
@@ -61,3 +62,25 @@ def test_parallel_coarse_build_equals_serial(stages, name, prob):
     # pass bit for bit
     cp = igamg._CProblem(prob())
     assert stages.coarse_dense_vs_serial(ctypes.byref(cp.s)) == 0
+
+
+def test_assembly_dispatches_stay_below_the_launch_limit(stages):
+    """Every per-slab launch of the device assembly stays below the 2^32
+    work-items of one dispatch (the launcher also refuses larger ones), for the
+    64-patch p=5 workload and for the largest 3D p=6 family the full serving
+    recipe can draw (its band capped at 60 GB)."""
+    limit = 2 ** 32 - 256
+
+    def items(prob):
+        cp = igamg._CProblem(prob)      # keeps the arrays the C struct points to alive
+        return stages.asm_max_dispatch_items(ctypes.byref(cp.s))
+
+    c4 = items(W.batched_patch_cube())
+    assert 0 < c4 < limit
+    fams = W.serving_families(64, 21, n_min=1e4, n_max=4e6, band_bytes_max=60e9, n0_max=8000)
+    big = [f for f in fams if f.dim == 3 and f.degree == 6]
+    for f in big:
+        assert 0 < items(f) < limit
+    # the largest 3D patch the smoother takes: 248 elements, p = 8, 254 interior functions
+    hw = items(W.box_grid(3, [1, 1, 1], 8, 31, 4, gdeg=1))
+    assert 0 < hw < limit, hw
