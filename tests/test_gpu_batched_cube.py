@@ -84,6 +84,15 @@ def test_replica_matches_oracle(torch_cuda):
     diff = float(np.linalg.norm(um.cpu().numpy() - u64.cpu().numpy()) / np.linalg.norm(u64.cpu().numpy()))
     _say(f"  |u_mixed - u_fp64| / |u_fp64| = {diff:.2e}")
     assert diff < 1e-5
+    # both against the oracle's own PCG solution (Sec. 4) of the same system
+    uo, ito, _ = H.pcg(f, tol=1e-8)
+    no = np.linalg.norm(uo)
+    e64 = float(np.linalg.norm(u64.cpu().numpy() - uo) / no)
+    em = float(np.linalg.norm(um.cpu().numpy() - uo) / no)
+    _say(f"  oracle PCG {ito} it; |u - u_oracle| / |u_oracle|: FP64 {e64:.2e}, mixed {em:.2e}")
+    # three solutions with residuals <= 1e-8 of an operator with the
+    # replica's conditioning agree to well below 1e-6
+    assert e64 < 1e-6 and em < 1e-6
 
 
 def test_concurrent_setups_factor_correctly(torch_cuda):
