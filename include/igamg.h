@@ -88,8 +88,10 @@ typedef struct {
   double sigma_scale;    /* sigma = sigma_scale * h^-2 in the interior smoother */
   int nu;                /* pre- and post-smoothing steps                    */
   int mu;                /* 1 = V-cycle, 2 = W-cycle                         */
-  int precision;         /* IGAMG_FP64, or IGAMG_MIXED (FP32 inner solve inside FP64
-                            iterative refinement)                          */
+  int precision;         /* IGAMG_FP64; IGAMG_MIXED (FP32 inner solve inside FP64 iterative
+                            refinement); IGAMG_MIXED_BF16 (the same with the smoother's mode
+                            products on the matrix cores from bfloat16 operands, FP32
+                            accumulation: IGAMG_MIXED with fd_mfma = 3)                    */
   int maxit;             /* iteration cap of igamg_solve                    */
   int geometry_scaling;  /* 0 (default): piece operators in parameter-domain units, as the
                             paper's Fichera iteration table indicates; 1: each scaled by
@@ -134,6 +136,7 @@ typedef struct {
 
 #define IGAMG_FP64 0
 #define IGAMG_MIXED 1
+#define IGAMG_MIXED_BF16 2
 
 typedef struct {
   int iterations;        /* PCG iterations (mixed: inner iterations summed) */

@@ -868,6 +868,11 @@ static void read_opts(const igamg_options* o, Options& O) {
   O.physical_h = o->physical_h;
   O.iface_direct = o->iface_direct;
   O.persistent = o->persistent;
+  if (O.precision == IGAMG_MIXED_BF16) {
+    if (O.fd_mfma != 0 && O.fd_mfma != 3) throw SetupError{IGAMG_EINVAL, "IGAMG_MIXED_BF16 sets fd_mfma = 3"};
+    O.precision = IGAMG_MIXED;
+    O.fd_mfma = 3;
+  }
   if (O.s1_sigma < 0 || O.s1_sigma > 1 || O.iface_multiplicity < 0 || O.iface_multiplicity > 1 || O.physical_h < 0 ||
       O.physical_h > 1 || O.geometry_scaling < 0 || O.geometry_scaling > 1 || O.iface_direct < 0 ||
       O.iface_direct > 1 || O.persistent < 0 || O.persistent > 1)

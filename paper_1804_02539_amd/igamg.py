@@ -18,7 +18,7 @@ _HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_HERE, "libigamg.so")
 
 OK, EINVAL, ETOPO, EGEOM, ENOMEM, ENOTSPD, ENOCONV, ENAN, EDEVICE = 0, -1, -2, -3, -4, -5, -6, -7, -8
-FP64, MIXED = 0, 1
+FP64, MIXED, MIXED_BF16 = 0, 1, 2
 FD_VEC8, FD_VEC4, FD_MFMA, FD_FUSED, FD_MFMA_BF16 = 0, 1, 2, 3, 4
 FD_NAMES = {FD_VEC8: "vec8", FD_VEC4: "vec4", FD_MFMA: "mfma", FD_FUSED: "fused", FD_MFMA_BF16: "mfma_bf16"}
 OP_APPLY, OP_SMOOTHER, OP_PROLONG, OP_RESTRICT, OP_COARSE, OP_CYCLE_FP32 = 0, 1, 2, 3, 4, 5

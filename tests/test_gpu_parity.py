@@ -372,3 +372,6 @@ def test_bf16_smoother_cycle_error_stated(torch_cuda, name):
          f"finest variant {igamg.FD_NAMES[S.tuning(-1, True)]}")
     assert S.tuning(-1, True) == igamg.FD_MFMA_BF16
     assert err < 3e-2
+    # the precision value IGAMG_MIXED_BF16 selects the same kernels
+    Sb = gpu_for(name, precision=igamg.MIXED_BF16)
+    assert bool(torch_cuda.equal(Sb.operator(igamg.OP_CYCLE_FP32, -1, r), S.operator(igamg.OP_CYCLE_FP32, -1, r)))

@@ -203,3 +203,16 @@ def test_noalloc_size_query_and_limits():
     assert need_dev.value >= need.value
     # a query needs somewhere to write the size
     assert lib.igamg_setup_noalloc(ctypes.byref(cp.s), ctypes.byref(opts), None, 0, None, None, None) == igamg.EINVAL
+
+
+def test_bf16_precision_value():
+    """IGAMG_MIXED_BF16 is IGAMG_MIXED with the bfloat16 matrix-core smoother
+    products (fd_mfma = 3); other precision values and a conflicting fd_mfma
+    are rejected."""
+    prob = W.square_4x4_bezier(levels=3)
+    mixed = igamg.workspace_size(prob, igamg.default_options(precision=igamg.MIXED))
+    assert igamg.workspace_size(prob, igamg.default_options(precision=igamg.MIXED_BF16)) == mixed
+    assert igamg.workspace_size(prob, igamg.default_options(precision=igamg.MIXED_BF16, fd_mfma=3)) == mixed
+    _expect(igamg.EINVAL, lambda: igamg.workspace_size(prob, igamg.default_options(precision=3)))
+    _expect(igamg.EINVAL, lambda: igamg.workspace_size(prob, igamg.default_options(precision=igamg.MIXED_BF16,
+                                                                                    fd_mfma=1)))
