@@ -120,7 +120,9 @@ def traffic_summary(workload, fetch_csv, write_csv, fetch_cmd, write_cmd):
                 if r.get("Counter_Name") == counter:
                     grid = r.get("Grid_Size", r.get("Grid_Size_X", "0"))
                     rows.append((r["Kernel_Name"], int(grid), float(r["Counter_Value"])))
-        copies = [v for n, g, v in rows if "copyBuffer" in n]
+        # the calibration copy: the copy dispatch whose counter is within a
+        # factor of 4 of its size (FETCH_SIZE counts half of it, WRITE_SIZE all)
+        copies = [v for n, g, v in rows if "copyBuffer" in n and 0.25 < v * 1024.0 / copy_bytes < 4.0]
         if not copies:
             raise SystemExit(f"{path}: no copy-calibration dispatch")
         out = {"copy_kib": max(copies)}
@@ -569,9 +571,10 @@ def main():
         "final_rel_residual": h["final_rel_residual"],
         "roofline": dict(h["roofline"]),
     }
-    cbw = copy_bandwidth(dev)
-    out["roofline"]["copy_GBps_measured"] = cbw
-    out["roofline"]["frac_of_measured_copy"] = out["roofline"]["achieved"] / cbw
+    if not a.copy_calibration:    # a counter run keeps its copies to the calibration
+        cbw = copy_bandwidth(dev)
+        out["roofline"]["copy_GBps_measured"] = cbw
+        out["roofline"]["frac_of_measured_copy"] = out["roofline"]["achieved"] / cbw
     for k, v in runs.items():
         out[k] = {kk: vv for kk, vv in v.items() if kk != "roofline"}
         out[k]["band_roofline_frac"] = v["roofline"]["frac"]
