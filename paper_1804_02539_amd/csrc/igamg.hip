@@ -726,7 +726,8 @@ static void cycle(igamg_ctx& C, int l, bool zero_init, hipStream_t st) {
   const igamg_ctx::Tail& tl = C.tail[std::is_same<T, float>::value ? 1 : 0];
   if (tl.nph > 0 && l == tl.level && zero_init) {
     // the whole cycle from here down, in one persistent launch
-    HIP_OK(launch_cycle_tail<T>(C.d, C.p, tl.prog, tl.nph, tl.total, tl.ctr, tl.grid, tl.lds, st));
+    HIP_OK(launch_cycle_tail<T>(C.d, C.p, tl.prog, tl.nph, tl.total, tl.ctr, tl.grid, tl.lds,
+                                dat<T>(C.dl[tl.level]).u, st));
     return;
   }
   LevelData<T>& X = dat<T>(C.dl[l]);

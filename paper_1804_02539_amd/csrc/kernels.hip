@@ -1725,18 +1725,28 @@ __global__ __launch_bounds__(64) void k_tail_reset(unsigned long long* __restric
   for (int i = threadIdx.x; i < n; i += blockDim.x) ctr[i] = 0ull;
 }
 
+// after the persistent launch, in stream order: a wait that exceeded its
+// bound left the work list's results unordered, so the cycle's output is
+// made a NaN, which the solve reports (ENAN) instead of a wrong result
+template <typename T>
+__global__ __launch_bounds__(64) void k_tail_check(const unsigned long long* __restrict__ ctr, int nph,
+                                                   T* __restrict__ out) {
+  if (threadIdx.x == 0 && ctr[1 + nph] != 0ull) out[0] = (T)NAN;
+}
+
 size_t cycle_tail_lds(int maxm, int max_dense, size_t elem) {
   return std::max({fd_slab_lds(maxm, elem), fd_dense_lds(max_dense, elem), fd_mid_lds(maxm, elem)});
 }
 
 template <typename T>
 hipError_t launch_cycle_tail(int d, int p, const Phase* prog, int nph, int64_t total, unsigned long long* ctr,
-                             int grid, size_t lds, hipStream_t st) {
+                             int grid, size_t lds, T* out, hipStream_t st) {
   if (total <= 0) return hipSuccess;
   hipLaunchKernelGGL(k_tail_reset, dim3(1), dim3(64), 0, st, ctr, nph + 2);
 #define IGAMG_TAIL_CASE(DD, PP)                                                                          \
   if (d == DD && p == PP) {                                                                              \
     hipLaunchKernelGGL((k_cycle_tail<DD, PP, T>), dim3(grid), dim3(256), lds, st, prog, nph, total, ctr); \
+    hipLaunchKernelGGL(k_tail_check<T>, dim3(1), dim3(64), 0, st, ctr, nph, out);                      \
     return hipGetLastError();                                                                            \
   }
   IGAMG_TAIL_CASE(2, 1) IGAMG_TAIL_CASE(2, 2) IGAMG_TAIL_CASE(2, 3) IGAMG_TAIL_CASE(2, 4)
@@ -1748,9 +1758,9 @@ hipError_t launch_cycle_tail(int d, int p, const Phase* prog, int nph, int64_t t
 }
 
 template hipError_t launch_cycle_tail<double>(int, int, const Phase*, int, int64_t, unsigned long long*, int, size_t,
-                                              hipStream_t);
+                                              double*, hipStream_t);
 template hipError_t launch_cycle_tail<float>(int, int, const Phase*, int, int64_t, unsigned long long*, int, size_t,
-                                             hipStream_t);
+                                             float*, hipStream_t);
 
 // ---------------------------------------------------------------------------
 // vector kernels of the PCG loop (deterministic two-stage reductions in FP64)

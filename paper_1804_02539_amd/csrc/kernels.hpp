@@ -103,7 +103,7 @@ void asm_slab_sizes(int d, const AsmPatch& P, size_t out[3]);
 size_t cycle_tail_lds(int maxm, int max_dense, size_t elem);
 template <typename T>
 hipError_t launch_cycle_tail(int d, int p, const Phase* prog, int nph, int64_t total, unsigned long long* ctr,
-                             int grid, size_t lds, hipStream_t st);
+                             int grid, size_t lds, T* out, hipStream_t st);
 // FP32 full band (all (2p+1)^d planes per tile) from the FP64 symmetric half band
 void launch_band_half_to_full(int d, int p, float* full, const double* half, const int* bpatch, const PatchDev* pd,
                               int64_t NL, hipStream_t st);
