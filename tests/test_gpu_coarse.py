@@ -75,3 +75,28 @@ def test_device_coarse_inverse_is_deterministic(torch_cuda):
     assert bool(torch_cuda.equal(y1, S2.operator(igamg.OP_COARSE, 0, x)))
     assert bool(torch_cuda.equal(y1, S1.operator(igamg.OP_COARSE, 0, x)))
     _say("two device factorizations give the same coarse solve bit for bit")
+
+
+def test_coarse_inverse_beyond_32_bit_indexing(torch_cuda):
+    """The Fichera corner, K = 448, p = 5, l = 1: N0 = 56,000, so A_0 has more
+    than 2^31 entries (the size at which 32-bit dense factorizations fail).
+    The device inverse applied to random vectors must give back x under the
+    oracle's A_0 (a residual check: the oracle's dense solve at this size is
+    too slow for a test), and the solve must converge as in the Fichera table."""
+    from oracle.multigrid import Level
+    from paper_1804_02539_amd import igamg
+    prob = W.fichera(5, 2, split=4)
+    S = igamg.Solver(prob)
+    L0 = Level(prob, 0)
+    assert L0.N == 56000 and L0.N ** 2 > 2 ** 31
+    rng = np.random.default_rng(13)
+    worst = 0.0
+    for _ in range(2):
+        x = rng.standard_normal(L0.N)
+        y = S.operator(igamg.OP_COARSE, 0, x).cpu().numpy()
+        worst = max(worst, float(np.linalg.norm(L0.A @ y - x) / np.linalg.norm(x)))
+    u, info = S.solve(S.load_vector(*prob.meta["source"][1:]))
+    _say(f"fichera448 p=5 l=1: N0 = {L0.N}, |A0 (A0^-1 x) - x| / |x| = {worst:.2e}; "
+         f"solve {info.iterations} iterations, residual {info.rel_residual:.2e}")
+    assert worst < 1e-9
+    assert info.converged and 20 <= info.iterations <= 28
