@@ -291,7 +291,8 @@ def serving_families(n_families, seed=5, n_min=1e4, n_max=3e5, band_bytes_max=1.
     subject to the FP64 band of the finest level staying under band_bytes_max,
     the coarsest level having at most n0_max unknowns (the dense coarse
     inverse is N0^2 doubles; up to 3,000 unknowns it is factored on the host)
-    and every patch having at most 84 interior functions per direction.
+    and every patch having at most 84 interior functions per direction (the
+    largest tensors the smoother kernels stage whole in LDS).
     2D families are biquadratic grids with seeded interior control points
     (Dirichlet on x=0 and y=0), 3D ones trilinear grids with every interior
     macro vertex moved by up to 10% of the patch width (full Dirichlet).
