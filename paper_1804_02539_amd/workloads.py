@@ -290,7 +290,8 @@ def serving_families(n_families, seed=5, n_min=1e4, n_max=3e5, band_bytes_max=1.
     the target (among the pairs inside [n_min, n_max] when there are any),
     subject to the FP64 band of the finest level staying under band_bytes_max,
     the coarsest level having at most n0_max unknowns (the dense coarse
-    inverse is N0^2 doubles; up to 3,000 unknowns it is factored on the host)
+    inverse is N0^2 / 2 doubles; up to 3,000 unknowns it is factored on the
+    host)
     and every patch having at most 84 interior functions per direction (the
     largest tensors the smoother kernels stage whole in LDS).
     2D families are biquadratic grids with seeded interior control points
