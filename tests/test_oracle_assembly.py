@@ -215,3 +215,18 @@ def test_matrix_equals_plain_quadrature_loop(case):
     ref = _plain_patch_matrix(prob.geo_degree[k], prob.geo_ctrl[k], p, nel)
     A = op.matrix().toarray()
     assert np.abs(A - ref).max() <= 1e-12 * np.abs(ref).max()
+
+
+def test_omega_of_boxes_closed_form():
+    """The geometry scale of the alternative smoother reading on axis-aligned
+    boxes, worked out by hand: |det J| = prod of the sides, J^{-1} J^{-T} =
+    diag(side^-2), so omega = prod(s) * sum(s^-2) / d (the side length for a
+    cube in 3D, 1 for any square in 2D)."""
+    import itertools
+    for sides in ([1.0, 2.0, 4.0], [0.25, 0.25, 0.25], [2.0, 3.0], [0.5, 0.5]):
+        d = len(sides)
+        corners = [np.array([s * c for s, c in zip(sides, idx[::-1])])
+                   for idx in itertools.product([0, 1], repeat=d)]      # x fastest
+        geo = geometry.BezierMap([1] * d, np.array(corners))
+        expect = np.prod(sides) * sum(1.0 / s ** 2 for s in sides) / d
+        assert abs(geometry.omega(geo) - expect) < 1e-13 * expect, (sides, geometry.omega(geo), expect)
