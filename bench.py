@@ -356,7 +356,7 @@ def serving(precision, n_requests, n_families, seed, dev):
                            "[1e4, 3e5] free dofs per family, fresh U[-1,1] rhs per request"}
 
 
-def serving_full(n_requests, n_families, rate, seed, dev, precision="mixed"):
+def serving_full(n_requests, n_families, rate, seed, dev, precision="mixed", workers=2):
     """The full serving recipe: ``n_requests`` seeded requests over
     ``n_families`` problem families (2D with 4-16 patches, 3D with 8-64, p in
     2..6, N log-uniform in [1e4, 4e6]) arriving as a Poisson process at
@@ -374,7 +374,7 @@ def serving_full(n_requests, n_families, rate, seed, dev, precision="mixed"):
     ws = [igamg.workspace_size(f, opts) for f in fams]
     log(f"serve-full: {n_families} families, workspaces {min(ws) / 1e6:.0f} MB .. {max(ws) / 1e9:.1f} GB "
         f"(sum {sum(ws) / 1e9:.0f} GB), budget {budget / 1e9:.0f} GB, {n_requests} requests at {rate}/s")
-    S = serve.Server(budget, opts=opts, device=dev, handles_per_key=1, setup_workers=2, keep_results=False)
+    S = serve.Server(budget, opts=opts, device=dev, handles_per_key=1, setup_workers=workers, keep_results=False)
     offs = serve.poisson_offsets(n_requests, rate, seed=seed)
 
     def progress(srv, t):
@@ -389,6 +389,7 @@ def serving_full(n_requests, n_families, rate, seed, dev, precision="mixed"):
     big = lat[np.array([r.n for r in S.finished]) >= 1e6]
     setups = sum(1 for e in S.events if e[1] == "resident")
     out = {"requests": n_requests, "families": n_families, "precision": precision, "arrival_rate_per_s": rate,
+           "setup_workers": workers,
            "finished": st["requests"], "rejected": st["rejected"], "failed": st["failed"],
            "free_dofs": {"min": int(n[0]), "median": int(np.median(n)), "max": int(n[-1]),
                          "requests_over_1e6": int((n >= 1e6).sum())},
@@ -469,6 +470,7 @@ def main():
     ap.add_argument("--serve-full-requests", type=int, default=256)
     ap.add_argument("--serve-full-families", type=int, default=64)
     ap.add_argument("--serve-rate", type=float, default=2.0, help="arrivals per second for --serve-full")
+    ap.add_argument("--serve-workers", type=int, default=2, help="setup worker threads for --serve-full")
     ap.add_argument("--fichera-table", default="",
                     help="instead of the benchmark line, print FP64 iteration counts on the Fichera corner "
                          "(K=448) for these degrees, e.g. 2,3,4, on the levels --fichera-levels")
@@ -504,8 +506,8 @@ def main():
 
     dev = "cuda:0"
     if a.serve_full:
-        print(json.dumps(serving_full(a.serve_full_requests, a.serve_full_families, a.serve_rate, 21, dev)),
-              flush=True)
+        print(json.dumps(serving_full(a.serve_full_requests, a.serve_full_families, a.serve_rate, 21, dev,
+                                      workers=a.serve_workers)), flush=True)
         return
     if a.fichera_table:
         degrees = [int(x) for x in a.fichera_table.split(",")]
