@@ -230,3 +230,24 @@ def test_omega_of_boxes_closed_form():
         geo = geometry.BezierMap([1] * d, np.array(corners))
         expect = np.prod(sides) * sum(1.0 / s ** 2 for s in sides) / d
         assert abs(geometry.omega(geo) - expect) < 1e-13 * expect, (sides, geometry.omega(geo), expect)
+
+
+def test_axis_lengths_closed_forms():
+    """The mean physical length of each parameter direction (the physical-h
+    reading): the sides of a box, and on a trapezoid with bottom a and top b,
+    G(xi, eta) = (xi (a + (b - a) eta), eta), the x-length (a + b) / 2 and the
+    y-length int_0^1 sqrt(1 + c^2 xi^2) dxi = sqrt(1 + c^2) / 2 + asinh(c) / (2 c),
+    c = b - a."""
+    import itertools
+    for sides in ([1.0, 2.0, 4.0], [3.0, 0.5]):
+        d = len(sides)
+        corners = [np.array([s * c for s, c in zip(sides, idx[::-1])])
+                   for idx in itertools.product([0, 1], repeat=d)]
+        geo = geometry.BezierMap([1] * d, np.array(corners))
+        assert np.allclose(geometry.axis_lengths(geo), sides, rtol=1e-13)
+    a, b = 1.0, 2.5
+    c = b - a
+    geo = geometry.BezierMap([1, 1], np.array([[0.0, 0.0], [a, 0.0], [0.0, 1.0], [b, 1.0]]))
+    lx, ly = geometry.axis_lengths(geo)
+    assert abs(lx - (a + b) / 2) < 1e-13
+    assert abs(ly - (np.sqrt(1 + c * c) / 2 + np.arcsinh(c) / (2 * c))) < 1e-9
