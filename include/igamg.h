@@ -117,8 +117,9 @@ typedef struct {
                             and uploaded (level 0, which forms the coarse matrix, is always assembled
                             on the host) */
   /* Readings of the smoother's constants, which the paper leaves to its
-   * references (Sec. 3) and to "spectrally equivalent up to geometry
-   * constants" (Sec. 2); the defaults are the library's reading:           */
+   * references (Sec. 3) and to an equivalence of the physical and the
+   * parameter-domain operators up to geometry-dependent factors (Sec. 2);
+   * the defaults are the library's reading:                                */
   int s1_sigma;           /* 1 (default): K + sigma M on the complement S1 of the interior
                              subspace corrected mass smoother; 0: K                        */
   int iface_multiplicity; /* 0 (default): face, edge and vertex operators as printed; 1: each

@@ -60,10 +60,11 @@ def omega(geo, nq=8):
     """Geometry scale of a patch: the parameter-domain average of
     |det J| tr(J^{-1} J^{-T}) / d with the nq-point Gauss rule per direction.
 
-    Reading of Sec. 2's remark that the physical and parameter-domain Laplacians
-    are spectrally equivalent up to geometry constants: every piece operator of
-    the smoother is multiplied by this constant (1 for any square in 2D, the
-    side length for a cube in 3D).
+    Used by the alternative reading (omega = "mean") of Sec. 2's remark that
+    the physical and parameter-domain Laplacians agree up to factors that
+    depend on the geometry: every piece operator of the smoother is then
+    multiplied by this constant (1 for any square in 2D, the side length for a
+    cube in 3D).  The default reading takes omega = 1.
     """
     x, w = bspline.gauss_legendre(nq)
     _, J = geo.eval_grid([x] * geo.d)

@@ -10,7 +10,7 @@ Readings:
 * coarse operators are re-discretised on every level (for affine maps this is
   identical to P^T A P, a pinned test);
 * the stopping test of the PCG is ||f - A u||_2 <= tol ||f||_2 on the free dofs,
-  starting from u = 0 (Sec. 5: "relative accuracy 1e-8").
+  starting from u = 0 (Sec. 5 solves to a relative accuracy of 1e-8).
 """
 import numpy as np
 import scipy.linalg as sla

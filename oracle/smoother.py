@@ -32,8 +32,9 @@ h for an interface piece is the geometric mean of the adjacent patches' h in
 their normal directions.
 
 The constants (omega, the operator on S1, h, multiplicities) are readings:
-the paper leaves them to its references and to "spectrally equivalent up to
-geometry constants" (Sec. 2).  The default was chosen by the PCG iteration
+the paper leaves them to its references and to an equivalence of the
+physical and parameter-domain operators up to geometry-dependent factors
+(Sec. 2).  The default was chosen by the PCG iteration
 counts on the Fichera corner with 448 patches, l = 1..4, p = 2..4, against the
 paper's table (Sec. 5): omega = 1 is the only reading whose counts grow with
 l as the paper's do (p = 2: 33, 32, 39, 44 against 30, 33, 39, 44), and
