@@ -312,8 +312,10 @@ int igamg_profile_read(igamg_handle h, int64_t* launches, double* ms, double* by
 
 /* The smoother variant level `level` (>= 1) uses in FP64 (fp32 = 0) or in
  * the FP32 inner solves (fp32 = 1).  With options.autotune = 1 setup times
- * each candidate (VEC8, VEC4, and MFMA for FP32 unless fd_mfma fixes it) on
- * the device over a few smoother applications and keeps the fastest.  The
+ * each candidate (VEC8, VEC4; for FP32 also MFMA, and FUSED on levels of 2D
+ * tensors, on levels whose tensors fit in LDS: sides up to 84; unless fd_mfma
+ * fixes the choice) on the device over a few smoother applications and keeps
+ * the fastest.  The
  * choice is cached per process under a key of the level's piece shapes, the
  * degree and the precision, so handles of the same problem agree (and their
  * results are identical); the environment variable IGAMG_TUNE_CACHE names a
