@@ -133,6 +133,14 @@ typedef struct {
   int persistent;         /* 1: the levels of at most 65536 local rows below the finest run as one
                              persistent launch per cycle (a work list of the cycle's phases,
                              V-cycle only); 0 (default): one launch per kernel               */
+  int band_form;          /* banded apply of the symmetric half band (Sec. 4's patch matrices):
+                             0 (default): 3D levels above 65536 local rows whose windows fit
+                             64 KiB of LDS in FP64 read each stored coefficient once and add its
+                             mirrored term through per-tile windows (two kernels; the FP32
+                             copy of those levels is the half band too); 1: every level reads
+                             the mirrored half from the rows it couples to (one kernel);
+                             2: the scatter form on every 3D level whose windows fit, the
+                             persistent cycle's levels (options.persistent) excepted          */
 } igamg_options;
 
 #define IGAMG_FP64 0

@@ -43,6 +43,8 @@ struct Options {
   int physical_h = 0;      // 1: h_c = (mean length of the c-th Jacobian column) / nel_c
   int iface_direct = 0;    // 1: edges and vertices solved with the exact restriction of A_l
   int persistent = 0;      // 1: the coarse levels of each cycle as one persistent launch
+  int band_form = 0;       // 0: scatter form of the symmetric band on large 3D levels, 1: gather form
+                           // everywhere, 2: scatter form on every 3D level that fits
 };
 
 // Error with an igamg return code.

@@ -48,6 +48,7 @@ struct DevLevel {
   int64_t NL = 0, N = 0, rows = 0;
   int nb = 0, nbh = 0, nfd = 0, nfd_int = 0, ndense = 0, WP = 0, WR = 0, fd_maxm = 1, max_dense = 1;
   int mfma_grid = 1;
+  int64_t sym_ws = 0;   // > 0: the banded apply in scatter form, sym_ws window values per tile
   int* bpatch = nullptr;
   PatchDev* pd = nullptr;
   uint8_t* isfree = nullptr;
@@ -117,6 +118,7 @@ struct igamg_ctx {
   int* dg_plane = nullptr;
   double* dg_out = nullptr;
   double* cb = nullptr;
+  void* symwin = nullptr;          // windows of the scatter-form banded apply (one level at a time)
   // the coarse levels of a cycle as one persistent launch (options.persistent)
   struct Tail {
     int level = 0, nph = 0, grid = 0;
@@ -162,8 +164,9 @@ static void plan_level_data(Bump& b, const LevelH& L, DevLevel& D, LevelData<T>&
   X.f = b.take<T>(L.NL);
   X.w = b.take<T>(L.NL);
   if (!solver_level) return;
-  // FP64: the symmetric half band; FP32: the full band
-  X.band = b.take<T>((size_t)(sizeof(T) == 8 ? D.nbh : D.nb) * L.NL);
+  // FP64: the symmetric half band; FP32: the full band, or the half band
+  // where the level applies it in scatter form
+  X.band = b.take<T>((size_t)(sizeof(T) == 8 || D.sym_ws > 0 ? D.nbh : D.nb) * L.NL);
   X.fdmat = b.take<T>(L.fdmat.size());
   X.densemat = b.take<T>(L.densemat.size());
   X.tr_val = b.take<T>(L.tr_val.size());
@@ -332,6 +335,20 @@ static void tail_program(igamg_ctx& C, igamg_ctx::Tail& tl) {
   if (tl.lds > 64 * 1024) tl = igamg_ctx::Tail{};   // pieces too large for one workgroup's default LDS
 }
 
+// Window values per tile of level L's banded apply in scatter form, or 0 for
+// the gather form: 3D levels whose windows fit BAND_SYM_MAX_LDS in FP64 and,
+// with options.band_form = 0, that have more than TAIL_MAX_ROWS rows (smaller
+// ones are launch-bound); never the levels of the persistent cycle, which
+// reads the gather form.
+static int64_t band_sym_ws(const Hierarchy& H, const LevelH& L) {
+  if (H.opt.band_form == 1 || H.prob.d != 3) return 0;
+  if (L.NL <= TAIL_MAX_ROWS && (H.opt.band_form == 0 || H.opt.persistent)) return 0;
+  int64_t n0 = 1;
+  for (const auto& n : L.n) n0 = std::max<int64_t>(n0, n[0]);
+  const int64_t ws = band_sym_window(H.prob.p, n0);
+  return (size_t)ws * sizeof(double) <= BAND_SYM_MAX_LDS ? ws : 0;
+}
+
 static size_t plan(igamg_ctx& C, char* base) {
   Bump b{base};
   const Hierarchy& H = C.H;
@@ -351,6 +368,7 @@ static size_t plan(igamg_ctx& C, char* base) {
     scratch_end = scratch_at + 256 + C.coarse_ws_bytes;
   }
   C.dl.assign(H.lv.size(), DevLevel{});
+  int64_t sym_values = 0;
   for (size_t l = 0; l < H.lv.size(); ++l) {
     const LevelH& L = H.lv[l];
     DevLevel& D = C.dl[l];
@@ -368,6 +386,8 @@ static size_t plan(igamg_ctx& C, char* base) {
     D.gptr = b.take<int64_t>(L.gptr.size());
     D.gidx = b.take<int64_t>(L.gidx.size());
     const bool sl = l > 0;
+    D.sym_ws = sl ? band_sym_ws(H, L) : 0;
+    sym_values = std::max(sym_values, D.sym_ws * (L.NL / ROW_ALIGN));
     plan_level_data(b, L, D, D.d64, sl);
     if (C.mixed) plan_level_data(b, L, D, D.d32, sl);
     if (!sl) continue;
@@ -419,6 +439,7 @@ static size_t plan(igamg_ctx& C, char* base) {
   }
   C.part = b.take<double>(2 * RED_BLOCKS);
   C.scal = b.take<double>(16);
+  C.symwin = sym_values > 0 ? static_cast<void*>(b.take<double>((size_t)sym_values)) : nullptr;
   C.scratch_at = scratch_at;
   if (assemble_on_device(H.opt, true) && H.lv.size() > 1) {
     // the setup-only scratch: at the end of the workspace, or in the static
@@ -514,6 +535,16 @@ static void factor_coarse_on_device(igamg_ctx& C, hipStream_t st) {
   setup_progress("coarse inverse on the device; unknowns", (double)n);
 }
 
+// The FP32 copy of a level's band from its FP64 half band on the device: the
+// half band rounded (scatter form) or the full band expanded from it.
+static void fp32_band(igamg_ctx& C, DevLevel& D, hipStream_t st) {
+  if (D.sym_ws > 0)
+    launch_to_float(D.d64.band, D.d32.band, (int64_t)D.nbh * D.NL, st);
+  else
+    launch_band_half_to_full(C.d, C.p, D.d32.band, D.d64.band, D.bpatch, D.pd, D.NL, st);
+  HIP_OK(hipGetLastError());
+}
+
 // Assembles level l's banded patch matrices on the device, straight into its
 // tiled FP64 band (and the FP32 copy); the level's patch table, free flags and
 // row-block map must be on the device already.
@@ -539,7 +570,7 @@ static void device_assemble(igamg_ctx& C, size_t l, hipStream_t st) {
   for (int k = 0; k < K; ++k)
     if ((flags[k] & 4) || ((flags[k] & 1) && (flags[k] & 2)))
       throw SetupError{IGAMG_EGEOM, "patch " + std::to_string(k) + ": det J vanishes or changes sign"};
-  if (C.mixed) launch_band_half_to_full(d, H.prob.p, D.d32.band, D.d64.band, D.bpatch, D.pd, D.NL, st);
+  if (C.mixed) fp32_band(C, D, st);
   HIP_OK(hipStreamSynchronize(st));
   setup_progress("assembled on the device: level", (double)l);
 }
@@ -597,7 +628,9 @@ static void upload(igamg_ctx& C, hipStream_t st) {
           std::memcpy(&tiled[((size_t)bk * D.nbh + pl) * ROW_ALIGN],
                       &L.band[(size_t)full_of[pl] * L.NL + bk * ROW_ALIGN], ROW_ALIGN * sizeof(double));
       up(D.d64.band, tiled, st);
-      if (C.mixed) {
+      if (C.mixed && D.sym_ws > 0) {
+        fp32_band(C, D, st);
+      } else if (C.mixed) {
         // the FP32 copy keeps every plane, band[(row/256)*nb*256 + o*256 + row%256]
         std::vector<float> full32((size_t)D.nb * L.NL);
         for (int64_t bk = 0; bk < nblk; ++bk)
@@ -646,16 +679,23 @@ template <typename T>
 static void band_op(igamg_ctx& C, int l, const T* u, const T* f, T* r, bool resid, hipStream_t st) {
   DevLevel& D = C.dl[l];
   const T* band = dat<T>(D).band;
+  T* win = static_cast<T*>(C.symwin);
   if (!C.prof) {
-    HIP_OK(launch_band<T>(C.d, C.p, band, u, f, r, D.bpatch, D.pd, D.NL, resid, st));
+    if (D.sym_ws > 0)
+      HIP_OK(launch_band_sym<T>(C.p, band, u, f, r, D.bpatch, D.pd, D.NL, D.sym_ws, win, resid, st));
+    else
+      HIP_OK(launch_band<T>(C.d, C.p, band, u, f, r, D.bpatch, D.pd, D.NL, resid, st));
     return;
   }
   igamg_ctx::Rec rc;
   rc.level = l + (sizeof(T) == 4 ? (int)C.dl.size() : 0);
-  rc.bytes = (double)D.rows * sizeof(T) * ((double)(sizeof(T) == 8 ? D.nbh : D.nb) + (resid ? 3 : 2));
+  rc.bytes = (double)D.rows * sizeof(T) * ((double)(sizeof(T) == 8 || D.sym_ws > 0 ? D.nbh : D.nb) + (resid ? 3 : 2));
   rc.a = next_event(C);
   rc.b = next_event(C);
-  HIP_OK(launch_band<T>(C.d, C.p, band, u, f, r, D.bpatch, D.pd, D.NL, resid, st, rc.a, rc.b));
+  if (D.sym_ws > 0)
+    HIP_OK(launch_band_sym<T>(C.p, band, u, f, r, D.bpatch, D.pd, D.NL, D.sym_ws, win, resid, st, rc.a, rc.b));
+  else
+    HIP_OK(launch_band<T>(C.d, C.p, band, u, f, r, D.bpatch, D.pd, D.NL, resid, st, rc.a, rc.b));
   C.recs.push_back(rc);
   C.prof_stream = st;
 }
@@ -869,6 +909,7 @@ static void read_opts(const igamg_options* o, Options& O) {
   O.physical_h = o->physical_h;
   O.iface_direct = o->iface_direct;
   O.persistent = o->persistent;
+  O.band_form = o->band_form;
   if (O.precision == IGAMG_MIXED_BF16) {
     if (O.fd_mfma != 0 && O.fd_mfma != 3) throw SetupError{IGAMG_EINVAL, "IGAMG_MIXED_BF16 sets fd_mfma = 3"};
     O.precision = IGAMG_MIXED;
@@ -876,7 +917,7 @@ static void read_opts(const igamg_options* o, Options& O) {
   }
   if (O.s1_sigma < 0 || O.s1_sigma > 1 || O.iface_multiplicity < 0 || O.iface_multiplicity > 1 || O.physical_h < 0 ||
       O.physical_h > 1 || O.geometry_scaling < 0 || O.geometry_scaling > 1 || O.iface_direct < 0 ||
-      O.iface_direct > 1 || O.persistent < 0 || O.persistent > 1)
+      O.iface_direct > 1 || O.persistent < 0 || O.persistent > 1 || O.band_form < 0 || O.band_form > 2)
     throw SetupError{IGAMG_EINVAL, "invalid options"};
   if (!(O.tau > 0) || !(O.sigma_scale > 0) || O.nu < 1 || O.nu > 8 || (O.mu != 1 && O.mu != 2) ||
       (O.precision != IGAMG_FP64 && O.precision != IGAMG_MIXED) || O.maxit < 1 || O.inner_maxit < 1 ||

@@ -259,6 +259,182 @@ __global__ __launch_bounds__(256) void k_band_full(const TB* __restrict__ band, 
   band_full_strip<D, P, RESID, TB, TV>(blockIdx.x, band, u, f, r, bpatch, pd);
 }
 
+// ---------------------------------------------------------------------------
+// The symmetric half band in scatter form (3D).  Every stored coefficient
+// a = A[j][j+d] (d >= 0) is fetched once and used twice: y_j += a u_{j+d}
+// (forward) and, d > 0, y_{j+d} += a u_j (its mirror, A[j+d][j] = a).  A
+// workgroup takes one 256-row tile (local rows s .. s+255) with one wave per
+// layer a2 = 0..P of the stored offsets (a0, a1, a2).  A wave adds the
+// mirrored terms of its layer into a window of LDS covering the rows they
+// reach: layer 0 the rows s .. s+255+W, layer a2 >= 1 the rows
+// s + a2 n0 n1 - W .. s + 255 + a2 n0 n1 + W, with W = P + P n0
+// (band_sym_reach).  Each window has one owner wave, which adds into it with
+// LDS atomics; a wave's LDS operations execute in program order, so every
+// position receives its terms in a fixed order.  The LDS windows are FP64
+// for both storage types: FP32 products are exact in FP64, and LDS FP32
+// atomic adds measured about 20x slower per instruction than FP64 ones on
+// this pattern (consecutive addresses, one instruction after another).  The
+// windows go to global
+// memory (per tile band_sym_window values: layer 0, then layers 1..P), the
+// first 256 positions of layer 0 with the tile's forward sums added, and
+// k_band_sym_reduce sums, for each row, the positions of the tiles whose
+// windows cover it, in a fixed order (layer, then tile), into r = f - y (or
+// y).  The windows cost (P+1)*256 + (2P+1)*W values per tile, written once
+// and read once, against nbh*256 coefficients.
+template <int P, typename T>
+__global__ __launch_bounds__(64 * (P + 1)) void k_band_sym_scatter(const T* __restrict__ band,
+                                                                   const T* __restrict__ u, T* __restrict__ win,
+                                                                   int64_t wstride, const int* __restrict__ bpatch,
+                                                                   const PatchDev* __restrict__ pd) {
+  constexpr int NB = 2 * P + 1, NBH = band_half_planes(3, P);
+  extern __shared__ __align__(16) unsigned char sym_lds[];
+  double* lds = reinterpret_cast<double*>(sym_lds);
+  // the layer is the wave index: uniform across the wave (a scalar)
+  const int lane = threadIdx.x & 63, kk = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+  const int64_t b = blockIdx.x;
+  const int k = bpatch[b];
+  if (k < 0) return;                                     // uniform: a padding tile
+  const int64_t off = pd[k].off, rows = pd[k].rows;
+  const int n0 = pd[k].n[0], n1 = pd[k].n[1], n2 = pd[k].n[2];
+  const int64_t n01 = (int64_t)n0 * n1;
+  const int W = (int)band_sym_reach(P, n0);
+  const int len = kk ? ROW_ALIGN + 2 * W : ROW_ALIGN + W;
+  const int wo = kk ? ROW_ALIGN + W + (kk - 1) * (ROW_ALIGN + 2 * W) : 0;
+  double* lw = lds + wo;                                 // this wave's window
+  for (int i = lane; i < len; i += 64) lw[i] = 0.0;
+  __syncthreads();
+  const int64_t s = b * ROW_ALIGN - off;
+  const T* ub = u + off;
+  // lines (a1) of this wave's layer: a1 = 0..P in layer 0 (the centre line
+  // a1 = 0 stores a0 = 0..P only), a1 = -P..P in the others
+  const int a1_first = kk ? -P : 0, nline = kk ? NB : P + 1;
+  const int plane0 = kk ? P + 1 + P * NB + (kk - 1) * NB * NB : 0;
+  T y[4];
+#pragma unroll 1
+  for (int g = 0; g < 4; ++g) {
+    const int64_t j = s + 64 * g + lane;
+    const bool valid = j < rows;                         // padding rows add nothing
+    const int64_t jr = valid ? j : rows - 1;
+    const int i0 = (int)(jr % n0);
+    const int64_t t = jr / n0;
+    const int i1 = (int)(t % n1), i2 = (int)(t / n1);
+    const T uj = valid ? ub[j] : T(0);
+    int c0[NB];
+#pragma unroll
+    for (int o = 0; o < NB; ++o) c0[o] = min(max(i0 + o - P, 0), n0 - 1);
+    // row j's plane q at bg[q * ROW_ALIGN]; out-of-patch offsets hold zeros
+    const T* bg = band + (b * NBH) * ROW_ALIGN + 64 * g + lane;
+    const T* uz = ub + (int64_t)min(i2 + kk, n2 - 1) * n01;
+    const int pos = 64 * g + lane + (kk ? W : 0);        // window position of row j itself
+    // The coefficients and u values of line li (a1 = a1_first + li), o0 = a0 + P.
+    auto load_line = [&](int li, T* vb, T* vu) {
+      const int a1 = a1_first + li;
+      const bool centre = kk == 0 && a1 == 0;
+      const T* bq = bg + (centre ? 0 : (plane0 + (kk ? li * NB : P + 1 + (a1 - 1) * NB))) * ROW_ALIGN;
+      const T* ur = uz + (int64_t)min(max(i1 + a1, 0), n1 - 1) * n0;
+#pragma unroll
+      for (int o0 = 0; o0 < NB; ++o0) {
+        if (centre && o0 < P) {                         // the centre line's lower half is not stored
+          vb[o0] = T(0);
+          vu[o0] = T(0);
+        } else {
+          vb[o0] = bq[(centre ? o0 - P : o0) * ROW_ALIGN];
+          vu[o0] = ur[c0[o0]];
+        }
+      }
+    };
+    T acc = T(0);
+    // forward terms of line li, and its mirrored terms into the window
+    auto add_line = [&](int li, const T* vb, const T* vu) {
+      const int a1 = a1_first + li;
+      const bool centre = kk == 0 && a1 == 0;
+      double* lq = lw + pos + a1 * n0 - P;
+#pragma unroll
+      for (int o0 = 0; o0 < NB; ++o0) {
+        acc += vb[o0] * vu[o0];
+        // the mirrored term of offset d > 0 (the centre line's a0 <= 0 has none)
+        if (!(centre && o0 <= P))
+          __hip_atomic_fetch_add(lq + o0, valid ? (double)vb[o0] * (double)uj : 0.0, __ATOMIC_RELAXED,
+                                 __HIP_MEMORY_SCOPE_WORKGROUP);
+      }
+    };
+    // Loads are not issued ahead of an earlier (ordered) LDS atomic, so the
+    // lines go through two register buffers: the loads of line li + 2 are
+    // issued right after the atomics of line li, and two lines are in flight.
+    // (nline >= 2; the main loop's loads are unconditional, the last two or
+    // three lines are peeled)
+    T b0[NB], u0[NB], b1[NB], u1[NB];
+    load_line(0, b0, u0);
+    load_line(1, b1, u1);
+    int li = 0;
+#pragma unroll 1
+    for (; li + 3 < nline; li += 2) {
+      add_line(li, b0, u0);
+      load_line(li + 2, b0, u0);
+      add_line(li + 1, b1, u1);
+      load_line(li + 3, b1, u1);
+    }
+    add_line(li, b0, u0);
+    if (li + 2 < nline) load_line(li + 2, b0, u0);
+    add_line(li + 1, b1, u1);
+    if (li + 2 < nline) add_line(li + 2, b0, u0);
+    y[g] = acc;
+  }
+  __syncthreads();
+  // the windows out; layer 0's first 256 positions wait for the forward sums
+  T* wg = win + b * wstride + wo;
+  for (int i = lane + (kk ? 0 : ROW_ALIGN); i < len; i += 64) wg[i] = (T)lw[i];
+  __syncthreads();
+  if (kk > 0) {
+#pragma unroll
+    for (int g = 0; g < 4; ++g) lw[64 * g + lane] = (double)y[g];
+  }
+  __syncthreads();
+  if (kk == 0) {
+#pragma unroll
+    for (int g = 0; g < 4; ++g) {
+      double fw = (double)y[g];
+      for (int q = 1; q <= P; ++q) fw += lds[ROW_ALIGN + W + (q - 1) * (ROW_ALIGN + 2 * W) + 64 * g + lane];
+      wg[64 * g + lane] = (T)(lw[64 * g + lane] + fw);
+    }
+  }
+}
+
+// One row per thread: the sum of the window positions that cover it (layer
+// 0..P, then tile, ascending, in FP64), and r = f - y (RESID) or r = y.
+template <int P, bool RESID, typename T>
+__global__ __launch_bounds__(256) void k_band_sym_reduce(const T* __restrict__ win, int64_t wstride,
+                                                         const T* __restrict__ f, T* __restrict__ r,
+                                                         const int* __restrict__ bpatch,
+                                                         const PatchDev* __restrict__ pd) {
+  const int64_t b = blockIdx.x;
+  const int k = bpatch[b];
+  if (k < 0) return;
+  const int64_t off = pd[k].off, rows = pd[k].rows;
+  const int64_t t = b * ROW_ALIGN - off + threadIdx.x;
+  if (t >= rows) return;
+  const int n0 = pd[k].n[0];
+  const int64_t n01 = (int64_t)n0 * pd[k].n[1];
+  const int W = (int)band_sym_reach(P, n0);
+  const int64_t ntile = (rows + ROW_ALIGN - 1) / ROW_ALIGN;
+  const T* wb = win + (off / ROW_ALIGN) * wstride;     // the patch's first tile
+  double acc = 0.0;
+#pragma unroll
+  for (int kk = 0; kk <= P; ++kk) {
+    const int len = kk ? ROW_ALIGN + 2 * W : ROW_ALIGN + W;
+    const int wo = kk ? ROW_ALIGN + W + (kk - 1) * (ROW_ALIGN + 2 * W) : 0;
+    // row t sits at position q - 256 sg of tile sg's layer-kk window
+    const int64_t q = kk ? t - kk * n01 + W : t;
+    if (q < 0) continue;
+    const int64_t lo = q - len + 1 <= 0 ? 0 : (q - len + ROW_ALIGN) / ROW_ALIGN;
+    const int64_t hi = min(ntile - 1, q / ROW_ALIGN);
+    for (int64_t sg = lo; sg <= hi; ++sg) acc += wb[sg * wstride + wo + (q - sg * ROW_ALIGN)];
+  }
+  const int64_t g = off + t;
+  if constexpr (RESID) r[g] = (T)((double)f[g] - acc);
+  else r[g] = (T)acc;
+}
+
 // The FP32 full band from the FP64 half band: entry (row, o) of the full
 // band is the stored plane of o at the row, or, for an offset of the lower
 // half, the stored plane of -o at row + d(o) (zero outside the patch).
@@ -349,6 +525,44 @@ hipError_t launch_band(int d, int p, const T* band, const T* u, const T* f, T* r
   IGAMG_BAND_CASE(3, 1) IGAMG_BAND_CASE(3, 2) IGAMG_BAND_CASE(3, 3) IGAMG_BAND_CASE(3, 4)
   IGAMG_BAND_CASE(3, 5) IGAMG_BAND_CASE(3, 6) IGAMG_BAND_CASE(3, 7) IGAMG_BAND_CASE(3, 8)
 #undef IGAMG_BAND_CASE
+  return hipErrorInvalidValue;
+}
+
+template <int P, typename T>
+static hipError_t launch_band_sym_p(const T* band, const T* u, const T* f, T* r, const int* bpatch,
+                                    const PatchDev* pd, int64_t NL, int64_t ws, T* win, bool resid, hipStream_t st,
+                                    hipEvent_t ev0, hipEvent_t ev1) {
+  const dim3 grid((unsigned)(NL / ROW_ALIGN)), b1(64 * (P + 1)), b2(256);
+  const size_t lds = (size_t)ws * sizeof(double);       // FP64 windows for both types
+  if (ev0) {
+    // timed: the start of the scatter pass to the end of the reduction
+    const void* f1 = reinterpret_cast<const void*>(&k_band_sym_scatter<P, T>);
+    const void* f2 = resid ? reinterpret_cast<const void*>(&k_band_sym_reduce<P, true, T>)
+                           : reinterpret_cast<const void*>(&k_band_sym_reduce<P, false, T>);
+    void* a1[] = {(void*)&band, (void*)&u, (void*)&win, (void*)&ws, (void*)&bpatch, (void*)&pd};
+    void* a2[] = {(void*)&win, (void*)&ws, (void*)&f, (void*)&r, (void*)&bpatch, (void*)&pd};
+    const hipError_t e = hipExtLaunchKernel(f1, grid, b1, a1, lds, st, ev0, nullptr, 0);
+    if (e != hipSuccess) return e;
+    return hipExtLaunchKernel(f2, grid, b2, a2, 0, st, nullptr, ev1, 0);
+  }
+  hipLaunchKernelGGL((k_band_sym_scatter<P, T>), grid, b1, lds, st, band, u, win, ws, bpatch, pd);
+  if (resid)
+    hipLaunchKernelGGL((k_band_sym_reduce<P, true, T>), grid, b2, 0, st, win, ws, f, r, bpatch, pd);
+  else
+    hipLaunchKernelGGL((k_band_sym_reduce<P, false, T>), grid, b2, 0, st, win, ws, f, r, bpatch, pd);
+  return hipSuccess;
+}
+
+template <typename T>
+hipError_t launch_band_sym(int p, const T* band, const T* u, const T* f, T* r, const int* bpatch,
+                           const PatchDev* pd, int64_t NL, int64_t ws, T* win, bool resid, hipStream_t st,
+                           hipEvent_t ev0, hipEvent_t ev1) {
+  if (ws <= 0 || (size_t)ws * sizeof(double) > BAND_SYM_MAX_LDS) return hipErrorInvalidValue;
+#define IGAMG_SYM_CASE(PP) \
+  if (p == PP) return launch_band_sym_p<PP, T>(band, u, f, r, bpatch, pd, NL, ws, win, resid, st, ev0, ev1);
+  IGAMG_SYM_CASE(1) IGAMG_SYM_CASE(2) IGAMG_SYM_CASE(3) IGAMG_SYM_CASE(4)
+  IGAMG_SYM_CASE(5) IGAMG_SYM_CASE(6) IGAMG_SYM_CASE(7) IGAMG_SYM_CASE(8)
+#undef IGAMG_SYM_CASE
   return hipErrorInvalidValue;
 }
 
@@ -1974,6 +2188,8 @@ void launch_add_f32(double* x, const float* d, int64_t n, hipStream_t st) {
 #define IGAMG_INST(T)                                                                                                  \
   template hipError_t launch_band<T>(int, int, const T*, const T*, const T*, T*, const int*, const PatchDev*, int64_t,   \
                                      bool, hipStream_t, hipEvent_t, hipEvent_t);                                       \
+  template hipError_t launch_band_sym<T>(int, const T*, const T*, const T*, T*, const int*, const PatchDev*, int64_t,   \
+                                         int64_t, T*, bool, hipStream_t, hipEvent_t, hipEvent_t);                     \
   template void launch_fd_fwd<T>(const FDItem*, int, int, int, size_t, const DensePiece*, const T*, const T*,          \
                                  const T*, T*, const int64_t*, const int64_t*, T*, double, bool, int, hipStream_t);    \
   template void launch_fd_mid<T>(const FDItem*, int, int, size_t, const T*, T*, hipStream_t);                          \

@@ -6,6 +6,7 @@
 // entries so that every 256-row block of a level belongs to one patch.
 #pragma once
 
+#include <cstddef>
 #include <cstdint>
 
 namespace igamg {
@@ -35,6 +36,17 @@ constexpr int band_half_plane(int d, int p, int o0, int L) {
          : L > (band_lines(d, p) - 1) / 2 ? p + 1 + (L - (band_lines(d, p) - 1) / 2 - 1) * (2 * p + 1) + o0
                                           : -1;
 }
+
+// Scatter form of the symmetric half-band apply (3D): the stored offsets of
+// a 256-row tile reach the rows of the tile shifted by a2 n0 n1 (layer a2 of
+// the stencil, 0..p) plus at most band_sym_reach = p + p n0 either way; the
+// tile's windows (layer 0: 256 + reach rows, layers 1..p: 256 + 2 reach)
+// hold band_sym_window values in all.
+constexpr int64_t band_sym_reach(int p, int64_t n0) { return p + p * n0; }
+constexpr int64_t band_sym_window(int p, int64_t n0) {
+  return (int64_t)(p + 1) * ROW_ALIGN + (2 * p + 1) * band_sym_reach(p, n0);
+}
+constexpr size_t BAND_SYM_MAX_LDS = 64 * 1024;   // windows of one tile in LDS, at most
 
 // One patch on one level l (coarse data refers to level l-1).
 struct PatchDev {

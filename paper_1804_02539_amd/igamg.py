@@ -49,7 +49,8 @@ class Options(ctypes.Structure):
                 ("inner_tol", ctypes.c_double), ("graphs", ctypes.c_int), ("fd_mfma", ctypes.c_int),
                 ("coarse_factor", ctypes.c_int), ("autotune", ctypes.c_int), ("assembly", ctypes.c_int),
                 ("s1_sigma", ctypes.c_int), ("iface_multiplicity", ctypes.c_int), ("physical_h", ctypes.c_int),
-                ("iface_direct", ctypes.c_int), ("persistent", ctypes.c_int)]
+                ("iface_direct", ctypes.c_int), ("persistent", ctypes.c_int),
+                ("band_form", ctypes.c_int)]
 
 
 class SolveInfo(ctypes.Structure):
