@@ -336,7 +336,7 @@ static void tail_program(igamg_ctx& C, igamg_ctx::Tail& tl) {
 }
 
 // Window values per tile of level L's banded apply in scatter form, or 0 for
-// the gather form: 3D levels whose windows fit BAND_SYM_MAX_LDS in FP64 and,
+// the gather form: 3D levels whose windows and u fit BAND_SYM_MAX_LDS in FP64 and,
 // with options.band_form = 0, that have more than TAIL_MAX_ROWS rows (smaller
 // ones are launch-bound); never the levels of the persistent cycle, which
 // reads the gather form.
@@ -346,7 +346,7 @@ static int64_t band_sym_ws(const Hierarchy& H, const LevelH& L) {
   int64_t n0 = 1;
   for (const auto& n : L.n) n0 = std::max<int64_t>(n0, n[0]);
   const int64_t ws = band_sym_window(H.prob.p, n0);
-  return (size_t)ws * sizeof(double) <= BAND_SYM_MAX_LDS ? ws : 0;
+  return (size_t)ws * 2 * sizeof(double) <= BAND_SYM_MAX_LDS ? ws : 0;
 }
 
 static size_t plan(igamg_ctx& C, char* base) {

@@ -281,30 +281,61 @@ __global__ __launch_bounds__(256) void k_band_full(const TB* __restrict__ band, 
 // windows cover it, in a fixed order (layer, then tile), into r = f - y (or
 // y).  The windows cost (P+1)*256 + (2P+1)*W values per tile, written once
 // and read once, against nbh*256 coefficients.
+// element idx of a uniform base, with a 32-bit byte offset (one VGPR per
+// address instead of two)
+template <typename T>
+__device__ __forceinline__ T ld_off32(const T* __restrict__ base, uint32_t idx) {
+  return *reinterpret_cast<const T*>(reinterpret_cast<const char*>(base) + idx * (uint32_t)sizeof(T));
+}
+
+// Lines of coefficients in flight per wave of k_band_sym_scatter: per degree
+// and type the deepest buffering (of 2..5 lines) that the compiler fits
+// without spilling at the occupancy the LDS allows, read off its register
+// counts.
+template <int P, typename T>
+constexpr int band_sym_nbuf() {
+  if (sizeof(T) == 4) return P == 7 ? 2 : (P == 4 || P == 8) ? 4 : 5;
+  return (P == 1 || P == 2) ? 5 : P == 3 ? 3 : P == 4 ? 4 : 2;
+}
+
 template <int P, typename T>
 __global__ __launch_bounds__(64 * (P + 1)) void k_band_sym_scatter(const T* __restrict__ band,
                                                                    const T* __restrict__ u, T* __restrict__ win,
                                                                    int64_t wstride, const int* __restrict__ bpatch,
                                                                    const PatchDev* __restrict__ pd) {
   constexpr int NB = 2 * P + 1, NBH = band_half_planes(3, P);
+  constexpr int NBUF = band_sym_nbuf<P, T>();
   extern __shared__ __align__(16) unsigned char sym_lds[];
-  double* lds = reinterpret_cast<double*>(sym_lds);
+  const int lane = threadIdx.x & 63;
   // the layer is the wave index: uniform across the wave (a scalar)
-  const int lane = threadIdx.x & 63, kk = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+  const int kk = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
   const int64_t b = blockIdx.x;
   const int k = bpatch[b];
   if (k < 0) return;                                     // uniform: a padding tile
   const int64_t off = pd[k].off, rows = pd[k].rows;
-  const int n0 = pd[k].n[0], n1 = pd[k].n[1], n2 = pd[k].n[2];
-  const int64_t n01 = (int64_t)n0 * n1;
+  const int n0 = pd[k].n[0];
+  const int64_t n01 = (int64_t)n0 * pd[k].n[1];
   const int W = (int)band_sym_reach(P, n0);
   const int len = kk ? ROW_ALIGN + 2 * W : ROW_ALIGN + W;
   const int wo = kk ? ROW_ALIGN + W + (kk - 1) * (ROW_ALIGN + 2 * W) : 0;
-  double* lw = lds + wo;                                 // this wave's window
-  for (int i = lane; i < len; i += 64) lw[i] = 0.0;
-  __syncthreads();
+  // LDS: the windows (FP64), then u at the same positions (storage type):
+  // position q of layer kk's window and segment is local row
+  // s + kk n0 n1 - (kk ? W : 0) + q, so the forward term of an offset reads
+  // u where its mirrored term goes.  Rows outside the patch read 0 (their
+  // coefficients are 0 too).
+  double* lw = reinterpret_cast<double*>(sym_lds) + wo;
+  T* lu = reinterpret_cast<T*>(reinterpret_cast<double*>(sym_lds) + wstride) + wo;
   const int64_t s = b * ROW_ALIGN - off;
   const T* ub = u + off;
+  const int64_t base = s + kk * n01 - (kk ? W : 0);
+  for (int i = lane; i < len; i += 64) {
+    lw[i] = 0.0;
+    const int64_t row = base + i;
+    lu[i] = (row >= 0 && row < rows) ? ub[row] : T(0);
+  }
+  __syncthreads();
+  // the tile's planes; loads index them with 32-bit offsets from this base
+  const T* bt = band + (b * NBH) * ROW_ALIGN;
   // lines (a1) of this wave's layer: a1 = 0..P in layer 0 (the centre line
   // a1 = 0 stores a0 = 0..P only), a1 = -P..P in the others
   const int a1_first = kk ? -P : 0, nline = kk ? NB : P + 1;
@@ -314,70 +345,61 @@ __global__ __launch_bounds__(64 * (P + 1)) void k_band_sym_scatter(const T* __re
   for (int g = 0; g < 4; ++g) {
     const int64_t j = s + 64 * g + lane;
     const bool valid = j < rows;                         // padding rows add nothing
-    const int64_t jr = valid ? j : rows - 1;
-    const int i0 = (int)(jr % n0);
-    const int64_t t = jr / n0;
-    const int i1 = (int)(t % n1), i2 = (int)(t / n1);
-    const T uj = valid ? ub[j] : T(0);
-    int c0[NB];
-#pragma unroll
-    for (int o = 0; o < NB; ++o) c0[o] = min(max(i0 + o - P, 0), n0 - 1);
-    // row j's plane q at bg[q * ROW_ALIGN]; out-of-patch offsets hold zeros
-    const T* bg = band + (b * NBH) * ROW_ALIGN + 64 * g + lane;
-    const T* uz = ub + (int64_t)min(i2 + kk, n2 - 1) * n01;
+    const double uj = valid ? (double)ub[j] : 0.0;
+    const uint32_t rt = 64 * g + lane;
     const int pos = 64 * g + lane + (kk ? W : 0);        // window position of row j itself
-    // The coefficients and u values of line li (a1 = a1_first + li), o0 = a0 + P.
-    auto load_line = [&](int li, T* vb, T* vu) {
+    // the coefficients of line li (a1 = a1_first + li), o0 = a0 + P; the
+    // centre line's lower half (o0 < P) is not stored and reads as 0
+    auto load_line = [&](int li, T* vb) {
       const int a1 = a1_first + li;
       const bool centre = kk == 0 && a1 == 0;
-      const T* bq = bg + (centre ? 0 : (plane0 + (kk ? li * NB : P + 1 + (a1 - 1) * NB))) * ROW_ALIGN;
-      const T* ur = uz + (int64_t)min(max(i1 + a1, 0), n1 - 1) * n0;
+      const uint32_t bq = (uint32_t)(centre ? -P : plane0 + (kk ? li * NB : P + 1 + (a1 - 1) * NB)) * ROW_ALIGN + rt;
 #pragma unroll
-      for (int o0 = 0; o0 < NB; ++o0) {
-        if (centre && o0 < P) {                         // the centre line's lower half is not stored
-          vb[o0] = T(0);
-          vu[o0] = T(0);
-        } else {
-          vb[o0] = bq[(centre ? o0 - P : o0) * ROW_ALIGN];
-          vu[o0] = ur[c0[o0]];
-        }
-      }
+      for (int o0 = 0; o0 < NB; ++o0) vb[o0] = (centre && o0 < P) ? T(0) : ld_off32(bt, bq + (uint32_t)(o0 * ROW_ALIGN));
     };
     T acc = T(0);
-    // forward terms of line li, and its mirrored terms into the window
-    auto add_line = [&](int li, const T* vb, const T* vu) {
+    // forward terms of line li from the staged u, its mirrored terms into
+    // the window (offsets d > 0: the centre line's a0 <= 0 has none)
+    auto add_line = [&](int li, const T* vb) {
       const int a1 = a1_first + li;
       const bool centre = kk == 0 && a1 == 0;
-      double* lq = lw + pos + a1 * n0 - P;
+      const int q0 = pos + a1 * n0 - P;
+      T uq[NB];
+#pragma unroll
+      for (int o0 = 0; o0 < NB; ++o0) uq[o0] = lu[(centre && o0 < P) ? q0 + P : q0 + o0];
 #pragma unroll
       for (int o0 = 0; o0 < NB; ++o0) {
-        acc += vb[o0] * vu[o0];
-        // the mirrored term of offset d > 0 (the centre line's a0 <= 0 has none)
+        acc += vb[o0] * uq[o0];
         if (!(centre && o0 <= P))
-          __hip_atomic_fetch_add(lq + o0, valid ? (double)vb[o0] * (double)uj : 0.0, __ATOMIC_RELAXED,
+          __hip_atomic_fetch_add(lw + q0 + o0, valid ? (double)vb[o0] * uj : 0.0, __ATOMIC_RELAXED,
                                  __HIP_MEMORY_SCOPE_WORKGROUP);
       }
     };
     // Loads are not issued ahead of an earlier (ordered) LDS atomic, so the
-    // lines go through two register buffers: the loads of line li + 2 are
-    // issued right after the atomics of line li, and two lines are in flight.
-    // (nline >= 2; the main loop's loads are unconditional, the last two or
-    // three lines are peeled)
-    T b0[NB], u0[NB], b1[NB], u1[NB];
-    load_line(0, b0, u0);
-    load_line(1, b1, u1);
+    // lines rotate through NBUF register buffers: the loads of line li + NBUF
+    // are issued right after the atomics of line li, and NBUF lines are in
+    // flight.  The main loop's loads are unconditional; the last lines are
+    // peeled.
+    T vb[NBUF][NB];
+#pragma unroll
+    for (int q = 0; q < NBUF; ++q)
+      if (q < nline) load_line(q, vb[q]);
     int li = 0;
 #pragma unroll 1
-    for (; li + 3 < nline; li += 2) {
-      add_line(li, b0, u0);
-      load_line(li + 2, b0, u0);
-      add_line(li + 1, b1, u1);
-      load_line(li + 3, b1, u1);
+    for (; li + 2 * NBUF - 1 < nline; li += NBUF) {
+#pragma unroll
+      for (int q = 0; q < NBUF; ++q) {
+        add_line(li + q, vb[q]);
+        load_line(li + q + NBUF, vb[q]);
+      }
     }
-    add_line(li, b0, u0);
-    if (li + 2 < nline) load_line(li + 2, b0, u0);
-    add_line(li + 1, b1, u1);
-    if (li + 2 < nline) add_line(li + 2, b0, u0);
+#pragma unroll
+    for (int q = 0; q < 2 * NBUF - 1; ++q) {
+      if (li + q < nline) {
+        add_line(li + q, vb[q % NBUF]);
+        if (li + q + NBUF < nline) load_line(li + q + NBUF, vb[q % NBUF]);
+      }
+    }
     y[g] = acc;
   }
   __syncthreads();
@@ -394,7 +416,7 @@ __global__ __launch_bounds__(64 * (P + 1)) void k_band_sym_scatter(const T* __re
 #pragma unroll
     for (int g = 0; g < 4; ++g) {
       double fw = (double)y[g];
-      for (int q = 1; q <= P; ++q) fw += lds[ROW_ALIGN + W + (q - 1) * (ROW_ALIGN + 2 * W) + 64 * g + lane];
+      for (int q = 1; q <= P; ++q) fw += reinterpret_cast<double*>(sym_lds)[ROW_ALIGN + W + (q - 1) * (ROW_ALIGN + 2 * W) + 64 * g + lane];
       wg[64 * g + lane] = (T)(lw[64 * g + lane] + fw);
     }
   }
@@ -532,8 +554,12 @@ template <int P, typename T>
 static hipError_t launch_band_sym_p(const T* band, const T* u, const T* f, T* r, const int* bpatch,
                                     const PatchDev* pd, int64_t NL, int64_t ws, T* win, bool resid, hipStream_t st,
                                     hipEvent_t ev0, hipEvent_t ev1) {
+  static const hipError_t attr = hipFuncSetAttribute(reinterpret_cast<const void*>(&k_band_sym_scatter<P, T>),
+                                                     hipFuncAttributeMaxDynamicSharedMemorySize,
+                                                     (int)BAND_SYM_MAX_LDS);
+  if (attr != hipSuccess) return attr;
   const dim3 grid((unsigned)(NL / ROW_ALIGN)), b1(64 * (P + 1)), b2(256);
-  const size_t lds = (size_t)ws * sizeof(double);       // FP64 windows for both types
+  const size_t lds = (size_t)ws * (sizeof(double) + sizeof(T));   // FP64 windows, u segments
   if (ev0) {
     // timed: the start of the scatter pass to the end of the reduction
     const void* f1 = reinterpret_cast<const void*>(&k_band_sym_scatter<P, T>);
@@ -557,7 +583,7 @@ template <typename T>
 hipError_t launch_band_sym(int p, const T* band, const T* u, const T* f, T* r, const int* bpatch,
                            const PatchDev* pd, int64_t NL, int64_t ws, T* win, bool resid, hipStream_t st,
                            hipEvent_t ev0, hipEvent_t ev1) {
-  if (ws <= 0 || (size_t)ws * sizeof(double) > BAND_SYM_MAX_LDS) return hipErrorInvalidValue;
+  if (ws <= 0 || (size_t)ws * (sizeof(double) + sizeof(T)) > BAND_SYM_MAX_LDS) return hipErrorInvalidValue;
 #define IGAMG_SYM_CASE(PP) \
   if (p == PP) return launch_band_sym_p<PP, T>(band, u, f, r, bpatch, pd, NL, ws, win, resid, st, ev0, ev1);
   IGAMG_SYM_CASE(1) IGAMG_SYM_CASE(2) IGAMG_SYM_CASE(3) IGAMG_SYM_CASE(4)

@@ -23,7 +23,8 @@ hipError_t launch_band(int d, int p, const T* band, const T* u, const T* f, T* r
 // The same in the scatter form of the symmetric half band (3D; two kernels,
 // each coefficient fetched once): `ws` = band_sym_window(p, largest n0 of the
 // level's patches) values of window per 256-row tile, `win` holds
-// NL / 256 * ws of them; ws * 8 <= BAND_SYM_MAX_LDS (FP64 windows in LDS).  The events
+// NL / 256 * ws of them; ws * (8 + sizeof(T)) <= BAND_SYM_MAX_LDS (FP64 windows and
+// the u of their rows in LDS).  The events
 // time both kernels together.
 template <typename T>
 hipError_t launch_band_sym(int p, const T* band, const T* u, const T* f, T* r, const int* bpatch,
