@@ -108,8 +108,10 @@ def traffic_summary(workload, fetch_csv, write_csv, fetch_cmd, write_cmd):
     rocprofv3 --pmc runs of the same bench command with --copy-calibration
     (FETCH_SIZE, then WRITE_SIZE; csv output).  Each counter is scaled by what
     it reads for the 256 MiB device copy of the calibration; the finest level
-    is the band launch with the largest grid.  Written beside the kernel
-    source hash, so that bench.py reports it only for the kernels measured."""
+    is the band launch with the largest grid.  An apply in scatter form is
+    its two kernels (k_band_sym_scatter, k_band_sym_reduce), each at its own
+    largest grid, summed.  Written beside the kernel source hash, so that
+    bench.py reports it only for the kernels measured."""
     import csv
     copy_bytes = 256 << 20
 
@@ -126,13 +128,21 @@ def traffic_summary(workload, fetch_csv, write_csv, fetch_cmd, write_cmd):
         if not copies:
             raise SystemExit(f"{path}: no copy-calibration dispatch")
         out = {"copy_kib": max(copies)}
-        for prec, key, typ in (("fp64", "k_band_half<", "double"), ("mixed", "k_band_full<", "float")):
+
+        def finest(key, typ):
             band = [(g, v) for n, g, v in rows if key in n and typ in n]
             if not band:
-                continue
+                return None
             gmax = max(g for g, _ in band)
             vals = [v for g, v in band if g == gmax]
-            out[prec] = (sum(vals) / len(vals), len(vals))
+            return sum(vals) / len(vals), len(vals)
+
+        for prec, key, typ in (("fp64", "k_band_half<", "double"), ("mixed", "k_band_full<", "float")):
+            sc, rd = finest("k_band_sym_scatter<", typ), finest("k_band_sym_reduce<", typ)
+            if sc and rd:
+                out[prec] = (sc[0] + rd[0], sc[1], "k_band_sym_scatter + k_band_sym_reduce")
+            elif finest(key, typ):
+                out[prec] = finest(key, typ) + (key.rstrip("<"),)
         return out
 
     fe, wr = read(fetch_csv, "FETCH_SIZE"), read(write_csv, "WRITE_SIZE")
@@ -144,7 +154,8 @@ def traffic_summary(workload, fetch_csv, write_csv, fetch_cmd, write_cmd):
            "write_copy_kib": wr["copy_kib"], "write_scale": ws, "write_command": write_cmd}
     for prec in ("fp64", "mixed"):
         if prec in fe and prec in wr:
-            res[prec] = {"fetch_kib_per_launch": fe[prec][0], "fetch_launches": fe[prec][1],
+            res[prec] = {"kernels": fe[prec][2],
+                         "fetch_kib_per_launch": fe[prec][0], "fetch_launches": fe[prec][1],
                          "write_kib_per_launch": wr[prec][0], "write_launches": wr[prec][1],
                          "hbm_bytes_per_launch": 1024.0 * (fe[prec][0] * fs + wr[prec][0] * ws)}
     path = os.path.join(ROOT, "profiles", f"band_apply_{workload}_traffic.json")
@@ -274,8 +285,12 @@ def run(workload, prob, precision, steps, warmup, dev, fd_mfma=0, profile_steps=
         "smoother_variant_finest": igamg.FD_NAMES[S.tuning(-1, precision == "mixed")],
         "setup_s": setup_s,
         "roofline": {"bound": "hbm",
-                     "kernel": ("k_band<float> finest-level FP32 banded residual/apply (inner solves)"
-                                if precision == "mixed" else "k_band<double> finest-level banded residual/apply"),
+                     "kernel": (("finest-level FP32 banded residual/apply (inner solves)" if precision == "mixed"
+                                 else "finest-level FP64 banded residual/apply")
+                                + (": k_band_sym_scatter + k_band_sym_reduce (half band, scatter form)"
+                                   if S.band_form(-1) == igamg.BAND_SCATTER else
+                                   ": k_band_full (full FP32 band)" if precision == "mixed"
+                                   else ": k_band_half (half band, gather form)")),
                      "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": achieved / HBM_PEAK_GBS,
                      "traffic": traffic_from_profiles(workload, precision),

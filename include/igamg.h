@@ -332,6 +332,16 @@ int igamg_profile_read(igamg_handle h, int64_t* launches, double* ms, double* by
  * JSON file that persists the cache between processes.                      */
 int igamg_tuning(igamg_handle h, int level, int fp32, int* variant);
 
+/* The form of level `level`'s (>= 1) banded apply, the same in both
+ * precisions (options.band_form): IGAMG_BAND_GATHER (each row reads the
+ * mirrored half of the symmetric band from the rows it couples to; the FP32
+ * copy is the full band) or IGAMG_BAND_SCATTER (each stored coefficient read
+ * once, its mirrored term added through per-tile windows; the FP32 copy is
+ * the half band).                                                           */
+#define IGAMG_BAND_GATHER 0
+#define IGAMG_BAND_SCATTER 1
+int igamg_band_form(igamg_handle h, int level, int* form);
+
 /* Release the handle (not the workspace).                                    */
 int igamg_destroy(igamg_handle h);
 

@@ -1618,6 +1618,17 @@ int igamg_tuning(igamg_handle h, int level, int fp32, int* variant) {
   API_END
 }
 
+int igamg_band_form(igamg_handle h, int level, int* form) {
+  API_BEGIN
+  if (!h || !form) return set_err(IGAMG_EINVAL, "null argument");
+  if (!h->on_device) return set_err(IGAMG_EINVAL, "handle has no device data");
+  level = check_level(h, level);
+  if (level < 1) return set_err(IGAMG_EINVAL, "no banded matrix on level 0");
+  *form = h->dl[level].sym_ws > 0 ? IGAMG_BAND_SCATTER : IGAMG_BAND_GATHER;
+  return IGAMG_OK;
+  API_END
+}
+
 int igamg_num_dofs(igamg_handle h, int level, int64_t* n_free, int64_t* n_local) {
   API_BEGIN
   if (!h) return set_err(IGAMG_EINVAL, "null handle");

@@ -89,6 +89,7 @@ def _load():
         "igamg_solve_batch": (ctypes.c_int, [P(vp), P(vp), P(vp), ctypes.c_int, ctypes.c_double, P(SolveInfo),
                                               P(ctypes.c_int), vp]),
         "igamg_tuning": (ctypes.c_int, [vp, ctypes.c_int, ctypes.c_int, P(ctypes.c_int)]),
+        "igamg_band_form": (ctypes.c_int, [vp, ctypes.c_int, P(ctypes.c_int)]),
         "igamg_destroy": (ctypes.c_int, [vp]),
         "igamg_last_error": (ctypes.c_char_p, []),
     }
@@ -105,8 +106,9 @@ EXPORTED = ["igamg_default_options", "igamg_workspace_size", "igamg_setup", "iga
             "igamg_export", "igamg_profile", "igamg_profile_read", "igamg_destroy",
             "igamg_last_error", "igamg_batch_create", "igamg_batch_destroy", "igamg_batch_add",
             "igamg_batch_step", "igamg_batch_poll", "igamg_batch_remove", "igamg_solve_batch", "igamg_tuning",
-            "igamg_setup_noalloc"]
+            "igamg_setup_noalloc", "igamg_band_form"]
 EXPORT_MATRIX, EXPORT_PROLONG = 0, 1
+BAND_GATHER, BAND_SCATTER = 0, 1
 
 
 def lib():
@@ -238,6 +240,13 @@ class Solver:
         L = self.prob.levels - 1 if level < 0 else level
         v = ctypes.c_int()
         _check(_lib.igamg_tuning(self.h, L, int(fp32), ctypes.byref(v)))
+        return v.value
+
+    def band_form(self, level=-1):
+        """BAND_GATHER or BAND_SCATTER: the form of a level's banded apply."""
+        L = self.prob.levels - 1 if level < 0 else level
+        v = ctypes.c_int()
+        _check(_lib.igamg_band_form(self.h, L, ctypes.byref(v)))
         return v.value
 
     def profile(self, enable):

@@ -74,6 +74,7 @@ def test_scatter_apply_matches_oracle(torch_cuda, name):
     S = gpu_for(name, band_form=2)
     rng = np.random.default_rng(11)
     for l in range(1, len(H.levels)):
+        assert S.band_form(l) == igamg.BAND_SCATTER, l
         x = rng.standard_normal(H.levels[l].N)
         y = S.operator(igamg.OP_APPLY, l, x).cpu().numpy()
         assert rel(y, H.levels[l].apply(x)) < 1e-12, l
@@ -91,6 +92,7 @@ def test_scatter_and_gather_forms_agree(torch_cuda, name):
     Sg = gpu_for(name, band_form=1)
     rng = np.random.default_rng(12)
     for l in range(1, len(H.levels)):
+        assert Sg.band_form(l) == igamg.BAND_GATHER, l
         x = rng.standard_normal(H.levels[l].N)
         ys = Ss.operator(igamg.OP_APPLY, l, x).cpu().numpy()
         yg = Sg.operator(igamg.OP_APPLY, l, x).cpu().numpy()
@@ -137,3 +139,17 @@ def test_scatter_fp32_cycle_and_mixed_solve(torch_cuda, name, fd_mfma):
     u, info = S.solve(f, tol=1e-8)
     res = np.linalg.norm(f - H.finest.apply(u.cpu().numpy())) / np.linalg.norm(f)
     assert info.converged and res <= 1.0001e-8
+
+
+def test_default_form_by_level_size(torch_cuda):
+    """options.band_form = 0: the scatter form on the 3D levels above 65536
+    local rows (padded), the gather form below and on 2D levels.  The 2x2x2
+    p=3 cube: 343,000 local rows on the finest level, 55,296 on the next."""
+    from paper_1804_02539_amd import igamg
+    S = igamg.Solver(W.cube_2x2x2_trilinear())
+    L = S.prob.levels - 1
+    assert S.num_dofs(L)[1] == 343000 and S.num_dofs(L - 1)[1] == 54872
+    assert S.band_form(L) == igamg.BAND_SCATTER
+    assert all(S.band_form(l) == igamg.BAND_GATHER for l in range(1, L))
+    S2 = igamg.Solver(W.square_4x4_bezier(levels=4))
+    assert all(S2.band_form(l) == igamg.BAND_GATHER for l in range(1, 4))
