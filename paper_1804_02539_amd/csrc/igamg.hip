@@ -302,7 +302,7 @@ static void tail_program(igamg_ctx& C, igamg_ctx::Tail& tl) {
     r.kind = PH_CREDUCE;
     r.gx = 1;
     r.len = C.N0;
-    r.n = (C.N0 + 255) / 256;
+    r.n = Tc;
     const void* b3[] = {C.cpart, X0.u, D0.gptr, D0.gidx};
     for (int i = 0; i < 4; ++i) r.a[i] = b3[i];
     push(r);

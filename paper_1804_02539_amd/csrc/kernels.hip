@@ -1776,14 +1776,25 @@ template <typename T>
 __device__ __forceinline__ void coarse_reduce_block(int64_t bx, const double* __restrict__ part, T* __restrict__ u0,
                                                     const int64_t* __restrict__ ptr, const int64_t* __restrict__ idx,
                                                     int64_t n) {
-  const int64_t row = bx * 256 + threadIdx.x;
-  if (row >= n) return;
+  // block bx = tile row R: wave w sums the partial products of tile
+  // columns [w T / 4, (w + 1) T / 4) for the tile's 64 rows, and wave 0 adds
+  // the four quarters in a fixed order
+  constexpr int CT = COARSE_TILE;
+  __shared__ double s_q[4][CT];
+  const int r = threadIdx.x & (CT - 1), w = threadIdx.x >> 6;
   const int64_t Tn = coarse_tiles(n);
-  const int64_t R = row / COARSE_TILE, r = row % COARSE_TILE;
-  const double* pr = part + R * Tn * COARSE_TILE + r;
+  const double* pr = part + bx * Tn * CT + r;
+  const int64_t x0 = Tn * w / 4, x1 = Tn * (w + 1) / 4;
   double s = 0.0;
-  for (int64_t x = 0; x < Tn; ++x) s += pr[x * COARSE_TILE];
-  for (int64_t c = ptr[row]; c < ptr[row + 1]; ++c) u0[idx[c]] = (T)s;
+#pragma unroll 4
+  for (int64_t x = x0; x < x1; ++x) s += pr[x * CT];
+  s_q[w][r] = s;
+  __syncthreads();
+  const int64_t row = bx * CT + r;
+  if (w == 0 && row < n) {
+    const double t = (s_q[0][r] + s_q[1][r]) + (s_q[2][r] + s_q[3][r]);
+    for (int64_t c = ptr[row]; c < ptr[row + 1]; ++c) u0[idx[c]] = (T)t;
+  }
 }
 
 template <typename M>
@@ -1818,7 +1829,7 @@ void launch_coarse(const T* Ainv, const T* f0, double* b, double* part, T* u0, c
   hipLaunchKernelGGL((k_gather_dist<T, double>), dim3((unsigned)((n + 255) / 256)), dim3(256), 0, st, f0, b, ptr, idx,
                      n);
   hipLaunchKernelGGL(k_coarse_tiles<T>, dim3((unsigned)(Tn * (Tn + 1) / 2)), dim3(256), 0, st, Ainv, b, part, n);
-  hipLaunchKernelGGL(k_coarse_reduce<T>, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, st, part, u0, ptr, idx, n);
+  hipLaunchKernelGGL(k_coarse_reduce<T>, dim3((unsigned)Tn), dim3(256), 0, st, part, u0, ptr, idx, n);
 }
 
 // ---------------------------------------------------------------------------

@@ -37,7 +37,12 @@ CASES = {
                                              dirichlet_sides=[0, 2, 4]),
     "box_p1_l4": lambda: W.box_grid(3, [1, 2, 1], 1, 2, 4, gdeg=1, dirichlet_sides=[0]),
     "box_p5_l2": lambda: W.box_grid(3, [1, 1, 1], 5, 2, 2, gdeg=1),
+    # windows of 6,046 values, 96.7 KB of LDS with u in FP64: the widest that fit
+    "wide_x_p5_fits": lambda: W.box_grid(3, [1, 1, 1], 5, [[38], [1], [1]], 2, gdeg=1),
 }
+# windows of 8,466 values (135 KB): above the LDS limit, so the level keeps the
+# gather form even with band_form = 2
+WIDE_GATHER = lambda: W.box_grid(3, [1, 1, 1], 5, [[60], [1], [1]], 2, gdeg=1)
 
 _ORACLE = {}
 _GPU = {}
@@ -153,3 +158,18 @@ def test_default_form_by_level_size(torch_cuda):
     assert all(S.band_form(l) == igamg.BAND_GATHER for l in range(1, L))
     S2 = igamg.Solver(W.square_4x4_bezier(levels=4))
     assert all(S2.band_form(l) == igamg.BAND_GATHER for l in range(1, 4))
+
+
+def test_windows_above_lds_limit_keep_gather_form(torch_cuda):
+    """A level whose windows and u exceed the LDS limit (p = 5, 125 functions
+    along x) keeps the gather form under band_form = 2, and applies A as the
+    oracle does."""
+    from oracle.multigrid import Hierarchy
+    from paper_1804_02539_amd import igamg
+    _say("windows above the LDS limit")
+    prob = WIDE_GATHER()
+    H = Hierarchy(prob)
+    S = igamg.Solver(WIDE_GATHER(), igamg.default_options(band_form=2))
+    assert S.band_form(1) == igamg.BAND_GATHER
+    x = np.random.default_rng(15).standard_normal(H.levels[1].N)
+    assert rel(S.operator(igamg.OP_APPLY, 1, x).cpu().numpy(), H.levels[1].apply(x)) < 1e-12
