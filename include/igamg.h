@@ -91,7 +91,11 @@ typedef struct {
   int precision;         /* IGAMG_FP64; IGAMG_MIXED (FP32 inner solve inside FP64 iterative
                             refinement); IGAMG_MIXED_BF16 (the same with the smoother's mode
                             products on the matrix cores from bfloat16 operands, FP32
-                            accumulation: IGAMG_MIXED with fd_mfma = 3)                    */
+                            accumulation: IGAMG_MIXED with fd_mfma = 3).  FP32 cannot
+                            resolve 3D patch operators of high degree (their condition
+                            grows fast with p): 3D p = 7 needs ~4x the FP64 iterations,
+                            and coarse-dominated 3D problems at p >= 7 end in ENOCONV or
+                            ENAN; use IGAMG_FP64 there                                     */
   int maxit;             /* iteration cap of igamg_solve                    */
   int geometry_scaling;  /* 0 (default): piece operators in parameter-domain units, as the
                             paper's Fichera iteration table indicates; 1: each scaled by
@@ -267,6 +271,9 @@ int igamg_solve_batch(igamg_handle const* hs, const double* const* rhs, double* 
  *   IGAMG_OP_COARSE    y = A_0^{-1} x                     (level 0)
  *   IGAMG_OP_CYCLE_FP32 y = B r with the FP32 data of a IGAMG_MIXED handle
  *                      (finest level; x rounded to FP32, y returned in FP64)
+ *   IGAMG_OP_APPLY_FP32 y = A_l x with the FP32 band of a IGAMG_MIXED handle
+ *                      (level >= 1; x rounded to FP32, the patch products in
+ *                      the level's band form, the copies summed in FP64)
  * Device vectors; x and y may not alias.                                      */
 #define IGAMG_OP_APPLY 0
 #define IGAMG_OP_SMOOTHER 1
@@ -274,6 +281,7 @@ int igamg_solve_batch(igamg_handle const* hs, const double* const* rhs, double* 
 #define IGAMG_OP_RESTRICT 3
 #define IGAMG_OP_COARSE 4
 #define IGAMG_OP_CYCLE_FP32 5
+#define IGAMG_OP_APPLY_FP32 6
 int igamg_operator(igamg_handle h, int op, int level, const double* x, double* y, void* stream);
 
 /* Copies of the global free dofs of a level in the library's patch-local

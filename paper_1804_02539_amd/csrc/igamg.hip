@@ -1728,6 +1728,16 @@ int igamg_operator(igamg_handle h, int op, int level, const double* x, double* y
       launch_gather(X.u, y, D.gptr, D.gidx, D.N, false, st);
       break;
     }
+    case IGAMG_OP_APPLY_FP32: {
+      if (!h->mixed) return set_err(IGAMG_EINVAL, "the FP32 apply needs precision IGAMG_MIXED");
+      if (level < 1) return set_err(IGAMG_EINVAL, "no banded matrix on level 0 (use IGAMG_OP_COARSE)");
+      launch_scatter(x, X.u, D.gptr, D.gidx, D.N, false, st);
+      launch_to_f32(D.d32.u, X.u, D.NL, st);
+      band_op<float>(*h, level, D.d32.u, nullptr, D.d32.w, false, st);
+      launch_to_f64(X.w, D.d32.w, D.NL, st);
+      launch_gather(X.w, y, D.gptr, D.gidx, D.N, true, st);
+      break;
+    }
     case IGAMG_OP_CYCLE_FP32: {
       if (!h->mixed) return set_err(IGAMG_EINVAL, "the FP32 cycle needs precision IGAMG_MIXED");
       if (level != h->L) return set_err(IGAMG_EINVAL, "the FP32 cycle runs on the finest level");

@@ -21,7 +21,7 @@ OK, EINVAL, ETOPO, EGEOM, ENOMEM, ENOTSPD, ENOCONV, ENAN, EDEVICE = 0, -1, -2, -
 FP64, MIXED, MIXED_BF16 = 0, 1, 2
 FD_VEC8, FD_VEC4, FD_MFMA, FD_FUSED, FD_MFMA_BF16 = 0, 1, 2, 3, 4
 FD_NAMES = {FD_VEC8: "vec8", FD_VEC4: "vec4", FD_MFMA: "mfma", FD_FUSED: "fused", FD_MFMA_BF16: "mfma_bf16"}
-OP_APPLY, OP_SMOOTHER, OP_PROLONG, OP_RESTRICT, OP_COARSE, OP_CYCLE_FP32 = 0, 1, 2, 3, 4, 5
+OP_APPLY, OP_SMOOTHER, OP_PROLONG, OP_RESTRICT, OP_COARSE, OP_CYCLE_FP32, OP_APPLY_FP32 = 0, 1, 2, 3, 4, 5, 6
 
 ERROR_NAMES = {EINVAL: "EINVAL", ETOPO: "ETOPO", EGEOM: "EGEOM", ENOMEM: "ENOMEM",
                ENOTSPD: "ENOTSPD", ENOCONV: "ENOCONV", ENAN: "ENAN", EDEVICE: "EDEVICE"}

@@ -37,6 +37,10 @@ CASES = {
                                              dirichlet_sides=[0, 2, 4]),
     "box_p1_l4": lambda: W.box_grid(3, [1, 2, 1], 1, 2, 4, gdeg=1, dirichlet_sides=[0]),
     "box_p5_l2": lambda: W.box_grid(3, [1, 1, 1], 5, 2, 2, gdeg=1),
+    # the high degrees (each degree and type has its own load-buffer depth)
+    "box_p6_l2": lambda: W.box_grid(3, [1, 1, 2], 6, 1, 2, gdeg=1),
+    "box_p7_l2": lambda: W.box_grid(3, [2, 1, 1], 7, 1, 2, gdeg=1, dirichlet_sides=[0, 2]),
+    "box_p8_l2": lambda: W.box_grid(3, [1, 1, 1], 8, 1, 2, gdeg=1),
     # windows of 6,046 values, 96.7 KB of LDS with u in FP64: the widest that fit
     "wide_x_p5_fits": lambda: W.box_grid(3, [1, 1, 1], 5, [[38], [1], [1]], 2, gdeg=1),
 }
@@ -46,6 +50,7 @@ WIDE_GATHER = lambda: W.box_grid(3, [1, 1, 1], 5, [[60], [1], [1]], 2, gdeg=1)
 
 _ORACLE = {}
 _GPU = {}
+_ABS = {}   # |A_k| per (case, level), for the FP32 rounding bound
 
 
 def oracle_for(name):
@@ -173,3 +178,34 @@ def test_windows_above_lds_limit_keep_gather_form(torch_cuda):
     assert S.band_form(1) == igamg.BAND_GATHER
     x = np.random.default_rng(15).standard_normal(H.levels[1].N)
     assert rel(S.operator(igamg.OP_APPLY, 1, x).cpu().numpy(), H.levels[1].apply(x)) < 1e-12
+
+
+@pytest.mark.parametrize("form", [2, 1])
+@pytest.mark.parametrize("name", list(CASES))
+def test_fp32_apply_within_rounding_bound(torch_cuda, name, form):
+    """y = A_l x with the FP32 band (IGAMG_OP_APPLY_FP32), both forms, on
+    every level: each row within the first-order bound of an FP32 product
+    sum, (n + 3) eps_32 sum_k (|A_k| |x_k|)_i over the patch matrices that
+    hold row i, n = (2p+1)^d terms per patch row (x and the coefficients
+    rounded once each, n additions, the result rounded once).  A wrong
+    coefficient or index costs O(1) of that sum."""
+    from paper_1804_02539_amd import igamg
+    _say(f"fp32 apply {name} band_form={form}")
+    H = oracle_for(name)
+    S = gpu_for(name, band_form=form, precision=igamg.MIXED)
+    prob = CASES[name]()
+    n_terms = (2 * prob.degree + 1) ** prob.dim
+    eps32 = float(np.finfo(np.float32).eps)
+    rng = np.random.default_rng(16)
+    for l in range(1, len(H.levels)):
+        lev = H.levels[l]
+        x = rng.standard_normal(lev.N)
+        y = S.operator(igamg.OP_APPLY_FP32, l, x).cpu().numpy()
+        key = (name, l)
+        if key not in _ABS:
+            _ABS[key] = [abs(op.matrix()).tocsr() for op in lev.ops]
+        bound = np.zeros(lev.N)
+        for Sel, absA in zip(lev.S, _ABS[key]):
+            bound += Sel @ (absA @ np.abs(Sel.T @ x))
+        excess = np.abs(y - lev.apply(x)) / ((n_terms + 3) * eps32 * bound)
+        assert excess.max() <= 1.0, (l, float(excess.max()))
