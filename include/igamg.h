@@ -159,6 +159,10 @@ typedef struct {
   int converged;         /* 1 if ||f - A u|| <= tol ||f||                    */
   double rel_residual;   /* final ||f - A u||_2 / ||f||_2 (FP64 residual)   */
   double solve_ms;       /* wall time of the call on the stream             */
+  int fp64_fallback;     /* mixed: 1 if a refinement asked for 10x cut the FP64 residual by
+                            less than 4x, or an inner FP32 solve broke down, and the solve
+                            was restarted as the FP64 PCG from u = 0 (iterations counts
+                            both phases)                                                    */
 } igamg_solve_info;
 
 typedef struct igamg_ctx* igamg_handle;

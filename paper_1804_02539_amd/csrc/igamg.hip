@@ -155,7 +155,9 @@ struct igamg_ctx {
   void* ws = nullptr;
   size_t bytes = 0;
   struct igamg_batch_ctx* solo = nullptr;   // driver of igamg_solve
-  hipGraphExec_t gx[2] = {nullptr, nullptr}; // PCG bodies A and B of this hierarchy as graphs
+  // PCG bodies A and B of this hierarchy as graphs: [0], [1] in the handle's
+  // precision; [2], [3] the FP64 bodies a mixed solve falls back to
+  hipGraphExec_t gx[4] = {nullptr, nullptr, nullptr, nullptr};
 };
 
 template <typename T>
@@ -1087,8 +1089,11 @@ struct Req {
   double tol = 1e-8;
   int state = RQ_FREE;
   bool mixed = false, first_outer = true, fresh_done = false;
+  // mixed: the FP32 inner solves stalled, and the solve was restarted as the
+  // FP64 PCG from u = 0
+  bool fp64_tail = false;
   int it = 0, iters = 0, outer = 0, code = IGAMG_OK;
-  double n02 = 0.0, nf2 = 0.0, rel = 1.0;
+  double n02 = 0.0, nf2 = 0.0, rel = 1.0, prev_rel = 1.0;
   double inner_target = 1e-4;   // relative residual reduction the current inner solve stops at
   std::chrono::steady_clock::time_point t0;
   double solve_ms = 0.0;
@@ -1139,10 +1144,11 @@ static void sync_driver(igamg_batch_ctx& B) { HIP_OK(hipStreamSynchronize(B.ds))
 
 static void body(Req& q, int which, hipStream_t st) {
   igamg_ctx& C = *q.C;
+  const bool f32 = q.mixed && !q.fp64_tail;
   if (which == 0) {
-    if (q.mixed) pcg_body_a<float>(C, st); else pcg_body_a<double>(C, st);
+    if (f32) pcg_body_a<float>(C, st); else pcg_body_a<double>(C, st);
   } else {
-    if (q.mixed) pcg_body_b<float>(C, st, true); else pcg_body_b<double>(C, st, false);
+    if (f32) pcg_body_b<float>(C, st, true); else pcg_body_b<double>(C, st, false);
   }
 }
 
@@ -1152,15 +1158,16 @@ static void body(Req& q, int which, hipStream_t st) {
 // The hierarchy's graph of body `which`, captured on first use.
 static hipGraphExec_t request_graph(igamg_batch_ctx& B, Req& q, int which) {
   igamg_ctx& C = *q.C;
-  if (!C.gx[which]) {
+  const int slot = which + (q.mixed && q.fp64_tail ? 2 : 0);
+  if (!C.gx[slot]) {
     hipGraph_t g = nullptr;
     HIP_OK(hipStreamBeginCapture(B.ds, hipStreamCaptureModeThreadLocal));
     body(q, which, B.ds);
     HIP_OK(hipStreamEndCapture(B.ds, &g));
-    HIP_OK(hipGraphInstantiate(&C.gx[which], g, nullptr, nullptr, 0));
+    HIP_OK(hipGraphInstantiate(&C.gx[slot], g, nullptr, nullptr, 0));
     HIP_OK(hipGraphDestroy(g));
   }
-  return C.gx[which];
+  return C.gx[slot];
 }
 
 // run body `which` for the requests in `set` on the driver stream
@@ -1221,14 +1228,33 @@ static void rq_outer_update(Req& q, hipStream_t st) {
   q.state = RQ_OUTER_READ;
 }
 
+// mixed: the inner FP32 solves stopped reducing the FP64 residual, or broke
+// down (a non-finite inner residual).  The solve restarts as the FP64 PCG
+// from u = 0, the FP64 handle's own algorithm: an iterate that FP32 could not
+// improve may lie far from the solution, and a correction solved from it
+// would need more than FP64's attainable accuracy on such ill-conditioned
+// operators.
+static void rq_fallback_fp64(Req& q, hipStream_t st) {
+  igamg_ctx& C = *q.C;
+  DevLevel& D = C.dl[C.L];
+  if (trace_enabled()) std::fprintf(stderr, "[igamg] %p FP64 PCG from u = 0 (rel %.3e)\n", (void*)q.C, q.rel);
+  launch_copy<double>(D.d64.f, C.fsave, D.NL, st);
+  q.fp64_tail = true;
+  q.rel = 1.0;
+  q.it = 0;
+  pcg_start<double>(C, st);
+  q.state = RQ_START_READ;
+}
+
 static void rq_begin(Req& q, hipStream_t st) {
   igamg_ctx& C = *q.C;
   DevLevel& D = C.dl[C.L];
   q.t0 = std::chrono::steady_clock::now();
   q.it = q.iters = q.outer = 0;
   q.code = IGAMG_OK;
-  q.rel = 1.0;
+  q.rel = q.prev_rel = 1.0;
   q.first_outer = true;
+  q.fp64_tail = false;
   if (!q.mixed) {
     launch_scatter(q.rhs, D.d64.f, D.gptr, D.gidx, D.N, true, st);
     pcg_start<double>(C, st);
@@ -1245,7 +1271,8 @@ static void rq_begin(Req& q, hipStream_t st) {
 
 static void trace_iter(const Req& q, double rel) {
   if (trace_enabled())
-    std::fprintf(stderr, "[igamg] %p pcg<%s> it %d rel %.3e\n", (void*)q.C, q.mixed ? "f32" : "f64", q.it, rel);
+    std::fprintf(stderr, "[igamg] %p pcg<%s> it %d rel %.3e\n", (void*)q.C, q.mixed && !q.fp64_tail ? "f32" : "f64",
+                 q.it, rel);
 }
 
 // process a request whose host readback (start or outer norm) is available
@@ -1256,14 +1283,14 @@ static void rq_process_read(Req& q, hipStream_t st) {
     const double n02 = C.host_scal[6];
     if (!std::isfinite(n02)) return rq_finish(q, IGAMG_ENAN, st);
     if (n02 == 0.0) {
-      if (!q.mixed) {
+      if (!q.mixed || q.fp64_tail) {
         q.rel = 0.0;
         return rq_finish(q, IGAMG_OK, st);
       }
       return rq_outer_update(q, st);
     }
     q.n02 = n02;
-    if (q.mixed) pcg_first<float>(C, st); else pcg_first<double>(C, st);
+    if (q.mixed && !q.fp64_tail) pcg_first<float>(C, st); else pcg_first<double>(C, st);
     q.state = RQ_ITER;
     return;
   }
@@ -1283,6 +1310,11 @@ static void rq_process_read(Req& q, hipStream_t st) {
       if (trace_enabled()) std::fprintf(stderr, "[igamg] %p refinement %d rel %.3e\n", (void*)q.C, q.outer, q.rel);
       if (q.rel <= q.tol) return rq_finish(q, IGAMG_OK, st);
       if (q.iters >= O.maxit || q.outer >= 60) return rq_finish(q, IGAMG_ENOCONV, st);
+      // a refinement asked for at least a 10x reduction that cut the
+      // residual by less than 4x: FP32 cannot resolve this operator (high
+      // degree in 3D), so finish in FP64
+      if (q.inner_target <= 0.1 && !(q.rel <= 0.25 * q.prev_rel)) return rq_fallback_fp64(q, st);
+      q.prev_rel = q.rel;
     }
     return rq_start_inner(q, st);
   }
@@ -1296,14 +1328,15 @@ static bool rq_after_iter(Req& q, hipStream_t st) {
   q.it++;
   q.iters++;
   if (!std::isfinite(rr)) {
-    rq_finish(q, IGAMG_ENAN, st);
+    if (q.mixed && !q.fp64_tail) rq_fallback_fp64(q, st);   // an FP32 breakdown
+    else rq_finish(q, IGAMG_ENAN, st);
     return false;
   }
   const double rel = std::sqrt(rr / q.n02);
   trace_iter(q, rel);
-  if (!q.mixed) {
+  if (!q.mixed || q.fp64_tail) {
     q.rel = rel;
-    if (rel <= q.tol) {
+    if (q.rel <= q.tol) {
       rq_finish(q, IGAMG_OK, st);
       return false;
     }
@@ -1313,7 +1346,9 @@ static bool rq_after_iter(Req& q, hipStream_t st) {
     }
     return true;
   }
-  if (rel <= q.inner_target || q.it >= O.inner_maxit || q.iters >= O.maxit) {
+  // an inner solve that has not halved its residual in 20 iterations is
+  // stalled: end it, and the outer test decides on the FP64 restart
+  if (rel <= q.inner_target || q.it >= O.inner_maxit || q.iters >= O.maxit || (q.it >= 20 && rel > 0.5)) {
     rq_outer_update(q, st);
     return false;
   }
@@ -1406,6 +1441,7 @@ static void fill_info(const Req& q, igamg_solve_info* info) {
   info->converged = (q.state == RQ_DONE && q.code == IGAMG_OK);
   info->rel_residual = q.rel;
   info->solve_ms = q.solve_ms;
+  info->fp64_fallback = q.fp64_tail ? 1 : 0;
 }
 
 // ---------------------------------------------------------------------------

@@ -56,7 +56,7 @@ class Options(ctypes.Structure):
 class SolveInfo(ctypes.Structure):
     _fields_ = [("iterations", ctypes.c_int), ("outer_iterations", ctypes.c_int),
                 ("converged", ctypes.c_int), ("rel_residual", ctypes.c_double),
-                ("solve_ms", ctypes.c_double)]
+                ("solve_ms", ctypes.c_double), ("fp64_fallback", ctypes.c_int)]
 
 
 def _load():
