@@ -138,14 +138,15 @@ typedef struct {
                              persistent launch per cycle (a work list of the cycle's phases,
                              V-cycle only); 0 (default): one launch per kernel               */
   int band_form;          /* banded apply of the symmetric half band (Sec. 4's patch matrices):
-                             0 (default): 3D levels above 65536 local rows read each stored
-                             coefficient once and add its mirrored term through per-tile
-                             windows (two kernels; the FP32 copy of those levels is the half
-                             band too), where a tile's windows and the u of their rows fit
-                             96 KiB of LDS in FP64: 16 ((p+1) 256 + (2p+1)(p + p n0)) bytes,
-                             n0 the level's largest patch size along x; 1: every level reads
-                             the mirrored half from the rows it couples to (one kernel);
-                             2: the scatter form on every 3D level whose windows fit, the
+                             0 (default): levels above 65536 local rows in 3D, or 2^19 in 2D,
+                             read each stored coefficient once and add its mirrored term
+                             through per-tile windows (two kernels; the FP32 copy of those
+                             levels is the half band too), where a tile's windows and the u
+                             of their rows fit 96 KiB of LDS in FP64: 16 ((p+1) 256 +
+                             (2p+1) W) bytes, W = p + p n0 in 3D (n0 the level's largest
+                             patch size along x) and p in 2D; 1: every level reads the
+                             mirrored half from the rows it couples to (one kernel);
+                             2: the scatter form on every level whose windows fit, the
                              persistent cycle's levels (options.persistent) excepted          */
 } igamg_options;
 

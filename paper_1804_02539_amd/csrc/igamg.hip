@@ -337,17 +337,25 @@ static void tail_program(igamg_ctx& C, igamg_ctx::Tail& tl) {
   if (tl.lds > 64 * 1024) tl = igamg_ctx::Tail{};   // pieces too large for one workgroup's default LDS
 }
 
+// Rows above which options.band_form = 0 applies a 2D level in scatter
+// form.  Measured at p = 4: at 282K rows the FP64 apply is 15% faster in
+// scatter form but the FP32 one 8% slower (the windows cost more in 2D, one
+// line per layer); from 1.1M rows both are faster (13-24% up to 10M rows).
+constexpr int64_t SYM_MIN_ROWS_2D = int64_t(1) << 19;
+
 // Window values per tile of level L's banded apply in scatter form, or 0 for
-// the gather form: 3D levels whose windows and u fit BAND_SYM_MAX_LDS in FP64 and,
-// with options.band_form = 0, that have more than TAIL_MAX_ROWS rows (smaller
-// ones are launch-bound); never the levels of the persistent cycle, which
-// reads the gather form.
+// the gather form: levels whose windows and u fit BAND_SYM_MAX_LDS in FP64
+// and, with options.band_form = 0, that have more than TAIL_MAX_ROWS rows in
+// 3D (smaller ones are launch-bound) or SYM_MIN_ROWS_2D in 2D; never the
+// levels of the persistent cycle, which reads the gather form.
 static int64_t band_sym_ws(const Hierarchy& H, const LevelH& L) {
-  if (H.opt.band_form == 1 || H.prob.d != 3) return 0;
-  if (L.NL <= TAIL_MAX_ROWS && (H.opt.band_form == 0 || H.opt.persistent)) return 0;
+  if (H.opt.band_form == 1) return 0;
+  const int64_t min_rows = H.prob.d == 3 ? TAIL_MAX_ROWS : SYM_MIN_ROWS_2D;
+  if (L.NL <= min_rows && H.opt.band_form == 0) return 0;
+  if (L.NL <= TAIL_MAX_ROWS && H.opt.persistent) return 0;
   int64_t n0 = 1;
   for (const auto& n : L.n) n0 = std::max<int64_t>(n0, n[0]);
-  const int64_t ws = band_sym_window(H.prob.p, n0);
+  const int64_t ws = band_sym_window(H.prob.d, H.prob.p, n0);
   return (size_t)ws * 2 * sizeof(double) <= BAND_SYM_MAX_LDS ? ws : 0;
 }
 
@@ -684,7 +692,7 @@ static void band_op(igamg_ctx& C, int l, const T* u, const T* f, T* r, bool resi
   T* win = static_cast<T*>(C.symwin);
   if (!C.prof) {
     if (D.sym_ws > 0)
-      HIP_OK(launch_band_sym<T>(C.p, band, u, f, r, D.bpatch, D.pd, D.NL, D.sym_ws, win, resid, st));
+      HIP_OK(launch_band_sym<T>(C.d, C.p, band, u, f, r, D.bpatch, D.pd, D.NL, D.sym_ws, win, resid, st));
     else
       HIP_OK(launch_band<T>(C.d, C.p, band, u, f, r, D.bpatch, D.pd, D.NL, resid, st));
     return;
@@ -695,7 +703,7 @@ static void band_op(igamg_ctx& C, int l, const T* u, const T* f, T* r, bool resi
   rc.a = next_event(C);
   rc.b = next_event(C);
   if (D.sym_ws > 0)
-    HIP_OK(launch_band_sym<T>(C.p, band, u, f, r, D.bpatch, D.pd, D.NL, D.sym_ws, win, resid, st, rc.a, rc.b));
+    HIP_OK(launch_band_sym<T>(C.d, C.p, band, u, f, r, D.bpatch, D.pd, D.NL, D.sym_ws, win, resid, st, rc.a, rc.b));
   else
     HIP_OK(launch_band<T>(C.d, C.p, band, u, f, r, D.bpatch, D.pd, D.NL, resid, st, rc.a, rc.b));
   C.recs.push_back(rc);

@@ -260,15 +260,16 @@ __global__ __launch_bounds__(256) void k_band_full(const TB* __restrict__ band, 
 }
 
 // ---------------------------------------------------------------------------
-// The symmetric half band in scatter form (3D).  Every stored coefficient
+// The symmetric half band in scatter form.  Every stored coefficient
 // a = A[j][j+d] (d >= 0) is fetched once and used twice: y_j += a u_{j+d}
 // (forward) and, d > 0, y_{j+d} += a u_j (its mirror, A[j+d][j] = a).  A
 // workgroup takes one 256-row tile (local rows s .. s+255) with one wave per
-// layer a2 = 0..P of the stored offsets (a0, a1, a2).  A wave adds the
-// mirrored terms of its layer into a window of LDS covering the rows they
-// reach: layer 0 the rows s .. s+255+W, layer a2 >= 1 the rows
-// s + a2 n0 n1 - W .. s + 255 + a2 n0 n1 + W, with W = P + P n0
-// (band_sym_reach).  Each window has one owner wave, which adds into it with
+// layer of the stored offsets: in 3D the layer a2 = 0..P of (a0, a1, a2),
+// stride LS = n0 n1 rows; in 2D the line a1 = 0..P of (a0, a1), stride
+// LS = n0.  A wave adds the mirrored terms of its layer into a window of LDS
+// covering the rows they reach: layer 0 the rows s .. s+255+W, layer kk >= 1
+// the rows s + kk LS - W .. s + 255 + kk LS + W, with W = P + P n0 in 3D and
+// P in 2D (band_sym_reach).  Each window has one owner wave, which adds into it with
 // LDS atomics; a wave's LDS operations execute in program order, so every
 // position receives its terms in a fixed order.  The LDS windows are FP64
 // for both storage types: FP32 products are exact in FP64, and LDS FP32
@@ -292,19 +293,20 @@ __device__ __forceinline__ T ld_off32(const T* __restrict__ base, uint32_t idx) 
 // and type the deepest buffering (of 2..5 lines) that the compiler fits
 // without spilling at the occupancy the LDS allows, read off its register
 // counts.
-template <int P, typename T>
+template <int D, int P, typename T>
 constexpr int band_sym_nbuf() {
+  if (D == 2) return 1;   // a 2D layer is a single line
   if (sizeof(T) == 4) return P == 7 ? 2 : (P == 4 || P == 8) ? 4 : 5;
   return (P == 1 || P == 2) ? 5 : P == 3 ? 3 : P == 4 ? 4 : 2;
 }
 
-template <int P, typename T>
+template <int D, int P, typename T>
 __global__ __launch_bounds__(64 * (P + 1)) void k_band_sym_scatter(const T* __restrict__ band,
                                                                    const T* __restrict__ u, T* __restrict__ win,
                                                                    int64_t wstride, const int* __restrict__ bpatch,
                                                                    const PatchDev* __restrict__ pd) {
-  constexpr int NB = 2 * P + 1, NBH = band_half_planes(3, P);
-  constexpr int NBUF = band_sym_nbuf<P, T>();
+  constexpr int NB = 2 * P + 1, NBH = band_half_planes(D, P);
+  constexpr int NBUF = band_sym_nbuf<D, P, T>();
   extern __shared__ __align__(16) unsigned char sym_lds[];
   const int lane = threadIdx.x & 63;
   // the layer is the wave index: uniform across the wave (a scalar)
@@ -314,20 +316,20 @@ __global__ __launch_bounds__(64 * (P + 1)) void k_band_sym_scatter(const T* __re
   if (k < 0) return;                                     // uniform: a padding tile
   const int64_t off = pd[k].off, rows = pd[k].rows;
   const int n0 = pd[k].n[0];
-  const int64_t n01 = (int64_t)n0 * pd[k].n[1];
-  const int W = (int)band_sym_reach(P, n0);
+  const int64_t LS = D == 3 ? (int64_t)n0 * pd[k].n[1] : n0;   // rows between layers
+  const int W = (int)band_sym_reach(D, P, n0);
   const int len = kk ? ROW_ALIGN + 2 * W : ROW_ALIGN + W;
   const int wo = kk ? ROW_ALIGN + W + (kk - 1) * (ROW_ALIGN + 2 * W) : 0;
   // LDS: the windows (FP64), then u at the same positions (storage type):
   // position q of layer kk's window and segment is local row
-  // s + kk n0 n1 - (kk ? W : 0) + q, so the forward term of an offset reads
-  // u where its mirrored term goes.  Rows outside the patch read 0 (their
+  // s + kk LS - (kk ? W : 0) + q, so the forward term of an offset reads u
+  // where its mirrored term goes.  Rows outside the patch read 0 (their
   // coefficients are 0 too).
   double* lw = reinterpret_cast<double*>(sym_lds) + wo;
   T* lu = reinterpret_cast<T*>(reinterpret_cast<double*>(sym_lds) + wstride) + wo;
   const int64_t s = b * ROW_ALIGN - off;
   const T* ub = u + off;
-  const int64_t base = s + kk * n01 - (kk ? W : 0);
+  const int64_t base = s + kk * LS - (kk ? W : 0);
   for (int i = lane; i < len; i += 64) {
     lw[i] = 0.0;
     const int64_t row = base + i;
@@ -336,10 +338,11 @@ __global__ __launch_bounds__(64 * (P + 1)) void k_band_sym_scatter(const T* __re
   __syncthreads();
   // the tile's planes; loads index them with 32-bit offsets from this base
   const T* bt = band + (b * NBH) * ROW_ALIGN;
-  // lines (a1) of this wave's layer: a1 = 0..P in layer 0 (the centre line
-  // a1 = 0 stores a0 = 0..P only), a1 = -P..P in the others
-  const int a1_first = kk ? -P : 0, nline = kk ? NB : P + 1;
-  const int plane0 = kk ? P + 1 + P * NB + (kk - 1) * NB * NB : 0;
+  // 3D: the lines (a1) of this wave's layer, a1 = 0..P in layer 0 (the
+  // centre line a1 = 0 stores a0 = 0..P only), a1 = -P..P in the others.
+  // 2D: the layer is the line a1 = kk (kk = 0: the centre line).
+  const int a1_first = (D == 3 && kk) ? -P : 0, nline = D == 2 ? 1 : kk ? NB : P + 1;
+  const int plane0 = D == 2 ? P + 1 + (kk - 1) * NB : kk ? P + 1 + P * NB + (kk - 1) * NB * NB : 0;
   T y[4];
 #pragma unroll 1
   for (int g = 0; g < 4; ++g) {
@@ -353,7 +356,8 @@ __global__ __launch_bounds__(64 * (P + 1)) void k_band_sym_scatter(const T* __re
     auto load_line = [&](int li, T* vb) {
       const int a1 = a1_first + li;
       const bool centre = kk == 0 && a1 == 0;
-      const uint32_t bq = (uint32_t)(centre ? -P : plane0 + (kk ? li * NB : P + 1 + (a1 - 1) * NB)) * ROW_ALIGN + rt;
+      const uint32_t bq =
+          (uint32_t)(centre ? -P : D == 2 ? plane0 : plane0 + (kk ? li * NB : P + 1 + (a1 - 1) * NB)) * ROW_ALIGN + rt;
 #pragma unroll
       for (int o0 = 0; o0 < NB; ++o0) vb[o0] = (centre && o0 < P) ? T(0) : ld_off32(bt, bq + (uint32_t)(o0 * ROW_ALIGN));
     };
@@ -363,7 +367,7 @@ __global__ __launch_bounds__(64 * (P + 1)) void k_band_sym_scatter(const T* __re
     auto add_line = [&](int li, const T* vb) {
       const int a1 = a1_first + li;
       const bool centre = kk == 0 && a1 == 0;
-      const int q0 = pos + a1 * n0 - P;
+      const int q0 = pos + (D == 3 ? a1 * n0 : 0) - P;
       T uq[NB];
 #pragma unroll
       for (int o0 = 0; o0 < NB; ++o0) uq[o0] = lu[(centre && o0 < P) ? q0 + P : q0 + o0];
@@ -424,7 +428,7 @@ __global__ __launch_bounds__(64 * (P + 1)) void k_band_sym_scatter(const T* __re
 
 // One row per thread: the sum of the window positions that cover it (layer
 // 0..P, then tile, ascending, in FP64), and r = f - y (RESID) or r = y.
-template <int P, bool RESID, typename T>
+template <int D, int P, bool RESID, typename T>
 __global__ __launch_bounds__(256) void k_band_sym_reduce(const T* __restrict__ win, int64_t wstride,
                                                          const T* __restrict__ f, T* __restrict__ r,
                                                          const int* __restrict__ bpatch,
@@ -436,8 +440,8 @@ __global__ __launch_bounds__(256) void k_band_sym_reduce(const T* __restrict__ w
   const int64_t t = b * ROW_ALIGN - off + threadIdx.x;
   if (t >= rows) return;
   const int n0 = pd[k].n[0];
-  const int64_t n01 = (int64_t)n0 * pd[k].n[1];
-  const int W = (int)band_sym_reach(P, n0);
+  const int64_t LS = D == 3 ? (int64_t)n0 * pd[k].n[1] : n0;
+  const int W = (int)band_sym_reach(D, P, n0);
   const int64_t ntile = (rows + ROW_ALIGN - 1) / ROW_ALIGN;
   const T* wb = win + (off / ROW_ALIGN) * wstride;     // the patch's first tile
   double acc = 0.0;
@@ -446,7 +450,7 @@ __global__ __launch_bounds__(256) void k_band_sym_reduce(const T* __restrict__ w
     const int len = kk ? ROW_ALIGN + 2 * W : ROW_ALIGN + W;
     const int wo = kk ? ROW_ALIGN + W + (kk - 1) * (ROW_ALIGN + 2 * W) : 0;
     // row t sits at position q - 256 sg of tile sg's layer-kk window
-    const int64_t q = kk ? t - kk * n01 + W : t;
+    const int64_t q = kk ? t - kk * LS + W : t;
     if (q < 0) continue;
     const int64_t lo = q - len + 1 <= 0 ? 0 : (q - len + ROW_ALIGN) / ROW_ALIGN;
     const int64_t hi = min(ntile - 1, q / ROW_ALIGN);
@@ -550,11 +554,11 @@ hipError_t launch_band(int d, int p, const T* band, const T* u, const T* f, T* r
   return hipErrorInvalidValue;
 }
 
-template <int P, typename T>
+template <int D, int P, typename T>
 static hipError_t launch_band_sym_p(const T* band, const T* u, const T* f, T* r, const int* bpatch,
                                     const PatchDev* pd, int64_t NL, int64_t ws, T* win, bool resid, hipStream_t st,
                                     hipEvent_t ev0, hipEvent_t ev1) {
-  static const hipError_t attr = hipFuncSetAttribute(reinterpret_cast<const void*>(&k_band_sym_scatter<P, T>),
+  static const hipError_t attr = hipFuncSetAttribute(reinterpret_cast<const void*>(&k_band_sym_scatter<D, P, T>),
                                                      hipFuncAttributeMaxDynamicSharedMemorySize,
                                                      (int)BAND_SYM_MAX_LDS);
   if (attr != hipSuccess) return attr;
@@ -562,32 +566,34 @@ static hipError_t launch_band_sym_p(const T* band, const T* u, const T* f, T* r,
   const size_t lds = (size_t)ws * (sizeof(double) + sizeof(T));   // FP64 windows, u segments
   if (ev0) {
     // timed: the start of the scatter pass to the end of the reduction
-    const void* f1 = reinterpret_cast<const void*>(&k_band_sym_scatter<P, T>);
-    const void* f2 = resid ? reinterpret_cast<const void*>(&k_band_sym_reduce<P, true, T>)
-                           : reinterpret_cast<const void*>(&k_band_sym_reduce<P, false, T>);
+    const void* f1 = reinterpret_cast<const void*>(&k_band_sym_scatter<D, P, T>);
+    const void* f2 = resid ? reinterpret_cast<const void*>(&k_band_sym_reduce<D, P, true, T>)
+                           : reinterpret_cast<const void*>(&k_band_sym_reduce<D, P, false, T>);
     void* a1[] = {(void*)&band, (void*)&u, (void*)&win, (void*)&ws, (void*)&bpatch, (void*)&pd};
     void* a2[] = {(void*)&win, (void*)&ws, (void*)&f, (void*)&r, (void*)&bpatch, (void*)&pd};
     const hipError_t e = hipExtLaunchKernel(f1, grid, b1, a1, lds, st, ev0, nullptr, 0);
     if (e != hipSuccess) return e;
     return hipExtLaunchKernel(f2, grid, b2, a2, 0, st, nullptr, ev1, 0);
   }
-  hipLaunchKernelGGL((k_band_sym_scatter<P, T>), grid, b1, lds, st, band, u, win, ws, bpatch, pd);
+  hipLaunchKernelGGL((k_band_sym_scatter<D, P, T>), grid, b1, lds, st, band, u, win, ws, bpatch, pd);
   if (resid)
-    hipLaunchKernelGGL((k_band_sym_reduce<P, true, T>), grid, b2, 0, st, win, ws, f, r, bpatch, pd);
+    hipLaunchKernelGGL((k_band_sym_reduce<D, P, true, T>), grid, b2, 0, st, win, ws, f, r, bpatch, pd);
   else
-    hipLaunchKernelGGL((k_band_sym_reduce<P, false, T>), grid, b2, 0, st, win, ws, f, r, bpatch, pd);
+    hipLaunchKernelGGL((k_band_sym_reduce<D, P, false, T>), grid, b2, 0, st, win, ws, f, r, bpatch, pd);
   return hipSuccess;
 }
 
 template <typename T>
-hipError_t launch_band_sym(int p, const T* band, const T* u, const T* f, T* r, const int* bpatch,
+hipError_t launch_band_sym(int d, int p, const T* band, const T* u, const T* f, T* r, const int* bpatch,
                            const PatchDev* pd, int64_t NL, int64_t ws, T* win, bool resid, hipStream_t st,
                            hipEvent_t ev0, hipEvent_t ev1) {
   if (ws <= 0 || (size_t)ws * (sizeof(double) + sizeof(T)) > BAND_SYM_MAX_LDS) return hipErrorInvalidValue;
-#define IGAMG_SYM_CASE(PP) \
-  if (p == PP) return launch_band_sym_p<PP, T>(band, u, f, r, bpatch, pd, NL, ws, win, resid, st, ev0, ev1);
-  IGAMG_SYM_CASE(1) IGAMG_SYM_CASE(2) IGAMG_SYM_CASE(3) IGAMG_SYM_CASE(4)
-  IGAMG_SYM_CASE(5) IGAMG_SYM_CASE(6) IGAMG_SYM_CASE(7) IGAMG_SYM_CASE(8)
+#define IGAMG_SYM_CASE(DD, PP) \
+  if (d == DD && p == PP) return launch_band_sym_p<DD, PP, T>(band, u, f, r, bpatch, pd, NL, ws, win, resid, st, ev0, ev1);
+  IGAMG_SYM_CASE(2, 1) IGAMG_SYM_CASE(2, 2) IGAMG_SYM_CASE(2, 3) IGAMG_SYM_CASE(2, 4)
+  IGAMG_SYM_CASE(2, 5) IGAMG_SYM_CASE(2, 6) IGAMG_SYM_CASE(2, 7) IGAMG_SYM_CASE(2, 8)
+  IGAMG_SYM_CASE(3, 1) IGAMG_SYM_CASE(3, 2) IGAMG_SYM_CASE(3, 3) IGAMG_SYM_CASE(3, 4)
+  IGAMG_SYM_CASE(3, 5) IGAMG_SYM_CASE(3, 6) IGAMG_SYM_CASE(3, 7) IGAMG_SYM_CASE(3, 8)
 #undef IGAMG_SYM_CASE
   return hipErrorInvalidValue;
 }
@@ -2225,8 +2231,8 @@ void launch_add_f32(double* x, const float* d, int64_t n, hipStream_t st) {
 #define IGAMG_INST(T)                                                                                                  \
   template hipError_t launch_band<T>(int, int, const T*, const T*, const T*, T*, const int*, const PatchDev*, int64_t,   \
                                      bool, hipStream_t, hipEvent_t, hipEvent_t);                                       \
-  template hipError_t launch_band_sym<T>(int, const T*, const T*, const T*, T*, const int*, const PatchDev*, int64_t,   \
-                                         int64_t, T*, bool, hipStream_t, hipEvent_t, hipEvent_t);                     \
+  template hipError_t launch_band_sym<T>(int, int, const T*, const T*, const T*, T*, const int*, const PatchDev*,        \
+                                         int64_t, int64_t, T*, bool, hipStream_t, hipEvent_t, hipEvent_t);            \
   template void launch_fd_fwd<T>(const FDItem*, int, int, int, size_t, const DensePiece*, const T*, const T*,          \
                                  const T*, T*, const int64_t*, const int64_t*, T*, double, bool, int, hipStream_t);    \
   template void launch_fd_mid<T>(const FDItem*, int, int, size_t, const T*, T*, hipStream_t);                          \

@@ -20,14 +20,14 @@ template <typename T>
 hipError_t launch_band(int d, int p, const T* band, const T* u, const T* f, T* r, const int* bpatch,
                        const PatchDev* pd, int64_t NL, bool resid, hipStream_t st, hipEvent_t ev0 = nullptr,
                        hipEvent_t ev1 = nullptr);
-// The same in the scatter form of the symmetric half band (3D; two kernels,
-// each coefficient fetched once): `ws` = band_sym_window(p, largest n0 of the
-// level's patches) values of window per 256-row tile, `win` holds
-// NL / 256 * ws of them; ws * (8 + sizeof(T)) <= BAND_SYM_MAX_LDS (FP64 windows and
-// the u of their rows in LDS).  The events
-// time both kernels together.
+// The same in the scatter form of the symmetric half band (two kernels,
+// each coefficient fetched once): `ws` = band_sym_window(d, p, largest n0 of
+// the level's patches) values of window per 256-row tile, `win` holds
+// NL / 256 * ws of them; ws * (8 + sizeof(T)) <= BAND_SYM_MAX_LDS (FP64
+// windows and the u of their rows in LDS).  The events time both kernels
+// together.
 template <typename T>
-hipError_t launch_band_sym(int p, const T* band, const T* u, const T* f, T* r, const int* bpatch,
+hipError_t launch_band_sym(int d, int p, const T* band, const T* u, const T* f, T* r, const int* bpatch,
                            const PatchDev* pd, int64_t NL, int64_t ws, T* win, bool resid, hipStream_t st,
                            hipEvent_t ev0 = nullptr, hipEvent_t ev1 = nullptr);
 

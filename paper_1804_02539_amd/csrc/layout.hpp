@@ -37,15 +37,16 @@ constexpr int band_half_plane(int d, int p, int o0, int L) {
                                           : -1;
 }
 
-// Scatter form of the symmetric half-band apply (3D): the stored offsets of
-// a 256-row tile reach the rows of the tile shifted by a2 n0 n1 (layer a2 of
-// the stencil, 0..p) plus at most band_sym_reach = p + p n0 either way; the
+// Scatter form of the symmetric half-band apply: the stored offsets of a
+// 256-row tile reach the rows of the tile shifted by a layer's stride (3D:
+// layer a2 = 0..p of the stencil, stride n0 n1; 2D: line a1 = 0..p, stride
+// n0) plus at most band_sym_reach either way (3D: p + p n0; 2D: p); the
 // tile's windows (layer 0: 256 + reach rows, layers 1..p: 256 + 2 reach)
 // hold band_sym_window values in all; a workgroup keeps them in LDS in FP64,
 // beside the u values of the same rows.
-constexpr int64_t band_sym_reach(int p, int64_t n0) { return p + p * n0; }
-constexpr int64_t band_sym_window(int p, int64_t n0) {
-  return (int64_t)(p + 1) * ROW_ALIGN + (2 * p + 1) * band_sym_reach(p, n0);
+constexpr int64_t band_sym_reach(int d, int p, int64_t n0) { return d == 3 ? p + p * n0 : p; }
+constexpr int64_t band_sym_window(int d, int p, int64_t n0) {
+  return (int64_t)(p + 1) * ROW_ALIGN + (2 * p + 1) * band_sym_reach(d, p, n0);
 }
 constexpr size_t BAND_SYM_MAX_LDS = 96 * 1024;   // windows and u of one tile in LDS, at most
 

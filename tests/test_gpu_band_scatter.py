@@ -1,10 +1,11 @@
-"""GPU parity of the scatter form of the symmetric half-band apply (3D): each
+"""GPU parity of the scatter form of the symmetric half-band apply: each
 stored coefficient fetched once, its mirrored term added through per-tile
 windows and a second, fixed-order reduction.  options.band_form = 2 puts it
-on every 3D level, so problems the oracle finishes in seconds (several tiles
-per patch, ragged last tiles, Dirichlet and Neumann sides, graded and
-curved patches, tensors wider than one tile's window reach) cover it; the
-full-size 3D tests cover its default use on levels above 65536 rows."""
+on every level, so problems the oracle finishes in seconds (2D and 3D,
+p = 1..8, several tiles per patch, ragged last tiles, Dirichlet and Neumann
+sides, graded and curved patches, tensors wider than one tile's window
+reach) cover it; the full-size 3D tests cover its default use on 3D levels
+above 65536 rows."""
 import sys
 
 import numpy as np
@@ -28,6 +29,12 @@ def torch_cuda():
 
 
 CASES = {
+    "square2x2_p2": lambda: W.unit_square_2x2(),
+    "square4x4_p4_l4": lambda: W.square_4x4_bezier(levels=4),
+    "single_patch_p5_l3": lambda: W.box_grid(2, [1, 1], 5, 2, 3, gdeg=1),
+    "box3x1_p1_l4": lambda: W.box_grid(2, [3, 1], 1, 2, 4, gdeg=1, dirichlet_sides=[0]),
+    "graded_square3x2_p3_l3": lambda: W.graded_square_3x2(),
+    "square_p8_l3": lambda: W.box_grid(2, [2, 2], 8, 2, 3, gdeg=1),
     "cube2x2x2_p3_l4": lambda: W.cube_2x2x2_trilinear(levels=4),
     "cube2x2x2_p2_l3": lambda: W.cube_2x2x2_trilinear(p=2, levels=3),
     "fichera7_p2_l3": lambda: W.fichera(2, 3),
@@ -92,7 +99,8 @@ def test_scatter_apply_matches_oracle(torch_cuda, name):
         assert np.array_equal(y, y2), l
 
 
-@pytest.mark.parametrize("name", ["cube2x2x2_p3_l4", "fichera7_p2_l3", "cube_p4_l3_neumann", "box_p5_l2"])
+@pytest.mark.parametrize("name", ["square4x4_p4_l4", "square_p8_l3", "cube2x2x2_p3_l4", "fichera7_p2_l3",
+                                  "cube_p4_l3_neumann", "box_p5_l2"])
 def test_scatter_and_gather_forms_agree(torch_cuda, name):
     """The two forms of the same half band differ by summation order only."""
     from paper_1804_02539_amd import igamg
@@ -109,8 +117,8 @@ def test_scatter_and_gather_forms_agree(torch_cuda, name):
         assert rel(ys, yg) < 1e-13, l
 
 
-@pytest.mark.parametrize("name", ["cube2x2x2_p3_l4", "fichera7_p2_l3", "graded_cube2x2x2_p2_l3",
-                                  "fine_cube_x_p2_m88"])
+@pytest.mark.parametrize("name", ["square4x4_p4_l4", "graded_square3x2_p3_l3", "cube2x2x2_p3_l4", "fichera7_p2_l3",
+                                  "graded_cube2x2x2_p2_l3", "fine_cube_x_p2_m88"])
 def test_scatter_cycle_and_solve_match_oracle(torch_cuda, name):
     """A V-cycle and a solve to 1e-8 with the scatter form on every level,
     against the oracle; graph replay and direct launches give the same bits."""
@@ -132,7 +140,8 @@ def test_scatter_cycle_and_solve_match_oracle(torch_cuda, name):
 
 
 @pytest.mark.parametrize("fd_mfma", [0, 1])
-@pytest.mark.parametrize("name", ["cube2x2x2_p3_l4", "fichera7_p2_l3", "cube_p4_l3_neumann", "box_p1_l4"])
+@pytest.mark.parametrize("name", ["square4x4_p4_l4", "cube2x2x2_p3_l4", "fichera7_p2_l3", "cube_p4_l3_neumann",
+                                  "box_p1_l4"])
 def test_scatter_fp32_cycle_and_mixed_solve(torch_cuda, name, fd_mfma):
     """FP32 half band in scatter form: the FP32 cycle within FP32 rounding of
     the oracle's FP64 cycle, and the mixed solve to the FP64 tolerance."""
@@ -153,8 +162,9 @@ def test_scatter_fp32_cycle_and_mixed_solve(torch_cuda, name, fd_mfma):
 
 def test_default_form_by_level_size(torch_cuda):
     """options.band_form = 0: the scatter form on the 3D levels above 65536
-    local rows (padded), the gather form below and on 2D levels.  The 2x2x2
-    p=3 cube: 343,000 local rows on the finest level, 55,296 on the next."""
+    local rows (padded), the gather form below, and on 2D levels up to 2^20
+    rows.  The 2x2x2 p=3 cube: 343,000 local rows on the finest level, 55,296
+    on the next."""
     from paper_1804_02539_amd import igamg
     S = igamg.Solver(W.cube_2x2x2_trilinear())
     L = S.prob.levels - 1
