@@ -28,19 +28,22 @@ def torch_cuda():
     return torch
 
 
+@pytest.mark.parametrize("band_form", [0, 2])
 @pytest.mark.parametrize("precision", [0, 1])
-def test_noalloc_setup_equals_setup_twice(torch_cuda, precision):
+def test_noalloc_setup_equals_setup_twice(torch_cuda, precision, band_form):
+    """band_form = 2 puts the scatter-form apply, and its windows in the
+    caller's workspace, on every level."""
     from paper_1804_02539_amd import igamg
     cases = [("cube2x2x2_p3_l4", lambda: W.cube_2x2x2_trilinear(levels=4)),
              ("square4x4_p3_l3", lambda: W.square_4x4_bezier(p=3, levels=3))]
     for name, make in cases:        # the second problem is the smaller one
         prob = make()
-        opts = igamg.default_options(precision=precision, autotune=0)
+        opts = igamg.default_options(precision=precision, autotune=0, band_form=band_form)
         ref = igamg.Solver(prob, opts)
         na = igamg.Solver(prob, opts, noalloc=True)
         assert na.N == ref.N
         nbytes = na.workspace.numel() - 256
-        _say(f"{name} precision={precision}: N = {na.N}, no-allocation workspace {nbytes} bytes, "
+        _say(f"{name} precision={precision} band_form={band_form}: N = {na.N}, no-allocation workspace {nbytes} bytes, "
              f"setup workspace {igamg.workspace_size(prob, opts)} bytes")
         assert nbytes <= igamg.workspace_size(prob, opts)
         r = np.random.default_rng(3).standard_normal(na.N)
