@@ -216,3 +216,31 @@ def test_bf16_precision_value():
     _expect(igamg.EINVAL, lambda: igamg.workspace_size(prob, igamg.default_options(precision=3)))
     _expect(igamg.EINVAL, lambda: igamg.workspace_size(prob, igamg.default_options(precision=igamg.MIXED_BF16,
                                                                                     fd_mfma=1)))
+
+
+def test_scatter_form_workspace_accounting():
+    """The workspace plan of the scatter-form apply, against the layout
+    formulas (host only).  The 2x2x2 p=3 cube: its finest level, 8 patches of
+    35^3 rows padded to 256 (344,064 rows, 1,344 tiles), is the only one
+    above 65,536 rows.  A tile's windows hold (p+1) 256 + (2p+1)(p + p n0)
+    = 1,780 values (n0 = 35), kept in FP64: 1,344 * 1,780 * 8 bytes more than
+    the gather form.  Mixed precision also stores that level's FP32 band as
+    the half band, nbh = 172 planes instead of 343."""
+    prob = W.cube_2x2x2_trilinear()
+    p, n0, tiles = 3, 35, 8 * ((35 ** 3 + 255) // 256)
+    assert tiles == 1344
+    ws = (p + 1) * 256 + (2 * p + 1) * (p + p * n0)
+    assert ws == 1780
+    windows = tiles * ws * 8
+    nb, nbh = (2 * p + 1) ** 3, ((2 * p + 1) ** 3 + 1) // 2
+    size = lambda **kw: igamg.workspace_size(prob, igamg.default_options(**kw))
+    assert size(band_form=0) - size(band_form=1) == windows
+    half32 = (nb - nbh) * tiles * 256 * 4
+    assert size(band_form=0, precision=igamg.MIXED) - size(band_form=1, precision=igamg.MIXED) == windows - half32
+    # 2D levels stay in the gather form below 2^19 rows, and band_form = 2
+    # adds windows of (p+1) 256 + (2p+1) p values per tile on every level
+    sq = W.square_4x4_bezier()
+    assert igamg.workspace_size(sq, igamg.default_options()) == igamg.workspace_size(sq, igamg.default_options(band_form=1))
+    assert igamg.workspace_size(sq, igamg.default_options(band_form=2)) > igamg.workspace_size(sq, igamg.default_options())
+    with pytest.raises(igamg.IgamgError):
+        igamg.workspace_size(prob, igamg.default_options(band_form=3))
