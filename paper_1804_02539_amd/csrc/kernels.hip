@@ -262,26 +262,32 @@ __global__ __launch_bounds__(256) void k_band_full(const TB* __restrict__ band, 
 // ---------------------------------------------------------------------------
 // The symmetric half band in scatter form.  Every stored coefficient
 // a = A[j][j+d] (d >= 0) is fetched once and used twice: y_j += a u_{j+d}
-// (forward) and, d > 0, y_{j+d} += a u_j (its mirror, A[j+d][j] = a).  A
-// workgroup takes one 256-row tile (local rows s .. s+255) with one wave per
-// layer of the stored offsets: in 3D the layer a2 = 0..P of (a0, a1, a2),
-// stride LS = n0 n1 rows; in 2D the line a1 = 0..P of (a0, a1), stride
-// LS = n0.  A wave adds the mirrored terms of its layer into a window of LDS
-// covering the rows they reach: layer 0 the rows s .. s+255+W, layer kk >= 1
-// the rows s + kk LS - W .. s + 255 + kk LS + W, with W = P + P n0 in 3D and
-// P in 2D (band_sym_reach).  Each window has one owner wave, which adds into it with
-// LDS atomics; a wave's LDS operations execute in program order, so every
-// position receives its terms in a fixed order.  The LDS windows are FP64
-// for both storage types: FP32 products are exact in FP64, and LDS FP32
-// atomic adds measured about 20x slower per instruction than FP64 ones on
-// this pattern (consecutive addresses, one instruction after another).  The
-// windows go to global
-// memory (per tile band_sym_window values: layer 0, then layers 1..P), the
-// first 256 positions of layer 0 with the tile's forward sums added, and
-// k_band_sym_reduce sums, for each row, the positions of the tiles whose
-// windows cover it, in a fixed order (layer, then tile), into r = f - y (or
-// y).  The windows cost (P+1)*256 + (2P+1)*W values per tile, written once
-// and read once, against nbh*256 coefficients.
+// (forward) and, d > 0, y_{j+d} += a u_j (its mirror, A[j+d][j] = a).
+//
+// A workgroup takes one 256-row tile (local rows s .. s+255) with one wave
+// per layer of the stored offsets: in 3D the layer a2 = 0..P of
+// (a0, a1, a2), LS = n0 n1 rows apart; in 2D the line a1 = 0..P of
+// (a0, a1), LS = n0 rows apart.  A wave adds the mirrored terms of its layer
+// into a window of LDS over the rows they reach: layer 0 the rows
+// s .. s+255+W, layer kk >= 1 the rows s + kk LS - W .. s + 255 + kk LS + W,
+// with W = P + P n0 in 3D and P in 2D (band_sym_reach).  Beside the window
+// it stages the u of the same rows, so a forward term reads u at the
+// position where its mirrored term lands.
+//
+// Each window has one owner wave, which adds into it with LDS atomics; a
+// wave's LDS operations execute in program order, so every position
+// receives its terms in a fixed order.  The windows are FP64 for both
+// storage types: FP32 products are exact in FP64, and LDS FP32 atomic adds
+// measured about 20x slower per instruction than FP64 ones on this pattern
+// (consecutive addresses, one instruction after another).
+//
+// The windows go to global memory (per tile band_sym_window values: layer 0,
+// then layers 1..P), the first 256 positions of layer 0 with the tile's
+// forward sums added, and k_band_sym_reduce sums, for each row, the
+// positions of the tiles whose windows cover it, in a fixed order (layer,
+// then tile), into r = f - y (or y).  The windows cost (P+1)*256 + (2P+1)*W
+// values per tile, written once and read once, against nbh*256 coefficients.
+
 // element idx of a uniform base, with a 32-bit byte offset (one VGPR per
 // address instead of two)
 template <typename T>
