@@ -138,7 +138,8 @@ typedef struct {
                              persistent launch per cycle (a work list of the cycle's phases,
                              V-cycle only); 0 (default): one launch per kernel               */
   int band_form;          /* banded apply of the symmetric half band (Sec. 4's patch matrices):
-                             0 (default): levels above 65536 local rows in 3D, or 2^19 in 2D,
+                             0 (default): levels above 65536 local rows in 3D, or in 2D
+                             2^17 (FP64 handles) or 2^19 (mixed handles),
                              read each stored coefficient once and add its mirrored term
                              through per-tile windows (two kernels; the FP32 copy of those
                              levels is the half band too), where a tile's windows and the u

@@ -338,19 +338,24 @@ static void tail_program(igamg_ctx& C, igamg_ctx::Tail& tl) {
 }
 
 // Rows above which options.band_form = 0 applies a 2D level in scatter
-// form.  Measured at p = 4: at 282K rows the FP64 apply is 15% faster in
-// scatter form but the FP32 one 8% slower (the windows cost more in 2D, one
-// line per layer); from 1.1M rows both are faster (13-24% up to 10M rows).
-constexpr int64_t SYM_MIN_ROWS_2D = int64_t(1) << 19;
+// form.  Measured at p = 4: at 78K rows both precisions are faster in the
+// gather form; at 282K rows the FP64 apply is 15% faster in scatter form but
+// the FP32 one 8% slower (the windows cost more in 2D, one line per layer);
+// from 1.1M rows both are faster (13-24% up to 10M rows).  A mixed handle's
+// levels take one form for both precisions.
+constexpr int64_t SYM_MIN_ROWS_2D_FP64 = int64_t(1) << 17;
+constexpr int64_t SYM_MIN_ROWS_2D_MIXED = int64_t(1) << 19;
 
 // Window values per tile of level L's banded apply in scatter form, or 0 for
 // the gather form: levels whose windows and u fit BAND_SYM_MAX_LDS in FP64
 // and, with options.band_form = 0, that have more than TAIL_MAX_ROWS rows in
-// 3D (smaller ones are launch-bound) or SYM_MIN_ROWS_2D in 2D; never the
+// 3D (smaller ones are launch-bound) or SYM_MIN_ROWS_2D_* in 2D; never the
 // levels of the persistent cycle, which reads the gather form.
 static int64_t band_sym_ws(const Hierarchy& H, const LevelH& L) {
   if (H.opt.band_form == 1) return 0;
-  const int64_t min_rows = H.prob.d == 3 ? TAIL_MAX_ROWS : SYM_MIN_ROWS_2D;
+  const int64_t min_rows = H.prob.d == 3                        ? TAIL_MAX_ROWS
+                           : H.opt.precision == IGAMG_MIXED ? SYM_MIN_ROWS_2D_MIXED
+                                                            : SYM_MIN_ROWS_2D_FP64;
   if (L.NL <= min_rows && H.opt.band_form == 0) return 0;
   if (L.NL <= TAIL_MAX_ROWS && H.opt.persistent) return 0;
   int64_t n0 = 1;

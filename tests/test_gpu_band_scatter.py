@@ -162,8 +162,8 @@ def test_scatter_fp32_cycle_and_mixed_solve(torch_cuda, name, fd_mfma):
 
 def test_default_form_by_level_size(torch_cuda):
     """options.band_form = 0: the scatter form on the 3D levels above 65536
-    local rows (padded), the gather form below, and on 2D levels up to 2^20
-    rows.  The 2x2x2 p=3 cube: 343,000 local rows on the finest level, 55,296
+    local rows (padded), the gather form below, and on 2D levels up to 2^17
+    rows (FP64) or 2^19 (mixed).  The 2x2x2 p=3 cube: 343,000 local rows on the finest level, 55,296
     on the next."""
     from paper_1804_02539_amd import igamg
     S = igamg.Solver(W.cube_2x2x2_trilinear())
@@ -173,6 +173,12 @@ def test_default_form_by_level_size(torch_cuda):
     assert all(S.band_form(l) == igamg.BAND_GATHER for l in range(1, L))
     S2 = igamg.Solver(W.square_4x4_bezier(levels=4))
     assert all(S2.band_form(l) == igamg.BAND_GATHER for l in range(1, 4))
+    # 2D, 282,624 rows on the finest level: above 2^17 (FP64 handles), not
+    # above 2^19 (mixed handles)
+    S7 = igamg.Solver(W.square_4x4_bezier(levels=7))
+    assert S7.band_form(-1) == igamg.BAND_SCATTER and S7.band_form(5) == igamg.BAND_GATHER
+    S7m = igamg.Solver(W.square_4x4_bezier(levels=7), igamg.default_options(precision=igamg.MIXED))
+    assert S7m.band_form(-1) == igamg.BAND_GATHER
 
 
 def test_windows_above_lds_limit_keep_gather_form(torch_cuda):

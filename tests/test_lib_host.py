@@ -237,10 +237,17 @@ def test_scatter_form_workspace_accounting():
     assert size(band_form=0) - size(band_form=1) == windows
     half32 = (nb - nbh) * tiles * 256 * 4
     assert size(band_form=0, precision=igamg.MIXED) - size(band_form=1, precision=igamg.MIXED) == windows - half32
-    # 2D levels stay in the gather form below 2^19 rows, and band_form = 2
-    # adds windows of (p+1) 256 + (2p+1) p values per tile on every level
+    # 2D: the 4x4 p=4 square keeps the gather form (its finest level has
+    # 77,824 rows); one level finer (16 patches of 132^2 rows: 1,104 tiles,
+    # 282,624 rows) takes the scatter form in an FP64 handle (above 2^17
+    # rows), with windows of 5 * 256 + 9 * 4 = 1,316 values per tile, and
+    # the gather form in a mixed one (up to 2^19 rows)
     sq = W.square_4x4_bezier()
     assert igamg.workspace_size(sq, igamg.default_options()) == igamg.workspace_size(sq, igamg.default_options(band_form=1))
     assert igamg.workspace_size(sq, igamg.default_options(band_form=2)) > igamg.workspace_size(sq, igamg.default_options())
+    sq7 = W.square_4x4_bezier(levels=7)
+    s7 = lambda **kw: igamg.workspace_size(sq7, igamg.default_options(**kw))
+    assert s7(band_form=0) - s7(band_form=1) == 1104 * 1316 * 8
+    assert s7(band_form=0, precision=igamg.MIXED) == s7(band_form=1, precision=igamg.MIXED)
     with pytest.raises(igamg.IgamgError):
         igamg.workspace_size(prob, igamg.default_options(band_form=3))
